@@ -1,0 +1,226 @@
+"""Throughput of the MD hot path on one MI355X.
+
+Headline: atom-timesteps/s of the 256,000-atom LJ melt (fcc 40^3 at reduced
+density 0.8442, rc 2.5, skin 0.3, T* 3.0, dt 0.005) in FP32-mixed precision
+with the thread-per-atom kernel; the plain FP64 path on the same workload,
+and the LJ adjoint (force VJP) throughput in atoms/s on eight 32,000-atom
+snapshots thermalised for 500 NVE steps, are reported beside it.
+
+Each "step" is one full velocity-Verlet step of md_step: kick + drift +
+displacement check, the rebuild chain when triggered (wrap, bin, sort, list),
+forces, kick, and thermo output every 100 steps.  Inputs are resident in HBM
+before the timed region starts.  Prints one JSON line on stdout.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
+THERMO_EVERY = 100
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def force_bytes_per_atom(mean_neigh: float) -> float:
+    """Algorithmic HBM bytes of one LJ force evaluation per atom: numneigh (4),
+    neighbour indices (4 per entry), own position (24) and force (24); the
+    neighbour positions are cache-served gathers (atoms are cell-sorted)."""
+    return 4.0 + 4.0 * mean_neigh + 24.0 + 24.0
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1009_4330_amd", "csrc", "md_forces.hip"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_name: str, launches_bytes: float):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current force-kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "force_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel_name)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def run_md(w, x, v, prec, kernel, steps, warmup):
+    import torch
+    from paper_1009_4330_amd import md
+    from paper_1009_4330_amd.system import MDSystem
+
+    sysm = MDSystem(w, x, v, prec, kernel)
+    sysm.setup(thermo=False)
+    if warmup:
+        sysm.run(warmup, THERMO_EVERY)
+    torch.cuda.synchronize()
+    md.md_timing_enable(10)
+    builds0 = md.md_nlist_status(sysm.nl)[md.MD_ST_BUILDS]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rows = sysm.run(steps, THERMO_EVERY)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    launches, ms = md.md_timing_read()
+    md.md_timing_enable(0)
+    words = md.md_nlist_status(sysm.nl)
+    nn = sysm.nl.numneigh.double().mean().item()
+    return dict(elapsed=elapsed, rows=rows, force_launches=launches,
+                force_ms_avg=ms / max(launches, 1), rebuilds=words[md.MD_ST_BUILDS] - builds0,
+                mean_neigh=nn, max_neigh=words[md.MD_ST_MAXNEIGH], n=w.natoms,
+                kernel=sysm.kernel)
+
+
+def bench_vjp(reps: int):
+    """Force-VJP atoms/s on the eight thermalised 32k-atom snapshots."""
+    import torch
+    from paper_1009_4330_amd import inputs as I
+    from paper_1009_4330_amd import md
+    from paper_1009_4330_amd.system import MDSystem
+
+    w = I.LJ_FM_32K
+    out = {}
+    for prec_name, prec in (("mixed", md.MD_MIXED), ("fp64", md.MD_FP64)):
+        total_t, total_atoms = 0.0, 0
+        for seed in I.FM_SEEDS:
+            x, v, box = I.initial_state(w, seed)
+            s = MDSystem(w, x, v, "fp64", "tpa")
+            s.setup(thermo=False)
+            s.run(w.steps, w.steps)
+            n = w.natoms
+            u = torch.randn(3, n, dtype=torch.float64, device="cuda",
+                            generator=torch.Generator(device="cuda").manual_seed(seed))
+            gx = torch.empty_like(u)
+            gp = torch.empty(2, dtype=torch.float64, device="cuda")
+            pot = md.lj_potential(w.rc, I.FM_TARGET[0], I.FM_TARGET[1], 0)
+            md.md_force_vjp(pot, s.state.x, s.box, s.nl, prec, u, gx, gp, s.ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                md.md_force_vjp(pot, s.state.x, s.box, s.nl, prec, u, gx, gp, s.ws)
+            torch.cuda.synchronize()
+            total_t += time.perf_counter() - t0
+            total_atoms += n * reps
+        out[prec_name] = total_atoms / total_t
+    return out
+
+
+def cpu_baseline(w, x, v, target_s: float = 15.0):
+    """The oracle's own NVE run on the host cores, on a bounded number of
+    steps of the same workload; setup (first build + forces) is subtracted."""
+    import oracle
+    p = oracle.params_for(w)
+    t0 = time.perf_counter()
+    oracle.md_run(p, x, v, w.box, 0, 1)
+    t_setup = time.perf_counter() - t0
+    probe = 5
+    t0 = time.perf_counter()
+    oracle.md_run(p, x, v, w.box, probe, probe)
+    per_step = max((time.perf_counter() - t0 - t_setup) / probe, 1e-4)
+    steps = int(max(probe, min(400, target_s / per_step)))
+    t0 = time.perf_counter()
+    oracle.md_run(p, x, v, w.box, steps, steps)
+    t = time.perf_counter() - t0 - t_setup
+    return dict(value=steps * w.natoms / t, unit="atom-timesteps/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=f"{steps} NVE steps of the {w.natoms}-atom LJ melt from the same seeded "
+                       f"state (FP64, setup excluded, {t:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time only the headline configuration")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1009_4330_amd import inputs as I
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    w = I.LJ_256K
+    x, v, _ = I.initial_state(w)
+    log(f"[bench] {w.name}: {w.natoms} atoms, mixed precision, thread-per-atom")
+    mixed = run_md(w, x, v, "mixed", "tpa", args.steps, args.warmup)
+    value = args.steps * w.natoms / mixed["elapsed"]
+    log(f"[bench] mixed: {value:.4g} atom-steps/s, {1e3 * mixed['elapsed'] / args.steps:.4f} "
+        f"ms/step, force avg {1e3 * mixed['force_ms_avg']:.2f} us")
+    extras = {}
+    if not args.no_extras:
+        fp64 = run_md(w, x, v, "fp64", "tpa", args.steps, args.warmup)
+        v64 = args.steps * w.natoms / fp64["elapsed"]
+        log(f"[bench] fp64: {v64:.4g} atom-steps/s, force avg {1e3 * fp64['force_ms_avg']:.2f} us")
+        vjp = bench_vjp(reps=20)
+        log(f"[bench] vjp atoms/s: {vjp}")
+        extras = {"fp64_atom_timesteps_per_s": v64, "mixed_over_fp64": value / v64,
+                  "fp64_force_kernel_us": 1e3 * fp64["force_ms_avg"],
+                  "adjoint_hvp_atoms_per_s": vjp["mixed"],
+                  "adjoint_hvp_atoms_per_s_fp64": vjp["fp64"]}
+
+    bpa = force_bytes_per_atom(mixed["mean_neigh"])
+    alg_bytes = bpa * w.natoms
+    avg_s = mixed["force_ms_avg"] * 1e-3
+    achieved = alg_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
+    kname = "k_lj_tpa<1, false>"
+    traffic = measured_traffic(kname, alg_bytes)
+    line = {
+        "metric": "atom-timesteps/s, LJ 256k atoms FP32-mixed vs FP64; adjoint HVP atoms/s",
+        "value": value,
+        "unit": "atom-timesteps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * mixed["elapsed"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair math, f64 positions/accumulation/integration",
+        "data": "synthetic",
+        "config": {"workload": "lj_melt_256k", "atoms": w.natoms, "lattice": "fcc 40^3",
+                   "density": 0.8442, "rc": w.rc, "skin": w.skin, "dt": w.dt, "temp": w.temp,
+                   "precision": "mixed", "kernel": "tpa", "thermo_every": THERMO_EVERY},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": kname, "bytes_per_atom": bpa,
+                     "launch_us": 1e3 * mixed["force_ms_avg"],
+                     "timed_launches": mixed["force_launches"]},
+        "rebuilds": mixed["rebuilds"],
+        "mean_neighbors": mixed["mean_neigh"],
+        **extras,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline(w, x, v)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

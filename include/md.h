@@ -1,0 +1,239 @@
+/*
+ * md.h -- C ABI of the MI355X short-range molecular-dynamics hot path.
+ *
+ * The operation is the per-atom pair-force evaluation over a full Verlet
+ * neighbour list described in the paper's section "Neighbor list approach"
+ * (the TpA and BpA listings: load atom i, loop over numneigh[i] entries of
+ * neighbors[i][.], accumulate the pair force, store f[i]), together with what
+ * feeds it on the GPU: cell binning of the periodic box (section "Cell list
+ * approach"), the list build with a skin and a half-skin rebuild trigger, and
+ * NVE velocity-Verlet integration ("NVE integrator", section "Design
+ * objectives, features and usage"); precision modes follow the same section
+ * (double, and mixed: pair forces in single precision, integration in double).
+ * Kernel choice follows the TpA / BpA discussion and the built-in
+ * mini-benchmark of section "Neighbor list approach".
+ *
+ * Conventions
+ *  - Every pointer is a DEVICE pointer unless marked [host].  The caller owns
+ *    every buffer; no call allocates or frees device memory, and no call
+ *    synchronises except md_step (once, at its end), md_nlist_status and
+ *    md_autoselect.  Work is enqueued on `stream` (a hipStream_t; NULL is the
+ *    default stream).
+ *  - Per-atom vectors are SoA FP64 [3][n]: n x values, then n y, then n z.
+ *  - The box is orthorhombic, periodic, with origin 0 and edges L[0..2].
+ *  - Errors are returned; nothing is thrown across the ABI.  Host-detectable
+ *    errors return before anything is enqueued.  Device-detected errors
+ *    (neighbour overflow, non-finite values) are recorded in nl->status and
+ *    reported by md_step / md_nlist_status.
+ *  - `ws` is a caller-owned device workspace of at least
+ *    md_workspace_bytes(...) bytes, 256-byte aligned.  Calls on one workspace
+ *    must not overlap in time (use one stream, or one workspace per stream).
+ */
+#ifndef MD_MI355X_H
+#define MD_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MD_OK = 0,
+  MD_ERR_INVALID_ARG = 1,    /* null pointer, n <= 0, bad enum, capacity < 1, ... */
+  MD_ERR_BOX_TOO_SMALL = 2,  /* some L_d <= 2 (rc + skin): minimum image not unique */
+  MD_ERR_NLIST_OVERFLOW = 3, /* an atom has more neighbours than nl->capacity */
+  MD_ERR_NONFINITE = 4,      /* a position or force became NaN / Inf */
+  MD_ERR_UNSUPPORTED = 5,    /* valid request the library does not implement */
+  MD_ERR_HIP = 6,            /* a HIP runtime call failed */
+  MD_ERR_WORKSPACE = 7       /* ws is NULL or smaller than md_workspace_bytes */
+} md_status;
+
+typedef enum { MD_FP64 = 0, MD_MIXED = 1 } md_precision;
+
+/* Force kernels.  The paper's thread-per-atom (TpA) and block-per-atom (BpA)
+   designs are the two ends of one family: K lanes of a 64-wide wavefront share
+   an atom and split its neighbour list, K a power of two in [1, 64].
+   MD_KERNEL_TPA is K = 1 (one lane per atom), MD_KERNEL_WPA is K = 64 (one
+   wavefront per atom, reduced with cross-lane operations); any power of two in
+   between may be passed as an md_kernel value.  MD_KERNEL_AUTO picks K with a
+   mini-benchmark (md_autoselect). */
+typedef enum { MD_KERNEL_AUTO = 0, MD_KERNEL_TPA = 1, MD_KERNEL_WPA = 64 } md_kernel;
+enum { MD_EFLAG = 1, MD_VFLAG = 2 };
+enum { MD_POT_LJ = 0, MD_POT_SC = 1 };
+
+/* Neighbour-list layout K (lanes per atom, as above): groups of G = 64 / K
+   consecutive atoms share rows of 64 ints, and entry m of atom i lives at
+     neigh[((i / G) * ceil(capacity / K) + m / K) * 64 + (i % G) * K + m % K],
+   so each row a wavefront reads is one contiguous 256-byte block.  K = 1:
+   entry m of atom i at ((i / 64) * capacity + m) * 64 + i % 64; K = 64: the
+   entries of atom i are consecutive.  A force kernel reads only a list of its
+   own K.  md_nlist_ints() gives the buffer size that fits every K. */
+enum { MD_LAYOUT_TPA = 1, MD_LAYOUT_WPA = 64 };
+
+/* nl->status words (device int[MD_STATUS_WORDS]). */
+enum {
+  MD_ST_ERRORS = 0,    /* bit 0: list overflow, bit 1: non-finite value */
+  MD_ST_MAXNEIGH = 1,  /* largest neighbour count of the last build (the required capacity) */
+  MD_ST_BUILDS = 2,    /* number of list builds so far (md_step increments it) */
+  MD_ST_REBUILD = 3,   /* internal: rebuild requested by the displacement check */
+  MD_STATUS_WORDS = 8
+};
+
+typedef struct { double L[3]; } md_box; /* [host] */
+
+/* [host] Potential.  LJ: phi(r) = 4 eps ((sigma/r)^12 - (sigma/r)^6) for r < rc
+   (lj/cut, the paper's Appendix A "LJ"); lj_shift != 0 subtracts phi(rc) from
+   the reported energy (forces unchanged).  SC (Sutton-Chen, standing in for the
+   paper's EAM benchmark): E = eps sum_i [1/2 sum_j (a/r_ij)^n - c sqrt(rho_i)],
+   rho_i = sum_j (a/r_ij)^m, both sums truncated at rc. */
+typedef struct {
+  int kind;          /* MD_POT_LJ or MD_POT_SC */
+  double rc;         /* force cutoff */
+  double lj_eps, lj_sigma;
+  int lj_shift;
+  double sc_eps, sc_a, sc_c;
+  int sc_n, sc_m;
+} md_potential;
+
+/* Cell grid: nc_d = floor(L_d / rl) cells per dimension (edge >= rl), linear
+   cell index cx + nc0 * (cy + nc1 * cz). */
+typedef struct {
+  int nc[3];           /* [out] set by md_bin_cells */
+  int64_t ncell_cap;   /* capacity: cell_start holds ncell_cap + 1 ints */
+  int* cell_start;     /* [ncell+1] first sorted slot of each cell */
+  int* atom_cell;      /* [n] cell of each atom (input order) */
+  int* perm;           /* [n] stable sort: atom indices cell by cell, increasing inside a cell */
+} md_cells;
+
+/* Full Verlet list: every ordered pair i != j with r_ij^2 < rl^2 appears in
+   row i, rl = rc + skin. */
+typedef struct {
+  int capacity;        /* entries per atom the neigh buffer holds */
+  int layout;          /* lanes per atom K (MD_LAYOUT_TPA = 1 ... MD_LAYOUT_WPA = 64) */
+  double rl;           /* [out] list radius of the last build */
+  int* neigh;          /* see layouts above */
+  int* numneigh;       /* [n] */
+  double* x_ref;       /* [3][n] positions at the last build (rebuild trigger reference) */
+  int* status;         /* [MD_STATUS_WORDS], zero it once before first use */
+} md_nlist;
+
+/* Dynamic state advanced by md_step.  Units: ftm2v converts force/mass * time
+   to velocity, mvv2e converts m v^2 to energy, boltz is k_B (all 1 in LJ
+   units). */
+typedef struct {
+  int64_t n;
+  double* x;           /* [3][n] */
+  double* v;           /* [3][n] */
+  double* f;           /* [3][n] */
+  int* id;             /* [n] caller's atom ids, permuted along with the atoms */
+  double mass;
+  double ftm2v, mvv2e, boltz;
+} md_state;
+
+/* Workspace bytes needed by any call for n atoms in this box with list radius
+   rl (covers the largest of all calls).  Returns 0 on invalid input. */
+size_t md_workspace_bytes(int64_t n, const md_box* box, double rl);
+
+/* Ints the neigh buffer must hold for n atoms and this capacity, in any
+   layout K (md_step and md_autoselect may switch layouts).  0 on bad input. */
+size_t md_nlist_ints(int64_t n, int capacity);
+
+/* Number of thermo rows md_step writes. */
+int md_thermo_rows(int nsteps, int thermo_every, int setup);
+
+/* Cell binning (wrap + bin + stable counting sort).  Wraps x in place into
+   [0, L) (x - L floor(x / L), an L result mapped to 0), bins each atom to
+   clamp((int)(x_d nc_d / L_d), 0, nc_d - 1), and writes atom_cell,
+   cell_start and perm.  Cells per dimension follow from box and rl; the call
+   fails with MD_ERR_INVALID_ARG if their product exceeds cells->ncell_cap. */
+md_status md_bin_cells(double* x, int64_t n, const md_box* box, double rl,
+                       md_cells* cells, void* ws, size_t ws_bytes, void* stream);
+
+/* Reorder atoms into cell order (slot k takes atom cells->perm[k]): x, v, id
+   and, when not NULL, f and x_ref are gathered through perm.  Makes neighbour
+   gathers spatially local (the paper assumes spatially ordered atoms for its
+   cached neighbour reads). */
+md_status md_sort_atoms(md_state* st, const md_cells* cells, double* x_ref, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/* Full neighbour list at rl = rc + skin from binned positions (x as wrapped by
+   md_bin_cells, in any atom order: cell members are taken through perm).
+   Distances use the minimum image d - L rint(d / L) and
+   r^2 = (dx dx + dy dy) + dz dz without fused multiply-add, so the pair set is
+   exactly that of the FP64 definition.  Sets nl->rl, copies x to nl->x_ref,
+   records the largest count in status[MD_ST_MAXNEIGH] and sets the overflow
+   bit if it exceeds nl->capacity (entries past capacity are dropped). */
+md_status md_build_neighbors(const double* x, int64_t n, const md_box* box,
+                             const md_cells* cells, double rc, double skin, md_nlist* nl,
+                             void* stream);
+
+/* Forces (and, on flags, energy / virial) from a list.  f [3][n] is
+   overwritten.  ev, when flags != 0, receives 7 doubles: energy, then virial
+   xx yy zz xy xz yz, W = 1/2 sum_i sum_j d_ij (x) F_ij.  Only pairs with
+   r^2 < rc^2 (FP64, as above) contribute, in either precision.  MD_MIXED
+   forms d and r^2 in FP64, evaluates the scalar pair function in FP32, and
+   accumulates forces, energy and virial in FP64.  k = AUTO uses the kernel
+   matching nl->layout; TPA / WPA must match the layout (else
+   MD_ERR_INVALID_ARG). */
+md_status md_compute_forces(const md_potential* p, const double* x, int64_t n,
+                            const md_box* box, const md_nlist* nl, md_precision prec,
+                            md_kernel k, int flags, double* f, double* ev, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/* nsteps of velocity-Verlet NVE (dtfm = (0.5 dt ftm2v) / mass):
+     v += dtfm f; x += dt v;
+     rebuild (wrap, bin, sort, list) if max_i |x_i - x_ref_i|^2 > (skin/2)^2;
+     f = forces(x); v += dtfm f.
+   With setup != 0 the state is first wrapped, binned, sorted and listed and
+   forces are computed (a thermo row for that state is written first).
+   thermo (device, md_thermo_rows(...) x 8 doubles, or NULL for none): for
+   each step s with s % thermo_every == 0: s, pe, ke, pe + ke,
+   T = 2 ke / ((3n - 3) kB), P = (2 ke + tr W) / (3 V), builds so far,
+   largest neighbour count.
+   Atoms are kept in cell order; st->id tracks them.  k = AUTO runs the
+   TpA / WPA mini-benchmark at setup (see md_autoselect).  Synchronises the
+   stream once at the end and returns the device status (overflow /
+   non-finite); after an overflow the state is not valid: grow the list and
+   restart from a saved state. */
+md_status md_step(md_state* st, const md_potential* p, const md_box* box, md_cells* cells,
+                  md_nlist* nl, md_precision prec, md_kernel k, double skin, double dt,
+                  int nsteps, int thermo_every, int setup, double* thermo, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/* Vector-Jacobian product of the LJ forces: gx = (dF/dx)^T u = -H u, with
+   u, gx [3][n]; gparam (may be NULL) receives dL/deps, dL/dsigma for the
+   cotangent u (2 doubles).  Pair set: listed pairs with r^2 < rc^2 (rc is not
+   scaled by sigma).  SC returns MD_ERR_UNSUPPORTED. */
+md_status md_force_vjp(const md_potential* p, const double* x, int64_t n, const md_box* box,
+                       const md_nlist* nl, md_precision prec, const double* u, double* gx,
+                       double* gparam, void* ws, size_t ws_bytes, void* stream);
+
+/* Mini-benchmark (the paper's setup-time TpA/BpA selection, over every K):
+   for K = 1, 2, 4, ..., 64 build the list in layout K from x and time `reps`
+   force launches; *choice [host] gets the fastest K.  The list is left in
+   that layout.  Synchronises.  The winner is cached per (potential type,
+   precision, neighbour-count bucket) and md_step's AUTO reuses it. */
+md_status md_autoselect(const md_potential* p, const double* x, int64_t n, const md_box* box,
+                        const md_cells* cells, double skin, md_nlist* nl, md_precision prec,
+                        int reps, md_kernel* choice, void* ws, size_t ws_bytes, void* stream);
+
+/* Copy the status words to the host (synchronises the stream). */
+md_status md_nlist_status(const md_nlist* nl, int* words /*[host] MD_STATUS_WORDS*/,
+                          void* stream);
+
+/* Kernel timing.  While enabled, every `every`-th force-kernel launch made by
+   md_step / md_compute_forces is bracketed by start/stop timestamps recorded
+   inside its dispatch (hipExtLaunchKernel events).  md_timing_read returns the
+   number of timed launches and their summed duration in ms, and resets the
+   sums.  Reading synchronises the device. */
+md_status md_timing_enable(int every);
+md_status md_timing_read(int64_t* launches /*[host]*/, double* total_ms /*[host]*/);
+
+const char* md_status_string(md_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MD_MI355X_H */

@@ -1,0 +1,766 @@
+// C ABI of the MD hot path: argument validation, workspace carve-up, and the
+// orchestration of the kernels in md_bin.hip, md_forces.hip and
+// md_integrate.hip.  Nothing here allocates device memory.
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "md_internal.hpp"
+
+using namespace md;
+
+namespace {
+
+#define MD_CK(call)                                   \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return MD_ERR_HIP;          \
+  } while (0)
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+md_status check_box(const md_box* box, double rl) {
+  if (!box || !finite_pos(rl)) return MD_ERR_INVALID_ARG;
+  for (int d = 0; d < 3; ++d) {
+    if (!finite_pos(box->L[d])) return MD_ERR_INVALID_ARG;
+    if (!(box->L[d] > 2.0 * rl)) return MD_ERR_BOX_TOO_SMALL;
+  }
+  return MD_OK;
+}
+
+bool cell_dims(const md_box* box, double rl, int nc[3], int64_t* ncell) {
+  int64_t prod = 1;
+  for (int d = 0; d < 3; ++d) {
+    const double q = std::floor(box->L[d] / rl);
+    if (!(q >= 1.0) || q > 1e6) return false;
+    nc[d] = (int)q;
+    prod *= nc[d];
+  }
+  if (prod > INT_MAX / 2) return false;
+  *ncell = prod;
+  return true;
+}
+
+BoxK make_box(const md_box* b) {
+  BoxK k;
+  for (int d = 0; d < 3; ++d) {
+    k.L[d] = b->L[d];
+    k.inv[d] = 1.0 / b->L[d];
+  }
+  return k;
+}
+
+bool n_ok(int64_t n) { return n >= 1 && n <= (int64_t)INT_MAX - 1024; }
+
+md_status check_pot(const md_potential* p) {
+  if (!p || !finite_pos(p->rc)) return MD_ERR_INVALID_ARG;
+  if (p->kind == MD_POT_LJ) {
+    if (!finite_pos(p->lj_eps) || !finite_pos(p->lj_sigma)) return MD_ERR_INVALID_ARG;
+    return MD_OK;
+  }
+  if (p->kind == MD_POT_SC) {
+    if (!finite_pos(p->sc_eps) || !finite_pos(p->sc_a) || !std::isfinite(p->sc_c) ||
+        p->sc_n < 1 || p->sc_m < 1 || p->sc_n > 64 || p->sc_m > 64)
+      return MD_ERR_INVALID_ARG;
+    return MD_OK;
+  }
+  return MD_ERR_INVALID_ARG;
+}
+
+LJK make_lj(const md_potential* p) {
+  LJK k;
+  const double eps = p->lj_eps, sig = p->lj_sigma;
+  k.rc2 = p->rc * p->rc;
+  k.sig2 = sig * sig;
+  k.eps4 = 4.0 * eps;
+  k.eps24 = 24.0 * eps;
+  k.eps48 = 48.0 * eps;
+  k.ecut = 0.0;
+  if (p->lj_shift) {
+    const double r = k.sig2 / k.rc2;
+    const double sr6 = r * r * r;
+    k.ecut = k.eps4 * (sr6 * sr6 - sr6);
+  }
+  k.sig2f = (float)k.sig2;
+  k.eps4f = (float)k.eps4;
+  k.eps24f = (float)k.eps24;
+  k.eps48f = (float)k.eps48;
+  k.ecutf = (float)k.ecut;
+  k.inv_sig = 1.0 / sig;
+  return k;
+}
+
+SCK make_sc(const md_potential* p) {
+  SCK k;
+  k.rc2 = p->rc * p->rc;
+  k.a2 = p->sc_a * p->sc_a;
+  k.eps = p->sc_eps;
+  k.neps = p->sc_n * p->sc_eps;
+  k.mepsc_half = 0.5 * p->sc_m * p->sc_eps * p->sc_c;
+  k.epsc = p->sc_eps * p->sc_c;
+  k.a2f = (float)k.a2;
+  k.nepsf = (float)k.neps;
+  k.mepsc_halff = (float)k.mepsc_half;
+  k.n = p->sc_n;
+  k.m = p->sc_m;
+  return k;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+md_status check_ws(void* ws, size_t ws_bytes, const WsLayout& L) {
+  if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return MD_ERR_WORKSPACE;
+  return MD_OK;
+}
+
+// ------------------------------------------------------------ timing --
+
+struct Timing {
+  std::mutex mu;
+  int every = 0;
+  int64_t counter = 0;
+  std::vector<hipEvent_t> pool;          // pairs: [2k] start, [2k+1] stop
+  size_t used = 0;                       // pairs recorded since the last read
+  int64_t launches = 0;
+  double total_ms = 0.0;
+};
+Timing g_timing;
+constexpr size_t kTimingPairs = 4096;
+
+// Events for the next force launch, or nulls when this launch is not sampled.
+void timing_events(hipEvent_t* t0, hipEvent_t* t1) {
+  *t0 = *t1 = nullptr;
+  std::lock_guard<std::mutex> lk(g_timing.mu);
+  if (g_timing.every <= 0) return;
+  if (g_timing.counter++ % g_timing.every != 0) return;
+  if (g_timing.used >= kTimingPairs || g_timing.pool.size() < 2 * kTimingPairs) return;
+  *t0 = g_timing.pool[2 * g_timing.used];
+  *t1 = g_timing.pool[2 * g_timing.used + 1];
+  ++g_timing.used;
+}
+
+// ------------------------------------------------------ AUTO selection --
+
+std::mutex g_auto_mu;
+std::map<std::tuple<int, int, int>, md_kernel> g_auto_cache;
+
+int count_bucket(int maxcount) {
+  int b = 0;
+  while ((1 << b) < maxcount && b < 30) ++b;
+  return b;
+}
+
+md_status force_dispatch(const md_potential* p, const ForceArgs& fa, md_precision prec,
+                         int kernel, double* sc_e, hipStream_t s) {
+  hipError_t e;
+  if (p->kind == MD_POT_LJ)
+    e = launch_lj(fa, make_lj(p), prec, kernel, s);
+  else
+    e = launch_sc(fa, make_sc(p), prec, kernel, sc_e, s);
+  return e == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+// Build a list in `layout` from positions x (sorted or input order).
+md_status build_list(const double* x, int n, int sorted, const md_box* box, const int nc[3],
+                     const md_cells* cells, double rl, md_nlist* nl, int layout,
+                     hipStream_t s) {
+  BuildArgs a{};
+  a.x = x;
+  a.n = n;
+  a.sorted = sorted;
+  a.box = make_box(box);
+  for (int d = 0; d < 3; ++d) a.nc[d] = nc[d];
+  a.cell_start = cells->cell_start;
+  a.atom_cell = cells->atom_cell;
+  a.perm = cells->perm;
+  a.rl2 = rl * rl;
+  a.cap = nl->capacity;
+  a.layout = layout;
+  a.neigh = nl->neigh;
+  a.numneigh = nl->numneigh;
+  a.x_ref = nl->x_ref;
+  a.status = nl->status;
+  MD_CK(launch_build(a, s));
+  nl->layout = layout;
+  nl->rl = rl;
+  return MD_OK;
+}
+
+// Time `reps` force launches for every lanes-per-atom count K = 1, 2, ..., 64
+// (each with its own list layout) and keep the fastest.  Leaves the list in
+// the winner's layout.  The trial builds are not counted as builds of the run.
+md_status autoselect_impl(const md_potential* p, const double* x, int n, int sorted,
+                          const md_box* box, const md_cells* cells, double rl, md_nlist* nl,
+                          md_precision prec, int reps, md_kernel* choice, void* ws,
+                          const WsLayout& L, hipStream_t s) {
+  int nc[3] = {cells->nc[0], cells->nc[1], cells->nc[2]};
+  int before[MD_STATUS_WORDS];
+  MD_CK(hipMemcpyAsync(before, nl->status, sizeof(before), hipMemcpyDeviceToHost, s));
+  MD_CK(hipStreamSynchronize(s));
+  hipEvent_t e0, e1;
+  MD_CK(hipEventCreate(&e0));
+  MD_CK(hipEventCreate(&e1));
+  float best = 1e30f;
+  int win = MD_KERNEL_TPA;
+  int maxcount = 0;
+  for (int k = 1; k <= kWave; k *= 2) {
+    md_status st = build_list(x, n, sorted, box, nc, cells, rl, nl, k, s);
+    if (st != MD_OK) return st;
+    ForceArgs fa{};
+    fa.x = x;
+    fa.n = n;
+    fa.box = make_box(box);
+    fa.neigh = nl->neigh;
+    fa.numneigh = nl->numneigh;
+    fa.cap = nl->capacity;
+    fa.f = at<double>(ws, L.tmp_f);   // scratch forces: the caller's f is untouched
+    st = force_dispatch(p, fa, prec, k, at<double>(ws, L.sc_e), s);
+    if (st != MD_OK) return st;
+    MD_CK(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) {
+      st = force_dispatch(p, fa, prec, k, at<double>(ws, L.sc_e), s);
+      if (st != MD_OK) return st;
+    }
+    MD_CK(hipEventRecord(e1, s));
+    MD_CK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    MD_CK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      win = k;
+    }
+  }
+  int words[MD_STATUS_WORDS];
+  MD_CK(hipMemcpyAsync(words, nl->status, sizeof(words), hipMemcpyDeviceToHost, s));
+  MD_CK(hipStreamSynchronize(s));
+  maxcount = words[MD_ST_MAXNEIGH];
+  MD_CK(hipEventDestroy(e0));
+  MD_CK(hipEventDestroy(e1));
+  if (win != kWave) {
+    md_status st = build_list(x, n, sorted, box, nc, cells, rl, nl, win, s);
+    if (st != MD_OK) return st;
+  }
+  MD_CK(hipMemcpyAsync(nl->status + MD_ST_BUILDS, before + MD_ST_BUILDS, sizeof(int),
+                       hipMemcpyHostToDevice, s));
+  MD_CK(hipStreamSynchronize(s));
+  {
+    std::lock_guard<std::mutex> lk(g_auto_mu);
+    g_auto_cache[std::make_tuple(p->kind, (int)prec, count_bucket(maxcount))] = (md_kernel)win;
+  }
+  *choice = (md_kernel)win;
+  return MD_OK;
+}
+
+// Cached AUTO winner for this potential, precision and neighbour-count bucket.
+bool cached_choice(const md_potential* p, md_precision prec, int maxcount, int* lanes) {
+  std::lock_guard<std::mutex> lk(g_auto_mu);
+  auto it = g_auto_cache.find(std::make_tuple(p->kind, (int)prec, count_bucket(maxcount)));
+  if (it == g_auto_cache.end()) return false;
+  *lanes = (int)it->second;
+  return true;
+}
+
+// The lanes-per-atom count a kernel request resolves to for a list layout,
+// or 0 when the request does not match the layout.
+int resolve_lanes(md_kernel k, int layout) {
+  if (!lanes_ok(layout)) return 0;
+  if (k == MD_KERNEL_AUTO) return layout;
+  return (int)k == layout ? layout : 0;
+}
+
+md_status status_from_words(const int* w) {
+  if (w[MD_ST_ERRORS] & 1) return MD_ERR_NLIST_OVERFLOW;
+  if (w[MD_ST_ERRORS] & 2) return MD_ERR_NONFINITE;
+  return MD_OK;
+}
+
+}  // namespace
+
+namespace md {
+
+WsLayout ws_layout(int64_t n, int64_t ncell) {
+  WsLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o += align256(bytes);
+    return r;
+  };
+  const size_t nn = (size_t)n;
+  L.count = take(sizeof(int) * (size_t)(ncell > 0 ? ncell : 1));
+  L.slot = take(sizeof(int) * nn);
+  L.tmp_perm = take(sizeof(int) * nn);
+  L.tmp_x = take(sizeof(double) * 3 * nn);
+  L.tmp_v = take(sizeof(double) * 3 * nn);
+  L.tmp_f = take(sizeof(double) * 3 * nn);
+  L.tmp_id = take(sizeof(int) * nn);
+  L.eatom = take(sizeof(double) * nn);
+  L.vatom = take(sizeof(double) * 6 * nn);
+  L.keatom = take(sizeof(double) * nn);
+  L.sc_e = take(sizeof(double) * nn);
+  L.partials = take(sizeof(double) * kReduceBlocks * kReduceCols);
+  L.scalars = take(sizeof(double) * 16);
+  L.ticket = take(sizeof(int) * 64);
+  L.total = o;
+  return L;
+}
+
+}  // namespace md
+
+extern "C" {
+
+size_t md_workspace_bytes(int64_t n, const md_box* box, double rl) {
+  if (!n_ok(n) || check_box(box, rl) != MD_OK) return 0;
+  int nc[3];
+  int64_t ncell;
+  if (!cell_dims(box, rl, nc, &ncell)) return 0;
+  return ws_layout(n, ncell).total;
+}
+
+size_t md_nlist_ints(int64_t n, int capacity) {
+  if (!n_ok(n) || capacity < 1) return 0;
+  size_t most = 0;
+  for (int k = 1; k <= kWave; k *= 2) {
+    const size_t groups = (size_t)((n + kWave / k - 1) / (kWave / k));
+    const size_t ints = groups * nl_rows(capacity, k) * kWave;
+    most = ints > most ? ints : most;
+  }
+  return most;
+}
+
+int md_thermo_rows(int nsteps, int thermo_every, int setup) {
+  if (nsteps < 0 || thermo_every < 1) return 0;
+  return nsteps / thermo_every + (setup ? 1 : 0);
+}
+
+const char* md_status_string(md_status s) {
+  switch (s) {
+    case MD_OK: return "ok";
+    case MD_ERR_INVALID_ARG: return "invalid argument";
+    case MD_ERR_BOX_TOO_SMALL: return "box edge not larger than twice the list radius";
+    case MD_ERR_NLIST_OVERFLOW: return "neighbour list capacity exceeded";
+    case MD_ERR_NONFINITE: return "non-finite position or force";
+    case MD_ERR_UNSUPPORTED: return "unsupported request";
+    case MD_ERR_HIP: return "HIP runtime error";
+    case MD_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+  }
+  return "unknown status";
+}
+
+md_status md_bin_cells(double* x, int64_t n, const md_box* box, double rl, md_cells* cells,
+                       void* ws, size_t ws_bytes, void* stream) {
+  if (!x || !cells || !cells->cell_start || !cells->atom_cell || !cells->perm || !n_ok(n))
+    return MD_ERR_INVALID_ARG;
+  md_status st = check_box(box, rl);
+  if (st != MD_OK) return st;
+  int nc[3];
+  int64_t ncell;
+  if (!cell_dims(box, rl, nc, &ncell) || ncell > cells->ncell_cap) return MD_ERR_INVALID_ARG;
+  const WsLayout L = ws_layout(n, ncell);
+  if ((st = check_ws(ws, ws_bytes, L)) != MD_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int ni = (int)n;
+  int* count = at<int>(ws, L.count);
+  MD_CK(launch_fill_int(count, ncell, 0, s));
+  MD_CK(launch_fill_int(at<int>(ws, L.ticket), 1, 0, s));
+  MD_CK(launch_bin_count(x, ni, make_box(box), nc, cells->atom_cell, count, at<int>(ws, L.slot),
+                         cells->cell_start, at<int>(ws, L.ticket), nullptr, s));
+  MD_CK(launch_scatter(cells->atom_cell, at<int>(ws, L.slot), cells->cell_start, ni,
+                       at<int>(ws, L.tmp_perm), nullptr, s));
+  MD_CK(launch_cell_sort(at<int>(ws, L.tmp_perm), cells->cell_start, (int)ncell, cells->perm,
+                         nullptr, nullptr, nullptr, nullptr, ni, nullptr, nullptr, nullptr,
+                         nullptr, nullptr, s));
+  for (int d = 0; d < 3; ++d) cells->nc[d] = nc[d];
+  return MD_OK;
+}
+
+md_status md_sort_atoms(md_state* st, const md_cells* cells, double* x_ref, void* ws,
+                        size_t ws_bytes, void* stream) {
+  if (!st || !cells || !cells->perm || !st->x || !st->v || !st->id || !n_ok(st->n))
+    return MD_ERR_INVALID_ARG;
+  const WsLayout L = ws_layout(st->n, 1);
+  md_status s0 = check_ws(ws, ws_bytes, L);
+  if (s0 != MD_OK) return s0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = (int)st->n;
+  double* tx = at<double>(ws, L.tmp_x);
+  double* tv = at<double>(ws, L.tmp_v);
+  double* tf = at<double>(ws, L.tmp_f);
+  int* tid = at<int>(ws, L.tmp_id);
+  MD_CK(launch_gather3(cells->perm, n, st->x, tx, s));
+  MD_CK(launch_gather3(cells->perm, n, st->v, tv, s));
+  MD_CK(launch_gather_int(cells->perm, n, st->id, tid, s));
+  if (st->f) MD_CK(launch_gather3(cells->perm, n, st->f, tf, s));
+  MD_CK(launch_copy_back(st->x, st->v, st->id, st->f, nullptr, tx, tv, tid, tf, n, s));
+  if (x_ref) {
+    MD_CK(launch_gather3(cells->perm, n, x_ref, tx, s));
+    MD_CK(launch_copy_back(x_ref, nullptr, nullptr, nullptr, nullptr, tx, nullptr, nullptr,
+                           nullptr, n, s));
+  }
+  return MD_OK;
+}
+
+md_status md_build_neighbors(const double* x, int64_t n, const md_box* box,
+                             const md_cells* cells, double rc, double skin, md_nlist* nl,
+                             void* stream) {
+  if (!x || !cells || !nl || !nl->neigh || !nl->numneigh || !nl->status || !n_ok(n) ||
+      nl->capacity < 1 || !(skin >= 0.0) || !std::isfinite(skin) || !lanes_ok(nl->layout) ||
+      !cells->cell_start || !cells->atom_cell || !cells->perm)
+    return MD_ERR_INVALID_ARG;
+  const double rl = rc + skin;
+  md_status st = check_box(box, rl);
+  if (st != MD_OK) return st;
+  int nc[3];
+  int64_t ncell;
+  if (!cell_dims(box, rl, nc, &ncell)) return MD_ERR_INVALID_ARG;
+  for (int d = 0; d < 3; ++d)
+    if (cells->nc[d] != nc[d]) return MD_ERR_INVALID_ARG;  // cells were binned at another rl
+  return build_list(x, (int)n, 0, box, nc, cells, rl, nl, nl->layout,
+                    static_cast<hipStream_t>(stream));
+}
+
+md_status md_compute_forces(const md_potential* p, const double* x, int64_t n,
+                            const md_box* box, const md_nlist* nl, md_precision prec,
+                            md_kernel k, int flags, double* f, double* ev, void* ws,
+                            size_t ws_bytes, void* stream) {
+  md_status st = check_pot(p);
+  if (st != MD_OK) return st;
+  if (!x || !nl || !nl->neigh || !nl->numneigh || !f || !n_ok(n) || nl->capacity < 1 ||
+      (prec != MD_FP64 && prec != MD_MIXED) || (flags & ~(MD_EFLAG | MD_VFLAG)) ||
+      (flags && !ev))
+    return MD_ERR_INVALID_ARG;
+  const int kernel = resolve_lanes(k, nl->layout);
+  if (!kernel) return MD_ERR_INVALID_ARG;
+  if ((st = check_box(box, nl->rl > p->rc ? nl->rl : p->rc)) != MD_OK) return st;
+  const WsLayout L = ws_layout(n, 1);
+  if ((st = check_ws(ws, ws_bytes, L)) != MD_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ForceArgs fa{};
+  fa.x = x;
+  fa.n = (int)n;
+  fa.box = make_box(box);
+  fa.neigh = nl->neigh;
+  fa.numneigh = nl->numneigh;
+  fa.cap = nl->capacity;
+  fa.f = f;
+  if (flags) {
+    fa.ev.eatom = at<double>(ws, L.eatom);
+    fa.ev.vatom = at<double>(ws, L.vatom);
+  }
+  timing_events(&fa.t0, &fa.t1);
+  if ((st = force_dispatch(p, fa, prec, kernel, at<double>(ws, L.sc_e), s)) != MD_OK) return st;
+  if (flags) {
+    SumArgs sa{};
+    sa.cols = 7;
+    sa.col[0] = fa.ev.eatom;
+    for (int q = 0; q < 6; ++q) sa.col[1 + q] = fa.ev.vatom + (size_t)q * n;
+    sa.n = (int)n;
+    sa.partials = at<double>(ws, L.partials);
+    sa.out = ev;
+    MD_CK(launch_sum(sa, s));
+  }
+  return MD_OK;
+}
+
+md_status md_force_vjp(const md_potential* p, const double* x, int64_t n, const md_box* box,
+                       const md_nlist* nl, md_precision prec, const double* u, double* gx,
+                       double* gparam, void* ws, size_t ws_bytes, void* stream) {
+  md_status st = check_pot(p);
+  if (st != MD_OK) return st;
+  if (p->kind != MD_POT_LJ) return MD_ERR_UNSUPPORTED;
+  if (!x || !nl || !nl->neigh || !nl->numneigh || !u || !gx || !n_ok(n) || nl->capacity < 1 ||
+      (prec != MD_FP64 && prec != MD_MIXED) || !lanes_ok(nl->layout))
+    return MD_ERR_INVALID_ARG;
+  if ((st = check_box(box, nl->rl > p->rc ? nl->rl : p->rc)) != MD_OK) return st;
+  const WsLayout L = ws_layout(n, 1);
+  if ((st = check_ws(ws, ws_bytes, L)) != MD_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ForceArgs fa{};
+  fa.x = x;
+  fa.n = (int)n;
+  fa.box = make_box(box);
+  fa.neigh = nl->neigh;
+  fa.numneigh = nl->numneigh;
+  fa.cap = nl->capacity;
+  timing_events(&fa.t0, &fa.t1);
+  double* pe = gparam ? at<double>(ws, L.eatom) : nullptr;
+  double* ps = gparam ? at<double>(ws, L.keatom) : nullptr;
+  MD_CK(launch_lj_vjp(fa, make_lj(p), prec, nl->layout, u, gx, pe, ps, s));
+  if (gparam) {
+    SumArgs sa{};
+    sa.cols = 2;
+    sa.col[0] = pe;
+    sa.col[1] = ps;
+    sa.n = (int)n;
+    sa.partials = at<double>(ws, L.partials);
+    sa.out = at<double>(ws, L.scalars);
+    MD_CK(launch_sum(sa, s));
+    // dL/deps = (sum_i u_i . F_i) / eps; the second sum is dL/dsigma already
+    MD_CK(launch_vjp_params(at<double>(ws, L.scalars), p->lj_eps, gparam, s));
+  }
+  return MD_OK;
+}
+
+md_status md_nlist_status(const md_nlist* nl, int* words, void* stream) {
+  if (!nl || !nl->status || !words) return MD_ERR_INVALID_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  MD_CK(hipMemcpyAsync(words, nl->status, sizeof(int) * MD_STATUS_WORDS, hipMemcpyDeviceToHost,
+                       s));
+  MD_CK(hipStreamSynchronize(s));
+  return MD_OK;
+}
+
+md_status md_autoselect(const md_potential* p, const double* x, int64_t n, const md_box* box,
+                        const md_cells* cells, double skin, md_nlist* nl, md_precision prec,
+                        int reps, md_kernel* choice, void* ws, size_t ws_bytes, void* stream) {
+  md_status st = check_pot(p);
+  if (st != MD_OK) return st;
+  if (!x || !cells || !nl || !nl->neigh || !nl->numneigh || !nl->status || !choice ||
+      !n_ok(n) || nl->capacity < 1 || reps < 1 || (prec != MD_FP64 && prec != MD_MIXED) ||
+      !(skin >= 0.0))
+    return MD_ERR_INVALID_ARG;
+  const double rl = p->rc + skin;
+  if ((st = check_box(box, rl)) != MD_OK) return st;
+  int nc[3];
+  int64_t ncell;
+  if (!cell_dims(box, rl, nc, &ncell)) return MD_ERR_INVALID_ARG;
+  for (int d = 0; d < 3; ++d)
+    if (cells->nc[d] != nc[d]) return MD_ERR_INVALID_ARG;
+  const WsLayout L = ws_layout(n, ncell);
+  if ((st = check_ws(ws, ws_bytes, L)) != MD_OK) return st;
+  return autoselect_impl(p, x, (int)n, 0, box, cells, rl, nl, prec, reps, choice, ws, L,
+                         static_cast<hipStream_t>(stream));
+}
+
+md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_cells* cells,
+                  md_nlist* nl, md_precision prec, md_kernel k, double skin, double dt,
+                  int nsteps, int thermo_every, int setup, double* thermo, void* ws,
+                  size_t ws_bytes, void* stream) {
+  md_status st = check_pot(p);
+  if (st != MD_OK) return st;
+  if (!stt || !stt->x || !stt->v || !stt->f || !stt->id || stt->n < 2 || !n_ok(stt->n) ||
+      !cells || !cells->cell_start || !cells->atom_cell || !cells->perm || !nl || !nl->neigh ||
+      !nl->numneigh || !nl->x_ref || !nl->status || nl->capacity < 1 || nsteps < 0 ||
+      thermo_every < 1 || !(skin > 0.0) || !std::isfinite(skin) || !finite_pos(dt) ||
+      !finite_pos(stt->mass) || !finite_pos(stt->ftm2v) || !finite_pos(stt->mvv2e) ||
+      !finite_pos(stt->boltz) || (prec != MD_FP64 && prec != MD_MIXED) ||
+      (k != MD_KERNEL_AUTO && !lanes_ok((int)k)))
+    return MD_ERR_INVALID_ARG;
+  const double rl = p->rc + skin;
+  if ((st = check_box(box, rl)) != MD_OK) return st;
+  int nc[3];
+  int64_t ncell;
+  if (!cell_dims(box, rl, nc, &ncell) || ncell > cells->ncell_cap) return MD_ERR_INVALID_ARG;
+  if (!setup) {
+    for (int d = 0; d < 3; ++d)
+      if (cells->nc[d] != nc[d]) return MD_ERR_INVALID_ARG;
+    if (!resolve_lanes(k, nl->layout)) return MD_ERR_INVALID_ARG;
+  }
+  const WsLayout L = ws_layout(stt->n, ncell);
+  if ((st = check_ws(ws, ws_bytes, L)) != MD_OK) return st;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = (int)stt->n;
+  const BoxK bk = make_box(box);
+  const double dtfm = (0.5 * dt * stt->ftm2v) / stt->mass;
+  const double trig = 0.5 * skin;
+  const double trig2 = trig * trig;
+  int* status = nl->status;
+  int* gate = status + MD_ST_REBUILD;
+  int* count = at<int>(ws, L.count);
+  int* slot = at<int>(ws, L.slot);
+  int* tmp_perm = at<int>(ws, L.tmp_perm);
+  double* sx = at<double>(ws, L.tmp_x);
+  double* sv = at<double>(ws, L.tmp_v);
+  int* sid = at<int>(ws, L.tmp_id);
+  double* eatom = at<double>(ws, L.eatom);
+  double* vatom = at<double>(ws, L.vatom);
+  double* keatom = at<double>(ws, L.keatom);
+  double* sums = at<double>(ws, L.scalars);
+
+  int* ticket = at<int>(ws, L.ticket);
+
+  // Rebuild chain: wrap + bin + count (+ scan in its last workgroup), scatter,
+  // stable in-cell order with the state gathered into staging, list build that
+  // copies the state back.  With a gate, every kernel returns at once unless
+  // the rebuild flag is set.
+  auto rebuild = [&](const int* g, int layout) -> md_status {
+    MD_CK(launch_bin_count(stt->x, n, bk, nc, cells->atom_cell, count, slot, cells->cell_start,
+                           ticket, g, s));
+    MD_CK(launch_scatter(cells->atom_cell, slot, cells->cell_start, n, tmp_perm, g, s));
+    MD_CK(launch_cell_sort(tmp_perm, cells->cell_start, (int)ncell, cells->perm, stt->x, stt->v,
+                           stt->id, nullptr, n, sx, sv, sid, nullptr, g, s));
+    BuildArgs a{};
+    a.x = sx;
+    a.n = n;
+    a.sorted = 1;
+    a.box = bk;
+    for (int d = 0; d < 3; ++d) a.nc[d] = nc[d];
+    a.cell_start = cells->cell_start;
+    a.atom_cell = cells->atom_cell;
+    a.perm = cells->perm;
+    a.rl2 = rl * rl;
+    a.cap = nl->capacity;
+    a.layout = layout;
+    a.neigh = nl->neigh;
+    a.numneigh = nl->numneigh;
+    a.x_ref = nl->x_ref;
+    a.status = status;
+    a.x_out = stt->x;
+    a.v_out = stt->v;
+    a.v_in = sv;
+    a.id_out = stt->id;
+    a.id_in = sid;
+    a.gate = g;
+    MD_CK(launch_build(a, s));
+    return MD_OK;
+  };
+
+  auto forces = [&](bool ev, int kernel) -> md_status {
+    ForceArgs fa{};
+    fa.x = stt->x;
+    fa.n = n;
+    fa.box = bk;
+    fa.neigh = nl->neigh;
+    fa.numneigh = nl->numneigh;
+    fa.cap = nl->capacity;
+    fa.f = stt->f;
+    if (ev) {
+      fa.ev.eatom = eatom;
+      fa.ev.vatom = vatom;
+    }
+    fa.clear = gate;
+    timing_events(&fa.t0, &fa.t1);
+    return force_dispatch(p, fa, prec, kernel, at<double>(ws, L.sc_e), s);
+  };
+
+  const double dof = 3.0 * (double)n - 3.0;
+  const double volume = box->L[0] * box->L[1] * box->L[2];
+  int row = 0;
+  auto thermo_out = [&](double stepno) -> md_status {
+    SumArgs sa{};
+    sa.cols = 8;
+    sa.col[0] = eatom;
+    for (int q = 0; q < 6; ++q) sa.col[1 + q] = vatom + (size_t)q * n;
+    sa.col[7] = keatom;
+    sa.n = n;
+    sa.partials = at<double>(ws, L.partials);
+    sa.out = sums;
+    MD_CK(launch_sum(sa, s));
+    ThermoArgs ta{};
+    ta.sums = sums;
+    ta.row = thermo + 8 * (size_t)row++;
+    ta.step = stepno;
+    ta.mass = stt->mass;
+    ta.mvv2e = stt->mvv2e;
+    ta.boltz = stt->boltz;
+    ta.dof = dof;
+    ta.volume = volume;
+    ta.status = status;
+    MD_CK(launch_thermo_row(ta, s));
+    return MD_OK;
+  };
+
+  int kernel = nl->layout;   // lanes per atom == list layout
+  // The binning counters must start at zero; every binning pass leaves them
+  // zero again, but the workspace may be fresh, so clear them once per call.
+  MD_CK(launch_fill_int(count, ncell, 0, s));
+  MD_CK(launch_fill_int(ticket, 1, 0, s));
+  if (setup) {
+    kernel = k == MD_KERNEL_AUTO ? MD_KERNEL_TPA : (int)k;
+    if ((st = rebuild(nullptr, kernel)) != MD_OK) return st;
+    for (int d = 0; d < 3; ++d) cells->nc[d] = nc[d];
+    nl->layout = kernel;
+    nl->rl = rl;
+    if (k == MD_KERNEL_AUTO) {
+      int words[MD_STATUS_WORDS];
+      MD_CK(hipMemcpyAsync(words, status, sizeof(words), hipMemcpyDeviceToHost, s));
+      MD_CK(hipStreamSynchronize(s));
+      int lanes = 0;
+      if (cached_choice(p, prec, words[MD_ST_MAXNEIGH], &lanes)) {
+        if (lanes != kernel) {
+          st = build_list(stt->x, n, 1, box, nc, cells, rl, nl, lanes, s);
+          if (st != MD_OK) return st;
+          MD_CK(hipMemcpyAsync(status + MD_ST_BUILDS, words + MD_ST_BUILDS, sizeof(int),
+                               hipMemcpyHostToDevice, s));
+          MD_CK(hipStreamSynchronize(s));
+        }
+        kernel = lanes;
+      } else {
+        md_kernel choice = MD_KERNEL_TPA;
+        st = autoselect_impl(p, stt->x, n, 1, box, cells, rl, nl, prec, 5, &choice, ws, L, s);
+        if (st != MD_OK) return st;
+        kernel = (int)choice;
+      }
+    }
+    const bool ev = thermo != nullptr;
+    if ((st = forces(ev, kernel)) != MD_OK) return st;
+    if (ev) {
+      MD_CK(launch_ke(stt->v, n, keatom, s));
+      if ((st = thermo_out(0.0)) != MD_OK) return st;
+    }
+  }
+  const int layout = kernel;
+  for (int step = 1; step <= nsteps; ++step) {
+    const bool th = thermo && (step % thermo_every) == 0;
+    MD_CK(launch_kick_drift_check(stt->x, stt->v, stt->f, nl->x_ref, n, dtfm, dt, trig2, status,
+                                  s));
+    if ((st = rebuild(gate, layout)) != MD_OK) return st;
+    if ((st = forces(th, kernel)) != MD_OK) return st;
+    MD_CK(launch_kick(stt->v, stt->f, n, dtfm, th ? keatom : nullptr, status, s));
+    if (th && (st = thermo_out((double)step)) != MD_OK) return st;
+  }
+  int words[MD_STATUS_WORDS];
+  MD_CK(hipMemcpyAsync(words, status, sizeof(words), hipMemcpyDeviceToHost, s));
+  MD_CK(hipStreamSynchronize(s));
+  return status_from_words(words);
+}
+
+md_status md_timing_enable(int every) {
+  std::lock_guard<std::mutex> lk(g_timing.mu);
+  if (every > 0 && g_timing.pool.empty()) {
+    g_timing.pool.resize(2 * kTimingPairs);
+    for (auto& e : g_timing.pool)
+      if (hipEventCreate(&e) != hipSuccess) {
+        g_timing.pool.clear();
+        return MD_ERR_HIP;
+      }
+  }
+  g_timing.every = every;
+  g_timing.counter = 0;
+  g_timing.used = 0;
+  g_timing.launches = 0;
+  g_timing.total_ms = 0.0;
+  return MD_OK;
+}
+
+md_status md_timing_read(int64_t* launches, double* total_ms) {
+  if (!launches || !total_ms) return MD_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_timing.mu);
+  if (g_timing.used) MD_CK(hipDeviceSynchronize());
+  for (size_t q = 0; q < g_timing.used; ++q) {
+    float ms = 0.f;
+    MD_CK(hipEventElapsedTime(&ms, g_timing.pool[2 * q], g_timing.pool[2 * q + 1]));
+    g_timing.total_ms += ms;
+    ++g_timing.launches;
+  }
+  g_timing.used = 0;
+  *launches = g_timing.launches;
+  *total_ms = g_timing.total_ms;
+  g_timing.launches = 0;
+  g_timing.total_ms = 0.0;
+  return MD_OK;
+}
+
+}  // extern "C"

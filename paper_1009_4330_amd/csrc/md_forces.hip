@@ -1,0 +1,483 @@
+// Pair-force kernels over a full Verlet list (the paper's section "Neighbor
+// list approach").  The paper's two designs are the ends of one family here:
+// K lanes of a 64-wide wavefront share one atom i and split its neighbour
+// list; K = 1 is thread-per-atom (the TpA listing), K = 64 is one wavefront per
+// atom (the block-per-atom listing, its block reduction becoming a register
+// butterfly with no LDS and no barrier).  Intermediate K trade per-lane loop
+// length (latency hiding, lane utilisation) against reduction cost; the
+// setup-time mini-benchmark picks K.  Potentials: 12-6 Lennard-Jones and
+// two-pass Sutton-Chen; plus the LJ force adjoint.
+//
+// Precision.  FP64: everything in double.  MIXED: d and r^2 = (dx dx + dy dy)
+// + dz dz and the cutoff test stay FP64 (so the interacting pair set equals the
+// FP64 one bit for bit), the scalar pair function is evaluated in FP32, and
+// the force vector, energy and virial are accumulated in FP64.
+#include <hip/hip_ext.h>
+
+#include "md_internal.hpp"
+
+namespace md {
+namespace {
+
+constexpr int kUnroll = 4;   // neighbour entries whose loads are issued together
+
+struct FK {
+  const double* __restrict__ x;
+  int n;
+  BoxK box;
+  const int* __restrict__ neigh;
+  const int* __restrict__ numneigh;
+  int cap;
+  double* __restrict__ f;
+  double* __restrict__ eatom;
+  double* __restrict__ vatom;
+  int* clear;
+};
+
+__device__ inline double min_image(double d, double L, double inv) {
+  return d - L * rint(d * inv);
+}
+
+// 1/s to full FP64 precision: hardware reciprocal estimate + two Newton steps.
+__device__ inline double rcp64(double s) {
+  double r = __builtin_amdgcn_rcp(s);
+  double e = fma(-s, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-s, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Sum over the K aligned lanes that share an atom (butterfly; every lane of
+// the group ends with the total).
+template <int K>
+__device__ inline double group_sum(double v) {
+#pragma unroll
+  for (int off = K / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Where this lane works: atom i, its sub-lane s, the first list entry of the
+// lane and how many entries (s, s+K, ...) it owns.
+template <int K>
+struct Lane {
+  int i;          // atom (may be >= n for padding lanes)
+  int s;          // sub-lane 0..K-1
+  bool live;      // i < n
+  const int* nb;  // entry t of this lane at nb[t * 64]
+  int count;      // entries owned by this lane
+  __device__ inline Lane(const FK& a) {
+    const int g = blockIdx.x * kBlock + threadIdx.x;
+    const int lane = g & (kWave - 1);
+    i = (g / kWave) * (kWave / K) + lane / K;
+    s = lane % K;
+    live = i < a.n;
+    const int nn = live ? min(a.numneigh[i], a.cap) : 0;
+    count = nn > s ? (nn - s + K - 1) / K : 0;
+    nb = a.neigh + (size_t)(g / kWave) * nl_rows(a.cap, K) * kWave + lane;
+  }
+};
+
+// Separations of up to kUnroll entries starting at entry t: all index loads are
+// issued first, then all position gathers, then the arithmetic.  Invalid slots
+// point at atom i itself and are masked by ok[].
+struct Batch {
+  int j[kUnroll];
+  bool ok[kUnroll];
+  double dx[kUnroll], dy[kUnroll], dz[kUnroll], s[kUnroll];
+};
+
+template <int K>
+__device__ inline void load_batch(const FK& a, const Lane<K>& ln, int t, int iself, double xi,
+                                  double yi, double zi, Batch& b) {
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    b.ok[u] = t + u < ln.count;
+    b.j[u] = b.ok[u] ? ln.nb[(size_t)(t + u) * kWave] : iself;
+  }
+  double xj[kUnroll], yj[kUnroll], zj[kUnroll];
+  const int n = a.n;
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    xj[u] = a.x[b.j[u]];
+    yj[u] = a.x[n + b.j[u]];
+    zj[u] = a.x[2 * n + b.j[u]];
+  }
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    b.dx[u] = min_image(xi - xj[u], a.box.L[0], a.box.inv[0]);
+    b.dy[u] = min_image(yi - yj[u], a.box.L[1], a.box.inv[1]);
+    b.dz[u] = min_image(zi - zj[u], a.box.L[2], a.box.inv[2]);
+    // (dx dx + dy dy) + dz dz, evaluated as written
+    b.s[u] = b.dx[u] * b.dx[u] + b.dy[u] * b.dy[u] + b.dz[u] * b.dz[u];
+  }
+}
+
+struct Acc {
+  double fx = 0, fy = 0, fz = 0, e = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0;
+  __device__ inline void add_force(double g, double dx, double dy, double dz) {
+    fx = fma(g, dx, fx);
+    fy = fma(g, dy, fy);
+    fz = fma(g, dz, fz);
+  }
+  __device__ inline void add_virial(double g, double dx, double dy, double dz) {
+    const double gx = g * dx, gy = g * dy;
+    w0 = fma(gx, dx, w0);
+    w1 = fma(gy, dy, w1);
+    w2 = fma(g * dz, dz, w2);
+    w3 = fma(gx, dy, w3);
+    w4 = fma(gx, dz, w4);
+    w5 = fma(gy, dz, w5);
+  }
+  template <int K>
+  __device__ inline void reduce(bool ev) {
+    fx = group_sum<K>(fx);
+    fy = group_sum<K>(fy);
+    fz = group_sum<K>(fz);
+    if (ev) {
+      e = group_sum<K>(e);
+      w0 = group_sum<K>(w0);
+      w1 = group_sum<K>(w1);
+      w2 = group_sum<K>(w2);
+      w3 = group_sum<K>(w3);
+      w4 = group_sum<K>(w4);
+      w5 = group_sum<K>(w5);
+    }
+  }
+  // Pair energy and virial are split half to each atom of the pair.
+  __device__ inline void store(const FK& a, int i, bool ev, double e_extra) const {
+    const int n = a.n;
+    a.f[i] = fx;
+    a.f[n + i] = fy;
+    a.f[2 * n + i] = fz;
+    if (ev) {
+      if (a.eatom) a.eatom[i] = 0.5 * e + e_extra;
+      if (a.vatom) {
+        a.vatom[i] = 0.5 * w0;
+        a.vatom[n + i] = 0.5 * w1;
+        a.vatom[2 * n + i] = 0.5 * w2;
+        a.vatom[3 * n + i] = 0.5 * w3;
+        a.vatom[4 * n + i] = 0.5 * w4;
+        a.vatom[5 * n + i] = 0.5 * w5;
+      }
+    }
+  }
+};
+
+// ------------------------------------------------------------------ LJ --
+
+// g(s) with F_ij = g d, and phi(s) (unshifted).
+template <int PREC>
+__device__ inline void lj_pair(double s, const LJK& p, double& g, double& phi) {
+  if (PREC == MD_FP64) {
+    const double r2i = rcp64(s);
+    const double sr2 = p.sig2 * r2i;
+    const double sr6 = sr2 * sr2 * sr2;
+    g = r2i * sr6 * fma(p.eps48, sr6, -p.eps24);
+    phi = sr6 * fma(p.eps4, sr6, -p.eps4);
+  } else {
+    const float r2i = __builtin_amdgcn_rcpf((float)s);
+    const float sr2 = p.sig2f * r2i;
+    const float sr6 = sr2 * sr2 * sr2;
+    g = (double)(r2i * sr6 * fmaf(p.eps48f, sr6, -p.eps24f));
+    phi = (double)(sr6 * fmaf(p.eps4f, sr6, -p.eps4f));
+  }
+}
+
+template <int PREC, bool EV, int K>
+__global__ __launch_bounds__(kBlock) void k_lj(FK a, LJK p) {
+  if (a.clear && blockIdx.x == 0 && threadIdx.x == 0) *a.clear = 0;
+  const Lane<K> ln(a);
+  const int n = a.n;
+  const int io = ln.live ? ln.i : n - 1;
+  const double xi = a.x[io], yi = a.x[n + io], zi = a.x[2 * n + io];
+  Acc acc;
+  for (int t = 0; t < ln.count; t += kUnroll) {
+    Batch b;
+    load_batch<K>(a, ln, t, io, xi, yi, zi, b);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (b.ok[u] && b.s[u] < p.rc2) {
+        double g, phi;
+        lj_pair<PREC>(b.s[u], p, g, phi);
+        acc.add_force(g, b.dx[u], b.dy[u], b.dz[u]);
+        if (EV) {
+          acc.e += phi - p.ecut;
+          acc.add_virial(g, b.dx[u], b.dy[u], b.dz[u]);
+        }
+      }
+    }
+  }
+  if (K > 1) acc.reduce<K>(EV);
+  if (ln.live && ln.s == 0) acc.store(a, ln.i, EV, 0.0);
+}
+
+// --------------------------------------------------------- Sutton-Chen --
+
+// t^(k/2) for integer k >= 0.
+template <typename T>
+__device__ inline T half_power(T t, int k) {
+  T r = (T)1;
+  for (int q = 0; q < k / 2; ++q) r *= t;
+  if (k & 1) r *= sqrt(t);
+  return r;
+}
+
+// Pass 1: rho_i = sum_j (a^2/s)^(m/2); stores e_i = rho_i^(-1/2) (0 if rho_i = 0)
+// and, with EV, the embedding energy -eps c sqrt(rho_i).
+template <int PREC, bool EV, int K>
+__global__ __launch_bounds__(kBlock) void k_sc_density(FK a, SCK p, double* __restrict__ e_out) {
+  const Lane<K> ln(a);
+  const int n = a.n;
+  const int io = ln.live ? ln.i : n - 1;
+  const double xi = a.x[io], yi = a.x[n + io], zi = a.x[2 * n + io];
+  double rho = 0.0;
+  for (int t = 0; t < ln.count; t += kUnroll) {
+    Batch b;
+    load_batch<K>(a, ln, t, io, xi, yi, zi, b);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (b.ok[u] && b.s[u] < p.rc2) {
+        if (PREC == MD_FP64)
+          rho += half_power(p.a2 * rcp64(b.s[u]), p.m);
+        else
+          rho += (double)half_power(p.a2f * __builtin_amdgcn_rcpf((float)b.s[u]), p.m);
+      }
+    }
+  }
+  if (K > 1) rho = group_sum<K>(rho);
+  if (!ln.live || ln.s != 0) return;
+  e_out[ln.i] = rho > 0.0 ? 1.0 / sqrt(rho) : 0.0;
+  if (EV && a.eatom) a.eatom[ln.i] = -p.epsc * sqrt(rho);
+}
+
+// Pass 2: F_ij = [n eps t^(n/2) - (m eps c / 2)(e_i + e_j) t^(m/2)] d / s, t = a^2/s.
+template <int PREC, bool EV, int K>
+__global__ __launch_bounds__(kBlock) void k_sc_force(FK a, SCK p,
+                                                      const double* __restrict__ e_in) {
+  if (a.clear && blockIdx.x == 0 && threadIdx.x == 0) *a.clear = 0;
+  const Lane<K> ln(a);
+  const int n = a.n;
+  const int io = ln.live ? ln.i : n - 1;
+  const double xi = a.x[io], yi = a.x[n + io], zi = a.x[2 * n + io];
+  const double ei = e_in[io];
+  Acc acc;
+  for (int t = 0; t < ln.count; t += kUnroll) {
+    Batch b;
+    load_batch<K>(a, ln, t, io, xi, yi, zi, b);
+    double ej[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) ej[u] = e_in[b.j[u]];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (b.ok[u] && b.s[u] < p.rc2) {
+        double h, pn;
+        if (PREC == MD_FP64) {
+          const double r2i = rcp64(b.s[u]);
+          const double tt = p.a2 * r2i;
+          pn = half_power(tt, p.n);
+          const double pm = half_power(tt, p.m);
+          h = (p.neps * pn - p.mepsc_half * (ei + ej[u]) * pm) * r2i;
+        } else {
+          const float r2i = __builtin_amdgcn_rcpf((float)b.s[u]);
+          const float tt = p.a2f * r2i;
+          const float pnf = half_power(tt, p.n);
+          const float pmf = half_power(tt, p.m);
+          const float eij = (float)(ei + ej[u]);
+          h = (double)((p.nepsf * pnf - p.mepsc_halff * eij * pmf) * r2i);
+          pn = (double)pnf;
+        }
+        acc.add_force(h, b.dx[u], b.dy[u], b.dz[u]);
+        if (EV) {
+          acc.e += pn;
+          acc.add_virial(h, b.dx[u], b.dy[u], b.dz[u]);
+        }
+      }
+    }
+  }
+  if (K > 1) acc.reduce<K>(EV);
+  if (!ln.live || ln.s != 0) return;
+  // energy: eps/2 sum_j t^(n/2) is the pair repulsion share, plus the embedding
+  // term pass 1 stored
+  const double emb = (EV && a.eatom) ? a.eatom[ln.i] : 0.0;
+  acc.e *= p.eps;
+  acc.store(a, ln.i, EV, emb);
+}
+
+// ------------------------------------------------------------- LJ VJP --
+
+// gx_i = sum_j [g (u_i - u_j) + 2 g' ((u_i - u_j) . d) d];
+// pe_i = u_i . F_i (for dL/deps = sum pe / eps); ps_i = sum_j (dg/dsigma)(u_i . d).
+template <int PREC, int K>
+__global__ __launch_bounds__(kBlock) void k_lj_vjp(FK a, LJK p, const double* __restrict__ u,
+                                                    double* __restrict__ gx,
+                                                    double* __restrict__ pe,
+                                                    double* __restrict__ ps) {
+  const Lane<K> ln(a);
+  const int n = a.n;
+  const int io = ln.live ? ln.i : n - 1;
+  const double xi = a.x[io], yi = a.x[n + io], zi = a.x[2 * n + io];
+  const double uxi = u[io], uyi = u[n + io], uzi = u[2 * n + io];
+  double gxa = 0, gya = 0, gza = 0, fx = 0, fy = 0, fz = 0, dsig = 0;
+  for (int t = 0; t < ln.count; t += kUnroll) {
+    Batch b;
+    load_batch<K>(a, ln, t, io, xi, yi, zi, b);
+    double ux[kUnroll], uy[kUnroll], uz[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      ux[q] = u[b.j[q]];
+      uy[q] = u[n + b.j[q]];
+      uz[q] = u[2 * n + b.j[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      if (!(b.ok[q] && b.s[q] < p.rc2)) continue;
+      double g, gp, dg;
+      if (PREC == MD_FP64) {
+        const double r2i = rcp64(b.s[q]);
+        const double sr2 = p.sig2 * r2i;
+        const double sr6 = sr2 * sr2 * sr2;
+        const double sr12 = sr6 * sr6;
+        g = r2i * (2.0 * p.eps24 * sr12 - p.eps24 * sr6);
+        gp = r2i * r2i * (-14.0 * p.eps24 * sr12 + 4.0 * p.eps24 * sr6);
+        dg = p.inv_sig * r2i * (24.0 * p.eps24 * sr12 - 6.0 * p.eps24 * sr6);
+      } else {
+        const float r2i = __builtin_amdgcn_rcpf((float)b.s[q]);
+        const float sr2 = p.sig2f * r2i;
+        const float sr6 = sr2 * sr2 * sr2;
+        const float sr12 = sr6 * sr6;
+        g = (double)(r2i * (2.0f * p.eps24f * sr12 - p.eps24f * sr6));
+        gp = (double)(r2i * r2i * (-14.0f * p.eps24f * sr12 + 4.0f * p.eps24f * sr6));
+        dg = p.inv_sig * (double)(r2i * (24.0f * p.eps24f * sr12 - 6.0f * p.eps24f * sr6));
+      }
+      const double dux = uxi - ux[q], duy = uyi - uy[q], duz = uzi - uz[q];
+      const double c2 = 2.0 * gp * (dux * b.dx[q] + duy * b.dy[q] + duz * b.dz[q]);
+      gxa += g * dux + c2 * b.dx[q];
+      gya += g * duy + c2 * b.dy[q];
+      gza += g * duz + c2 * b.dz[q];
+      fx = fma(g, b.dx[q], fx);
+      fy = fma(g, b.dy[q], fy);
+      fz = fma(g, b.dz[q], fz);
+      dsig += dg * (uxi * b.dx[q] + uyi * b.dy[q] + uzi * b.dz[q]);
+    }
+  }
+  if (K > 1) {
+    gxa = group_sum<K>(gxa);
+    gya = group_sum<K>(gya);
+    gza = group_sum<K>(gza);
+    fx = group_sum<K>(fx);
+    fy = group_sum<K>(fy);
+    fz = group_sum<K>(fz);
+    dsig = group_sum<K>(dsig);
+  }
+  if (!ln.live || ln.s != 0) return;
+  const int i = ln.i;
+  gx[i] = gxa;
+  gx[n + i] = gya;
+  gx[2 * n + i] = gza;
+  if (pe) pe[i] = uxi * fx + uyi * fy + uzi * fz;
+  if (ps) ps[i] = dsig;
+}
+
+// ------------------------------------------------------------ launching --
+
+FK make_fk(const ForceArgs& a) {
+  FK k;
+  k.x = a.x;
+  k.n = a.n;
+  k.box = a.box;
+  k.neigh = a.neigh;
+  k.numneigh = a.numneigh;
+  k.cap = a.cap;
+  k.f = a.f;
+  k.eatom = a.ev.eatom;
+  k.vatom = a.ev.vatom;
+  k.clear = a.clear;
+  return k;
+}
+
+template <typename... KArgs, typename... Args>
+hipError_t launch_timed(void (*kern)(KArgs...), unsigned grid, hipStream_t s, hipEvent_t t0,
+                        hipEvent_t t1, Args... args) {
+  if (t0 && t1)
+    hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, args...);
+  else
+    kern<<<grid, kBlock, 0, s>>>(args...);
+  return hipGetLastError();
+}
+
+// Workgroups covering n atoms with K lanes each.
+unsigned grid_for(int n, int k) {
+  const int64_t lanes = (int64_t)((n + (kWave / k) - 1) / (kWave / k)) * kWave;
+  return (unsigned)((lanes + kBlock - 1) / kBlock);
+}
+
+// Calls f(std::integral_constant<int, K>) for the runtime lane count.
+template <typename F>
+hipError_t with_lanes(int k, F&& f) {
+  switch (k) {
+    case 1: return f(std::integral_constant<int, 1>());
+    case 2: return f(std::integral_constant<int, 2>());
+    case 4: return f(std::integral_constant<int, 4>());
+    case 8: return f(std::integral_constant<int, 8>());
+    case 16: return f(std::integral_constant<int, 16>());
+    case 32: return f(std::integral_constant<int, 32>());
+    case 64: return f(std::integral_constant<int, 64>());
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_lj(const ForceArgs& a, const LJK& p, int prec, int lanes, hipStream_t s) {
+  const FK k = make_fk(a);
+  const bool ev = a.ev.eatom || a.ev.vatom;
+  return with_lanes(lanes, [&](auto kc) -> hipError_t {
+    constexpr int K = decltype(kc)::value;
+    const unsigned g = grid_for(a.n, K);
+    if (prec == MD_FP64)
+      return ev ? launch_timed(k_lj<MD_FP64, true, K>, g, s, a.t0, a.t1, k, p)
+                : launch_timed(k_lj<MD_FP64, false, K>, g, s, a.t0, a.t1, k, p);
+    return ev ? launch_timed(k_lj<MD_MIXED, true, K>, g, s, a.t0, a.t1, k, p)
+              : launch_timed(k_lj<MD_MIXED, false, K>, g, s, a.t0, a.t1, k, p);
+  });
+}
+
+hipError_t launch_sc(const ForceArgs& a, const SCK& p, int prec, int lanes, double* sc_e,
+                     hipStream_t s) {
+  const FK k = make_fk(a);
+  const bool ev = a.ev.eatom || a.ev.vatom;
+  return with_lanes(lanes, [&](auto kc) -> hipError_t {
+    constexpr int K = decltype(kc)::value;
+    const unsigned g = grid_for(a.n, K);
+    const double* e = sc_e;
+    // pass 1 (density) is not timed; the timed launch is the force pass
+    if (prec == MD_FP64) {
+      if (ev) {
+        k_sc_density<MD_FP64, true, K><<<g, kBlock, 0, s>>>(k, p, sc_e);
+        return launch_timed(k_sc_force<MD_FP64, true, K>, g, s, a.t0, a.t1, k, p, e);
+      }
+      k_sc_density<MD_FP64, false, K><<<g, kBlock, 0, s>>>(k, p, sc_e);
+      return launch_timed(k_sc_force<MD_FP64, false, K>, g, s, a.t0, a.t1, k, p, e);
+    }
+    if (ev) {
+      k_sc_density<MD_MIXED, true, K><<<g, kBlock, 0, s>>>(k, p, sc_e);
+      return launch_timed(k_sc_force<MD_MIXED, true, K>, g, s, a.t0, a.t1, k, p, e);
+    }
+    k_sc_density<MD_MIXED, false, K><<<g, kBlock, 0, s>>>(k, p, sc_e);
+    return launch_timed(k_sc_force<MD_MIXED, false, K>, g, s, a.t0, a.t1, k, p, e);
+  });
+}
+
+hipError_t launch_lj_vjp(const ForceArgs& a, const LJK& p, int prec, int lanes,
+                         const double* u, double* gx, double* pe, double* ps, hipStream_t s) {
+  const FK k = make_fk(a);
+  return with_lanes(lanes, [&](auto kc) -> hipError_t {
+    constexpr int K = decltype(kc)::value;
+    const unsigned g = grid_for(a.n, K);
+    if (prec == MD_FP64)
+      return launch_timed(k_lj_vjp<MD_FP64, K>, g, s, a.t0, a.t1, k, p, u, gx, pe, ps);
+    return launch_timed(k_lj_vjp<MD_MIXED, K>, g, s, a.t0, a.t1, k, p, u, gx, pe, ps);
+  });
+}
+
+}  // namespace md

@@ -1,0 +1,188 @@
+// Internal declarations of the MI355X MD library: kernel parameter blocks,
+// workspace layout and the host-side launchers each .hip file provides.
+// All device code is compiled with -ffp-contract=off: every FMA in the force
+// math is written out with fma()/fmaf(), and the distance / cutoff / wrap /
+// integration arithmetic is evaluated exactly as written.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "md.h"
+
+namespace md {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts)
+constexpr int kWave = 64;            // CDNA wavefront width
+#define kWaveConst 64
+constexpr int kReduceBlocks = 512;   // first-stage blocks of the deterministic sums
+constexpr int kReduceCols = 8;       // values reduced per thermo / energy pass
+
+// Neighbour-list layout with K lanes per atom (K a power of two in [1, 64]):
+// groups of G = 64 / K consecutive atoms share rows of 64 ints, and entry m of
+// atom i lives at ((i / G) * ceil(cap / K) + m / K) * 64 + (i % G) * K + m % K.
+// Lane (i % G) * K + s of a wavefront reads entries m = s, s + K, ... of atom
+// i, so each row of 64 entries is one contiguous 256-byte read.  K = 1 is the
+// thread-per-atom list, K = 64 one row-major list per atom.
+__host__ __device__ inline size_t nl_rows(int cap, int k) { return (size_t)((cap + k - 1) / k); }
+__host__ __device__ inline size_t nl_index(int i, int m, int cap, int k) {
+  const int g = kWaveConst / k;
+  return ((size_t)(i / g) * nl_rows(cap, k) + (size_t)(m / k)) * kWaveConst + (i % g) * k + m % k;
+}
+inline bool lanes_ok(int k) { return k >= 1 && k <= 64 && (k & (k - 1)) == 0; }
+
+// Periodic box as kernels see it: edges and their reciprocals (the reciprocal
+// only picks the image index; the image shift itself is d - L * k).
+struct BoxK {
+  double L[3];
+  double inv[3];
+};
+
+// Lennard-Jones constants in both precisions.
+struct LJK {
+  double rc2, sig2, eps4, eps24, eps48, ecut;
+  float sig2f, eps4f, eps24f, eps48f, ecutf;
+  double inv_sig;   // 1/sigma, for dg/dsigma in the adjoint
+};
+
+// Sutton-Chen constants.
+struct SCK {
+  double rc2, a2, eps, neps, mepsc_half, epsc;
+  float a2f, nepsf, mepsc_halff;
+  int n, m;
+};
+
+// Where per-atom energy / virial / kinetic terms go for the thermo sums.
+struct EVOut {
+  double* eatom;   // [n] or null
+  double* vatom;   // [6][n] or null
+};
+
+// Workspace carve-up (offsets in bytes from the workspace base).
+struct WsLayout {
+  size_t count;      // int [ncell]       per-cell counters (kept zero between uses)
+  size_t slot;       // int [n]           arrival slot of each atom in its cell
+  size_t tmp_perm;   // int [n]           unsorted cell members
+  size_t tmp_x;      // double [3][n]     sorted staging of x
+  size_t tmp_v;      // double [3][n]     sorted staging of v
+  size_t tmp_f;      // double [3][n]     sorted staging of f / x_ref
+  size_t tmp_id;     // int [n]           sorted staging of ids
+  size_t eatom;      // double [n]
+  size_t vatom;      // double [6][n]
+  size_t keatom;     // double [n]
+  size_t sc_e;       // double [n]        Sutton-Chen rho^-1/2
+  size_t partials;   // double [kReduceBlocks][kReduceCols]
+  size_t scalars;    // double [16]       reduced values
+  size_t ticket;     // int [64]          finished-workgroup counter of the binning pass
+  size_t total;
+};
+
+WsLayout ws_layout(int64_t n, int64_t ncell);
+
+// ------------------------------------------------------------ launchers --
+// Every launcher enqueues on `s` and returns hipGetLastError().
+
+// Binning.  `gate` (nullable) makes the kernels return at once when *gate == 0.
+// launch_bin_count wraps, bins and counts, and its last workgroup writes
+// cell_start and clears count and *ticket (both must be zero on entry).
+hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t s);
+hipError_t launch_bin_count(double* x, int n, BoxK box, const int nc[3], int* atom_cell,
+                            int* count, int* slot, int* cell_start, int* ticket,
+                            const int* gate, hipStream_t s);
+hipError_t launch_scatter(const int* atom_cell, const int* slot, const int* cell_start, int n,
+                          int* tmp_perm, const int* gate, hipStream_t s);
+// Stable order inside each cell; optionally gathers x, v, id (and f, xr) into
+// the sorted staging buffers (null sources are skipped).
+hipError_t launch_cell_sort(const int* tmp_perm, const int* cell_start, int ncell, int* perm,
+                            const double* x, const double* v, const int* id, const double* f,
+                            int n, double* sx, double* sv, int* sid, double* sf,
+                            const int* gate, hipStream_t s);
+hipError_t launch_copy_back(double* x, double* v, int* id, double* f, double* xr,
+                            const double* sx, const double* sv, const int* sid,
+                            const double* sf, int n, hipStream_t s);
+
+hipError_t launch_gather3(const int* perm, int n, const double* src, double* dst,
+                          hipStream_t s);
+hipError_t launch_gather_int(const int* perm, int n, const int* src, int* dst, hipStream_t s);
+
+// Neighbour list.  sorted == 0: x is in input order and the members of cell c
+// are perm[cell_start[c] .. cell_start[c+1]); sorted != 0: x is in cell order
+// (slot k holds atom perm[k]) and the members are the slots themselves.  With
+// x_out (md_step), x is the sorted staging buffer and the same kernel copies
+// the state (x, v, id) back from staging.
+struct BuildArgs {
+  const double* x;       // positions the list is built from
+  int n;
+  int sorted;
+  BoxK box;
+  int nc[3];
+  const int* cell_start;
+  const int* atom_cell;  // cell of each atom, input order
+  const int* perm;
+  double rl2;
+  int cap, layout;
+  int* neigh;
+  int* numneigh;
+  double* x_ref;
+  int* status;
+  // md_step extras
+  double* x_out;
+  double* v_out;
+  const double* v_in;
+  int* id_out;
+  const int* id_in;
+  const int* gate;
+};
+hipError_t launch_build(const BuildArgs& a, hipStream_t s);
+
+// Forces.  kernel: MD_KERNEL_TPA / MD_KERNEL_WPA.  clear (nullable) is zeroed
+// by the first thread, after every rebuild kernel of the step has finished.
+struct ForceArgs {
+  const double* x;
+  int n;
+  BoxK box;
+  const int* neigh;
+  const int* numneigh;
+  int cap;
+  double* f;
+  EVOut ev;
+  int* clear;
+  hipEvent_t t0, t1;     // non-null: timed launch
+};
+hipError_t launch_lj(const ForceArgs& a, const LJK& p, int prec, int kernel, hipStream_t s);
+hipError_t launch_sc(const ForceArgs& a, const SCK& p, int prec, int kernel, double* sc_e,
+                     hipStream_t s);
+hipError_t launch_lj_vjp(const ForceArgs& a, const LJK& p, int prec, int kernel,
+                         const double* u, double* gx, double* pe, double* ps, hipStream_t s);
+
+// Integration.
+hipError_t launch_kick_drift_check(double* x, double* v, const double* f, const double* xr,
+                                   int n, double dtfm, double dt, double trig2, int* status,
+                                   hipStream_t s);
+hipError_t launch_kick(double* v, const double* f, int n, double dtfm, double* keatom,
+                       int* status, hipStream_t s);
+hipError_t launch_ke(const double* v, int n, double* keatom, hipStream_t s);
+
+// Deterministic sums: cols arrays of n doubles (col c at base[c] ) -> out[cols].
+struct SumArgs {
+  const double* col[kReduceCols];
+  int cols;
+  int n;
+  double* partials;
+  double* out;
+};
+hipError_t launch_sum(const SumArgs& a, hipStream_t s);
+// Thermo row from out = {pe, W0..W5, sv} sums.
+struct ThermoArgs {
+  const double* sums;  // pe, w0..w5, sum v^2
+  double* row;
+  double step, mass, mvv2e, boltz, dof, volume;
+  const int* status;
+};
+hipError_t launch_thermo_row(const ThermoArgs& a, hipStream_t s);
+// gparam[0] = sums[0] / eps, gparam[1] = sums[1].
+hipError_t launch_vjp_params(const double* sums, double eps, double* gparam, hipStream_t s);
+
+}  // namespace md

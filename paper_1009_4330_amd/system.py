@@ -1,0 +1,135 @@
+"""Buffers and run loop for one MD system on the GPU (host-side plumbing).
+
+MDSystem owns the device state, cell arrays, neighbour list and workspace for
+a workload and drives md_step in chunks.  When a list build overflows its
+capacity, the chunk is rerun from a device copy of the state taken before it,
+with the capacity raised to the required count plus headroom.
+"""
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import md
+from .inputs import Workload
+
+PREC = {"fp64": md.MD_FP64, "mixed": md.MD_MIXED}
+KERNEL = {"auto": md.MD_KERNEL_AUTO, "tpa": md.MD_KERNEL_TPA, "wpa": md.MD_KERNEL_WPA,
+          **{f"k{k}": k for k in md.LANES}}
+
+
+def potential_of(w: Workload, **over) -> md.md_potential:
+    if w.potential == "lj":
+        return md.lj_potential(w.rc, over.get("eps", w.lj_eps), over.get("sigma", w.lj_sigma),
+                               w.lj_shift)
+    return md.sc_potential(w.rc, w.sc_eps, w.sc_a, w.sc_c, w.sc_n, w.sc_m)
+
+
+def capacity_guess(w: Workload) -> int:
+    """Neighbour capacity from the mean count in the list sphere, with
+    headroom for density fluctuations of a liquid."""
+    rho = 4.0 / w.a ** 3
+    mean = rho * 4.0 / 3.0 * math.pi * (w.rc + w.skin) ** 3
+    return int(mean * 1.35 + 4.0 * math.sqrt(mean) + 16)
+
+
+class MDSystem:
+    def __init__(self, w: Workload, x: np.ndarray, v: np.ndarray, prec: str = "fp64",
+                 kernel: str = "tpa", capacity: Optional[int] = None, device="cuda"):
+        self.w = w
+        self.prec = PREC[prec]
+        self.kernel = KERNEL[kernel]
+        self.box = md.make_box(w.box)
+        self.pot = potential_of(w)
+        self.rl = w.rc + w.skin
+        n = x.shape[1]
+        self.n = n
+        u = w.units
+        self.state = md.State(torch.as_tensor(x, dtype=torch.float64, device=device),
+                              torch.as_tensor(v, dtype=torch.float64, device=device),
+                              w.mass, u.ftm2v, u.mvv2e, u.boltz)
+        ncell = int(np.prod([math.floor(L / self.rl) for L in w.box]))
+        self.cells = md.Cells(n, ncell, device)
+        self.nl = md.NList(n, capacity or capacity_guess(w), md.MD_LAYOUT_TPA, device)
+        self.ws = md.workspace(n, self.box, self.rl, device)
+        self.ready = False
+        self.steps_done = 0
+        self.device = device
+
+    # -- helpers -------------------------------------------------------------
+    def _snapshot(self):
+        s = self.state
+        return (s.x.clone(), s.v.clone(), s.f.clone(), s.id.clone(), self.nl.x_ref.clone(),
+                self.nl.status.clone())
+
+    def _restore(self, snap):
+        s = self.state
+        for dst, src in zip((s.x, s.v, s.f, s.id, self.nl.x_ref, self.nl.status), snap):
+            dst.copy_(src)
+
+    def _grow(self, need: int):
+        cap = int(need * 1.2) + 16
+        layout = self.nl.layout
+        self.nl = md.NList(self.n, cap, layout, self.device)
+
+    def setup(self, thermo: bool = True) -> Optional[np.ndarray]:
+        """Wrap, bin, sort, build and evaluate forces for the current state."""
+        while True:
+            snap = self._snapshot()
+            rows = torch.zeros(1, 8, dtype=torch.float64, device=self.device) if thermo else None
+            try:
+                md.md_step(self.state, self.pot, self.box, self.cells, self.nl, self.prec,
+                           self.kernel, self.w.skin, self.w.dt, 0, 1, 1, rows, self.ws)
+            except md.MDError as e:
+                if e.code != md.MD_ERR_NLIST_OVERFLOW:
+                    raise
+                need = md.md_nlist_status(self.nl)[md.MD_ST_MAXNEIGH]
+                self._restore(snap)
+                self._grow(need)
+                continue
+            self.ready = True
+            self.kernel = self.nl.layout      # lanes per atom the run settled on
+            return rows.cpu().numpy() if thermo else None
+
+    def run(self, nsteps: int, thermo_every: int = 0, chunk: int = 0) -> np.ndarray:
+        """Advance nsteps; returns thermo rows (every thermo_every steps)."""
+        if not self.ready:
+            self.setup(thermo=False)
+        every = thermo_every if thermo_every > 0 else max(nsteps, 1)
+        chunk = chunk or nsteps
+        out = []
+        done = 0
+        while done < nsteps:
+            k = min(chunk, nsteps - done)
+            rows_n = md.md_thermo_rows(k, every, 0)
+            snap = self._snapshot()
+            th = torch.zeros(max(rows_n, 1), 8, dtype=torch.float64, device=self.device)
+            try:
+                md.md_step(self.state, self.pot, self.box, self.cells, self.nl, self.prec,
+                           self.kernel, self.w.skin, self.w.dt, k, every, 0,
+                           th if rows_n else None, self.ws)
+            except md.MDError as e:
+                if e.code != md.MD_ERR_NLIST_OVERFLOW:
+                    raise
+                need = md.md_nlist_status(self.nl)[md.MD_ST_MAXNEIGH]
+                self._restore(snap)
+                self._grow(need)
+                self.ready = False
+                self.setup(thermo=False)
+                continue
+            if rows_n:
+                r = th[:rows_n].cpu().numpy()
+                r[:, 0] += self.steps_done
+                out.append(r)
+            done += k
+            self.steps_done += k
+        return np.concatenate(out) if out else np.zeros((0, 8))
+
+    def host_state(self):
+        """(x, v, f) as numpy [3][n] arrays in the caller's original atom order."""
+        order = torch.argsort(self.state.id.long())
+        get = lambda t: t[:, order].cpu().numpy()
+        return get(self.state.x), get(self.state.v), get(self.state.f)

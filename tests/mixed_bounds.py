@@ -1,0 +1,89 @@
+"""Rounding-error bounds for MIXED-precision totals (test-side numpy).
+
+In MIXED the scalar pair function is evaluated in FP32: every pair term is a
+difference of two positive parts (LJ: repulsion - attraction; Sutton-Chen:
+pair repulsion - embedding attraction), each carrying a relative FP32
+rounding of a few units of u32 = 2^-24.  The error of any sum of such terms is
+therefore bounded by K u32 times the sum of the *magnitudes* of the parts, not
+by the size of the (often heavily cancelled) total.  These helpers form those
+magnitude sums per pair from the oracle's neighbour list, so a test can assert
+|GPU - oracle| <= K u32 M.  K = 32 allows for the handful of FP32 operations
+(reciprocal, powers, products) per pair term.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+U32 = 2.0 ** -24
+U64 = 2.0 ** -53
+K = 32.0
+VPAIRS = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
+
+
+def pair_geometry(x, box, onl, rc):
+    """Ordered pairs (i, j) of the oracle list with s < rc^2, their d and s."""
+    p = onl.pairs()
+    i, j = p[:, 0], p[:, 1]
+    L = np.asarray(box, dtype=np.float64)[:, None]
+    d = x[:, i] - x[:, j]
+    d = d - L * np.rint(d / L)
+    s = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
+    m = s < rc * rc
+    return i[m], j[m], d[:, m], s[m]
+
+
+def _per_atom(n, i, vals):
+    out = np.zeros(n)
+    np.add.at(out, i, vals)
+    return out
+
+
+def lj_magnitudes(x, box, onl, rc, eps, sigma, u=None):
+    """Magnitude sums for LJ: 'f' [n] per-atom force-term sums, 'e' energy,
+    'w' [6] virial, and with a cotangent u: 'gx' [n], 'geps', 'gsig'."""
+    n = x.shape[1]
+    i, j, d, s = pair_geometry(x, box, onl, rc)
+    sr6 = (sigma * sigma / s) ** 3
+    mag_g = (48.0 * eps * sr6 * sr6 + 24.0 * eps * sr6) / s
+    dn = np.sqrt(s)
+    out = {"f": _per_atom(n, i, mag_g * dn),
+           "e": 0.5 * np.sum(4.0 * eps * (sr6 * sr6 + sr6)),
+           "w": np.array([0.5 * np.sum(np.abs(d[a] * d[b]) * mag_g) for a, b in VPAIRS])}
+    if u is not None:
+        du = u[:, i] - u[:, j]
+        dun = np.sqrt(np.sum(du * du, axis=0))
+        mag_gp = (336.0 * eps * sr6 * sr6 + 96.0 * eps * sr6) / (s * s)
+        out["gx"] = _per_atom(n, i, mag_g * dun + 2.0 * mag_gp * dun * s)
+        un = np.sqrt(np.sum(u[:, i] ** 2, axis=0))
+        out["geps"] = np.sum(un * mag_g * dn) / eps
+        mag_dg = 24.0 * eps / sigma * (24.0 * sr6 * sr6 + 6.0 * sr6) / s
+        out["gsig"] = np.sum(mag_dg * un * dn)
+    return out
+
+
+def sc_magnitudes(x, box, onl, rc, eps, a, c, nexp, mexp, rho):
+    """Magnitude sums for Sutton-Chen, given the oracle's densities rho [n]."""
+    n = x.shape[1]
+    i, j, d, s = pair_geometry(x, box, onl, rc)
+    t = a * a / s
+    pn = t ** (0.5 * nexp)
+    pm = t ** (0.5 * mexp)
+    e = np.where(rho > 0, 1.0 / np.sqrt(np.where(rho > 0, rho, 1.0)), 0.0)
+    mag_h = (nexp * eps * pn + 0.5 * mexp * eps * c * (e[i] + e[j]) * pm) / s
+    dn = np.sqrt(s)
+    return {"f": _per_atom(n, i, mag_h * dn),
+            "e": 0.5 * eps * np.sum(pn) + eps * c * np.sum(np.sqrt(rho)),
+            "w": np.array([0.5 * np.sum(np.abs(d[a_] * d[b_]) * mag_h) for a_, b_ in VPAIRS])}
+
+
+def assert_total(got, want, mag, u=U32, what=""):
+    err = abs(got - want)
+    bound = K * u * mag
+    assert err <= bound, f"{what}: |{got} - {want}| = {err:.3e} > {bound:.3e}"
+
+
+def assert_vector(got, want, mag_per_atom, u=U32, what=""):
+    """Norm-wise: ||got - want|| <= K u ||per-atom magnitude||."""
+    err = float(np.linalg.norm((np.asarray(got) - np.asarray(want)).ravel()))
+    bound = K * u * float(np.linalg.norm(mag_per_atom))
+    assert err <= bound, f"{what}: error {err:.3e} > bound {bound:.3e}"

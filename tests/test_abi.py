@@ -1,0 +1,146 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point the
+header declares, and rejects invalid host arguments before touching the GPU;
+plus the seeded input generators."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1009_4330_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "md.h")
+
+
+@pytest.fixture(scope="module")
+def mdlib():
+    from paper_1009_4330_amd import md
+    if not os.path.exists(md.LIB_PATH):
+        from paper_1009_4330_amd import build
+        build.build()
+    return md
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(md_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_five_calls():
+    names = declared_functions()
+    for call in ("md_bin_cells", "md_build_neighbors", "md_compute_forces", "md_step",
+                 "md_force_vjp"):
+        assert call in names
+
+
+def test_library_exports_every_declared_symbol(mdlib):
+    lib = mdlib.lib()
+    names = declared_functions()
+    assert set(names) == set(mdlib.EXPORTS)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(mdlib):
+    for code in range(8):
+        assert mdlib.status_string(code)
+    assert mdlib.status_string(3) == "neighbour list capacity exceeded"
+
+
+def test_workspace_and_rows_host_logic(mdlib):
+    lib = mdlib.lib()
+    box = mdlib.make_box((16.8, 16.8, 16.8))
+    b = lib.md_workspace_bytes(4000, ctypes.byref(box), 2.8)
+    assert b > 4000 * (8 * 3 * 3 + 8 * 9) and b % 256 == 0
+    assert lib.md_workspace_bytes(4000, ctypes.byref(mdlib.make_box((5.0, 16.8, 16.8))), 2.8) == 0
+    assert lib.md_workspace_bytes(0, ctypes.byref(box), 2.8) == 0
+    # the neighbour buffer fits every lanes-per-atom layout K (see md.h)
+    for n, cap in ((4000, 100), (1, 1), (100, 7), (256000, 130)):
+        want = max(-(-n // (64 // k)) * -(-cap // k) * 64 for k in mdlib.LANES)
+        assert mdlib.md_nlist_ints(n, cap) == want
+    assert lib.md_nlist_ints(10, 0) == 0
+    assert mdlib.md_thermo_rows(100, 10, 1) == 11
+    assert mdlib.md_thermo_rows(100, 7, 0) == 14
+    assert mdlib.md_thermo_rows(-1, 10, 0) == 0
+
+
+def test_host_validation_precedes_any_launch(mdlib):
+    """Each of these returns its code from host checks alone (no device)."""
+    lib = mdlib.lib()
+    fake = ctypes.c_void_p(0x1000)
+    box = mdlib.make_box(I.LJ_4K.box)
+    small = mdlib.make_box((5.0, 16.8, 16.8))
+    cells = mdlib.md_cells(ncell_cap=125, cell_start=0x1000, atom_cell=0x1000, perm=0x1000)
+    nl = mdlib.md_nlist(capacity=100, layout=1, rl=2.8, neigh=0x1000, numneigh=0x1000,
+                        x_ref=0x1000, status=0x1000)
+    lj = mdlib.lj_potential(2.5)
+    R = ctypes.byref
+    assert lib.md_bin_cells(None, 4000, R(box), 2.8, R(cells), fake, 1 << 30, None) == 1
+    assert lib.md_bin_cells(fake, 4000, R(small), 2.8, R(cells), fake, 1 << 30, None) == 2
+    assert lib.md_bin_cells(fake, 0, R(box), 2.8, R(cells), fake, 1 << 30, None) == 1
+    assert lib.md_bin_cells(fake, 4000, R(box), 2.8, R(cells), fake, 16, None) == 7
+    tiny_cells = mdlib.md_cells(ncell_cap=10, cell_start=0x1000, atom_cell=0x1000, perm=0x1000)
+    assert lib.md_bin_cells(fake, 4000, R(box), 2.8, R(tiny_cells), fake, 1 << 30, None) == 1
+    # wrong kernel / layout pairing, bad precision, bad flags
+    assert lib.md_compute_forces(R(lj), fake, 4000, R(box), R(nl), 0, 2, 0, fake, None, fake,
+                                 1 << 30, None) == 1
+    assert lib.md_compute_forces(R(lj), fake, 4000, R(box), R(nl), 7, 1, 0, fake, None, fake,
+                                 1 << 30, None) == 1
+    assert lib.md_compute_forces(R(lj), fake, 4000, R(box), R(nl), 0, 1, 1, fake, None, fake,
+                                 1 << 30, None) == 1
+    bad = mdlib.lj_potential(-1.0)
+    assert lib.md_compute_forces(R(bad), fake, 4000, R(box), R(nl), 0, 1, 0, fake, None, fake,
+                                 1 << 30, None) == 1
+    sc = mdlib.sc_potential(7.22, 0.012, 3.61, 39.4, 9, 6)
+    assert lib.md_force_vjp(R(sc), fake, 4000, R(box), R(nl), 0, fake, fake, None, fake,
+                            1 << 30, None) == 5
+    nl0 = mdlib.md_nlist(capacity=0, layout=1, rl=2.8, neigh=0x1000, numneigh=0x1000,
+                         x_ref=0x1000, status=0x1000)
+    assert lib.md_build_neighbors(fake, 4000, R(box), R(cells), 2.5, 0.3, R(nl0), None) == 1
+    st = mdlib.md_state(n=4000, x=0x1000, v=0x1000, f=0x1000, id=0x1000, mass=1.0, ftm2v=1.0,
+                        mvv2e=1.0, boltz=1.0)
+    assert lib.md_step(R(st), R(lj), R(small), R(cells), R(nl), 0, 1, 0.3, 0.005, 10, 10, 1,
+                       fake, fake, 1 << 30, None) == 2
+    assert lib.md_step(R(st), R(lj), R(box), R(cells), R(nl), 0, 1, 0.3, -0.005, 10, 10, 1,
+                       fake, fake, 1 << 30, None) == 1
+    assert lib.md_step(R(st), R(lj), R(box), R(cells), R(nl), 0, 1, 0.3, 0.005, 10, 0, 1,
+                       None, fake, 1 << 30, None) == 1
+
+
+# ------------------------------------------------------------ inputs --
+
+
+def test_fcc_lattice_counts_and_spacing():
+    x = I.fcc_positions(3, 2.0)
+    assert x.shape == (3, 108)
+    L = 6.0
+    d = x[:, :, None] - x[:, None, :]
+    d -= L * np.round(d / L)
+    r = np.sqrt((d * d).sum(axis=0))
+    np.fill_diagonal(r, np.inf)
+    assert np.allclose(r.min(axis=1), 2.0 / math.sqrt(2.0))
+    assert np.all((r < 1.5).sum(axis=1) == 12)
+
+
+def test_workload_sizes():
+    assert I.LJ_4K.natoms == 4000 and I.LJ_256K.natoms == 256000
+    assert I.LJ_HI_108K.natoms == 108000 and I.SC_500K.natoms == 500000
+    assert I.LJ_FM_32K.natoms == 32000
+    assert I.LJ_256K.box[0] == pytest.approx(40 * (4 / 0.8442) ** (1 / 3))
+    assert 4 * I.LJ_4K.ncell ** 3 / I.LJ_4K.box[0] ** 3 == pytest.approx(0.8442)
+
+
+def test_velocities_seeded_zero_momentum_exact_temperature():
+    v1 = I.gaussian_velocities(4000, 3.0, 1.0, I.LJ_UNITS, 4000)
+    v2 = I.gaussian_velocities(4000, 3.0, 1.0, I.LJ_UNITS, 4000)
+    assert np.array_equal(v1, v2)
+    assert np.abs(v1.sum(axis=1)).max() < 1e-10
+    t = np.sum(v1 * v1) / (3 * 4000 - 3)
+    assert t == pytest.approx(3.0, rel=1e-14)
+    vm = I.gaussian_velocities(500, 600.0, 63.55, I.METAL_UNITS, 5)
+    tm = 63.55 * I.METAL_MVV2E * np.sum(vm * vm) / ((3 * 500 - 3) * I.METAL_BOLTZ)
+    assert tm == pytest.approx(600.0, rel=1e-14)

@@ -1,0 +1,136 @@
+"""md_step (velocity Verlet + half-skin rebuilds, all on the device) against
+the oracle's NVE run from the same seeded state."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import SC_KW, dev, forces_gpu, gpu_list, lj_liquid, rel
+from paper_1009_4330_amd import inputs as I
+from paper_1009_4330_amd import md
+from paper_1009_4330_amd.system import MDSystem
+
+pytestmark = pytest.mark.gpu
+
+
+def min_image_diff(a, b, box):
+    L = np.array(box)[:, None]
+    d = a - b
+    return d - L * np.round(d / L)
+
+
+def run_both(orc, w, x, v, prec="fp64", kernel="tpa", steps=None, every=1, capacity=None):
+    steps = w.steps if steps is None else steps
+    ref = orc.md_run(orc.params_for(w), x, v, w.box, steps, every)
+    sysm = MDSystem(w, x, v, prec, kernel, capacity=capacity)
+    row0 = sysm.setup(thermo=True)
+    rows = np.concatenate([row0, sysm.run(steps, every)])
+    gx, gv, gf = sysm.host_state()
+    return ref, rows, gx, gv, gf, sysm
+
+
+@pytest.mark.parametrize("kernel", ["tpa", "wpa", "auto"])
+def test_c1_fp64_trajectory_and_rebuild_schedule(orc, kernel):
+    w = I.LJ_4K
+    x, v, box = I.initial_state(w)
+    ref, rows, gx, gv, gf, _ = run_both(orc, w, x, v, "fp64", kernel)
+    # same rebuild steps: cumulative build counts after every step agree
+    want_builds = np.cumsum(ref.rebuilt)
+    assert np.array_equal(rows[:, 6].astype(int), want_builds)
+    assert np.array_equal(rows[:, 7].astype(int), ref.thermo[:, 7].astype(int))
+    assert np.array_equal(rows[:, 0], ref.thermo[:, 0])
+    # thermo quantities (pe, ke, etot, T, P)
+    for c in (1, 2, 3, 4, 5):
+        assert rel(rows[:, c], ref.thermo[:, c]) < 1e-10, c
+    assert np.abs(min_image_diff(gx, ref.x, box)).max() < 1e-9
+    assert np.abs(gv - ref.v).max() < 1e-9
+    assert rel(gf, ref.f) < 1e-8
+
+
+def test_step_is_deterministic():
+    w = I.scaled(I.LJ_4K, 8, steps=60)
+    x, v, box = I.initial_state(w)
+    outs = []
+    for _ in range(2):
+        s = MDSystem(w, x, v, "fp64", "wpa")
+        rows = np.concatenate([s.setup(True), s.run(60, 10)])
+        outs.append((rows, *s.host_state()))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_c1_mixed_energy_drift_and_force_error(orc):
+    """MIXED NVE from the C1 state: shifted total energy drift stays within
+    twice the FP64 run's, and the force error against the FP64 oracle at the
+    oracle's own trajectory snapshots stays below 1e-6 rel-RMS."""
+    w = I.LJ_4K
+    x, v, box = I.initial_state(w)
+    drift = {}
+    for prec in ("fp64", "mixed"):
+        s = MDSystem(w, x, v, prec, "tpa")
+        rows = np.concatenate([s.setup(True), s.run(w.steps, 1)])
+        e = rows[:, 3]
+        drift[prec] = np.max(np.abs(e - e[0])) / abs(e[0])
+    print(f"max |dE/E0| over 100 steps: fp64 {drift['fp64']:.3e} mixed {drift['mixed']:.3e}")
+    assert drift["mixed"] < 2.0 * drift["fp64"] + 1e-6
+    errs = []
+    xs, vs = x, v
+    for k in range(5):
+        snap = orc.md_run(orc.params_for(w), xs, vs, box, 20, 20)
+        xs, vs = snap.x, snap.v
+        xg, cells, nl, ws, mbox = gpu_list(xs, box, 2.5, 0.3, md.MD_LAYOUT_TPA, 160)
+        f, _ = forces_gpu(md.lj_potential(2.5), xg, mbox, nl, md.MD_MIXED, md.MD_KERNEL_TPA, ws,
+                          flags=0)
+        onl, oc = orc.build_nlist(xs, box, 2.8)
+        errs.append(rel(f, orc.lj_forces(oc.x, box, onl, 2.5).f))
+    print("mixed force rel-RMS at oracle snapshots:", ["%.2e" % e for e in errs])
+    assert max(errs) < 1e-6
+
+
+def test_sutton_chen_step_fp64(orc):
+    w = I.scaled(I.SC_500K, 6, steps=20)
+    x, v, box = I.initial_state(w)
+    ref, rows, gx, gv, gf, _ = run_both(orc, w, x, v, "fp64", "tpa", every=5)
+    assert np.array_equal(rows[:, 6].astype(int), ref.thermo[:, 6].astype(int))
+    for c in (1, 2, 3, 4, 5):
+        assert rel(rows[:, c], ref.thermo[:, c]) < 1e-10, c
+    assert np.abs(min_image_diff(gx, ref.x, box)).max() < 1e-9
+    assert rel(gf, ref.f) < 1e-9
+
+
+def test_overflow_recovery_gives_same_run(orc):
+    """Starting from a list far too small, the run loop grows the capacity and
+    repeats the chunk; the trajectory matches the oracle."""
+    w = I.scaled(I.LJ_4K, 6, steps=30, temp=2.0)
+    x, v, box = I.initial_state(w)
+    ref, rows, gx, gv, gf, s = run_both(orc, w, x, v, "fp64", "tpa", every=10, capacity=8)
+    assert s.nl.capacity > 8
+    assert rel(rows[:, 3], ref.thermo[:, 3]) < 1e-10
+    assert np.abs(min_image_diff(gx, ref.x, box)).max() < 1e-9
+
+
+def test_step_reports_overflow_and_nonfinite():
+    w = I.scaled(I.LJ_4K, 6, steps=5)
+    x, v, box = I.initial_state(w)
+    s = MDSystem(w, x, v, "fp64", "tpa", capacity=8)
+    with pytest.raises(md.MDError) as ei:
+        md.md_step(s.state, s.pot, s.box, s.cells, s.nl, s.prec, s.kernel, w.skin, w.dt, 0, 1, 1,
+                   None, s.ws)
+    assert ei.value.code == md.MD_ERR_NLIST_OVERFLOW
+    assert md.md_nlist_status(s.nl)[md.MD_ST_MAXNEIGH] > 8
+    xb = x.copy()
+    xb[0, 7] = np.nan
+    s2 = MDSystem(w, xb, v, "fp64", "tpa", capacity=200)
+    with pytest.raises(md.MDError) as ei:
+        md.md_step(s2.state, s2.pot, s2.box, s2.cells, s2.nl, s2.prec, s2.kernel, w.skin, w.dt, 2,
+                   1, 1, None, s2.ws)
+    assert ei.value.code == md.MD_ERR_NONFINITE
+
+
+def test_momentum_conserved_mixed():
+    w = I.scaled(I.LJ_4K, 10, steps=200)
+    x, v, box = I.initial_state(w)
+    s = MDSystem(w, x, v, "mixed", "tpa")
+    s.setup(False)
+    s.run(200, 200)
+    p = s.state.v.sum(dim=1).cpu().numpy()
+    assert np.abs(p).max() < 1e-10 * w.natoms
