@@ -2,7 +2,8 @@
 
 Headline: atom-timesteps/s of the 256,000-atom LJ melt (fcc 40^3 at reduced
 density 0.8442, rc 2.5, skin 0.3, T* 3.0, dt 0.005) in FP32-mixed precision
-with the thread-per-atom kernel; the plain FP64 path on the same workload,
+with the force kernel the setup mini-benchmark picks (K lanes per atom); the
+plain FP64 path and the thread-per-atom kernel (K = 1) on the same workload,
 and the LJ adjoint (force VJP) throughput in atoms/s on eight 32,000-atom
 snapshots thermalised for 500 NVE steps, are reported beside it.
 
@@ -146,6 +147,38 @@ def cpu_baseline(w, x, v, target_s: float = 15.0):
                        f"state (FP64, setup excluded, {t:.1f} s)")
 
 
+def profile_force(launches: int, kernel: str):
+    """For hardware-counter passes: the headline state after a short warm-up,
+    then `launches` force evaluations alone, then a plain device copy of known
+    size (256 MiB read + 256 MiB written, 4 times) that calibrates the byte
+    counters."""
+    import torch
+    from paper_1009_4330_amd import inputs as I
+    from paper_1009_4330_amd import md
+    from paper_1009_4330_amd.system import MDSystem
+
+    w = I.LJ_256K
+    x, v, _ = I.initial_state(w)
+    s = MDSystem(w, x, v, "mixed", kernel)
+    s.setup(thermo=False)
+    s.run(20, 20)
+    f = torch.empty_like(s.state.f)
+    for _ in range(launches):
+        md.md_compute_forces(s.pot, s.state.x, s.box, s.nl, s.prec, md.MD_KERNEL_AUTO, 0, f,
+                             None, s.ws)
+    torch.cuda.synchronize()
+    nbytes = 256 << 20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(4):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"force_launches": launches, "atoms": w.natoms,
+                      "mean_neighbors": s.nl.numneigh.double().mean().item(),
+                      "lanes_per_atom": s.nl.layout, "copy_bytes_read": nbytes,
+                      "copy_bytes_written": nbytes, "copy_launches": 4}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,7 +187,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="time only the headline configuration")
+    ap.add_argument("--kernel", default="auto",
+                    help="force kernel: tpa, wpa, auto or kN (N lanes per atom)")
+    ap.add_argument("--profile-force", type=int, default=0, metavar="N",
+                    help="run N force-only launches and a calibration copy (for counters)")
     args = ap.parse_args()
+    if args.profile_force:
+        profile_force(args.profile_force, args.kernel)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
@@ -168,20 +208,30 @@ def main():
         sys.exit(1)
     w = I.LJ_256K
     x, v, _ = I.initial_state(w)
-    log(f"[bench] {w.name}: {w.natoms} atoms, mixed precision, thread-per-atom")
-    mixed = run_md(w, x, v, "mixed", "tpa", args.steps, args.warmup)
+    log(f"[bench] {w.name}: {w.natoms} atoms, mixed precision, kernel {args.kernel}")
+    mixed = run_md(w, x, v, "mixed", args.kernel, args.steps, args.warmup)
     value = args.steps * w.natoms / mixed["elapsed"]
-    log(f"[bench] mixed: {value:.4g} atom-steps/s, {1e3 * mixed['elapsed'] / args.steps:.4f} "
-        f"ms/step, force avg {1e3 * mixed['force_ms_avg']:.2f} us")
+    lanes = mixed["kernel"]
+    log(f"[bench] mixed K={lanes}: {value:.4g} atom-steps/s, "
+        f"{1e3 * mixed['elapsed'] / args.steps:.4f} ms/step, "
+        f"force avg {1e3 * mixed['force_ms_avg']:.2f} us, rebuilds {mixed['rebuilds']}")
     extras = {}
     if not args.no_extras:
-        fp64 = run_md(w, x, v, "fp64", "tpa", args.steps, args.warmup)
+        fp64 = run_md(w, x, v, "fp64", args.kernel, args.steps, args.warmup)
         v64 = args.steps * w.natoms / fp64["elapsed"]
-        log(f"[bench] fp64: {v64:.4g} atom-steps/s, force avg {1e3 * fp64['force_ms_avg']:.2f} us")
+        log(f"[bench] fp64 K={fp64['kernel']}: {v64:.4g} atom-steps/s, "
+            f"force avg {1e3 * fp64['force_ms_avg']:.2f} us")
+        tpa = run_md(w, x, v, "mixed", "tpa", args.steps, args.warmup)
+        vt = args.steps * w.natoms / tpa["elapsed"]
+        log(f"[bench] mixed K=1 (thread per atom): {vt:.4g} atom-steps/s, "
+            f"force avg {1e3 * tpa['force_ms_avg']:.2f} us")
         vjp = bench_vjp(reps=20)
         log(f"[bench] vjp atoms/s: {vjp}")
         extras = {"fp64_atom_timesteps_per_s": v64, "mixed_over_fp64": value / v64,
                   "fp64_force_kernel_us": 1e3 * fp64["force_ms_avg"],
+                  "fp64_lanes_per_atom": fp64["kernel"],
+                  "mixed_tpa_atom_timesteps_per_s": vt,
+                  "mixed_tpa_force_kernel_us": 1e3 * tpa["force_ms_avg"],
                   "adjoint_hvp_atoms_per_s": vjp["mixed"],
                   "adjoint_hvp_atoms_per_s_fp64": vjp["fp64"]}
 
@@ -189,7 +239,7 @@ def main():
     alg_bytes = bpa * w.natoms
     avg_s = mixed["force_ms_avg"] * 1e-3
     achieved = alg_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
-    kname = "k_lj_tpa<1, false>"
+    kname = f"k_lj<MIXED, no energy/virial, K={lanes}>"
     traffic = measured_traffic(kname, alg_bytes)
     line = {
         "metric": "atom-timesteps/s, LJ 256k atoms FP32-mixed vs FP64; adjoint HVP atoms/s",
@@ -206,7 +256,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "lj_melt_256k", "atoms": w.natoms, "lattice": "fcc 40^3",
                    "density": 0.8442, "rc": w.rc, "skin": w.skin, "dt": w.dt, "temp": w.temp,
-                   "precision": "mixed", "kernel": "tpa", "thermo_every": THERMO_EVERY},
+                   "precision": "mixed", "kernel_selection": args.kernel,
+                   "lanes_per_atom": lanes, "thermo_every": THERMO_EVERY},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kname, "bytes_per_atom": bpa,

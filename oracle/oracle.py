@@ -7,6 +7,7 @@ largest neighbour count so callers can grow the list and retry).
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import subprocess
@@ -39,6 +40,30 @@ def build(force: bool = True) -> str:
 
 
 _lib = None
+
+
+@contextlib.contextmanager
+def using(path: str):
+    """Temporarily route every wrapper through another build of the oracle
+    (used by the tests that plant mistakes in a copy of the source)."""
+    global _lib
+    old = _lib
+    L = ctypes.CDLL(path)
+    _declare(L)
+    _lib = L
+    try:
+        yield
+    finally:
+        _lib = old
+
+
+def build_variant(source_text: str, out_path: str) -> str:
+    """Compile an edited copy of md_oracle.c with the oracle's own flags."""
+    src = out_path + ".c"
+    with open(src, "w") as fh:
+        fh.write(source_text)
+    subprocess.check_call(["gcc", *CFLAGS, "-o", out_path, src, "-lm"])
+    return out_path
 
 
 def lib():

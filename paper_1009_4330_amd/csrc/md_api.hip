@@ -712,14 +712,28 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
     }
   }
   const int layout = kernel;
+  // Step s: [closing kick of s-1 +] kick + drift + check, gated rebuild,
+  // forces.  The closing kick of step s-1 is fused into step s's first kernel;
+  // the thermo row of step s-1 is summed right after it, before step s's
+  // forces overwrite the per-atom energies.  The last step's closing kick runs
+  // on its own at the end, so every call returns a full-step state.
+  auto is_thermo = [&](int step) { return thermo && step >= 1 && step % thermo_every == 0; };
   for (int step = 1; step <= nsteps; ++step) {
-    const bool th = thermo && (step % thermo_every) == 0;
-    MD_CK(launch_kick_drift_check(stt->x, stt->v, stt->f, nl->x_ref, n, dtfm, dt, trig2, status,
-                                  s));
+    const bool th_prev = is_thermo(step - 1);
+    if (step == 1)
+      MD_CK(launch_kick_drift_check(stt->x, stt->v, stt->f, nl->x_ref, n, dtfm, dt, trig2,
+                                    status, s));
+    else
+      MD_CK(launch_vv_step(stt->x, stt->v, stt->f, nl->x_ref, n, dtfm, dt, trig2,
+                           th_prev ? keatom : nullptr, status, s));
+    if (th_prev && (st = thermo_out((double)(step - 1))) != MD_OK) return st;
     if ((st = rebuild(gate, layout)) != MD_OK) return st;
-    if ((st = forces(th, kernel)) != MD_OK) return st;
+    if ((st = forces(is_thermo(step), kernel)) != MD_OK) return st;
+  }
+  if (nsteps > 0) {
+    const bool th = is_thermo(nsteps);
     MD_CK(launch_kick(stt->v, stt->f, n, dtfm, th ? keatom : nullptr, status, s));
-    if (th && (st = thermo_out((double)step)) != MD_OK) return st;
+    if (th && (st = thermo_out((double)nsteps)) != MD_OK) return st;
   }
   int words[MD_STATUS_WORDS];
   MD_CK(hipMemcpyAsync(words, status, sizeof(words), hipMemcpyDeviceToHost, s));

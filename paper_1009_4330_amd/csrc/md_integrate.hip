@@ -31,6 +31,39 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift_check(
   if (!finite) atomicOr(&status[MD_ST_ERRORS], 2);
 }
 
+// Two velocity-Verlet halves in one pass: the closing kick of step s-1
+// (v += dtfm f, optionally |v|^2 of that full-step velocity for step s-1's
+// kinetic energy), then step s's kick, drift and displacement check.  The
+// arithmetic is exactly that of k_kick followed by k_kick_drift_check.
+__global__ __launch_bounds__(kBlock) void k_vv_step(
+    double* __restrict__ x, double* __restrict__ v, const double* __restrict__ f,
+    const double* __restrict__ xr, int n, double dtfm, double dt, double trig2,
+    double* __restrict__ keatom, int* __restrict__ status) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  bool finite = true;
+  double vh[3], dd[3];
+  for (int d = 0; d < 3; ++d) {
+    const int q = d * n + i;
+    const double fq = f[q];
+    finite = finite && isfinite(fq);
+    vh[d] = v[q] + dtfm * fq;
+  }
+  if (keatom) keatom[i] = vh[0] * vh[0] + vh[1] * vh[1] + vh[2] * vh[2];
+  for (int d = 0; d < 3; ++d) {
+    const int q = d * n + i;
+    const double vn = vh[d] + dtfm * f[q];
+    const double xn = x[q] + dt * vn;
+    v[q] = vn;
+    x[q] = xn;
+    dd[d] = xn - xr[q];
+    finite = finite && isfinite(xn);
+  }
+  const double d2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
+  if (d2 > trig2) atomicOr(&status[MD_ST_REBUILD], 1);
+  if (!finite) atomicOr(&status[MD_ST_ERRORS], 2);
+}
+
 // v += dtfm f; optionally the per-atom |v|^2 for the kinetic energy.
 __global__ __launch_bounds__(kBlock) void k_kick(double* __restrict__ v,
                                                   const double* __restrict__ f, int n,
@@ -125,6 +158,13 @@ hipError_t launch_kick_drift_check(double* x, double* v, const double* f, const 
                                    int n, double dtfm, double dt, double trig2, int* status,
                                    hipStream_t s) {
   k_kick_drift_check<<<blocks_for(n), kBlock, 0, s>>>(x, v, f, xr, n, dtfm, dt, trig2, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_vv_step(double* x, double* v, const double* f, const double* xr, int n,
+                          double dtfm, double dt, double trig2, double* keatom, int* status,
+                          hipStream_t s) {
+  k_vv_step<<<blocks_for(n), kBlock, 0, s>>>(x, v, f, xr, n, dtfm, dt, trig2, keatom, status);
   return hipGetLastError();
 }
 

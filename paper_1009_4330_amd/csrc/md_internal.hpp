@@ -164,6 +164,11 @@ hipError_t launch_kick_drift_check(double* x, double* v, const double* f, const 
 hipError_t launch_kick(double* v, const double* f, int n, double dtfm, double* keatom,
                        int* status, hipStream_t s);
 hipError_t launch_ke(const double* v, int n, double* keatom, hipStream_t s);
+// Closing kick of the previous step (|v|^2 into keatom when not null) fused
+// with this step's kick, drift and displacement check.
+hipError_t launch_vv_step(double* x, double* v, const double* f, const double* xr, int n,
+                          double dtfm, double dt, double trig2, double* keatom, int* status,
+                          hipStream_t s);
 
 // Deterministic sums: cols arrays of n doubles (col c at base[c] ) -> out[cols].
 struct SumArgs {

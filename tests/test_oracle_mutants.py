@@ -1,0 +1,76 @@
+"""The oracle's pins are sensitive: each test plants one plausible mistake in
+a copy of the oracle's source, builds it, and checks that at least one of the
+pins named for it fails (all on the CPU; the product library is not involved).
+"""
+import os
+import tempfile
+
+import pytest
+
+import test_oracle as T
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle",
+                   "md_oracle.c")
+
+# name -> (original text, planted mistake, pins expected to catch it)
+MUTANTS = {
+    "virial_sign": ("wi[0] += 0.5 * d[0] * d[0] * g;", "wi[0] -= 0.5 * d[0] * d[0] * g;",
+                    ["lattice", "brute_lj"]),
+    "energy_half_dropped": ("ei += 0.5 * phi;", "ei += phi;", ["lattice", "two_atom"]),
+    "no_minimum_image": ("return d - L * rint(d / L);", "return d;", ["brute_list"]),
+    "lj_force_factor": ("double g = 24.0 * eps * sr6 * (2.0 * sr6 - 1.0) / s;",
+                        "double g = 24.0 * eps * sr6 * (sr6 - 1.0) / s;", ["fd_lj", "two_atom"]),
+    "sc_embedding_index": ("(em[i] + em[j])", "(em[i] + em[i])", ["fd_sc", "brute_sc"]),
+    "sc_density_power": ("ri += pow(a2 / s, 0.5 * mexp);", "ri += pow(a2 / s, mexp);",
+                         ["sc_lattice", "brute_sc"]),
+    "vjp_second_term_sign": ("gi[q] += g * du[q] + 2.0 * gp * dud * d[q];",
+                             "gi[q] += g * du[q] - 2.0 * gp * dud * d[q];", ["fd_vjp", "sym_vjp"]),
+    "vjp_sigma_term": ("dsig += dg * (ui[0] * d[0] + ui[1] * d[1] + ui[2] * d[2]);",
+                       "dsig += dg * (ui[0] * d[0] + ui[1] * d[1]);", ["fd_vjp"]),
+    "full_kick_per_half": ("const double dtfm = (0.5 * p->dt * p->ftm2v) / p->mass;",
+                           "const double dtfm = (p->dt * p->ftm2v) / p->mass;",
+                           ["verlet_order", "reversible"]),
+    "trigger_full_skin": ("int reb = dmax > trig2;", "int reb = dmax > 4.0 * trig2;",
+                          ["schedule"]),
+    "stencil_duplicates": ("if (!dup) out[k++] = v;", "out[k++] = v;", ["brute_list"]),
+    "kinetic_half_dropped": ("double ke = 0.5 * p->mvv2e * p->mass * sv;",
+                             "double ke = p->mvv2e * p->mass * sv;", ["temperature"]),
+    "cell_index_scale": ("int c = (int)((r * (double)nc) / L);",
+                         "int c = (int)((r * (double)(nc - 1)) / L);", ["bin_sort", "brute_list"]),
+}
+
+PINS = {
+    "lattice": lambda o: T.test_lj_perfect_lattice_closed_form(o, 2.5),
+    "two_atom": lambda o: T.test_lj_two_atom_golden(o),
+    "brute_lj": lambda o: T.test_lj_equals_all_image_brute_force(o, 4, 0.3, 21),
+    "brute_list": lambda o: T.test_nlist_equals_all_image_brute_force(o, 4, 0.3, 11, 0.0),
+    "fd_lj": lambda o: T.test_lj_forces_are_minus_energy_gradient(o),
+    "fd_sc": lambda o: T.test_sc_forces_are_minus_energy_gradient(o),
+    "brute_sc": lambda o: T.test_sc_equals_all_image_brute_force(o),
+    "sc_lattice": lambda o: T.test_sc_perfect_lattice_closed_form(o),
+    "fd_vjp": lambda o: T.test_vjp_matches_central_differences(o),
+    "sym_vjp": lambda o: T.test_vjp_symmetry_translation_and_linearity(o),
+    "verlet_order": lambda o: T.test_nve_energy_error_is_second_order_in_dt(o),
+    "reversible": lambda o: T.test_nve_time_reversible(o),
+    "schedule": lambda o: T.test_rebuild_schedule_follows_half_skin(o),
+    "temperature": lambda o: T.test_initial_temperature_and_momentum(o),
+    "bin_sort": lambda o: T.test_bin_is_stable_counting_sort(o, 4, 1),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(orc, name):
+    original, planted, pins = MUTANTS[name]
+    text = open(SRC).read()
+    assert text.count(original) == 1, f"mutation site for {name} not unique"
+    with tempfile.TemporaryDirectory() as tmp:
+        path = orc.oracle.build_variant(text.replace(original, planted),
+                                        os.path.join(tmp, f"mut_{name}.so"))
+        caught = []
+        with orc.oracle.using(path):
+            for pin in pins:
+                try:
+                    PINS[pin](orc)
+                except (AssertionError, orc.OracleError):
+                    caught.append(pin)
+    assert caught, f"planted mistake {name!r} passed every pin in {pins}"
