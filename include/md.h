@@ -47,7 +47,8 @@ typedef enum {
   MD_ERR_NONFINITE = 4,      /* a position or force became NaN / Inf */
   MD_ERR_UNSUPPORTED = 5,    /* valid request the library does not implement */
   MD_ERR_HIP = 6,            /* a HIP runtime call failed */
-  MD_ERR_WORKSPACE = 7       /* ws is NULL or smaller than md_workspace_bytes */
+  MD_ERR_WORKSPACE = 7,      /* ws is NULL or smaller than md_workspace_bytes */
+  MD_ERR_UNSTABLE = 8        /* md_step: an atom moved more than a cell edge between builds */
 } md_status;
 
 typedef enum { MD_FP64 = 0, MD_MIXED = 1 } md_precision;
@@ -187,7 +188,11 @@ md_status md_compute_forces(const md_potential* p, const double* x, int64_t n,
      rebuild (wrap, bin, sort, list) if max_i |x_i - x_ref_i|^2 > (skin/2)^2;
      f = forces(x); v += dtfm f.
    With setup != 0 the state is first wrapped, binned, sorted and listed and
-   forces are computed (a thermo row for that state is written first).
+   forces are computed (a thermo row for that state is written first).  With
+   setup == 0, st, cells and nl must be as a previous md_step on the same
+   system left them (atoms in cell order, list and forces current); rebuilds
+   then re-sort by gathering each cell's atoms from the previous cell ranges,
+   and MD_ERR_UNSTABLE reports an atom that moved more than a cell edge.
    thermo (device, md_thermo_rows(...) x 8 doubles, or NULL for none): for
    each step s with s % thermo_every == 0: s, pe, ke, pe + ke,
    T = 2 ke / ((3n - 3) kB), P = (2 ke + tr W) / (3 V), builds so far,

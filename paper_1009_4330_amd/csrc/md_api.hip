@@ -49,6 +49,12 @@ bool cell_dims(const md_box* box, double rl, int nc[3], int64_t* ncell) {
   return true;
 }
 
+// Margin of the interior fast path: an atom at least r_l + skin = 2 r_l - r_c
+// from every face has all its list partners in its own periodic image.
+double interior_margin(const md_potential* p, double rl) {
+  return rl > p->rc ? 2.0 * rl - p->rc : HUGE_VAL;
+}
+
 BoxK make_box(const md_box* b) {
   BoxK k;
   for (int d = 0; d < 3; ++d) {
@@ -221,6 +227,7 @@ md_status autoselect_impl(const md_potential* p, const double* x, int n, int sor
     fa.x = x;
     fa.n = n;
     fa.box = make_box(box);
+    fa.margin = interior_margin(p, rl);
     fa.neigh = nl->neigh;
     fa.numneigh = nl->numneigh;
     fa.cap = nl->capacity;
@@ -280,8 +287,9 @@ int resolve_lanes(md_kernel k, int layout) {
 }
 
 md_status status_from_words(const int* w) {
-  if (w[MD_ST_ERRORS] & 1) return MD_ERR_NLIST_OVERFLOW;
   if (w[MD_ST_ERRORS] & 2) return MD_ERR_NONFINITE;
+  if (w[MD_ST_ERRORS] & 4) return MD_ERR_UNSTABLE;
+  if (w[MD_ST_ERRORS] & 1) return MD_ERR_NLIST_OVERFLOW;
   return MD_OK;
 }
 
@@ -312,6 +320,7 @@ WsLayout ws_layout(int64_t n, int64_t ncell) {
   L.partials = take(sizeof(double) * kReduceBlocks * kReduceCols);
   L.scalars = take(sizeof(double) * 16);
   L.ticket = take(sizeof(int) * 64);
+  L.new_start = take(sizeof(int) * (size_t)((ncell > 0 ? ncell : 1) + 1));
   L.total = o;
   return L;
 }
@@ -354,6 +363,7 @@ const char* md_status_string(md_status s) {
     case MD_ERR_UNSUPPORTED: return "unsupported request";
     case MD_ERR_HIP: return "HIP runtime error";
     case MD_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+    case MD_ERR_UNSTABLE: return "an atom moved more than a cell edge between list builds";
   }
   return "unknown status";
 }
@@ -450,6 +460,7 @@ md_status md_compute_forces(const md_potential* p, const double* x, int64_t n,
   fa.x = x;
   fa.n = (int)n;
   fa.box = make_box(box);
+  fa.margin = interior_margin(p, nl->rl);
   fa.neigh = nl->neigh;
   fa.numneigh = nl->numneigh;
   fa.cap = nl->capacity;
@@ -490,6 +501,7 @@ md_status md_force_vjp(const md_potential* p, const double* x, int64_t n, const 
   fa.x = x;
   fa.n = (int)n;
   fa.box = make_box(box);
+  fa.margin = interior_margin(p, nl->rl);
   fa.neigh = nl->neigh;
   fa.numneigh = nl->numneigh;
   fa.cap = nl->capacity;
@@ -591,23 +603,35 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
 
   int* ticket = at<int>(ws, L.ticket);
 
-  // Rebuild chain: wrap + bin + count (+ scan in its last workgroup), scatter,
-  // stable in-cell order with the state gathered into staging, list build that
-  // copies the state back.  With a gate, every kernel returns at once unless
-  // the rebuild flag is set.
+  int* new_start = at<int>(ws, L.new_start);
+
+  // Rebuild chain.  At setup (no gate; atoms in arbitrary order): wrap + bin +
+  // count (+ scan in its last workgroup), scatter, stable in-cell order with
+  // the state gathered into staging, list build that copies the state back.
+  // During a run (gated; atoms in the previous build's cell order): wrap + bin
+  // + count into new_start, gather-sort from the previous cell ranges, list
+  // build, which also copies new_start into cells->cell_start.  Gated kernels
+  // return at once unless the rebuild flag is set.
   auto rebuild = [&](const int* g, int layout) -> md_status {
-    MD_CK(launch_bin_count(stt->x, n, bk, nc, cells->atom_cell, count, slot, cells->cell_start,
+    int* starts = g ? new_start : cells->cell_start;
+    MD_CK(launch_bin_count(stt->x, n, bk, nc, cells->atom_cell, count, g ? nullptr : slot, starts,
                            ticket, g, s));
-    MD_CK(launch_scatter(cells->atom_cell, slot, cells->cell_start, n, tmp_perm, g, s));
-    MD_CK(launch_cell_sort(tmp_perm, cells->cell_start, (int)ncell, cells->perm, stt->x, stt->v,
-                           stt->id, nullptr, n, sx, sv, sid, nullptr, g, s));
+    if (g) {
+      MD_CK(launch_gather_sort(cells->cell_start, new_start, cells->atom_cell, nc, cells->perm,
+                               stt->x, stt->v, stt->id, n, sx, sv, sid, status, g, s));
+    } else {
+      MD_CK(launch_scatter(cells->atom_cell, slot, starts, n, tmp_perm, g, s));
+      MD_CK(launch_cell_sort(tmp_perm, starts, (int)ncell, cells->perm, stt->x, stt->v, stt->id,
+                             nullptr, n, sx, sv, sid, nullptr, g, s));
+    }
     BuildArgs a{};
     a.x = sx;
     a.n = n;
     a.sorted = 1;
     a.box = bk;
     for (int d = 0; d < 3; ++d) a.nc[d] = nc[d];
-    a.cell_start = cells->cell_start;
+    a.cell_start = starts;
+    a.cell_start_out = g ? cells->cell_start : nullptr;
     a.atom_cell = cells->atom_cell;
     a.perm = cells->perm;
     a.rl2 = rl * rl;
@@ -632,6 +656,7 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
     fa.x = stt->x;
     fa.n = n;
     fa.box = bk;
+    fa.margin = interior_margin(p, rl);
     fa.neigh = nl->neigh;
     fa.numneigh = nl->numneigh;
     fa.cap = nl->capacity;

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(double* __restrict__ x, in
     base = atomicAdd(&count[c], live_end - lane);
   }
   base = __shfl(base, hl < 0 ? 0 : hl, kWave);
-  if (live) slot[i] = base + (lane - hl);
+  if (live && slot) slot[i] = base + (lane - hl);
 
   // last workgroup: scan
   __threadfence();
@@ -104,23 +104,26 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(double* __restrict__ x, in
   if (threadIdx.x == 0) is_last = atomicAdd(ticket, 1) == (int)gridDim.x - 1;
   __syncthreads();
   if (!is_last) return;
+  // The counters were only touched by device-scope atomics, which live in L2;
+  // after this acquire fence plain loads see their final values.
   __threadfence();
   const int ncell = nc0 * nc1 * nc2;
-  volatile int* vcount = count;
-  int carry = 0;
-  for (int t0 = 0; t0 < ncell; t0 += kBlock) {
-    const int cc = t0 + (int)threadIdx.x;
-    const int v = cc < ncell ? vcount[cc] : 0;
-    int tot;
-    const int ex = block_excl_scan(v, sh, &tot);
-    if (cc < ncell) {
-      cell_start[cc] = carry + ex;
-      count[cc] = 0;
-    }
-    carry += tot;
+  const int per = (ncell + kBlock - 1) / kBlock;
+  const int c0 = min(ncell, (int)threadIdx.x * per), c1 = min(ncell, c0 + per);
+  int sum = 0;
+#pragma unroll 8
+  for (int cc = c0; cc < c1; ++cc) sum += count[cc];
+  int tot;
+  int run = block_excl_scan(sum, sh, &tot);
+#pragma unroll 8
+  for (int cc = c0; cc < c1; ++cc) {
+    const int v = count[cc];
+    cell_start[cc] = run;
+    run += v;
+    count[cc] = 0;
   }
   if (threadIdx.x == 0) {
-    cell_start[ncell] = carry;
+    cell_start[ncell] = tot;
     *ticket = 0;
   }
 }
@@ -177,6 +180,110 @@ __global__ __launch_bounds__(kBlock) void k_cell_sort(
   }
 }
 
+// Wrapped coordinates of the (up to 27) distinct cells around `cell`, one per
+// lane 0..26 in z, y, x offset order; *kept is false for lanes >= 27 and for
+// offsets that wrap onto an earlier offset's cell (fewer than 3 cells in a
+// dimension).
+__device__ inline int stencil_lane(int cell, int lane, const int* nc, bool* kept) {
+  *kept = false;
+  if (lane >= 27) return 0;
+  const int o[3] = {lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1};
+  const int home[3] = {cell % nc[0], (cell / nc[0]) % nc[1], cell / (nc[0] * nc[1])};
+  int w[3];
+  bool k = true;
+  for (int d = 0; d < 3; ++d) {
+    int v = home[d] + o[d];
+    v = v < 0 ? v + nc[d] : (v >= nc[d] ? v - nc[d] : v);
+    w[d] = v;
+    for (int e = -1; e < o[d]; ++e) {
+      int u = home[d] + e;
+      u = u < 0 ? u + nc[d] : (u >= nc[d] ? u - nc[d] : u);
+      k = k && u != v;
+    }
+  }
+  *kept = k;
+  return w[0] + nc[0] * (w[1] + nc[1] * w[2]);
+}
+
+// Rebuild-time sort of atoms that are already in the previous build's cell
+// order and have moved less than a cell edge since: one wavefront per new
+// cell collects its members from the old ranges of the surrounding cells,
+// visited in increasing cell index (so in increasing atom index), which is the
+// stable counting-sort order without any atomic arrival slots.  The state is
+// gathered into the sorted staging buffers.  If fewer members are found than
+// were counted (an atom moved further than a cell edge), status bit 2 is set.
+__global__ __launch_bounds__(kBlock) void k_gather_sort(
+    const int* __restrict__ old_start, const int* __restrict__ new_start,
+    const int* __restrict__ atom_cell, int nc0, int nc1, int nc2, int* __restrict__ perm,
+    const double* __restrict__ x, const double* __restrict__ v, const int* __restrict__ id,
+    int n, double* __restrict__ sx, double* __restrict__ sv, int* __restrict__ sid,
+    int* __restrict__ status, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int cell = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int ncell = nc0 * nc1 * nc2;
+  if (cell >= ncell) return;
+  const int nc[3] = {nc0, nc1, nc2};
+  bool kept;
+  const int c2 = stencil_lane(cell, lane, nc, &kept);
+  const int key = kept ? c2 : 0x7fffffff;
+  int b = 0, e = 0;
+  if (kept) {
+    b = old_start[c2];
+    e = old_start[c2 + 1];
+  }
+  int rank = 0;
+  for (int q = 0; q < 27; ++q) rank += __shfl(key, q, kWave) < key ? 1 : 0;
+  const int nkept = __popcll(__ballot(kept));
+  const int base = new_start[cell];
+  const int want = new_start[cell + 1] - base;
+  const unsigned long long below = (1ull << lane) - 1;
+  int found = 0;
+  // Take one member candidate (lane-th atom of a range, first 64 atoms of
+  // ranges r..r+3 at once so their cell loads overlap), then any tail.
+  auto take = [&](int i, bool mine) {
+    const unsigned long long m = __ballot(mine);
+    if (mine) {
+      const int pos = found + __popcll(m & below);
+      if (pos < want) {
+        const int p = base + pos;
+        perm[p] = i;
+        sx[p] = x[i];
+        sx[n + p] = x[n + i];
+        sx[2 * n + p] = x[2 * n + i];
+        sv[p] = v[i];
+        sv[n + p] = v[n + i];
+        sv[2 * n + p] = v[2 * n + i];
+        sid[p] = id[i];
+      }
+    }
+    found += __popcll(m);
+  };
+  constexpr int U = 4;
+  for (int r0 = 0; r0 < nkept; r0 += U) {
+    int rb[U], re[U], ci[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = r0 + u;
+      const unsigned long long sel = __ballot(kept && rank == r);
+      const int src = sel ? __ffsll((long long)sel) - 1 : 0;
+      rb[u] = sel ? __shfl(b, src, kWave) : 0;
+      re[u] = sel ? __shfl(e, src, kWave) : 0;
+      const int i = rb[u] + lane;
+      ci[u] = i < re[u] ? atom_cell[i] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      take(rb[u] + lane, ci[u] == cell);
+      for (int t = rb[u] + kWave; t < re[u]; t += kWave) {
+        const int i = t + lane;
+        take(i, i < re[u] && atom_cell[i] == cell);
+      }
+    }
+  }
+  if (lane == 0 && found != want) atomicOr(&status[MD_ST_ERRORS], 4);
+}
+
 __global__ __launch_bounds__(kBlock) void k_copy_back(double* __restrict__ x,
                                                        double* __restrict__ v,
                                                        int* __restrict__ id,
@@ -215,20 +322,6 @@ __global__ __launch_bounds__(kBlock) void k_gather_int(const int* __restrict__ p
   if (p < n) dst[p] = src[perm[p]];
 }
 
-// Distinct neighbour cells along one dimension: c-1, c, c+1 (mod nc) in that
-// order, duplicates dropped (nc < 3).
-__device__ inline int stencil1(int c, int nc, int* out) {
-  int k = 0;
-  for (int o = -1; o <= 1; ++o) {
-    int v = c + o;
-    v = v < 0 ? v + nc : (v >= nc ? v - nc : v);
-    bool dup = false;
-    for (int q = 0; q < k; ++q) dup |= out[q] == v;
-    if (!dup) out[k++] = v;
-  }
-  return k;
-}
-
 // Minimum image d - L rint(d / L); the image index is taken from d * (1/L),
 // which selects the same image as d / L except within rounding of |d| = L/2,
 // a separation never inside the list radius because L > 2 rl.
@@ -242,6 +335,53 @@ __device__ inline int wave_max(int v) {
   return v;
 }
 
+// Home atoms of one staged chunk: each wavefront takes home atoms in turn and
+// tests 64 staged candidates at a time; accepted candidates are appended in
+// candidate order through a ballot prefix count.  WRAP applies the minimum
+// image (home cells touching a box face).
+template <bool WRAP>
+__device__ inline void build_home(const BuildArgs& a, const double* cxs, const double* cys,
+                                  const double* czs, const int* cjs, int c0, int clen, int hb,
+                                  int he, int lane, int wave, unsigned long long below) {
+  const int n = a.n;
+  const double* __restrict__ x = a.x;
+  const bool sorted = a.sorted != 0;
+  // layout K = 2^lk lanes per atom: index arithmetic by shifts and masks
+  const int lk = __ffs(a.layout) - 1;
+  const int gs = 6 - lk;
+  const size_t rows = nl_rows(a.cap, a.layout);
+  for (int h = hb + wave; h < he; h += kBlock / kWave) {
+    const int i = sorted ? h : a.perm[h];
+    const double xi = x[i], yi = x[n + i], zi = x[2 * n + i];
+    int* __restrict__ row0 =
+        a.neigh + (size_t)(i >> gs) * rows * kWave + ((i & ((1 << gs) - 1)) << lk);
+    int cnt = c0 == 0 ? 0 : a.numneigh[i];
+    for (int t = 0; t < clen; t += kWave) {
+      const int q = t + lane;
+      bool take = false;
+      int j = 0;
+      if (q < clen) {
+        j = cjs[q];
+        double dx = xi - cxs[q], dy = yi - cys[q], dz = zi - czs[q];
+        if (WRAP) {
+          dx = min_image(dx, a.box.L[0], a.box.inv[0]);
+          dy = min_image(dy, a.box.L[1], a.box.inv[1]);
+          dz = min_image(dz, a.box.L[2], a.box.inv[2]);
+        }
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        take = (j != i) && (r2 < a.rl2);
+      }
+      const unsigned long long m = __ballot(take);
+      if (take) {
+        const int pos = cnt + __popcll(m & below);
+        if (pos < a.cap) row0[(size_t)(pos >> lk) * kWave + (pos & ((1 << lk) - 1))] = j;
+      }
+      cnt += __popcll(m);
+    }
+    if (lane == 0) a.numneigh[i] = cnt;
+  }
+}
+
 // One workgroup per cell.  The candidates -- atoms of the (up to) 27
 // surrounding cells, in cell order and slot order inside a cell -- are staged
 // in LDS in chunks; each wavefront takes home atoms in turn and tests 64
@@ -252,7 +392,7 @@ __global__ __launch_bounds__(kBlock) void k_build(BuildArgs a) {
   if (a.gate && *a.gate == 0) return;
   __shared__ double cxs[kBuildChunk], cys[kBuildChunk], czs[kBuildChunk];
   __shared__ int cjs[kBuildChunk];
-  __shared__ int st_start[27], st_cnt[27], st_n;
+  __shared__ int st_start[27], st_cnt[27], st_off[28], st_n;
   __shared__ int red[kBlock / kWave];
   const int cell = blockIdx.x;
   const int tid = threadIdx.x;
@@ -261,34 +401,56 @@ __global__ __launch_bounds__(kBlock) void k_build(BuildArgs a) {
   const double* __restrict__ x = a.x;
   const bool sorted = a.sorted != 0;
   if (cell == 0 && tid == 0) atomicAdd(&a.status[MD_ST_BUILDS], 1);
-  if (tid == 0) {
-    const int cx = cell % a.nc[0], cy = (cell / a.nc[0]) % a.nc[1];
-    const int cz = cell / (a.nc[0] * a.nc[1]);
-    int ox[3], oy[3], oz[3];
-    const int kx = stencil1(cx, a.nc[0], ox), ky = stencil1(cy, a.nc[1], oy),
-              kz = stencil1(cz, a.nc[2], oz);
-    int q = 0;
-    for (int p = 0; p < kz; ++p)
-      for (int r = 0; r < ky; ++r)
-        for (int s = 0; s < kx; ++s) {
-          const int c2 = ox[s] + a.nc[0] * (oy[r] + a.nc[1] * oz[p]);
-          st_start[q] = a.cell_start[c2];
-          st_cnt[q] = a.cell_start[c2 + 1] - st_start[q];
-          ++q;
-        }
-    st_n = q;
+  if (wave == 0) {
+    // Stencil entry (oz, oy, ox) = lane, all 27 looked up at once; the kept
+    // entries keep the z, y, x offset order of the FP64 definition.
+    bool kept;
+    const int c2 = stencil_lane(cell, lane, a.nc, &kept);
+    const unsigned long long km = __ballot(kept);
+    if (kept) {
+      const int pos = __popcll(km & ((1ull << lane) - 1));
+      const int b = a.cell_start[c2];
+      st_start[pos] = b;
+      st_cnt[pos] = a.cell_start[c2 + 1] - b;
+    }
+    if (lane == 0) st_n = __popcll(km);
   }
   __syncthreads();
-  int total = 0;
-  for (int q = 0; q < st_n; ++q) total += st_cnt[q];
+  if (tid == 0) {
+    int acc = 0;
+    for (int q = 0; q < st_n; ++q) {
+      st_off[q] = acc;
+      acc += st_cnt[q];
+    }
+    st_off[st_n] = acc;
+  }
+  __syncthreads();
+  const int total = st_off[st_n];
   const int hb = a.cell_start[cell], he = a.cell_start[cell + 1];
+  // A home cell at least one cell away from every box face (with >= 3 cells
+  // per dimension) has an unwrapped stencil: candidate and home positions are
+  // wrapped into [0, L) and at most two cell edges apart, so an accepted pair
+  // has rint(d / L) = 0 and d = x_i - x_j is the FP64 minimum image bit for bit,
+  // while any other image is at least L / 3 >= r_l away.
+  bool wrap = false;
+  {
+    const int home[3] = {cell % a.nc[0], (cell / a.nc[0]) % a.nc[1],
+                         cell / (a.nc[0] * a.nc[1])};
+    for (int d = 0; d < 3; ++d)
+      wrap = wrap || a.nc[d] < 3 || home[d] == 0 || home[d] == a.nc[d] - 1;
+  }
+  if (a.cell_start_out && tid == 0) {
+    a.cell_start_out[cell] = hb;
+    if (cell == (int)gridDim.x - 1) a.cell_start_out[cell + 1] = he;
+  }
   const unsigned long long below = (1ull << lane) - 1;
   for (int c0 = 0; c0 < total; c0 += kBuildChunk) {
     const int clen = min(kBuildChunk, total - c0);
     for (int q = tid; q < clen; q += kBlock) {
-      int idx = c0 + q, sc = 0;
-      while (idx >= st_cnt[sc]) idx -= st_cnt[sc++];
-      const int sl = st_start[sc] + idx;
+      const int idx = c0 + q;
+      int sc = 0;
+      while (idx >= st_off[sc + 1]) ++sc;
+      const int sl = st_start[sc] + (idx - st_off[sc]);
       const int j = sorted ? sl : a.perm[sl];
       cjs[q] = j;
       cxs[q] = x[j];
@@ -296,31 +458,10 @@ __global__ __launch_bounds__(kBlock) void k_build(BuildArgs a) {
       czs[q] = x[2 * n + j];
     }
     __syncthreads();
-    for (int h = hb + wave; h < he; h += kBlock / kWave) {
-      const int i = sorted ? h : a.perm[h];
-      const double xi = x[i], yi = x[n + i], zi = x[2 * n + i];
-      int cnt = c0 == 0 ? 0 : a.numneigh[i];
-      for (int t = 0; t < clen; t += kWave) {
-        const int q = t + lane;
-        bool take = false;
-        int j = 0;
-        if (q < clen) {
-          j = cjs[q];
-          const double dx = min_image(xi - cxs[q], a.box.L[0], a.box.inv[0]);
-          const double dy = min_image(yi - cys[q], a.box.L[1], a.box.inv[1]);
-          const double dz = min_image(zi - czs[q], a.box.L[2], a.box.inv[2]);
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          take = (j != i) && (r2 < a.rl2);
-        }
-        const unsigned long long m = __ballot(take);
-        if (take) {
-          const int pos = cnt + __popcll(m & below);
-          if (pos < a.cap) a.neigh[nl_index(i, pos, a.cap, a.layout)] = j;
-        }
-        cnt += __popcll(m);
-      }
-      if (lane == 0) a.numneigh[i] = cnt;
-    }
+    if (wrap)
+      build_home<true>(a, cxs, cys, czs, cjs, c0, clen, hb, he, lane, wave, below);
+    else
+      build_home<false>(a, cxs, cys, czs, cjs, c0, clen, hb, he, lane, wave, below);
     __syncthreads();
   }
   // per-atom bookkeeping of the home atoms (after every wave has written numneigh)
@@ -385,6 +526,17 @@ hipError_t launch_cell_sort(const int* tmp_perm, const int* cell_start, int ncel
                             const int* gate, hipStream_t s) {
   k_cell_sort<<<blocks_for((int64_t)ncell * kWave), kBlock, 0, s>>>(
       tmp_perm, cell_start, ncell, perm, x, v, id, f, n, sx, sv, sid, sf, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_sort(const int* old_start, const int* new_start, const int* atom_cell,
+                              const int nc[3], int* perm, const double* x, const double* v,
+                              const int* id, int n, double* sx, double* sv, int* sid,
+                              int* status, const int* gate, hipStream_t s) {
+  const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+  k_gather_sort<<<blocks_for(ncell * kWave), kBlock, 0, s>>>(old_start, new_start, atom_cell,
+                                                             nc[0], nc[1], nc[2], perm, x, v, id,
+                                                             n, sx, sv, sid, status, gate);
   return hipGetLastError();
 }
 

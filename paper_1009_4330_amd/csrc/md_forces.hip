@@ -25,6 +25,7 @@ struct FK {
   const double* __restrict__ x;
   int n;
   BoxK box;
+  double margin;          // interior test: every coordinate in [margin, L - margin)
   const int* __restrict__ neigh;
   const int* __restrict__ numneigh;
   int cap;
@@ -33,6 +34,29 @@ struct FK {
   double* __restrict__ vatom;
   int* clear;
 };
+
+// Raw buffer view of an array of doubles: 32-bit byte offsets, one offset
+// register shared by the x, y and z rows (scalar row offsets), and hardware
+// range checking (reads past num_records return 0).
+constexpr int kBufWord3 = 0x00020000;   // gfx9-family raw buffer, 32-bit data format
+__device__ inline __amdgpu_buffer_rsrc_t buffer_of(const double* p, int count) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), (short)0,
+                                           count * (int)sizeof(double), kBufWord3);
+}
+__device__ inline double load_f64(__amdgpu_buffer_rsrc_t r, int byte_off, int row_off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, row_off, 0));
+}
+
+// An atom is "interior" when every coordinate lies in [margin, L - margin),
+// margin = r_l + skin.  Its list partners then sit within r_l + skin of it in
+// the same periodic image (positions are wrapped at each build and move at most
+// skin/2 before the next), so d = x_i - x_j already is the minimum image:
+// rint(d / L) = 0 and d - L * 0 == d bit for bit.
+__device__ inline bool interior(double xi, double yi, double zi, const FK& a) {
+  const double m = a.margin;
+  return xi >= m && xi < a.box.L[0] - m && yi >= m && yi < a.box.L[1] - m && zi >= m &&
+         zi < a.box.L[2] - m;
+}
 
 __device__ inline double min_image(double d, double L, double inv) {
   return d - L * rint(d * inv);
@@ -65,6 +89,7 @@ struct Lane {
   bool live;      // i < n
   const int* nb;  // entry t of this lane at nb[t * 64]
   int count;      // entries owned by this lane
+  int rows;       // rows of 64 entries per atom group (ceil(cap / K))
   __device__ inline Lane(const FK& a) {
     const int g = blockIdx.x * kBlock + threadIdx.x;
     const int lane = g & (kWave - 1);
@@ -73,42 +98,80 @@ struct Lane {
     live = i < a.n;
     const int nn = live ? min(a.numneigh[i], a.cap) : 0;
     count = nn > s ? (nn - s + K - 1) / K : 0;
-    nb = a.neigh + (size_t)(g / kWave) * nl_rows(a.cap, K) * kWave + lane;
+    rows = (int)nl_rows(a.cap, K);
+    nb = a.neigh + (size_t)(g / kWave) * rows * kWave + lane;
   }
 };
 
-// Separations of up to kUnroll entries starting at entry t: all index loads are
-// issued first, then all position gathers, then the arithmetic.  Invalid slots
-// point at atom i itself and are masked by ok[].
+// Separations of up to kUnroll entries starting at entry t: the index loads
+// are issued first (rows past the lane's count are clamped into its own rows,
+// read and masked by ok[], so no branch splits the loads), then the position
+// gathers through the buffer view, then the arithmetic.  WRAP applies the
+// minimum image; interior wavefronts skip it (see interior()).
 struct Batch {
   int j[kUnroll];
   bool ok[kUnroll];
   double dx[kUnroll], dy[kUnroll], dz[kUnroll], s[kUnroll];
 };
 
-template <int K>
-__device__ inline void load_batch(const FK& a, const Lane<K>& ln, int t, int iself, double xi,
-                                  double yi, double zi, Batch& b) {
+struct XView {
+  __amdgpu_buffer_rsrc_t r;   // the [3][n] position array
+  int row;                    // n * 8 bytes: offset of the y row (z at 2 * row)
+};
+
+template <int K, bool WRAP>
+__device__ inline void load_batch(const FK& a, const XView& xv, const Lane<K>& ln, int t,
+                                  double xi, double yi, double zi, Batch& b) {
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) {
     b.ok[u] = t + u < ln.count;
-    b.j[u] = b.ok[u] ? ln.nb[(size_t)(t + u) * kWave] : iself;
+    b.j[u] = ln.nb[(size_t)min(t + u, ln.rows - 1) * kWave];
   }
   double xj[kUnroll], yj[kUnroll], zj[kUnroll];
-  const int n = a.n;
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) {
-    xj[u] = a.x[b.j[u]];
-    yj[u] = a.x[n + b.j[u]];
-    zj[u] = a.x[2 * n + b.j[u]];
+    const int off = b.j[u] * (int)sizeof(double);
+    xj[u] = load_f64(xv.r, off, 0);
+    yj[u] = load_f64(xv.r, off, xv.row);
+    zj[u] = load_f64(xv.r, off, 2 * xv.row);
   }
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) {
-    b.dx[u] = min_image(xi - xj[u], a.box.L[0], a.box.inv[0]);
-    b.dy[u] = min_image(yi - yj[u], a.box.L[1], a.box.inv[1]);
-    b.dz[u] = min_image(zi - zj[u], a.box.L[2], a.box.inv[2]);
+    b.dx[u] = xi - xj[u];
+    b.dy[u] = yi - yj[u];
+    b.dz[u] = zi - zj[u];
+    if (WRAP) {
+      b.dx[u] = min_image(b.dx[u], a.box.L[0], a.box.inv[0]);
+      b.dy[u] = min_image(b.dy[u], a.box.L[1], a.box.inv[1]);
+      b.dz[u] = min_image(b.dz[u], a.box.L[2], a.box.inv[2]);
+    }
     // (dx dx + dy dy) + dz dz, evaluated as written
     b.s[u] = b.dx[u] * b.dx[u] + b.dy[u] * b.dy[u] + b.dz[u] * b.dz[u];
+  }
+}
+
+__device__ inline XView xview(const FK& a) {
+  return XView{buffer_of(a.x, 3 * a.n), a.n * (int)sizeof(double)};
+}
+
+// Runs body(batch) over this lane's list entries.  The choice between the
+// plain and the minimum-image separation is uniform over the wavefront.
+template <int K, typename F>
+__device__ inline void for_each_batch(const FK& a, const Lane<K>& ln, double xi, double yi,
+                                      double zi, F&& body) {
+  const XView xv = xview(a);
+  if (__all(interior(xi, yi, zi, a))) {
+    for (int t = 0; t < ln.count; t += kUnroll) {
+      Batch b;
+      load_batch<K, false>(a, xv, ln, t, xi, yi, zi, b);
+      body(b);
+    }
+  } else {
+    for (int t = 0; t < ln.count; t += kUnroll) {
+      Batch b;
+      load_batch<K, true>(a, xv, ln, t, xi, yi, zi, b);
+      body(b);
+    }
   }
 }
 
@@ -191,9 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_lj(FK a, LJK p) {
   const int io = ln.live ? ln.i : n - 1;
   const double xi = a.x[io], yi = a.x[n + io], zi = a.x[2 * n + io];
   Acc acc;
-  for (int t = 0; t < ln.count; t += kUnroll) {
-    Batch b;
-    load_batch<K>(a, ln, t, io, xi, yi, zi, b);
+  for_each_batch<K>(a, ln, xi, yi, zi, [&](const Batch& b) {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       if (b.ok[u] && b.s[u] < p.rc2) {
@@ -206,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_lj(FK a, LJK p) {
         }
       }
     }
-  }
+  });
   if (K > 1) acc.reduce<K>(EV);
   if (ln.live && ln.s == 0) acc.store(a, ln.i, EV, 0.0);
 }
@@ -231,9 +292,7 @@ __global__ __launch_bounds__(kBlock) void k_sc_density(FK a, SCK p, double* __re
   const int io = ln.live ? ln.i : n - 1;
   const double xi = a.x[io], yi = a.x[n + io], zi = a.x[2 * n + io];
   double rho = 0.0;
-  for (int t = 0; t < ln.count; t += kUnroll) {
-    Batch b;
-    load_batch<K>(a, ln, t, io, xi, yi, zi, b);
+  for_each_batch<K>(a, ln, xi, yi, zi, [&](const Batch& b) {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       if (b.ok[u] && b.s[u] < p.rc2) {
@@ -243,7 +302,7 @@ __global__ __launch_bounds__(kBlock) void k_sc_density(FK a, SCK p, double* __re
           rho += (double)half_power(p.a2f * __builtin_amdgcn_rcpf((float)b.s[u]), p.m);
       }
     }
-  }
+  });
   if (K > 1) rho = group_sum<K>(rho);
   if (!ln.live || ln.s != 0) return;
   e_out[ln.i] = rho > 0.0 ? 1.0 / sqrt(rho) : 0.0;
@@ -261,9 +320,7 @@ __global__ __launch_bounds__(kBlock) void k_sc_force(FK a, SCK p,
   const double xi = a.x[io], yi = a.x[n + io], zi = a.x[2 * n + io];
   const double ei = e_in[io];
   Acc acc;
-  for (int t = 0; t < ln.count; t += kUnroll) {
-    Batch b;
-    load_batch<K>(a, ln, t, io, xi, yi, zi, b);
+  for_each_batch<K>(a, ln, xi, yi, zi, [&](const Batch& b) {
     double ej[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) ej[u] = e_in[b.j[u]];
@@ -293,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_sc_force(FK a, SCK p,
         }
       }
     }
-  }
+  });
   if (K > 1) acc.reduce<K>(EV);
   if (!ln.live || ln.s != 0) return;
   // energy: eps/2 sum_j t^(n/2) is the pair repulsion share, plus the embedding
@@ -318,9 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_lj_vjp(FK a, LJK p, const double* __
   const double xi = a.x[io], yi = a.x[n + io], zi = a.x[2 * n + io];
   const double uxi = u[io], uyi = u[n + io], uzi = u[2 * n + io];
   double gxa = 0, gya = 0, gza = 0, fx = 0, fy = 0, fz = 0, dsig = 0;
-  for (int t = 0; t < ln.count; t += kUnroll) {
-    Batch b;
-    load_batch<K>(a, ln, t, io, xi, yi, zi, b);
+  for_each_batch<K>(a, ln, xi, yi, zi, [&](const Batch& b) {
     double ux[kUnroll], uy[kUnroll], uz[kUnroll];
 #pragma unroll
     for (int q = 0; q < kUnroll; ++q) {
@@ -359,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_lj_vjp(FK a, LJK p, const double* __
       fz = fma(g, b.dz[q], fz);
       dsig += dg * (uxi * b.dx[q] + uyi * b.dy[q] + uzi * b.dz[q]);
     }
-  }
+  });
   if (K > 1) {
     gxa = group_sum<K>(gxa);
     gya = group_sum<K>(gya);
@@ -385,6 +440,7 @@ FK make_fk(const ForceArgs& a) {
   k.x = a.x;
   k.n = a.n;
   k.box = a.box;
+  k.margin = a.margin;
   k.neigh = a.neigh;
   k.numneigh = a.numneigh;
   k.cap = a.cap;

@@ -76,6 +76,7 @@ struct WsLayout {
   size_t partials;   // double [kReduceBlocks][kReduceCols]
   size_t scalars;    // double [16]       reduced values
   size_t ticket;     // int [64]          finished-workgroup counter of the binning pass
+  size_t new_start;  // int [ncell + 1]   cell starts of a rebuild in progress
   size_t total;
 };
 
@@ -99,6 +100,13 @@ hipError_t launch_cell_sort(const int* tmp_perm, const int* cell_start, int ncel
                             const double* x, const double* v, const int* id, const double* f,
                             int n, double* sx, double* sv, int* sid, double* sf,
                             const int* gate, hipStream_t s);
+// Rebuild-time sort for atoms already in the previous build's cell order that
+// moved less than a cell edge: gathers the state into staging in the stable
+// order and sets status bit 2 if some atom moved further.
+hipError_t launch_gather_sort(const int* old_start, const int* new_start, const int* atom_cell,
+                              const int nc[3], int* perm, const double* x, const double* v,
+                              const int* id, int n, double* sx, double* sv, int* sid,
+                              int* status, const int* gate, hipStream_t s);
 hipError_t launch_copy_back(double* x, double* v, int* id, double* f, double* xr,
                             const double* sx, const double* sv, const int* sid,
                             const double* sf, int n, hipStream_t s);
@@ -119,6 +127,7 @@ struct BuildArgs {
   BoxK box;
   int nc[3];
   const int* cell_start;
+  int* cell_start_out;   // nullable: receives a copy of cell_start
   const int* atom_cell;  // cell of each atom, input order
   const int* perm;
   double rl2;
@@ -143,6 +152,7 @@ struct ForceArgs {
   const double* x;
   int n;
   BoxK box;
+  double margin;         // interior margin r_l + skin = 2 r_l - r_c (+inf: always wrap)
   const int* neigh;
   const int* numneigh;
   int cap;

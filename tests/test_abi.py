@@ -46,8 +46,8 @@ def test_library_exports_every_declared_symbol(mdlib):
 
 
 def test_status_strings(mdlib):
-    for code in range(8):
-        assert mdlib.status_string(code)
+    for code in range(9):
+        assert mdlib.status_string(code) != "unknown status"
     assert mdlib.status_string(3) == "neighbour list capacity exceeded"
 
 

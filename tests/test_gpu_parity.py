@@ -226,8 +226,11 @@ def test_autoselect_choice_matches_layout(orc):
     nl = md.NList(x_np.shape[1], 160)
     pot = md.lj_potential(2.5)
     choice = md.md_autoselect(pot, x, mbox, cells, 0.3, nl, md.MD_FP64, 3, ws)
-    assert choice in (md.MD_KERNEL_TPA, md.MD_KERNEL_WPA)
-    assert nl.layout == (md.MD_LAYOUT_WPA if choice == md.MD_KERNEL_WPA else md.MD_LAYOUT_TPA)
+    print(f"auto-selected {choice} lanes per atom")
+    assert choice in md.LANES
+    assert nl.layout == choice
+    words = md.md_nlist_status(nl)
+    assert words[md.MD_ST_BUILDS] == 0     # trial builds are not counted
     f, ev = forces_gpu(pot, x, mbox, nl, md.MD_FP64, md.MD_KERNEL_AUTO, ws)
     ref, _ = oracle_lj(orc, x_np, box)
     assert rel(f, ref.f) < 1e-12
