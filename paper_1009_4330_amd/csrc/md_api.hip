@@ -319,7 +319,7 @@ WsLayout ws_layout(int64_t n, int64_t ncell) {
   L.sc_e = take(sizeof(double) * nn);
   L.partials = take(sizeof(double) * kReduceBlocks * kReduceCols);
   L.scalars = take(sizeof(double) * 16);
-  L.ticket = take(sizeof(int) * 64);
+  L.scount = take(sizeof(int) * (size_t)(((ncell > 0 ? ncell : 1) >> kSuperShift) + 1));
   L.new_start = take(sizeof(int) * (size_t)((ncell > 0 ? ncell : 1) + 1));
   L.total = o;
   return L;
@@ -383,9 +383,11 @@ md_status md_bin_cells(double* x, int64_t n, const md_box* box, double rl, md_ce
   const int ni = (int)n;
   int* count = at<int>(ws, L.count);
   MD_CK(launch_fill_int(count, ncell, 0, s));
-  MD_CK(launch_fill_int(at<int>(ws, L.ticket), 1, 0, s));
-  MD_CK(launch_bin_count(x, ni, make_box(box), nc, cells->atom_cell, count, at<int>(ws, L.slot),
-                         cells->cell_start, at<int>(ws, L.ticket), nullptr, s));
+  int* scount = at<int>(ws, L.scount);
+  MD_CK(launch_fill_int(scount, (ncell >> kSuperShift) + 1, 0, s));
+  MD_CK(launch_bin_count(x, ni, make_box(box), nc, cells->atom_cell, count, scount,
+                         at<int>(ws, L.slot), nullptr, s));
+  MD_CK(launch_scan_cells(count, (int)ncell, cells->cell_start, s));
   MD_CK(launch_scatter(cells->atom_cell, at<int>(ws, L.slot), cells->cell_start, ni,
                        at<int>(ws, L.tmp_perm), nullptr, s));
   MD_CK(launch_cell_sort(at<int>(ws, L.tmp_perm), cells->cell_start, (int)ncell, cells->perm,
@@ -601,7 +603,7 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
   double* keatom = at<double>(ws, L.keatom);
   double* sums = at<double>(ws, L.scalars);
 
-  int* ticket = at<int>(ws, L.ticket);
+  int* scount = at<int>(ws, L.scount);
 
   int* new_start = at<int>(ws, L.new_start);
 
@@ -614,12 +616,14 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
   // return at once unless the rebuild flag is set.
   auto rebuild = [&](const int* g, int layout) -> md_status {
     int* starts = g ? new_start : cells->cell_start;
-    MD_CK(launch_bin_count(stt->x, n, bk, nc, cells->atom_cell, count, g ? nullptr : slot, starts,
-                           ticket, g, s));
+    MD_CK(launch_bin_count(stt->x, n, bk, nc, cells->atom_cell, count, scount,
+                           g ? nullptr : slot, g, s));
     if (g) {
-      MD_CK(launch_gather_sort(cells->cell_start, new_start, cells->atom_cell, nc, cells->perm,
-                               stt->x, stt->v, stt->id, n, sx, sv, sid, status, g, s));
+      MD_CK(launch_gather_sort(cells->cell_start, new_start, count, scount, cells->atom_cell, nc,
+                               cells->perm, stt->x, stt->v, stt->id, n, sx, sv, sid, status, g,
+                               s));
     } else {
+      MD_CK(launch_scan_cells(count, (int)ncell, starts, s));
       MD_CK(launch_scatter(cells->atom_cell, slot, starts, n, tmp_perm, g, s));
       MD_CK(launch_cell_sort(tmp_perm, starts, (int)ncell, cells->perm, stt->x, stt->v, stt->id,
                              nullptr, n, sx, sv, sid, nullptr, g, s));
@@ -632,6 +636,8 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
     for (int d = 0; d < 3; ++d) a.nc[d] = nc[d];
     a.cell_start = starts;
     a.cell_start_out = g ? cells->cell_start : nullptr;
+    a.count_clear = count;
+    a.scount_clear = scount;
     a.atom_cell = cells->atom_cell;
     a.perm = cells->perm;
     a.rl2 = rl * rl;
@@ -701,7 +707,7 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
   // The binning counters must start at zero; every binning pass leaves them
   // zero again, but the workspace may be fresh, so clear them once per call.
   MD_CK(launch_fill_int(count, ncell, 0, s));
-  MD_CK(launch_fill_int(ticket, 1, 0, s));
+  MD_CK(launch_fill_int(scount, (ncell >> kSuperShift) + 1, 0, s));
   if (setup) {
     kernel = k == MD_KERNEL_AUTO ? MD_KERNEL_TPA : (int)k;
     if ((st = rebuild(nullptr, kernel)) != MD_OK) return st;

@@ -51,22 +51,19 @@ __device__ inline int block_excl_scan(int v, int* sh, int* total) {
   return x - v + before;
 }
 
-// Wrap x in place, bin, and count atoms per cell.  Runs of equal cells inside
-// a wavefront (the common case once atoms are cell-sorted) take one atomic per
-// run; each atom's arrival slot in its cell is written to slot[].  The last
-// workgroup to finish turns the counts into cell_start (exclusive scan) and
-// clears the counters and the ticket for the next use.
+// Wrap x in place, bin, and count atoms per cell and per super-cell (64
+// consecutive cells).  Runs of equal cells inside a wavefront (the common case
+// once atoms are cell-sorted) take one atomic per run; with slot != null each
+// atom's arrival slot in its cell is written too.  No fence: the counts are
+// read by later kernels.
 __global__ __launch_bounds__(kBlock) void k_bin_count(double* __restrict__ x, int n, BoxK box,
                                                        int nc0, int nc1, int nc2,
                                                        int* __restrict__ atom_cell,
                                                        int* __restrict__ count,
+                                                       int* __restrict__ scount,
                                                        int* __restrict__ slot,
-                                                       int* __restrict__ cell_start,
-                                                       int* __restrict__ ticket,
                                                        const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
-  __shared__ int sh[kBlock / kWave];
-  __shared__ int is_last;
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
   const bool live = i < n;
@@ -92,22 +89,19 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(double* __restrict__ x, in
   const int next = after ? __ffsll((long long)after) - 1 : kWave;  // next run's head
   int base = 0;
   if (head) {
-    const int live_end = min(next, n - (i - lane));              // lanes of this run that are live
-    base = atomicAdd(&count[c], live_end - lane);
+    const int len = min(next, n - (i - lane)) - lane;            // live lanes of this run
+    base = atomicAdd(&count[c], len);
+    atomicAdd(&scount[c >> kSuperShift], len);
   }
   base = __shfl(base, hl < 0 ? 0 : hl, kWave);
   if (live && slot) slot[i] = base + (lane - hl);
+}
 
-  // last workgroup: scan
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) is_last = atomicAdd(ticket, 1) == (int)gridDim.x - 1;
-  __syncthreads();
-  if (!is_last) return;
-  // The counters were only touched by device-scope atomics, which live in L2;
-  // after this acquire fence plain loads see their final values.
-  __threadfence();
-  const int ncell = nc0 * nc1 * nc2;
+// One workgroup: exclusive scan of the per-cell counts into cell_start[0..ncell]
+// (each thread a contiguous chunk, loads unrolled).
+__global__ __launch_bounds__(kBlock) void k_scan_cells(const int* __restrict__ count, int ncell,
+                                                        int* __restrict__ cell_start) {
+  __shared__ int sh[kBlock / kWave];
   const int per = (ncell + kBlock - 1) / kBlock;
   const int c0 = min(ncell, (int)threadIdx.x * per), c1 = min(ncell, c0 + per);
   int sum = 0;
@@ -117,15 +111,10 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(double* __restrict__ x, in
   int run = block_excl_scan(sum, sh, &tot);
 #pragma unroll 8
   for (int cc = c0; cc < c1; ++cc) {
-    const int v = count[cc];
     cell_start[cc] = run;
-    run += v;
-    count[cc] = 0;
+    run += count[cc];
   }
-  if (threadIdx.x == 0) {
-    cell_start[ncell] = tot;
-    *ticket = 0;
-  }
+  if (threadIdx.x == 0) cell_start[ncell] = tot;
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(const int* __restrict__ atom_cell,
@@ -212,15 +201,19 @@ __device__ inline int stencil_lane(int cell, int lane, const int* nc, bool* kept
 // stable counting-sort order without any atomic arrival slots.  The state is
 // gathered into the sorted staging buffers.  If fewer members are found than
 // were counted (an atom moved further than a cell edge), status bit 2 is set.
+// The cell's first slot is the count of all earlier cells, summed from the
+// per-super-cell counts before its super-cell plus the counts of the earlier
+// cells of its own super-cell; it is written to new_start.
 __global__ __launch_bounds__(kBlock) void k_gather_sort(
-    const int* __restrict__ old_start, const int* __restrict__ new_start,
+    const int* __restrict__ old_start, int* __restrict__ new_start,
+    const int* __restrict__ count, const int* __restrict__ scount,
     const int* __restrict__ atom_cell, int nc0, int nc1, int nc2, int* __restrict__ perm,
     const double* __restrict__ x, const double* __restrict__ v, const int* __restrict__ id,
     int n, double* __restrict__ sx, double* __restrict__ sv, int* __restrict__ sid,
     int* __restrict__ status, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
   const int lane = threadIdx.x & (kWave - 1);
-  const int cell = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int cell = (xcd_block() * kBlock + threadIdx.x) / kWave;
   const int ncell = nc0 * nc1 * nc2;
   if (cell >= ncell) return;
   const int nc[3] = {nc0, nc1, nc2};
@@ -235,8 +228,18 @@ __global__ __launch_bounds__(kBlock) void k_gather_sort(
   int rank = 0;
   for (int q = 0; q < 27; ++q) rank += __shfl(key, q, kWave) < key ? 1 : 0;
   const int nkept = __popcll(__ballot(kept));
-  const int base = new_start[cell];
-  const int want = new_start[cell + 1] - base;
+  int part = 0;
+  const int sc = cell >> kSuperShift;
+  for (int q = lane; q < sc; q += kWave) part += scount[q];
+  if ((sc << kSuperShift) + lane < cell) part += count[(sc << kSuperShift) + lane];
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, kWave);
+  const int base = part;
+  const int want = count[cell];
+  if (lane == 0) {
+    new_start[cell] = base;
+    if (cell == ncell - 1) new_start[ncell] = base + want;
+  }
   const unsigned long long below = (1ull << lane) - 1;
   int found = 0;
   // Take one member candidate (lane-th atom of a range, first 64 atoms of
@@ -390,11 +393,11 @@ __device__ inline void build_home(const BuildArgs& a, const double* cxs, const d
 // FP64 definition.  Status words get one atomic per workgroup.
 __global__ __launch_bounds__(kBlock) void k_build(BuildArgs a) {
   if (a.gate && *a.gate == 0) return;
+  const int cell = xcd_block();
   __shared__ double cxs[kBuildChunk], cys[kBuildChunk], czs[kBuildChunk];
   __shared__ int cjs[kBuildChunk];
   __shared__ int st_start[27], st_cnt[27], st_off[28], st_n;
   __shared__ int red[kBlock / kWave];
-  const int cell = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1), wave = tid / kWave;
   const int n = a.n;
@@ -439,9 +442,15 @@ __global__ __launch_bounds__(kBlock) void k_build(BuildArgs a) {
     for (int d = 0; d < 3; ++d)
       wrap = wrap || a.nc[d] < 3 || home[d] == 0 || home[d] == a.nc[d] - 1;
   }
-  if (a.cell_start_out && tid == 0) {
-    a.cell_start_out[cell] = hb;
-    if (cell == (int)gridDim.x - 1) a.cell_start_out[cell + 1] = he;
+  if (tid == 0) {
+    if (a.cell_start_out) {
+      a.cell_start_out[cell] = hb;
+      if (cell == (int)gridDim.x - 1) a.cell_start_out[cell + 1] = he;
+    }
+    // the binning counters have been consumed: clear them for the next rebuild
+    if (a.count_clear) a.count_clear[cell] = 0;
+    if (a.scount_clear && (cell & ((1 << kSuperShift) - 1)) == 0)
+      a.scount_clear[cell >> kSuperShift] = 0;
   }
   const unsigned long long below = (1ull << lane) - 1;
   for (int c0 = 0; c0 < total; c0 += kBuildChunk) {
@@ -491,7 +500,11 @@ __global__ __launch_bounds__(kBlock) void k_build(BuildArgs a) {
   if (tid == 0) {
     int m = red[0];
     for (int w = 1; w < kBlock / kWave; ++w) m = max(m, red[w]);
-    if (m > 0) atomicMax(&a.status[MD_ST_MAXNEIGH], m);
+    // one device-scope atomic per workgroup at most: skipped when the word
+    // already holds at least m (a stale read only costs an extra atomic)
+    if (m > 0 && m > __hip_atomic_load(&a.status[MD_ST_MAXNEIGH], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(&a.status[MD_ST_MAXNEIGH], m);
     if (m > a.cap) atomicOr(&a.status[MD_ST_ERRORS], 1);
   }
 }
@@ -507,10 +520,9 @@ hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t s) {
 }
 
 hipError_t launch_bin_count(double* x, int n, BoxK box, const int nc[3], int* atom_cell,
-                            int* count, int* slot, int* cell_start, int* ticket,
-                            const int* gate, hipStream_t s) {
+                            int* count, int* scount, int* slot, const int* gate, hipStream_t s) {
   k_bin_count<<<blocks_for(n), kBlock, 0, s>>>(x, n, box, nc[0], nc[1], nc[2], atom_cell, count,
-                                                slot, cell_start, ticket, gate);
+                                                scount, slot, gate);
   return hipGetLastError();
 }
 
@@ -529,14 +541,20 @@ hipError_t launch_cell_sort(const int* tmp_perm, const int* cell_start, int ncel
   return hipGetLastError();
 }
 
-hipError_t launch_gather_sort(const int* old_start, const int* new_start, const int* atom_cell,
-                              const int nc[3], int* perm, const double* x, const double* v,
-                              const int* id, int n, double* sx, double* sv, int* sid,
-                              int* status, const int* gate, hipStream_t s) {
+hipError_t launch_gather_sort(const int* old_start, int* new_start, const int* count,
+                              const int* scount, const int* atom_cell, const int nc[3],
+                              int* perm, const double* x, const double* v, const int* id, int n,
+                              double* sx, double* sv, int* sid, int* status, const int* gate,
+                              hipStream_t s) {
   const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
-  k_gather_sort<<<blocks_for(ncell * kWave), kBlock, 0, s>>>(old_start, new_start, atom_cell,
-                                                             nc[0], nc[1], nc[2], perm, x, v, id,
-                                                             n, sx, sv, sid, status, gate);
+  k_gather_sort<<<blocks_for(ncell * kWave), kBlock, 0, s>>>(
+      old_start, new_start, count, scount, atom_cell, nc[0], nc[1], nc[2], perm, x, v, id, n, sx,
+      sv, sid, status, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_cells(const int* count, int ncell, int* cell_start, hipStream_t s) {
+  k_scan_cells<<<1, kBlock, 0, s>>>(count, ncell, cell_start);
   return hipGetLastError();
 }
 

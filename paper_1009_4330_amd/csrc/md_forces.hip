@@ -91,7 +91,7 @@ struct Lane {
   int count;      // entries owned by this lane
   int rows;       // rows of 64 entries per atom group (ceil(cap / K))
   __device__ inline Lane(const FK& a) {
-    const int g = blockIdx.x * kBlock + threadIdx.x;
+    const int g = xcd_block() * kBlock + threadIdx.x;   // contiguous atoms per XCD
     const int lane = g & (kWave - 1);
     i = (g / kWave) * (kWave / K) + lane / K;
     s = lane % K;

@@ -33,6 +33,19 @@ __host__ __device__ inline size_t nl_index(int i, int m, int cap, int k) {
 }
 inline bool lanes_ok(int k) { return k >= 1 && k <= 64 && (k & (k - 1)) == 0; }
 
+// MI355X spreads the workgroups of a dispatch round-robin over its 8 XCDs, each
+// with its own L2.  Renumbering so that XCD x runs one contiguous range of
+// logical blocks keeps each XCD's gathers (neighbour positions of cell-sorted
+// atoms) inside its own L2 instead of every XCD touching the whole box.
+constexpr int kXcds = 8;
+__device__ inline int xcd_block() {
+  const int b = blockIdx.x, nb = gridDim.x;
+  const int q = nb / kXcds, r = nb % kXcds;
+  const int xcd = b % kXcds, local = b / kXcds;
+  return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+constexpr int kSuperShift = 6;       // 64 cells per super-cell for the two-level cell scan
+
 // Periodic box as kernels see it: edges and their reciprocals (the reciprocal
 // only picks the image index; the image shift itself is d - L * k).
 struct BoxK {
@@ -75,7 +88,7 @@ struct WsLayout {
   size_t sc_e;       // double [n]        Sutton-Chen rho^-1/2
   size_t partials;   // double [kReduceBlocks][kReduceCols]
   size_t scalars;    // double [16]       reduced values
-  size_t ticket;     // int [64]          finished-workgroup counter of the binning pass
+  size_t scount;     // int [ncell/64+1]  per-super-cell counters
   size_t new_start;  // int [ncell + 1]   cell starts of a rebuild in progress
   size_t total;
 };
@@ -86,12 +99,14 @@ WsLayout ws_layout(int64_t n, int64_t ncell);
 // Every launcher enqueues on `s` and returns hipGetLastError().
 
 // Binning.  `gate` (nullable) makes the kernels return at once when *gate == 0.
-// launch_bin_count wraps, bins and counts, and its last workgroup writes
-// cell_start and clears count and *ticket (both must be zero on entry).
+// launch_bin_count wraps, bins and adds to the per-cell and per-super-cell
+// counters (zero on entry; the list build clears them again); with slot it
+// also records each atom's arrival slot.  launch_scan_cells turns the counts
+// into cell_start.
 hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t s);
 hipError_t launch_bin_count(double* x, int n, BoxK box, const int nc[3], int* atom_cell,
-                            int* count, int* slot, int* cell_start, int* ticket,
-                            const int* gate, hipStream_t s);
+                            int* count, int* scount, int* slot, const int* gate, hipStream_t s);
+hipError_t launch_scan_cells(const int* count, int ncell, int* cell_start, hipStream_t s);
 hipError_t launch_scatter(const int* atom_cell, const int* slot, const int* cell_start, int n,
                           int* tmp_perm, const int* gate, hipStream_t s);
 // Stable order inside each cell; optionally gathers x, v, id (and f, xr) into
@@ -102,11 +117,13 @@ hipError_t launch_cell_sort(const int* tmp_perm, const int* cell_start, int ncel
                             const int* gate, hipStream_t s);
 // Rebuild-time sort for atoms already in the previous build's cell order that
 // moved less than a cell edge: gathers the state into staging in the stable
-// order and sets status bit 2 if some atom moved further.
-hipError_t launch_gather_sort(const int* old_start, const int* new_start, const int* atom_cell,
-                              const int nc[3], int* perm, const double* x, const double* v,
-                              const int* id, int n, double* sx, double* sv, int* sid,
-                              int* status, const int* gate, hipStream_t s);
+// order, writes the new cell starts, and sets status bit 2 if some atom moved
+// further.
+hipError_t launch_gather_sort(const int* old_start, int* new_start, const int* count,
+                              const int* scount, const int* atom_cell, const int nc[3],
+                              int* perm, const double* x, const double* v, const int* id, int n,
+                              double* sx, double* sv, int* sid, int* status, const int* gate,
+                              hipStream_t s);
 hipError_t launch_copy_back(double* x, double* v, int* id, double* f, double* xr,
                             const double* sx, const double* sv, const int* sid,
                             const double* sf, int n, hipStream_t s);
@@ -128,6 +145,8 @@ struct BuildArgs {
   int nc[3];
   const int* cell_start;
   int* cell_start_out;   // nullable: receives a copy of cell_start
+  int* count_clear;      // nullable: per-cell counters to zero
+  int* scount_clear;     // nullable: per-super-cell counters to zero
   const int* atom_cell;  // cell of each atom, input order
   const int* perm;
   double rl2;
