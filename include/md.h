@@ -20,6 +20,7 @@
  *    md_autoselect.  Work is enqueued on `stream` (a hipStream_t; NULL is the
  *    default stream).
  *  - Per-atom vectors are SoA FP64 [3][n]: n x values, then n y, then n z.
+  - n (atoms) is at most MD_MAX_ATOMS; larger n returns MD_ERR_INVALID_ARG.
  *  - The box is orthorhombic, periodic, with origin 0 and edges L[0..2].
  *  - Errors are returned; nothing is thrown across the ABI.  Host-detectable
  *    errors return before anything is enqueued.  Device-detected errors
@@ -38,6 +39,10 @@
 #ifdef __cplusplus
 extern "C" {
 #endif
+
+/* Largest atom count: the force kernels address positions with 32-bit byte
+   offsets into 32-byte records. */
+#define MD_MAX_ATOMS 134217727
 
 typedef enum {
   MD_OK = 0,
@@ -192,7 +197,8 @@ md_status md_compute_forces(const md_potential* p, const double* x, int64_t n,
    setup == 0, st, cells and nl must be as a previous md_step on the same
    system left them (atoms in cell order, list and forces current); rebuilds
    then re-sort by gathering each cell's atoms from the previous cell ranges,
-   and MD_ERR_UNSTABLE reports an atom that moved more than a cell edge.
+   and MD_ERR_UNSTABLE reports an atom that moved more than a cell edge (the
+   state is then unusable; this status takes precedence over every other).
    thermo (device, md_thermo_rows(...) x 8 doubles, or NULL for none): for
    each step s with s % thermo_every == 0: s, pe, ke, pe + ke,
    T = 2 ke / ((3n - 3) kB), P = (2 ke + tr W) / (3 V), builds so far,

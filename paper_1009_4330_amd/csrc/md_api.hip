@@ -64,7 +64,7 @@ BoxK make_box(const md_box* b) {
   return k;
 }
 
-bool n_ok(int64_t n) { return n >= 1 && n <= (int64_t)INT_MAX - 1024; }
+bool n_ok(int64_t n) { return n >= 1 && n <= (int64_t)MD_MAX_ATOMS; }
 
 md_status check_pot(const md_potential* p) {
   if (!p || !finite_pos(p->rc)) return MD_ERR_INVALID_ARG;
@@ -220,11 +220,13 @@ md_status autoselect_impl(const md_potential* p, const double* x, int n, int sor
   float best = 1e30f;
   int win = MD_KERNEL_TPA;
   int maxcount = 0;
+  double* xq = at<double>(ws, L.xq);
+  MD_CK(launch_pack_positions(x, n, xq, s));
   for (int k = 1; k <= kWave; k *= 2) {
     md_status st = build_list(x, n, sorted, box, nc, cells, rl, nl, k, s);
     if (st != MD_OK) return st;
     ForceArgs fa{};
-    fa.x = x;
+    fa.xq = xq;
     fa.n = n;
     fa.box = make_box(box);
     fa.margin = interior_margin(p, rl);
@@ -287,8 +289,8 @@ int resolve_lanes(md_kernel k, int layout) {
 }
 
 md_status status_from_words(const int* w) {
-  if (w[MD_ST_ERRORS] & 2) return MD_ERR_NONFINITE;
   if (w[MD_ST_ERRORS] & 4) return MD_ERR_UNSTABLE;
+  if (w[MD_ST_ERRORS] & 2) return MD_ERR_NONFINITE;
   if (w[MD_ST_ERRORS] & 1) return MD_ERR_NLIST_OVERFLOW;
   return MD_OK;
 }
@@ -321,6 +323,7 @@ WsLayout ws_layout(int64_t n, int64_t ncell) {
   L.scalars = take(sizeof(double) * 16);
   L.scount = take(sizeof(int) * (size_t)(((ncell > 0 ? ncell : 1) >> kSuperShift) + 1));
   L.new_start = take(sizeof(int) * (size_t)((ncell > 0 ? ncell : 1) + 1));
+  L.xq = take(sizeof(double) * 4 * nn);
   L.total = o;
   return L;
 }
@@ -383,10 +386,8 @@ md_status md_bin_cells(double* x, int64_t n, const md_box* box, double rl, md_ce
   const int ni = (int)n;
   int* count = at<int>(ws, L.count);
   MD_CK(launch_fill_int(count, ncell, 0, s));
-  int* scount = at<int>(ws, L.scount);
-  MD_CK(launch_fill_int(scount, (ncell >> kSuperShift) + 1, 0, s));
-  MD_CK(launch_bin_count(x, ni, make_box(box), nc, cells->atom_cell, count, scount,
-                         at<int>(ws, L.slot), nullptr, s));
+  MD_CK(launch_bin_count(x, ni, make_box(box), nc, cells->atom_cell, count, at<int>(ws, L.slot),
+                         s));
   MD_CK(launch_scan_cells(count, (int)ncell, cells->cell_start, s));
   MD_CK(launch_scatter(cells->atom_cell, at<int>(ws, L.slot), cells->cell_start, ni,
                        at<int>(ws, L.tmp_perm), nullptr, s));
@@ -458,8 +459,10 @@ md_status md_compute_forces(const md_potential* p, const double* x, int64_t n,
   const WsLayout L = ws_layout(n, 1);
   if ((st = check_ws(ws, ws_bytes, L)) != MD_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  double* xq = at<double>(ws, L.xq);
+  MD_CK(launch_pack_positions(x, (int)n, xq, s));
   ForceArgs fa{};
-  fa.x = x;
+  fa.xq = xq;
   fa.n = (int)n;
   fa.box = make_box(box);
   fa.margin = interior_margin(p, nl->rl);
@@ -499,8 +502,10 @@ md_status md_force_vjp(const md_potential* p, const double* x, int64_t n, const 
   const WsLayout L = ws_layout(n, 1);
   if ((st = check_ws(ws, ws_bytes, L)) != MD_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  double* xq = at<double>(ws, L.xq);
+  MD_CK(launch_pack_positions(x, (int)n, xq, s));
   ForceArgs fa{};
-  fa.x = x;
+  fa.xq = xq;
   fa.n = (int)n;
   fa.box = make_box(box);
   fa.margin = interior_margin(p, nl->rl);
@@ -606,23 +611,26 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
   int* scount = at<int>(ws, L.scount);
 
   int* new_start = at<int>(ws, L.new_start);
+  double* xq = at<double>(ws, L.xq);
 
   // Rebuild chain.  At setup (no gate; atoms in arbitrary order): wrap + bin +
-  // count (+ scan in its last workgroup), scatter, stable in-cell order with
-  // the state gathered into staging, list build that copies the state back.
-  // During a run (gated; atoms in the previous build's cell order): wrap + bin
-  // + count into new_start, gather-sort from the previous cell ranges, list
-  // build, which also copies new_start into cells->cell_start.  Gated kernels
-  // return at once unless the rebuild flag is set.
+  // count, scan, scatter, stable in-cell order with the state gathered into
+  // staging, list build that copies the state back.  During a run (gated;
+  // atoms in the previous build's cell order, their new cells recorded by the
+  // drift kernel): per-cell counts from the previous ranges, gather-sort with
+  // the new cell starts, list build, which also copies the new starts into
+  // cells->cell_start.  Gated kernels return at once unless the rebuild flag
+  // is set.
   auto rebuild = [&](const int* g, int layout) -> md_status {
     int* starts = g ? new_start : cells->cell_start;
-    MD_CK(launch_bin_count(stt->x, n, bk, nc, cells->atom_cell, count, scount,
-                           g ? nullptr : slot, g, s));
     if (g) {
+      MD_CK(launch_cell_count(cells->cell_start, cells->atom_cell, nc, count, scount, g, s));
       MD_CK(launch_gather_sort(cells->cell_start, new_start, count, scount, cells->atom_cell, nc,
-                               cells->perm, stt->x, stt->v, stt->id, n, sx, sv, sid, status, g,
-                               s));
+                               bk, cells->perm, stt->x, stt->v, stt->id, n, sx, sv, sid, status,
+                               g, s));
     } else {
+      MD_CK(launch_fill_int(count, ncell, 0, s));
+      MD_CK(launch_bin_count(stt->x, n, bk, nc, cells->atom_cell, count, slot, s));
       MD_CK(launch_scan_cells(count, (int)ncell, starts, s));
       MD_CK(launch_scatter(cells->atom_cell, slot, starts, n, tmp_perm, g, s));
       MD_CK(launch_cell_sort(tmp_perm, starts, (int)ncell, cells->perm, stt->x, stt->v, stt->id,
@@ -636,8 +644,6 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
     for (int d = 0; d < 3; ++d) a.nc[d] = nc[d];
     a.cell_start = starts;
     a.cell_start_out = g ? cells->cell_start : nullptr;
-    a.count_clear = count;
-    a.scount_clear = scount;
     a.atom_cell = cells->atom_cell;
     a.perm = cells->perm;
     a.rl2 = rl * rl;
@@ -647,6 +653,7 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
     a.numneigh = nl->numneigh;
     a.x_ref = nl->x_ref;
     a.status = status;
+    a.xq_out = xq;
     a.x_out = stt->x;
     a.v_out = stt->v;
     a.v_in = sv;
@@ -659,7 +666,7 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
 
   auto forces = [&](bool ev, int kernel) -> md_status {
     ForceArgs fa{};
-    fa.x = stt->x;
+    fa.xq = xq;
     fa.n = n;
     fa.box = bk;
     fa.margin = interior_margin(p, rl);
@@ -704,10 +711,6 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
   };
 
   int kernel = nl->layout;   // lanes per atom == list layout
-  // The binning counters must start at zero; every binning pass leaves them
-  // zero again, but the workspace may be fresh, so clear them once per call.
-  MD_CK(launch_fill_int(count, ncell, 0, s));
-  MD_CK(launch_fill_int(scount, (ncell >> kSuperShift) + 1, 0, s));
   if (setup) {
     kernel = k == MD_KERNEL_AUTO ? MD_KERNEL_TPA : (int)k;
     if ((st = rebuild(nullptr, kernel)) != MD_OK) return st;
@@ -743,6 +746,11 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
     }
   }
   const int layout = kernel;
+  BinOut bin{};
+  bin.box = bk;
+  for (int d = 0; d < 3; ++d) bin.nc[d] = nc[d];
+  bin.atom_cell = cells->atom_cell;
+  bin.xq = xq;
   // Step s: [closing kick of s-1 +] kick + drift + check, gated rebuild,
   // forces.  The closing kick of step s-1 is fused into step s's first kernel;
   // the thermo row of step s-1 is summed right after it, before step s's
@@ -753,10 +761,10 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
     const bool th_prev = is_thermo(step - 1);
     if (step == 1)
       MD_CK(launch_kick_drift_check(stt->x, stt->v, stt->f, nl->x_ref, n, dtfm, dt, trig2,
-                                    status, s));
+                                    status, bin, s));
     else
       MD_CK(launch_vv_step(stt->x, stt->v, stt->f, nl->x_ref, n, dtfm, dt, trig2,
-                           th_prev ? keatom : nullptr, status, s));
+                           th_prev ? keatom : nullptr, status, bin, s));
     if (th_prev && (st = thermo_out((double)(step - 1))) != MD_OK) return st;
     if ((st = rebuild(gate, layout)) != MD_OK) return st;
     if ((st = forces(is_thermo(step), kernel)) != MD_OK) return st;

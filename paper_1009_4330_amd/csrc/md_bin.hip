@@ -7,25 +7,11 @@
 namespace md {
 namespace {
 
-constexpr int kBuildChunk = 1024;   // candidates staged in LDS per pass (32 KB)
 
 __global__ __launch_bounds__(kBlock) void k_fill_int(int* __restrict__ p, int64_t count,
                                                       int value) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < count) p[i] = value;
-}
-
-// Wrap one coordinate into [0, L): x - L floor(x / L), an exact L mapped to 0.
-__device__ inline double wrap_coord(double x, double L) {
-  double r = x - L * floor(x / L);
-  if (r < 0.0) r += L;
-  if (r >= L) r = 0.0;
-  return r;
-}
-
-__device__ inline int cell_coord(double r, int nc, double L) {
-  int c = (int)((r * (double)nc) / L);
-  return c < 0 ? 0 : (c > nc - 1 ? nc - 1 : c);
 }
 
 // Exclusive scan of one int per thread over a 256-thread block; *total gets
@@ -51,19 +37,15 @@ __device__ inline int block_excl_scan(int v, int* sh, int* total) {
   return x - v + before;
 }
 
-// Wrap x in place, bin, and count atoms per cell and per super-cell (64
-// consecutive cells).  Runs of equal cells inside a wavefront (the common case
-// once atoms are cell-sorted) take one atomic per run; with slot != null each
-// atom's arrival slot in its cell is written too.  No fence: the counts are
-// read by later kernels.
+// Wrap x in place, bin, and count atoms per cell; each atom's arrival slot in
+// its cell is recorded for the scatter.  Runs of equal cells inside a
+// wavefront (the common case once atoms are cell-sorted) take one atomic per
+// run.
 __global__ __launch_bounds__(kBlock) void k_bin_count(double* __restrict__ x, int n, BoxK box,
                                                        int nc0, int nc1, int nc2,
                                                        int* __restrict__ atom_cell,
                                                        int* __restrict__ count,
-                                                       int* __restrict__ scount,
-                                                       int* __restrict__ slot,
-                                                       const int* __restrict__ gate) {
-  if (gate && *gate == 0) return;
+                                                       int* __restrict__ slot) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
   const bool live = i < n;
@@ -91,10 +73,9 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(double* __restrict__ x, in
   if (head) {
     const int len = min(next, n - (i - lane)) - lane;            // live lanes of this run
     base = atomicAdd(&count[c], len);
-    atomicAdd(&scount[c >> kSuperShift], len);
   }
   base = __shfl(base, hl < 0 ? 0 : hl, kWave);
-  if (live && slot) slot[i] = base + (lane - hl);
+  if (live) slot[i] = base + (lane - hl);
 }
 
 // One workgroup: exclusive scan of the per-cell counts into cell_start[0..ncell]
@@ -194,42 +175,170 @@ __device__ inline int stencil_lane(int cell, int lane, const int* nc, bool* kept
   return w[0] + nc[0] * (w[1] + nc[1] * w[2]);
 }
 
+// k-th smallest of the distinct cells {c - 1, c, c + 1} of a periodic
+// dimension with nc cells (min(nc, 3) of them).
+__device__ inline int nbr_sorted(int c, int nc, int k) {
+  if (nc < 3) return k;
+  if (c == 0) return k == 2 ? nc - 1 : k;
+  if (c == nc - 1) return k == 0 ? 0 : nc - 3 + k;
+  return c - 1 + k;
+}
+
+// The same cells along x as runs of consecutive cells: [*a, *b) for run k of
+// the returned count (1, or 2 when the stencil wraps around the box).
+__device__ inline int x_runs(int c, int nc) { return nc >= 3 && (c == 0 || c == nc - 1) ? 2 : 1; }
+__device__ inline void x_run(int c, int nc, int k, int* a, int* b) {
+  if (nc < 3) {
+    *a = 0;
+    *b = nc;
+  } else if (c == 0) {
+    *a = k == 0 ? 0 : nc - 1;
+    *b = k == 0 ? 2 : nc;
+  } else if (c == nc - 1) {
+    *a = k == 0 ? 0 : nc - 2;
+    *b = k == 0 ? 1 : nc;
+  } else {
+    *a = c - 1;
+    *b = c + 2;
+  }
+}
+
+// The previous build's atoms around a cell as contiguous segments: each (z, y)
+// row of the 3x3x3 stencil is one or two runs of consecutive cells, whose
+// atoms are contiguous in the previous cell order.  Lane s < n holds segment
+// s's range [b, b + len); segments come in increasing cell index, so visiting
+// s = 0, 1, ... visits the atoms in increasing index (the previous order).
+constexpr int kMaxSegs = 18;
+struct Segs {
+  int b, len;
+  int n;       // segments (wave-uniform, at most 18)
+  bool fits;   // every segment holds at most 128 atoms (wave-uniform)
+};
+
+__device__ inline Segs old_segments(int cell, int lane, const int* nc,
+                                    const int* __restrict__ old_start) {
+  const int cx = cell % nc[0], cy = (cell / nc[0]) % nc[1], cz = cell / (nc[0] * nc[1]);
+  const int nxs = x_runs(cx, nc[0]), ny = min(nc[1], 3), nz = min(nc[2], 3);
+  Segs S;
+  S.n = nxs * ny * nz;
+  S.b = 0;
+  S.len = 0;
+  if (lane < S.n) {
+    const int xr = lane % nxs, yr = (lane / nxs) % ny, zr = lane / (nxs * ny);
+    int xa, xb;
+    x_run(cx, nc[0], xr, &xa, &xb);
+    const int row = (nbr_sorted(cz, nc[2], zr) * nc[1] + nbr_sorted(cy, nc[1], yr)) * nc[0];
+    S.b = old_start[row + xa];
+    S.len = old_start[row + xb] - S.b;
+  }
+  S.fits = __ballot(S.len > 2 * kWave) == 0;
+  return S;
+}
+
+// Short segments (S.fits): the new cell of atoms b + lane and b + 64 + lane of
+// every segment, all loads in flight together; -1 past a segment's end.
+__device__ inline void seg_cells(const Segs& S, int lane, const int* __restrict__ atom_cell,
+                                 int (*cid)[2], int* sb) {
+#pragma unroll
+  for (int q = 0; q < kMaxSegs; ++q) {
+    int b = 0, len = 0;
+    if (q < S.n) {
+      b = __builtin_amdgcn_readlane(S.b, q);
+      len = __builtin_amdgcn_readlane(S.len, q);
+    }
+    sb[q] = b;
+    cid[q][0] = lane < len ? atom_cell[b + lane] : -1;
+    cid[q][1] = lane + kWave < len ? atom_cell[b + kWave + lane] : -1;
+  }
+}
+
+// One wavefront per new cell, 16 per workgroup (one super-cell): the number
+// of atoms of the surrounding old ranges whose new cell this is, and the
+// super-cell's total.  Plain stores only.
+constexpr int kCountBlock = kWave * kSuperCells;
+
+__global__ __launch_bounds__(kCountBlock) void k_cell_count(
+    const int* __restrict__ old_start, const int* __restrict__ atom_cell, int nc0, int nc1,
+    int nc2, int* __restrict__ count, int* __restrict__ scount, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  __shared__ int part[kSuperCells];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int sc = xcd_block();
+  const int cell = __builtin_amdgcn_readfirstlane(sc * kSuperCells + wave);
+  const int nc[3] = {nc0, nc1, nc2};
+  int cnt = 0;
+  if (cell < nc0 * nc1 * nc2) {
+    const Segs S = old_segments(cell, lane, nc, old_start);
+    if (S.fits) {
+      int cid[kMaxSegs][2], sb[kMaxSegs];
+      seg_cells(S, lane, atom_cell, cid, sb);
+#pragma unroll
+      for (int q = 0; q < kMaxSegs; ++q)
+        cnt += __popcll(__ballot(cid[q][0] == cell)) + __popcll(__ballot(cid[q][1] == cell));
+    } else {
+      for (int q = 0; q < S.n; ++q) {
+        const int b = __builtin_amdgcn_readlane(S.b, q);
+        const int len = __builtin_amdgcn_readlane(S.len, q);
+        for (int t = 0; t < len; t += kWave)
+          cnt += __popcll(__ballot(t + lane < len && atom_cell[b + t + lane] == cell));
+      }
+    }
+    if (lane == 0) count[cell] = cnt;
+  }
+  if (lane == 0) part[wave] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+#pragma unroll
+    for (int w = 0; w < kSuperCells; ++w) tot += part[w];
+    scount[sc] = tot;
+  }
+}
+
+// Gather member i into sorted slot p (x wrapped into the box).
+__device__ inline void put_member(int i, int p, int n, const BoxK& box, const double* __restrict__ x,
+                                  const double* __restrict__ v, const int* __restrict__ id,
+                                  int* __restrict__ perm, double* __restrict__ sx,
+                                  double* __restrict__ sv, int* __restrict__ sid) {
+  const double x0 = x[i], x1 = x[n + i], x2 = x[2 * n + i];
+  const double v0 = v[i], v1 = v[n + i], v2 = v[2 * n + i];
+  const int idi = id[i];
+  perm[p] = i;
+  sx[p] = wrap_coord(x0, box.L[0]);
+  sx[n + p] = wrap_coord(x1, box.L[1]);
+  sx[2 * n + p] = wrap_coord(x2, box.L[2]);
+  sv[p] = v0;
+  sv[n + p] = v1;
+  sv[2 * n + p] = v2;
+  sid[p] = idi;
+}
+
 // Rebuild-time sort of atoms that are already in the previous build's cell
 // order and have moved less than a cell edge since: one wavefront per new
 // cell collects its members from the old ranges of the surrounding cells,
 // visited in increasing cell index (so in increasing atom index), which is the
 // stable counting-sort order without any atomic arrival slots.  The state is
-// gathered into the sorted staging buffers.  If fewer members are found than
-// were counted (an atom moved further than a cell edge), status bit 2 is set.
-// The cell's first slot is the count of all earlier cells, summed from the
-// per-super-cell counts before its super-cell plus the counts of the earlier
-// cells of its own super-cell; it is written to new_start.
+// gathered into the sorted staging buffers.  The cell's first slot is the
+// count of all earlier cells: the super-cell totals before its super-cell
+// plus the counts of the earlier cells of its own; it is written to
+// new_start.  If the counts do not add up to n, status bit 2 is set.
 __global__ __launch_bounds__(kBlock) void k_gather_sort(
     const int* __restrict__ old_start, int* __restrict__ new_start,
     const int* __restrict__ count, const int* __restrict__ scount,
-    const int* __restrict__ atom_cell, int nc0, int nc1, int nc2, int* __restrict__ perm,
-    const double* __restrict__ x, const double* __restrict__ v, const int* __restrict__ id,
-    int n, double* __restrict__ sx, double* __restrict__ sv, int* __restrict__ sid,
-    int* __restrict__ status, const int* __restrict__ gate) {
+    const int* __restrict__ atom_cell, int nc0, int nc1, int nc2, BoxK box,
+    int* __restrict__ perm, const double* __restrict__ x, const double* __restrict__ v,
+    const int* __restrict__ id, int n, double* __restrict__ sx, double* __restrict__ sv,
+    int* __restrict__ sid, int* __restrict__ status, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int cell = (xcd_block() * kBlock + threadIdx.x) / kWave;
+  __shared__ int members[kBlock];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int cell = __builtin_amdgcn_readfirstlane((xcd_block() * kBlock + threadIdx.x) / kWave);
   const int ncell = nc0 * nc1 * nc2;
   if (cell >= ncell) return;
   const int nc[3] = {nc0, nc1, nc2};
-  bool kept;
-  const int c2 = stencil_lane(cell, lane, nc, &kept);
-  const int key = kept ? c2 : 0x7fffffff;
-  int b = 0, e = 0;
-  if (kept) {
-    b = old_start[c2];
-    e = old_start[c2 + 1];
-  }
-  int rank = 0;
-  for (int q = 0; q < 27; ++q) rank += __shfl(key, q, kWave) < key ? 1 : 0;
-  const int nkept = __popcll(__ballot(kept));
-  int part = 0;
+  const Segs S = old_segments(cell, lane, nc, old_start);
   const int sc = cell >> kSuperShift;
+  int part = 0;
   for (int q = lane; q < sc; q += kWave) part += scount[q];
   if ((sc << kSuperShift) + lane < cell) part += count[(sc << kSuperShift) + lane];
 #pragma unroll
@@ -238,49 +347,43 @@ __global__ __launch_bounds__(kBlock) void k_gather_sort(
   const int want = count[cell];
   if (lane == 0) {
     new_start[cell] = base;
-    if (cell == ncell - 1) new_start[ncell] = base + want;
+    if (cell == ncell - 1) {
+      new_start[ncell] = base + want;
+      if (base + want != n) atomicOr(&status[MD_ST_ERRORS], 4);
+    }
   }
   const unsigned long long below = (1ull << lane) - 1;
   int found = 0;
-  // Take one member candidate (lane-th atom of a range, first 64 atoms of
-  // ranges r..r+3 at once so their cell loads overlap), then any tail.
-  auto take = [&](int i, bool mine) {
-    const unsigned long long m = __ballot(mine);
-    if (mine) {
-      const int pos = found + __popcll(m & below);
-      if (pos < want) {
-        const int p = base + pos;
-        perm[p] = i;
-        sx[p] = x[i];
-        sx[n + p] = x[n + i];
-        sx[2 * n + p] = x[2 * n + i];
-        sv[p] = v[i];
-        sv[n + p] = v[n + i];
-        sv[2 * n + p] = v[2 * n + i];
-        sid[p] = id[i];
+  if (S.fits && want <= kWave) {
+    // member indices in order into this wave's LDS row, then one gather
+    int cid[kMaxSegs][2], sb[kMaxSegs];
+    seg_cells(S, lane, atom_cell, cid, sb);
+    int* row = members + wave * kWave;
+#pragma unroll
+    for (int q = 0; q < kMaxSegs; ++q) {
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const bool mine = cid[q][hh] == cell;
+        const unsigned long long m = __ballot(mine);
+        const int pos = found + __popcll(m & below);
+        if (mine && pos < kWave) row[pos] = sb[q] + hh * kWave + lane;
+        found += __popcll(m);
       }
     }
-    found += __popcll(m);
-  };
-  constexpr int U = 4;
-  for (int r0 = 0; r0 < nkept; r0 += U) {
-    int rb[U], re[U], ci[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int r = r0 + u;
-      const unsigned long long sel = __ballot(kept && rank == r);
-      const int src = sel ? __ffsll((long long)sel) - 1 : 0;
-      rb[u] = sel ? __shfl(b, src, kWave) : 0;
-      re[u] = sel ? __shfl(e, src, kWave) : 0;
-      const int i = rb[u] + lane;
-      ci[u] = i < re[u] ? atom_cell[i] : -1;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      take(rb[u] + lane, ci[u] == cell);
-      for (int t = rb[u] + kWave; t < re[u]; t += kWave) {
-        const int i = t + lane;
-        take(i, i < re[u] && atom_cell[i] == cell);
+    __builtin_amdgcn_wave_barrier();   // a wavefront's LDS accesses complete in order
+    if (lane < want && lane < found)
+      put_member(row[lane], base + lane, n, box, x, v, id, perm, sx, sv, sid);
+  } else {
+    for (int q = 0; q < S.n; ++q) {
+      const int b = __builtin_amdgcn_readlane(S.b, q);
+      const int len = __builtin_amdgcn_readlane(S.len, q);
+      for (int t = 0; t < len; t += kWave) {
+        const int i = b + t + lane;
+        const bool mine = t + lane < len && atom_cell[i] == cell;
+        const unsigned long long m = __ballot(mine);
+        const int pos = found + __popcll(m & below);
+        if (mine && pos < want) put_member(i, base + pos, n, box, x, v, id, perm, sx, sv, sid);
+        found += __popcll(m);
       }
     }
   }
@@ -338,175 +441,617 @@ __device__ inline int wave_max(int v) {
   return v;
 }
 
-// Home atoms of one staged chunk: each wavefront takes home atoms in turn and
-// tests 64 staged candidates at a time; accepted candidates are appended in
-// candidate order through a ballot prefix count.  WRAP applies the minimum
-// image (home cells touching a box face).
-template <bool WRAP>
-__device__ inline void build_home(const BuildArgs& a, const double* cxs, const double* cys,
-                                  const double* czs, const int* cjs, int c0, int clen, int hb,
-                                  int he, int lane, int wave, unsigned long long below) {
+// Append candidate j at position pos of the list whose first row starts at
+// row0 (K = 2^lk lanes per atom: entry pos sits in row pos / K, column pos % K).
+__device__ inline void put_entry(int* __restrict__ row0, int pos, int lk, int j) {
+  row0[((pos >> lk) << 6) + (pos & ((1 << lk) - 1))] = j;
+}
+
+// LDS of the list-build kernels.
+constexpr int kListBuf = 128;   // buffered list entries per home atom and pass
+constexpr int kListRow = 2 * kListBuf + kWave;   // per wavefront: two buffers and a sink row
+struct BuildLds {
+  double* cxs;   // staged candidates: positions and indices
+  double* cys;
+  double* czs;
+  int* cjs;
+  int* hcnt;     // [kBlock] list lengths of the current cell's first 256 home atoms
+  int* lbuf;     // [waves][kListRow] accepted entries of a wavefront's two home atoms
+};
+
+// Where one pass finds its candidates: LDS slots [base[s], base[s] + pad[s]) of
+// each of n segments, every segment padded to a multiple of 64 with entries
+// that are never accepted (NaN position, index -1).
+struct CandSegs {
+  int base[3];
+  int pad[3];
+  int n;
+};
+
+// Home atoms of one pass, two at a time per wavefront: every candidate of the
+// pass (64 at a time) is tested against both, and accepted ones are appended
+// in candidate order through a ballot prefix count -- into the wavefront's
+// LDS buffer (anything past kListBuf straight to the list), copied into the
+// list layout when the atom's pass is done.  WRAP applies the minimum image
+// (home cells touching a box face).  HOME_LDS: the home atoms are staged at
+// LDS slots hl, hl + 1, ...; otherwise their positions are read from x (one
+// address space per instantiation, so no access goes through a flat
+// pointer, which would make LDS waits wait for global memory too).  FIRST:
+// the lists start empty, else they continue from hcnt / numneigh.  Each home
+// atom's count goes to numneigh and, for the first 256, to hcnt.
+template <bool WRAP, bool HOME_LDS, bool FIRST>
+__device__ inline void build_home(const BuildArgs& a, const BuildLds& L, const CandSegs& cs,
+                                  int hl, int hb, int he, int lane, int wave) {
   const int n = a.n;
   const double* __restrict__ x = a.x;
   const bool sorted = a.sorted != 0;
+  const double nan = __builtin_nan("");
   // layout K = 2^lk lanes per atom: index arithmetic by shifts and masks
   const int lk = __ffs(a.layout) - 1;
   const int gs = 6 - lk;
   const size_t rows = nl_rows(a.cap, a.layout);
-  for (int h = hb + wave; h < he; h += kBlock / kWave) {
-    const int i = sorted ? h : a.perm[h];
-    const double xi = x[i], yi = x[n + i], zi = x[2 * n + i];
-    int* __restrict__ row0 =
-        a.neigh + (size_t)(i >> gs) * rows * kWave + ((i & ((1 << gs) - 1)) << lk);
-    int cnt = c0 == 0 ? 0 : a.numneigh[i];
-    for (int t = 0; t < clen; t += kWave) {
-      const int q = t + lane;
-      bool take = false;
-      int j = 0;
-      if (q < clen) {
-        j = cjs[q];
-        double dx = xi - cxs[q], dy = yi - cys[q], dz = zi - czs[q];
-        if (WRAP) {
-          dx = min_image(dx, a.box.L[0], a.box.inv[0]);
-          dy = min_image(dy, a.box.L[1], a.box.inv[1]);
-          dz = min_image(dz, a.box.L[2], a.box.inv[2]);
-        }
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        take = (j != i) && (r2 < a.rl2);
-      }
-      const unsigned long long m = __ballot(take);
-      if (take) {
-        const int pos = cnt + __popcll(m & below);
-        if (pos < a.cap) row0[(size_t)(pos >> lk) * kWave + (pos & ((1 << lk) - 1))] = j;
-      }
-      cnt += __popcll(m);
+  const double rl2 = a.rl2;
+  // this wavefront's LDS row: buffer of atom 0, buffer of atom 1, then one
+  // sink slot per lane where rejected candidates land
+  int* __restrict__ lrow = L.lbuf + wave * kListRow;
+  const int sink = 2 * kListBuf + lane;
+  for (int h = __builtin_amdgcn_readfirstlane(hb + 2 * wave); h < he;
+       h += 2 * (kBlock / kWave)) {
+    const bool two = h + 1 < he;
+    const int i0 = sorted ? h : a.perm[h];
+    const int i1 = two ? (sorted ? h + 1 : a.perm[h + 1]) : -1;
+    const int k1 = two ? i1 : i0;   // a valid index for the address arithmetic
+    double x0, y0, z0, x1, y1, z1;
+    if (HOME_LDS) {
+      const int q0 = hl + (h - hb);
+      x0 = L.cxs[q0];
+      y0 = L.cys[q0];
+      z0 = L.czs[q0];
+      x1 = L.cxs[q0 + 1];
+      y1 = L.cys[q0 + 1];
+      z1 = L.czs[q0 + 1];
+    } else {
+      x0 = x[i0];
+      y0 = x[n + i0];
+      z0 = x[2 * n + i0];
+      x1 = x[k1];
+      y1 = x[n + k1];
+      z1 = x[2 * n + k1];
     }
-    if (lane == 0) a.numneigh[i] = cnt;
+    if (!two) x1 = y1 = z1 = nan;
+    int* __restrict__ r0 =
+        a.neigh + (size_t)(i0 >> gs) * rows * kWave + ((i0 & ((1 << gs) - 1)) << lk);
+    int* __restrict__ r1 =
+        a.neigh + (size_t)(k1 >> gs) * rows * kWave + ((k1 & ((1 << gs) - 1)) << lk);
+    int base0 = 0, base1 = 0;
+    if (!FIRST) {
+      base0 = h - hb < kBlock ? L.hcnt[h - hb] : a.numneigh[i0];
+      if (two) base1 = h + 1 - hb < kBlock ? L.hcnt[h + 1 - hb] : a.numneigh[k1];
+    }
+    // entries of this pass, relative to base0 / base1
+    int cnt0 = 0, cnt1 = 0;
+    for (int sg = 0; sg < cs.n; ++sg) {
+      const int sbase = cs.base[sg], spad = cs.pad[sg];
+      for (int t = 0; t < spad; t += kWave) {
+        const int q = sbase + t + lane;
+        const int j = L.cjs[q];
+        const double cx = L.cxs[q], cy = L.cys[q], cz = L.czs[q];
+        double ax = x0 - cx, ay = y0 - cy, az = z0 - cz;
+        double bx = x1 - cx, by = y1 - cy, bz = z1 - cz;
+        if (WRAP) {
+          ax = min_image(ax, a.box.L[0], a.box.inv[0]);
+          ay = min_image(ay, a.box.L[1], a.box.inv[1]);
+          az = min_image(az, a.box.L[2], a.box.inv[2]);
+          bx = min_image(bx, a.box.L[0], a.box.inv[0]);
+          by = min_image(by, a.box.L[1], a.box.inv[1]);
+          bz = min_image(bz, a.box.L[2], a.box.inv[2]);
+        }
+        const double ra = ax * ax + ay * ay + az * az;
+        const double rb = bx * bx + by * by + bz * bz;
+        const bool ta = (ra < rl2) & (j != i0);
+        const bool tb = (rb < rl2) & (j != i1);
+        // each ballot taken straight from one compare (no mask materialised in VGPRs)
+        const unsigned long long ma =
+            __builtin_amdgcn_ballot_w64(ra < rl2) & __builtin_amdgcn_ballot_w64(j != i0);
+        const unsigned long long mb =
+            __builtin_amdgcn_ballot_w64(rb < rl2) & __builtin_amdgcn_ballot_w64(j != i1);
+        const int pa = cnt0 + __builtin_amdgcn_mbcnt_hi(
+                                  (unsigned)(ma >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)ma, 0u));
+        const int pb = cnt1 + __builtin_amdgcn_mbcnt_hi(
+                                  (unsigned)(mb >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mb, 0u));
+        const int na = __popcll(ma), nb = __popcll(mb);
+        // every lane writes its LDS slot, rejected (or past-the-buffer) ones
+        // into their sink, so no lane mask changes on the common path
+        lrow[ta && pa < kListBuf ? pa : sink] = j;
+        lrow[tb && pb < kListBuf ? kListBuf + pb : sink] = j;
+        if (cnt0 + na > kListBuf || cnt1 + nb > kListBuf) {   // wave-uniform, long lists only
+          if (ta && pa >= kListBuf && base0 + pa < a.cap) put_entry(r0, base0 + pa, lk, j);
+          if (tb && pb >= kListBuf && base1 + pb < a.cap) put_entry(r1, base1 + pb, lk, j);
+        }
+        cnt0 += na;
+        cnt1 += nb;
+      }
+    }
+    // copy the buffered entries into the list layout (this wave's own LDS
+    // rows; a wavefront's LDS accesses complete in order)
+    __builtin_amdgcn_wave_barrier();
+    const int lim0 = min(min(cnt0, kListBuf), a.cap - base0);
+    const int lim1 = min(min(cnt1, kListBuf), a.cap - base1);
+    for (int m = lane; m < lim0; m += kWave) put_entry(r0, base0 + m, lk, lrow[m]);
+    for (int m = lane; m < lim1; m += kWave) put_entry(r1, base1 + m, lk, lrow[kListBuf + m]);
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+      a.numneigh[i0] = base0 + cnt0;
+      if (h - hb < kBlock) L.hcnt[h - hb] = base0 + cnt0;
+      if (two) {
+        a.numneigh[i1] = base1 + cnt1;
+        if (h + 1 - hb < kBlock) L.hcnt[h + 1 - hb] = base1 + cnt1;
+      }
+    }
   }
 }
 
-// One workgroup per cell.  The candidates -- atoms of the (up to) 27
-// surrounding cells, in cell order and slot order inside a cell -- are staged
-// in LDS in chunks; each wavefront takes home atoms in turn and tests 64
-// candidates at a time, appending accepted ones in candidate order through a
-// ballot prefix count.  r^2 = (dx dx + dy dy) + dz dz < rl^2 exactly as the
-// FP64 definition.  Status words get one atomic per workgroup.
-__global__ __launch_bounds__(kBlock) void k_build(BuildArgs a) {
-  if (a.gate && *a.gate == 0) return;
-  const int cell = xcd_block();
-  __shared__ double cxs[kBuildChunk], cys[kBuildChunk], czs[kBuildChunk];
-  __shared__ int cjs[kBuildChunk];
-  __shared__ int st_start[27], st_cnt[27], st_off[28], st_n;
-  __shared__ int red[kBlock / kWave];
-  const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1), wave = tid / kWave;
-  const int n = a.n;
-  const double* __restrict__ x = a.x;
-  const bool sorted = a.sorted != 0;
-  if (cell == 0 && tid == 0) atomicAdd(&a.status[MD_ST_BUILDS], 1);
-  if (wave == 0) {
-    // Stencil entry (oz, oy, ox) = lane, all 27 looked up at once; the kept
-    // entries keep the z, y, x offset order of the FP64 definition.
-    bool kept;
-    const int c2 = stencil_lane(cell, lane, a.nc, &kept);
-    const unsigned long long km = __ballot(kept);
-    if (kept) {
-      const int pos = __popcll(km & ((1ull << lane) - 1));
-      const int b = a.cell_start[c2];
-      st_start[pos] = b;
-      st_cnt[pos] = a.cell_start[c2 + 1] - b;
-    }
-    if (lane == 0) st_n = __popcll(km);
-  }
-  __syncthreads();
-  if (tid == 0) {
-    int acc = 0;
-    for (int q = 0; q < st_n; ++q) {
-      st_off[q] = acc;
-      acc += st_cnt[q];
-    }
-    st_off[st_n] = acc;
-  }
-  __syncthreads();
-  const int total = st_off[st_n];
-  const int hb = a.cell_start[cell], he = a.cell_start[cell + 1];
-  // A home cell at least one cell away from every box face (with >= 3 cells
-  // per dimension) has an unwrapped stencil: candidate and home positions are
-  // wrapped into [0, L) and at most two cell edges apart, so an accepted pair
-  // has rint(d / L) = 0 and d = x_i - x_j is the FP64 minimum image bit for bit,
-  // while any other image is at least L / 3 >= r_l away.
-  bool wrap = false;
-  {
-    const int home[3] = {cell % a.nc[0], (cell / a.nc[0]) % a.nc[1],
-                         cell / (a.nc[0] * a.nc[1])};
-    for (int d = 0; d < 3; ++d)
-      wrap = wrap || a.nc[d] < 3 || home[d] == 0 || home[d] == a.nc[d] - 1;
-  }
-  if (tid == 0) {
-    if (a.cell_start_out) {
-      a.cell_start_out[cell] = hb;
-      if (cell == (int)gridDim.x - 1) a.cell_start_out[cell + 1] = he;
-    }
-    // the binning counters have been consumed: clear them for the next rebuild
-    if (a.count_clear) a.count_clear[cell] = 0;
-    if (a.scount_clear && (cell & ((1 << kSuperShift) - 1)) == 0)
-      a.scount_clear[cell >> kSuperShift] = 0;
-  }
-  const unsigned long long below = (1ull << lane) - 1;
-  for (int c0 = 0; c0 < total; c0 += kBuildChunk) {
-    const int clen = min(kBuildChunk, total - c0);
-    for (int q = tid; q < clen; q += kBlock) {
-      const int idx = c0 + q;
-      int sc = 0;
-      while (idx >= st_off[sc + 1]) ++sc;
-      const int sl = st_start[sc] + (idx - st_off[sc]);
-      const int j = sorted ? sl : a.perm[sl];
-      cjs[q] = j;
-      cxs[q] = x[j];
-      cys[q] = x[n + j];
-      czs[q] = x[2 * n + j];
-    }
-    __syncthreads();
-    if (wrap)
-      build_home<true>(a, cxs, cys, czs, cjs, c0, clen, hb, he, lane, wave, below);
+// A home cell at least one cell away from every box face (with >= 3 cells per
+// dimension) has an unwrapped stencil: candidate and home positions are
+// wrapped into [0, L) and at most two cell edges apart, so an accepted pair
+// has rint(d / L) = 0 and d = x_i - x_j is the FP64 minimum image bit for bit,
+// while any other image is at least L / 3 >= r_l away.
+__device__ inline bool cell_wraps(int cx, int cy, int cz, const int* nc) {
+  const int c[3] = {cx, cy, cz};
+  bool w = false;
+  for (int d = 0; d < 3; ++d) w = w || nc[d] < 3 || c[d] == 0 || c[d] == nc[d] - 1;
+  return w;
+}
+
+// build_home for the per-cell path's runtime cases.
+template <bool WRAP>
+__device__ inline void build_home_any(const BuildArgs& a, const BuildLds& L, const CandSegs& cs,
+                                      bool first, int hl, int hb, int he, int lane, int wave) {
+  if (first) {
+    if (hl >= 0)
+      build_home<WRAP, true, true>(a, L, cs, hl, hb, he, lane, wave);
     else
-      build_home<false>(a, cxs, cys, czs, cjs, c0, clen, hb, he, lane, wave, below);
-    __syncthreads();
+      build_home<WRAP, false, true>(a, L, cs, hl, hb, he, lane, wave);
+  } else {
+    if (hl >= 0)
+      build_home<WRAP, true, false>(a, L, cs, hl, hb, he, lane, wave);
+    else
+      build_home<WRAP, false, false>(a, L, cs, hl, hb, he, lane, wave);
   }
-  // per-atom bookkeeping of the home atoms (after every wave has written numneigh)
-  int mx = 0;
-  for (int h = hb + tid; h < he; h += kBlock) {
-    const int i = sorted ? h : a.perm[h];
-    mx = max(mx, a.numneigh[i]);
-    const double xi = x[i], yi = x[n + i], zi = x[2 * n + i];
-    if (a.x_ref) {
-      a.x_ref[i] = xi;
-      a.x_ref[n + i] = yi;
-      a.x_ref[2 * n + i] = zi;
-    }
-    if (a.x_out) {
-      a.x_out[i] = xi;
-      a.x_out[n + i] = yi;
-      a.x_out[2 * n + i] = zi;
+}
+
+// Copies of the home atoms' state after their lists are done: lengths for the
+// running maximum, x_ref / packed / sorted-back positions (HOME_LDS: from LDS
+// slot hl + t, else from x), and v, id back from staging (thread t's first
+// atom from the prefetched pv / pid).  Lengths of the first 256 home atoms
+// come from hcnt, of any further ones from numneigh.  Returns this thread's
+// largest list length.
+template <bool HOME_LDS>
+__device__ inline void finish_one(const BuildArgs& a, const BuildLds& L, int hl, int t, int i,
+                                  bool mine, double pv0, double pv1, double pv2, int pid) {
+  const int n = a.n;
+  double xi, yi, zi;
+  if (HOME_LDS) {
+    xi = L.cxs[hl + t];
+    yi = L.cys[hl + t];
+    zi = L.czs[hl + t];
+  } else {
+    xi = a.x[i];
+    yi = a.x[n + i];
+    zi = a.x[2 * n + i];
+  }
+  if (a.x_ref) {
+    a.x_ref[i] = xi;
+    a.x_ref[n + i] = yi;
+    a.x_ref[2 * n + i] = zi;
+  }
+  if (a.xq_out) store_packed(a.xq_out, i, xi, yi, zi);
+  if (a.x_out) {
+    a.x_out[i] = xi;
+    a.x_out[n + i] = yi;
+    a.x_out[2 * n + i] = zi;
+    if (mine) {
+      a.v_out[i] = pv0;
+      a.v_out[n + i] = pv1;
+      a.v_out[2 * n + i] = pv2;
+      a.id_out[i] = pid;
+    } else {
       a.v_out[i] = a.v_in[i];
       a.v_out[n + i] = a.v_in[n + i];
       a.v_out[2 * n + i] = a.v_in[2 * n + i];
       a.id_out[i] = a.id_in[i];
     }
   }
+}
+
+template <bool HOME_LDS>
+__device__ inline int finish_home(const BuildArgs& a, const BuildLds& L, int hl, int hb, int he,
+                                  int tid, bool pre, int pi, double pv0, double pv1, double pv2,
+                                  int pid) {
+  const bool sorted = a.sorted != 0;
+  int mx = 0;
+  if (hb + tid < he) {
+    const int i = pre ? pi : (sorted ? hb + tid : a.perm[hb + tid]);
+    mx = L.hcnt[tid];
+    finish_one<HOME_LDS>(a, L, hl, tid, i, pre, pv0, pv1, pv2, pid);
+  }
+  for (int h = hb + tid + kBlock; h < he; h += kBlock) {
+    const int i = sorted ? h : a.perm[h];
+    mx = max(mx, a.numneigh[i]);
+    finish_one<HOME_LDS>(a, L, hl, h - hb, i, false, 0.0, 0.0, 0.0, 0);
+  }
+  return mx;
+}
+
+// Prefetch of the state finish_home copies back (thread t: home atom hb + t).
+struct HomePrefetch {
+  bool pre = false;
+  int pi = 0, pid = 0;
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+  __device__ inline void load(const BuildArgs& a, int hb, int he, int tid) {
+    pre = a.x_out && hb + tid < he;
+    if (pre) {
+      pi = a.sorted ? hb + tid : a.perm[hb + tid];
+      v0 = a.v_in[pi];
+      v1 = a.v_in[a.n + pi];
+      v2 = a.v_in[2 * a.n + pi];
+      pid = a.id_in[pi];
+    }
+  }
+};
+
+constexpr int kSlabCap = 256;                  // candidates per slab slot (9 cells), a multiple of 64
+constexpr int kSlabRounds = (kSlabCap + kBlock - 1) / kBlock;   // slab candidates per thread
+static_assert(kSlabCap % 64 == 0, "a padded slab stays inside its slot");
+constexpr int kBuildChunk = 3 * kSlabCap;      // candidates per pass of the per-cell path
+constexpr int kStageHalf = 4;   // stencil entries per wave staged together (two halves cover 27)
+static_assert(2 * kStageHalf * (kBlock / kWave) >= 27, "staging covers the stencil");
+
+// Per-cell path: wave w stages stencil entries w + 4 (k0 + k), k < kStageHalf,
+// the first 64 in-chunk atoms of each with all loads in flight together.
+__device__ inline void stage_entries(const BuildArgs& a, const BuildLds& L, int k0, int c0,
+                                     int clen, int nst, const int* st_start, const int* st_off,
+                                     int lane, int wave) {
+  const int n = a.n;
+  const double* __restrict__ x = a.x;
+  const bool sorted = a.sorted != 0;
+  double sx[kStageHalf], sy[kStageHalf], sz[kStageHalf];
+  int sj[kStageHalf], sq[kStageHalf];
+#pragma unroll
+  for (int k = 0; k < kStageHalf; ++k) {
+    const int e = wave + (k0 + k) * (kBlock / kWave);
+    sq[k] = -1;
+    sj[k] = 0;
+    if (e < nst) {
+      const int lo = max(st_off[e], c0), hi = min(st_off[e + 1], c0 + clen);
+      const int q = lo + lane;
+      if (q < hi) {
+        const int sl = st_start[e] + (q - st_off[e]);
+        sq[k] = q - c0;
+        sj[k] = sorted ? sl : a.perm[sl];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kStageHalf; ++k) {
+    if (sq[k] >= 0) {
+      sx[k] = x[sj[k]];
+      sy[k] = x[n + sj[k]];
+      sz[k] = x[2 * n + sj[k]];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kStageHalf; ++k) {
+    if (sq[k] >= 0) {
+      L.cjs[sq[k]] = sj[k];
+      L.cxs[sq[k]] = sx[k];
+      L.cys[sq[k]] = sy[k];
+      L.czs[sq[k]] = sz[k];
+    }
+  }
+}
+
+__device__ inline void pad_slots(const BuildLds& L, int from, int to, int tid) {
+  for (int q = from + tid; q < to; q += kBlock) {
+    L.cjs[q] = -1;
+    L.cxs[q] = __builtin_nan("");
+    L.cys[q] = __builtin_nan("");
+    L.czs[q] = __builtin_nan("");
+  }
+}
+
+// The list of one cell, general path: the (up to) 27 stencil entries, in
+// stencil order and slot order inside a cell, staged in chunks of
+// kBuildChunk.  Every thread of the workgroup calls it.  Returns this
+// thread's largest list length; copies cell_start into cell_start_out.
+__device__ inline int build_cell(const BuildArgs& a, const BuildLds& L, int cell, int* st_start,
+                                 int* st_off, int* st_meta) {
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wave = tid / kWave;
+  const int hb = a.cell_start[cell], he = a.cell_start[cell + 1];
+  HomePrefetch P;
+  P.load(a, hb, he, tid);
+  if (wave == 0) {
+    // Stencil entry (oz, oy, ox) = lane, all 27 looked up at once; the kept
+    // entries keep the z, y, x offset order, their offsets by a wave scan.
+    bool kept;
+    const int c2 = stencil_lane(cell, lane, a.nc, &kept);
+    const unsigned long long km = __ballot(kept);
+    int b = 0, cnt = 0;
+    if (kept) {
+      b = a.cell_start[c2];
+      cnt = a.cell_start[c2 + 1] - b;
+    }
+    int inc = cnt;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const int y = __shfl_up(inc, off, kWave);
+      if (lane >= off) inc += y;
+    }
+    if (kept) {
+      const int pos = __popcll(km & ((1ull << lane) - 1));
+      st_start[pos] = b;
+      st_off[pos] = inc - cnt;
+      if (c2 == cell) st_meta[1] = pos;
+    }
+    if (lane == kWave - 1) {
+      st_meta[0] = __popcll(km);
+      st_off[__popcll(km)] = inc;
+    }
+  }
+  __syncthreads();
+  const int nst = st_meta[0];
+  const int total = st_off[nst];
+  const int home_off = st_off[st_meta[1]];
+  const int cx = cell % a.nc[0], cy = (cell / a.nc[0]) % a.nc[1], cz = cell / (a.nc[0] * a.nc[1]);
+  const bool wrap = cell_wraps(cx, cy, cz, a.nc);
+  if (tid == 0 && a.cell_start_out) {
+    a.cell_start_out[cell] = hb;
+    if (cell == a.nc[0] * a.nc[1] * a.nc[2] - 1) a.cell_start_out[cell + 1] = he;
+  }
+  // home atoms staged in the chunk that holds them all, else read from x
+  int hl_last = -1;
+  for (int c0 = 0; c0 < total; c0 += kBuildChunk) {
+    const int clen = min(kBuildChunk, total - c0);
+    const int cpad = (clen + kWave - 1) & ~(kWave - 1);
+    stage_entries(a, L, 0, c0, clen, nst, st_start, st_off, lane, wave);
+    stage_entries(a, L, kStageHalf, c0, clen, nst, st_start, st_off, lane, wave);
+    for (int e = wave; e < nst; e += kBlock / kWave) {
+      const int lo = max(st_off[e], c0), hi = min(st_off[e + 1], c0 + clen);
+      for (int q = lo + kWave + lane; q < hi; q += kWave) {
+        const int sl = st_start[e] + (q - st_off[e]);
+        const int j = a.sorted ? sl : a.perm[sl];
+        L.cjs[q - c0] = j;
+        L.cxs[q - c0] = a.x[j];
+        L.cys[q - c0] = a.x[a.n + j];
+        L.czs[q - c0] = a.x[2 * a.n + j];
+      }
+    }
+    pad_slots(L, clen, cpad, tid);
+    __syncthreads();
+    const int hl = home_off >= c0 && home_off + (he - hb) <= c0 + clen ? home_off - c0 : -1;
+    CandSegs cs;
+    cs.n = 1;
+    cs.base[0] = 0;
+    cs.pad[0] = cpad;
+    if (wrap)
+      build_home_any<true>(a, L, cs, c0 == 0, hl, hb, he, lane, wave);
+    else
+      build_home_any<false>(a, L, cs, c0 == 0, hl, hb, he, lane, wave);
+    __syncthreads();
+    hl_last = hl;
+  }
+  const int mx =
+      hl_last >= 0 ? finish_home<true>(a, L, hl_last, hb, he, tid, P.pre, P.pi, P.v0, P.v1, P.v2,
+                                       P.pid)
+                   : finish_home<false>(a, L, hl_last, hb, he, tid, P.pre, P.pi, P.v0, P.v1,
+                                        P.v2, P.pid);
+  __syncthreads();   // LDS (candidates, hcnt) free for the next cell
+  return mx;
+}
+
+// Running maximum and overflow flag: one device-scope atomic per workgroup at
+// most, skipped when the word already holds at least m (a stale read only
+// costs an extra atomic).
+__device__ inline void report_max(const BuildArgs& a, int mx, int* red) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   mx = wave_max(mx);
   if (lane == 0) red[wave] = mx;
   __syncthreads();
-  if (tid == 0) {
+  if (threadIdx.x == 0) {
     int m = red[0];
     for (int w = 1; w < kBlock / kWave; ++w) m = max(m, red[w]);
-    // one device-scope atomic per workgroup at most: skipped when the word
-    // already holds at least m (a stale read only costs an extra atomic)
     if (m > 0 && m > __hip_atomic_load(&a.status[MD_ST_MAXNEIGH], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT))
       atomicMax(&a.status[MD_ST_MAXNEIGH], m);
     if (m > a.cap) atomicOr(&a.status[MD_ST_ERRORS], 1);
   }
+}
+
+// One workgroup per cell (general path).
+__global__ __launch_bounds__(kBlock) void k_build(BuildArgs a) {
+  if (a.gate && *a.gate == 0) return;
+  __shared__ double cxs[kBuildChunk], cys[kBuildChunk], czs[kBuildChunk];
+  __shared__ int cjs[kBuildChunk];
+  __shared__ int hcnt[kBlock];
+  __shared__ int lbuf[(kBlock / kWave) * kListRow];
+  __shared__ int st_start[27], st_off[28], st_meta[2];
+  __shared__ int red[kBlock / kWave];
+  const BuildLds L{cxs, cys, czs, cjs, hcnt, lbuf};
+  const int cell = xcd_block();
+  if (cell == 0 && threadIdx.x == 0) atomicAdd(&a.status[MD_ST_BUILDS], 1);
+  const int mx = build_cell(a, L, cell, st_start, st_off, st_meta);
+  report_max(a, mx, red);
+}
+
+// Slab u of a row segment: the (up to 9) cells (wy, wz) around the row at one
+// x index, their atoms contiguous in the slab in increasing cell order.  Slab
+// tables hold each cell's first slot (ts) and its offset in the slab (to, with
+// to[ncs] the slab's length).
+struct SlabRegs {
+  double x[kSlabRounds], y[kSlabRounds], z[kSlabRounds];
+  int j[kSlabRounds];
+};
+
+__device__ inline void slab_load(const BuildArgs& a, const int* ts, const int* to, int ncs,
+                                 int tid, SlabRegs& R) {
+  const int len = to[ncs];
+#pragma unroll
+  for (int r = 0; r < kSlabRounds; ++r) {
+    const int q = tid + r * kBlock;
+    R.j[r] = -1;
+    if (q < len) {
+      int e = 0;
+      for (int k = 1; k < ncs; ++k) e += q >= to[k] ? 1 : 0;
+      R.j[r] = ts[e] + (q - to[e]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kSlabRounds; ++r) {
+    if (R.j[r] >= 0) {
+      R.x[r] = a.x[R.j[r]];
+      R.y[r] = a.x[a.n + R.j[r]];
+      R.z[r] = a.x[2 * a.n + R.j[r]];
+    }
+  }
+}
+
+__device__ inline void slab_store(const BuildLds& L, int base, int len, int tid,
+                                  const SlabRegs& R) {
+#pragma unroll
+  for (int r = 0; r < kSlabRounds; ++r) {
+    const int q = tid + r * kBlock;
+    if (R.j[r] >= 0) {
+      L.cjs[base + q] = R.j[r];
+      L.cxs[base + q] = R.x[r];
+      L.cys[base + q] = R.y[r];
+      L.czs[base + q] = R.z[r];
+    }
+  }
+  pad_slots(L, base + len, base + ((len + kWave - 1) & ~(kWave - 1)), tid);
+}
+
+// Rank of c among the distinct cells {c - 1, c, c + 1} in increasing order
+// (see nbr_sorted).
+__device__ inline int self_rank(int c, int nc) {
+  if (nc < 3) return c;
+  return c == 0 ? 0 : (c == nc - 1 ? 2 : 1);
+}
+
+// Sorted atoms, at least 3 cells along x: one workgroup per run of up to
+// kRowCells consecutive cells of an x row.  Moving one cell along x drops one
+// slab of 9 cells from the 27-cell stencil and adds one, so the workgroup
+// keeps three slab slots in LDS and loads the next slab into registers while
+// the current cell's lists are built.  A home cell's candidates are the three
+// slots (each padded to a multiple of 64), its home atoms the middle slab's
+// home cell.  Runs with a slab over kSlabCap atoms take the per-cell path.
+constexpr int kRowCells = 4;
+constexpr int kMaxSlabs = kRowCells + 2;
+
+__global__ __launch_bounds__(kBlock) void k_build_rows(BuildArgs a) {
+  if (a.gate && *a.gate == 0) return;
+  __shared__ double cxs[kBuildChunk], cys[kBuildChunk], czs[kBuildChunk];
+  __shared__ int cjs[kBuildChunk];
+  __shared__ int hcnt[kBlock];
+  __shared__ int lbuf[(kBlock / kWave) * kListRow];
+  __shared__ int t_start[kMaxSlabs * 9], t_off[kMaxSlabs * 10];
+  __shared__ int st_start[27], st_off[28], st_meta[2];
+  __shared__ int red[kBlock / kWave];
+  __shared__ int big;
+  const BuildLds L{cxs, cys, czs, cjs, hcnt, lbuf};
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wave = tid / kWave;
+  const int nc0 = a.nc[0], nc1 = a.nc[1], nc2 = a.nc[2];
+  const int spr = (nc0 + kRowCells - 1) / kRowCells;   // row segments per row
+  const int wg = xcd_block();
+  const int row = wg / spr, seg = wg % spr;
+  const int cy = row % nc1, cz = row / nc1;
+  const int cx0 = seg * kRowCells;
+  const int nh = min(kRowCells, nc0 - cx0);
+  const int nslab = nh + 2;
+  const int ny = min(nc1, 3), nz = min(nc2, 3), ncs = ny * nz;
+  if (wg == 0 && tid == 0) atomicAdd(&a.status[MD_ST_BUILDS], 1);
+  if (wave == 0) {
+    // slab u = lane / ncs (x index cx0 - 1 + u), cell e = lane % ncs of it
+    const int u = lane / ncs, e = lane % ncs;
+    const bool ok = lane < nslab * ncs;
+    int b = 0, cnt = 0;
+    if (ok) {
+      int sx = cx0 - 1 + u;
+      sx = sx < 0 ? sx + nc0 : (sx >= nc0 ? sx - nc0 : sx);
+      const int c = (nbr_sorted(cz, nc2, e / ny) * nc1 + nbr_sorted(cy, nc1, e % ny)) * nc0 + sx;
+      b = a.cell_start[c];
+      cnt = a.cell_start[c + 1] - b;
+    }
+    int inc = cnt;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const int y = __shfl_up(inc, off, kWave);
+      if (lane >= off) inc += y;
+    }
+    const int first = u * ncs;
+    const int before = __shfl(inc, first > 0 ? first - 1 : 0, kWave);
+    const int sbase = first > 0 ? before : 0;
+    const bool last = ok && e == ncs - 1;
+    if (ok) {
+      t_start[u * 9 + e] = b;
+      t_off[u * 10 + e] = inc - cnt - sbase;
+      if (last) t_off[u * 10 + ncs] = inc - sbase;
+    }
+    const unsigned long long over = __ballot(last && inc - sbase > kSlabCap);
+    if (lane == 0) big = over != 0ull;
+  }
+  __syncthreads();
+  int mx = 0;
+  if (big) {
+    for (int k = 0; k < nh; ++k)
+      mx = max(mx, build_cell(a, L, (cz * nc1 + cy) * nc0 + cx0 + k, st_start, st_off, st_meta));
+  } else {
+    const int eh = self_rank(cz, nc2) * ny + self_rank(cy, nc1);   // home cell within a slab
+    {
+      SlabRegs R0, R1, R2;
+      slab_load(a, &t_start[0], &t_off[0], ncs, tid, R0);
+      slab_load(a, &t_start[9], &t_off[10], ncs, tid, R1);
+      slab_load(a, &t_start[18], &t_off[20], ncs, tid, R2);
+      slab_store(L, 0, t_off[ncs], tid, R0);
+      slab_store(L, kSlabCap, t_off[10 + ncs], tid, R1);
+      slab_store(L, 2 * kSlabCap, t_off[20 + ncs], tid, R2);
+    }
+    __syncthreads();
+    for (int k = 0; k < nh; ++k) {
+      const int cell = (cz * nc1 + cy) * nc0 + cx0 + k;
+      const int* to = &t_off[(k + 1) * 10];
+      const int hb = t_start[(k + 1) * 9 + eh];
+      const int he = hb + (to[eh + 1] - to[eh]);
+      const int hl = ((k + 1) % 3) * kSlabCap + to[eh];
+      HomePrefetch P;
+      P.load(a, hb, he, tid);
+      SlabRegs N;
+      const bool more = k + 3 < nslab;
+      if (more) slab_load(a, &t_start[(k + 3) * 9], &t_off[(k + 3) * 10], ncs, tid, N);
+      CandSegs cs;
+      cs.n = 3;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const int len = t_off[(k + m) * 10 + ncs];
+        cs.base[m] = ((k + m) % 3) * kSlabCap;
+        cs.pad[m] = (len + kWave - 1) & ~(kWave - 1);
+      }
+      if (cell_wraps(cx0 + k, cy, cz, a.nc))
+        build_home<true, true, true>(a, L, cs, hl, hb, he, lane, wave);
+      else
+        build_home<false, true, true>(a, L, cs, hl, hb, he, lane, wave);
+      __syncthreads();
+      mx = max(mx, finish_home<true>(a, L, hl, hb, he, tid, P.pre, P.pi, P.v0, P.v1, P.v2, P.pid));
+      if (tid == 0 && a.cell_start_out) {
+        a.cell_start_out[cell] = hb;
+        if (cell == nc0 * nc1 * nc2 - 1) a.cell_start_out[cell + 1] = he;
+      }
+      if (more) slab_store(L, (k % 3) * kSlabCap, t_off[(k + 3) * 10 + ncs], tid, N);
+      __syncthreads();
+    }
+  }
+  report_max(a, mx, red);
 }
 
 inline unsigned blocks_for(int64_t n, int per = kBlock) { return (unsigned)((n + per - 1) / per); }
@@ -520,9 +1065,17 @@ hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t s) {
 }
 
 hipError_t launch_bin_count(double* x, int n, BoxK box, const int nc[3], int* atom_cell,
-                            int* count, int* scount, int* slot, const int* gate, hipStream_t s) {
+                            int* count, int* slot, hipStream_t s) {
   k_bin_count<<<blocks_for(n), kBlock, 0, s>>>(x, n, box, nc[0], nc[1], nc[2], atom_cell, count,
-                                                scount, slot, gate);
+                                                slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_count(const int* old_start, const int* atom_cell, const int nc[3],
+                             int* count, int* scount, const int* gate, hipStream_t s) {
+  const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+  k_cell_count<<<blocks_for(ncell, kSuperCells), kCountBlock, 0, s>>>(
+      old_start, atom_cell, nc[0], nc[1], nc[2], count, scount, gate);
   return hipGetLastError();
 }
 
@@ -542,14 +1095,14 @@ hipError_t launch_cell_sort(const int* tmp_perm, const int* cell_start, int ncel
 }
 
 hipError_t launch_gather_sort(const int* old_start, int* new_start, const int* count,
-                              const int* scount, const int* atom_cell, const int nc[3],
+                              const int* scount, const int* atom_cell, const int nc[3], BoxK box,
                               int* perm, const double* x, const double* v, const int* id, int n,
                               double* sx, double* sv, int* sid, int* status, const int* gate,
                               hipStream_t s) {
   const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
   k_gather_sort<<<blocks_for(ncell * kWave), kBlock, 0, s>>>(
-      old_start, new_start, count, scount, atom_cell, nc[0], nc[1], nc[2], perm, x, v, id, n, sx,
-      sv, sid, status, gate);
+      old_start, new_start, count, scount, atom_cell, nc[0], nc[1], nc[2], box, perm, x, v, id, n,
+      sx, sv, sid, status, gate);
   return hipGetLastError();
 }
 
@@ -577,8 +1130,13 @@ hipError_t launch_gather_int(const int* perm, int n, const int* src, int* dst, h
 }
 
 hipError_t launch_build(const BuildArgs& a, hipStream_t s) {
-  const unsigned ncell = (unsigned)(a.nc[0] * a.nc[1] * a.nc[2]);
-  k_build<<<ncell, kBlock, 0, s>>>(a);
+  if (a.sorted && a.nc[0] >= 3) {
+    const unsigned segs = (unsigned)((a.nc[0] + kRowCells - 1) / kRowCells * a.nc[1] * a.nc[2]);
+    k_build_rows<<<segs, kBlock, 0, s>>>(a);
+  } else {
+    const unsigned ncell = (unsigned)(a.nc[0] * a.nc[1] * a.nc[2]);
+    k_build<<<ncell, kBlock, 0, s>>>(a);
+  }
   return hipGetLastError();
 }
 

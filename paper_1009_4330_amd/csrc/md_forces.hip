@@ -22,7 +22,7 @@ namespace {
 constexpr int kUnroll = 4;   // neighbour entries whose loads are issued together
 
 struct FK {
-  const double* __restrict__ x;
+  const double* __restrict__ xq;   // packed positions, atom i at xq[4 i]
   int n;
   BoxK box;
   double margin;          // interior test: every coordinate in [margin, L - margin)
@@ -35,16 +35,28 @@ struct FK {
   int* clear;
 };
 
-// Raw buffer view of an array of doubles: 32-bit byte offsets, one offset
-// register shared by the x, y and z rows (scalar row offsets), and hardware
-// range checking (reads past num_records return 0).
+// Raw buffer view of the packed positions: 32-bit byte offsets (record j at
+// 32 j) and hardware range checking (reads past num_records return 0).
 constexpr int kBufWord3 = 0x00020000;   // gfx9-family raw buffer, 32-bit data format
-__device__ inline __amdgpu_buffer_rsrc_t buffer_of(const double* p, int count) {
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+__device__ inline __amdgpu_buffer_rsrc_t buffer_of(const double* p, int n_records) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), (short)0,
-                                           count * (int)sizeof(double), kBufWord3);
+                                           (int)((unsigned)n_records * 32u), kBufWord3);
 }
-__device__ inline double load_f64(__amdgpu_buffer_rsrc_t r, int byte_off, int row_off) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, row_off, 0));
+// x and y of a record (one 16-byte load), z (8 bytes at +16).
+__device__ inline f64x2 load_xy(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+  return __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)byte_off, 0, 0));
+}
+__device__ inline double load_z(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+  return __builtin_bit_cast(double,
+                            __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 16, 0));
+}
+// Home atom position (plain loads).
+__device__ inline void home_pos(const FK& a, int i, double& x, double& y, double& z) {
+  const double2 q = *reinterpret_cast<const double2*>(a.xq + 4 * (size_t)i);
+  x = q.x;
+  y = q.y;
+  z = a.xq[4 * (size_t)i + 2];
 }
 
 // An atom is "interior" when every coordinate lies in [margin, L - margin),
@@ -115,8 +127,7 @@ struct Batch {
 };
 
 struct XView {
-  __amdgpu_buffer_rsrc_t r;   // the [3][n] position array
-  int row;                    // n * 8 bytes: offset of the y row (z at 2 * row)
+  __amdgpu_buffer_rsrc_t r;   // the packed [n][4] positions
 };
 
 template <int K, bool WRAP>
@@ -130,10 +141,11 @@ __device__ inline void load_batch(const FK& a, const XView& xv, const Lane<K>& l
   double xj[kUnroll], yj[kUnroll], zj[kUnroll];
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) {
-    const int off = b.j[u] * (int)sizeof(double);
-    xj[u] = load_f64(xv.r, off, 0);
-    yj[u] = load_f64(xv.r, off, xv.row);
-    zj[u] = load_f64(xv.r, off, 2 * xv.row);
+    const unsigned off = (unsigned)b.j[u] * 32u;
+    const f64x2 xy = load_xy(xv.r, off);
+    xj[u] = xy.x;
+    yj[u] = xy.y;
+    zj[u] = load_z(xv.r, off);
   }
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) {
@@ -150,9 +162,7 @@ __device__ inline void load_batch(const FK& a, const XView& xv, const Lane<K>& l
   }
 }
 
-__device__ inline XView xview(const FK& a) {
-  return XView{buffer_of(a.x, 3 * a.n), a.n * (int)sizeof(double)};
-}
+__device__ inline XView xview(const FK& a) { return XView{buffer_of(a.xq, a.n)}; }
 
 // Runs body(batch) over this lane's list entries.  The choice between the
 // plain and the minimum-image separation is uniform over the wavefront.
@@ -252,7 +262,8 @@ __global__ __launch_bounds__(kBlock) void k_lj(FK a, LJK p) {
   const Lane<K> ln(a);
   const int n = a.n;
   const int io = ln.live ? ln.i : n - 1;
-  const double xi = a.x[io], yi = a.x[n + io], zi = a.x[2 * n + io];
+  double xi, yi, zi;
+  home_pos(a, io, xi, yi, zi);
   Acc acc;
   for_each_batch<K>(a, ln, xi, yi, zi, [&](const Batch& b) {
 #pragma unroll
@@ -290,7 +301,8 @@ __global__ __launch_bounds__(kBlock) void k_sc_density(FK a, SCK p, double* __re
   const Lane<K> ln(a);
   const int n = a.n;
   const int io = ln.live ? ln.i : n - 1;
-  const double xi = a.x[io], yi = a.x[n + io], zi = a.x[2 * n + io];
+  double xi, yi, zi;
+  home_pos(a, io, xi, yi, zi);
   double rho = 0.0;
   for_each_batch<K>(a, ln, xi, yi, zi, [&](const Batch& b) {
 #pragma unroll
@@ -317,7 +329,8 @@ __global__ __launch_bounds__(kBlock) void k_sc_force(FK a, SCK p,
   const Lane<K> ln(a);
   const int n = a.n;
   const int io = ln.live ? ln.i : n - 1;
-  const double xi = a.x[io], yi = a.x[n + io], zi = a.x[2 * n + io];
+  double xi, yi, zi;
+  home_pos(a, io, xi, yi, zi);
   const double ei = e_in[io];
   Acc acc;
   for_each_batch<K>(a, ln, xi, yi, zi, [&](const Batch& b) {
@@ -372,7 +385,8 @@ __global__ __launch_bounds__(kBlock) void k_lj_vjp(FK a, LJK p, const double* __
   const Lane<K> ln(a);
   const int n = a.n;
   const int io = ln.live ? ln.i : n - 1;
-  const double xi = a.x[io], yi = a.x[n + io], zi = a.x[2 * n + io];
+  double xi, yi, zi;
+  home_pos(a, io, xi, yi, zi);
   const double uxi = u[io], uyi = u[n + io], uzi = u[2 * n + io];
   double gxa = 0, gya = 0, gza = 0, fx = 0, fy = 0, fz = 0, dsig = 0;
   for_each_batch<K>(a, ln, xi, yi, zi, [&](const Batch& b) {
@@ -437,7 +451,7 @@ __global__ __launch_bounds__(kBlock) void k_lj_vjp(FK a, LJK p, const double* __
 
 FK make_fk(const ForceArgs& a) {
   FK k;
-  k.x = a.x;
+  k.xq = a.xq;
   k.n = a.n;
   k.box = a.box;
   k.margin = a.margin;
@@ -459,6 +473,12 @@ hipError_t launch_timed(void (*kern)(KArgs...), unsigned grid, hipStream_t s, hi
   else
     kern<<<grid, kBlock, 0, s>>>(args...);
   return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_pack_positions(const double* __restrict__ x, int n,
+                                                            double* __restrict__ xq) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) store_packed(xq, i, x[i], x[n + i], x[2 * n + i]);
 }
 
 // Workgroups covering n atoms with K lanes each.
@@ -483,6 +503,11 @@ hipError_t with_lanes(int k, F&& f) {
 }
 
 }  // namespace
+
+hipError_t launch_pack_positions(const double* x, int n, double* xq, hipStream_t s) {
+  k_pack_positions<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(x, n, xq);
+  return hipGetLastError();
+}
 
 hipError_t launch_lj(const ForceArgs& a, const LJK& p, int prec, int lanes, hipStream_t s) {
   const FK k = make_fk(a);

@@ -44,13 +44,52 @@ __device__ inline int xcd_block() {
   const int xcd = b % kXcds, local = b / kXcds;
   return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
 }
-constexpr int kSuperShift = 6;       // 64 cells per super-cell for the two-level cell scan
+constexpr int kSuperShift = 4;       // 16 cells per super-cell for the two-level cell scan
+constexpr int kSuperCells = 1 << kSuperShift;
 
 // Periodic box as kernels see it: edges and their reciprocals (the reciprocal
 // only picks the image index; the image shift itself is d - L * k).
 struct BoxK {
   double L[3];
   double inv[3];
+};
+
+// Wrap one coordinate into [0, L): x - L floor(x / L), an exact L mapped to 0.
+__device__ inline double wrap_coord(double x, double L) {
+  double r = x - L * floor(x / L);
+  if (r < 0.0) r += L;
+  if (r >= L) r = 0.0;
+  return r;
+}
+
+// Cell coordinate floor(r nc / L) of a wrapped coordinate, clamped to [0, nc).
+__device__ inline int cell_coord(double r, int nc, double L) {
+  int c = (int)((r * (double)nc) / L);
+  return c < 0 ? 0 : (c > nc - 1 ? nc - 1 : c);
+}
+
+// Cell of the wrapped image of (x, y, z), x fastest.
+__device__ inline int cell_of(double x, double y, double z, const BoxK& box, const int* nc) {
+  return cell_coord(wrap_coord(x, box.L[0]), nc[0], box.L[0]) +
+         nc[0] * (cell_coord(wrap_coord(y, box.L[1]), nc[1], box.L[1]) +
+                  nc[1] * cell_coord(wrap_coord(z, box.L[2]), nc[2], box.L[2]));
+}
+
+// Where the integrator records each atom's cell after the drift (the cell of
+// its wrapped image), for the gated rebuild; atom_cell == null skips it.
+// Packed position record of atom i: (x, y, z, 0) at xq[4 i], 32-byte aligned.
+__device__ inline void store_packed(double* xq, int i, double x, double y, double z) {
+  double2* q = reinterpret_cast<double2*>(xq + 4 * (size_t)i);
+  q[0] = make_double2(x, y);
+  q[1] = make_double2(z, 0.0);
+}
+
+// The integrator also refreshes the packed positions the force kernels read.
+struct BinOut {
+  BoxK box;
+  int nc[3];
+  int* atom_cell;
+  double* xq;   // nullable: packed [n][4] copy of x
 };
 
 // Lennard-Jones constants in both precisions.
@@ -88,8 +127,9 @@ struct WsLayout {
   size_t sc_e;       // double [n]        Sutton-Chen rho^-1/2
   size_t partials;   // double [kReduceBlocks][kReduceCols]
   size_t scalars;    // double [16]       reduced values
-  size_t scount;     // int [ncell/64+1]  per-super-cell counters
+  size_t scount;     // int [ncell/16+1]  per-super-cell counts
   size_t new_start;  // int [ncell + 1]   cell starts of a rebuild in progress
+  size_t xq;         // double [n][4]     packed positions (x, y, z, 0) for the force gathers
   size_t total;
 };
 
@@ -99,13 +139,12 @@ WsLayout ws_layout(int64_t n, int64_t ncell);
 // Every launcher enqueues on `s` and returns hipGetLastError().
 
 // Binning.  `gate` (nullable) makes the kernels return at once when *gate == 0.
-// launch_bin_count wraps, bins and adds to the per-cell and per-super-cell
-// counters (zero on entry; the list build clears them again); with slot it
-// also records each atom's arrival slot.  launch_scan_cells turns the counts
-// into cell_start.
+// launch_bin_count wraps x in place, bins and adds to the per-cell counters
+// (zero on entry) and records each atom's arrival slot in its cell.
+// launch_scan_cells turns the counts into cell_start.
 hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t s);
 hipError_t launch_bin_count(double* x, int n, BoxK box, const int nc[3], int* atom_cell,
-                            int* count, int* scount, int* slot, const int* gate, hipStream_t s);
+                            int* count, int* slot, hipStream_t s);
 hipError_t launch_scan_cells(const int* count, int ncell, int* cell_start, hipStream_t s);
 hipError_t launch_scatter(const int* atom_cell, const int* slot, const int* cell_start, int n,
                           int* tmp_perm, const int* gate, hipStream_t s);
@@ -116,11 +155,16 @@ hipError_t launch_cell_sort(const int* tmp_perm, const int* cell_start, int ncel
                             int n, double* sx, double* sv, int* sid, double* sf,
                             const int* gate, hipStream_t s);
 // Rebuild-time sort for atoms already in the previous build's cell order that
-// moved less than a cell edge: gathers the state into staging in the stable
-// order, writes the new cell starts, and sets status bit 2 if some atom moved
-// further.
+// moved less than a cell edge, with atom_cell holding their new cells:
+// launch_cell_count counts each new cell's members among the old ranges of
+// its 27 neighbours (plain stores into count, and per-super-cell sums into
+// scount); launch_gather_sort gathers the state (x wrapped) into staging in
+// the stable order and writes the new cell starts.  Status bit 2 is set if
+// the counts do not add up to n (some atom moved further).
+hipError_t launch_cell_count(const int* old_start, const int* atom_cell, const int nc[3],
+                             int* count, int* scount, const int* gate, hipStream_t s);
 hipError_t launch_gather_sort(const int* old_start, int* new_start, const int* count,
-                              const int* scount, const int* atom_cell, const int nc[3],
+                              const int* scount, const int* atom_cell, const int nc[3], BoxK box,
                               int* perm, const double* x, const double* v, const int* id, int n,
                               double* sx, double* sv, int* sid, int* status, const int* gate,
                               hipStream_t s);
@@ -145,8 +189,6 @@ struct BuildArgs {
   int nc[3];
   const int* cell_start;
   int* cell_start_out;   // nullable: receives a copy of cell_start
-  int* count_clear;      // nullable: per-cell counters to zero
-  int* scount_clear;     // nullable: per-super-cell counters to zero
   const int* atom_cell;  // cell of each atom, input order
   const int* perm;
   double rl2;
@@ -155,6 +197,7 @@ struct BuildArgs {
   int* numneigh;
   double* x_ref;
   int* status;
+  double* xq_out;        // nullable: packed [n][4] copy of the home atoms' positions
   // md_step extras
   double* x_out;
   double* v_out;
@@ -167,8 +210,10 @@ hipError_t launch_build(const BuildArgs& a, hipStream_t s);
 
 // Forces.  kernel: MD_KERNEL_TPA / MD_KERNEL_WPA.  clear (nullable) is zeroed
 // by the first thread, after every rebuild kernel of the step has finished.
+// Positions come packed: atom i at xq[4 i .. 4 i + 2], xq[4 i + 3] = 0, so one
+// neighbour is one aligned 32-byte record (two loads, one cache line).
 struct ForceArgs {
-  const double* x;
+  const double* xq;
   int n;
   BoxK box;
   double margin;         // interior margin r_l + skin = 2 r_l - r_c (+inf: always wrap)
@@ -180,6 +225,7 @@ struct ForceArgs {
   int* clear;
   hipEvent_t t0, t1;     // non-null: timed launch
 };
+hipError_t launch_pack_positions(const double* x, int n, double* xq, hipStream_t s);
 hipError_t launch_lj(const ForceArgs& a, const LJK& p, int prec, int kernel, hipStream_t s);
 hipError_t launch_sc(const ForceArgs& a, const SCK& p, int prec, int kernel, double* sc_e,
                      hipStream_t s);
@@ -189,7 +235,7 @@ hipError_t launch_lj_vjp(const ForceArgs& a, const LJK& p, int prec, int kernel,
 // Integration.
 hipError_t launch_kick_drift_check(double* x, double* v, const double* f, const double* xr,
                                    int n, double dtfm, double dt, double trig2, int* status,
-                                   hipStream_t s);
+                                   const BinOut& bin, hipStream_t s);
 hipError_t launch_kick(double* v, const double* f, int n, double dtfm, double* keatom,
                        int* status, hipStream_t s);
 hipError_t launch_ke(const double* v, int n, double* keatom, hipStream_t s);
@@ -197,7 +243,7 @@ hipError_t launch_ke(const double* v, int n, double* keatom, hipStream_t s);
 // with this step's kick, drift and displacement check.
 hipError_t launch_vv_step(double* x, double* v, const double* f, const double* xr, int n,
                           double dtfm, double dt, double trig2, double* keatom, int* status,
-                          hipStream_t s);
+                          const BinOut& bin, hipStream_t s);
 
 // Deterministic sums: cols arrays of n doubles (col c at base[c] ) -> out[cols].
 struct SumArgs {

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmd_mi355
 MD_OK, MD_ERR_INVALID_ARG, MD_ERR_BOX_TOO_SMALL, MD_ERR_NLIST_OVERFLOW = 0, 1, 2, 3
 MD_ERR_NONFINITE, MD_ERR_UNSUPPORTED, MD_ERR_HIP, MD_ERR_WORKSPACE = 4, 5, 6, 7
 MD_ERR_UNSTABLE = 8
+MD_MAX_ATOMS = 134217727          # md.h: largest atom count
 MD_FP64, MD_MIXED = 0, 1
 MD_KERNEL_AUTO, MD_KERNEL_TPA, MD_KERNEL_WPA = 0, 1, 64
 LANES = (1, 2, 4, 8, 16, 32, 64)

@@ -58,6 +58,10 @@ def test_workspace_and_rows_host_logic(mdlib):
     assert b > 4000 * (8 * 3 * 3 + 8 * 9) and b % 256 == 0
     assert lib.md_workspace_bytes(4000, ctypes.byref(mdlib.make_box((5.0, 16.8, 16.8))), 2.8) == 0
     assert lib.md_workspace_bytes(0, ctypes.byref(box), 2.8) == 0
+    # atom-count limit (32-byte position records addressed with 32-bit offsets)
+    big = mdlib.make_box((400.0, 400.0, 400.0))
+    assert lib.md_workspace_bytes(mdlib.MD_MAX_ATOMS, ctypes.byref(big), 2.8) > 0
+    assert lib.md_workspace_bytes(mdlib.MD_MAX_ATOMS + 1, ctypes.byref(big), 2.8) == 0
     # the neighbour buffer fits every lanes-per-atom layout K (see md.h)
     for n, cap in ((4000, 100), (1, 1), (100, 7), (256000, 130)):
         want = max(-(-n // (64 // k)) * -(-cap // k) * 64 for k in mdlib.LANES)

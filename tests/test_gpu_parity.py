@@ -6,6 +6,8 @@ all components, the FP64 summation order being the only difference); MIXED
 (FP32 pair function, FP64 separation, cutoff test and accumulation) within
 1e-6 relative RMS of the FP64 oracle.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -15,6 +17,7 @@ from gpu_helpers import (SC_KW, dev, forces_gpu, gpu_bin, gpu_list, gpu_pairs, l
                          sc_solid)
 from paper_1009_4330_amd import inputs as I
 from paper_1009_4330_amd import md
+from paper_1009_4330_amd.system import MDSystem
 
 pytestmark = pytest.mark.gpu
 
@@ -87,6 +90,40 @@ def test_neighbor_pairs_bit_exact(orc, case, layout, kernel):
     assert np.array_equal(nl.numneigh.cpu().numpy(), ref.numneigh)
     assert np.array_equal(nl.x_ref.cpu().numpy(), ocells.x)
     words = md.md_nlist_status(nl)
+    assert words[md.MD_ST_ERRORS] == 0 and words[md.MD_ST_MAXNEIGH] == ref.max_count
+
+
+@pytest.mark.parametrize("case", ["liquid4k_nc5", "jitter864_nc3", "liquid4k_rc5"])
+def test_step_setup_list_bit_exact(orc, case):
+    """md_step's own build (atoms sorted into cell order, lists built along x
+    rows of cells; the rc = 5 case has slabs too large for that path and takes
+    the per-cell one) against the oracle's list on the oracle's own wrapped,
+    cell-sorted positions."""
+    rc = 2.5
+    if case == "liquid4k_nc5":
+        x_np, v_np, box, w = lj_liquid(orc, 10, 21)
+    elif case == "jitter864_nc3":
+        x_np, box = jittered_lj(6, 22)
+        w = I.scaled(I.LJ_4K, 6)
+        v_np = I.random_unit_vectors(x_np.shape[1], 23)
+    else:
+        rc = 5.0
+        x_np, v_np, box, w = lj_liquid(orc, 10, 24)
+        w = dataclasses.replace(w, rc=rc)
+    s = MDSystem(w, x_np, v_np, "fp64", "k4", capacity=700 if rc > 3 else 160)
+    s.setup(thermo=False)
+    rl = rc + w.skin
+    oc = orc.bin_cells(x_np, box, rl)
+    xs = np.ascontiguousarray(oc.x[:, oc.perm])          # oracle's wrapped, sorted positions
+    ref, _ = orc.build_nlist(xs, box, rl)
+    assert np.array_equal(s.state.id.cpu().numpy(), oc.perm)
+    assert np.array_equal(s.state.x.cpu().numpy(), xs)
+    assert np.array_equal(s.nl.x_ref.cpu().numpy(), xs)
+    assert np.array_equal(s.cells.cell_start.cpu().numpy()[: len(oc.cell_start)],
+                          oc.cell_start)
+    assert np.array_equal(gpu_pairs(s.nl), ref.pairs())
+    assert np.array_equal(s.nl.numneigh.cpu().numpy(), ref.numneigh)
+    words = md.md_nlist_status(s.nl)
     assert words[md.MD_ST_ERRORS] == 0 and words[md.MD_ST_MAXNEIGH] == ref.max_count
 
 

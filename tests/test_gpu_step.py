@@ -126,6 +126,25 @@ def test_step_reports_overflow_and_nonfinite():
     assert ei.value.code == md.MD_ERR_NONFINITE
 
 
+def test_step_reports_atom_jumping_cells():
+    """An atom that crosses more than a cell edge between two builds is outside
+    every old range its new cell gathers from: the counts fall short of n and
+    md_step reports MD_ERR_UNSTABLE."""
+    w = I.scaled(I.LJ_4K, 10, steps=1)
+    x, v, box = I.initial_state(w)
+    rl = w.rc + w.skin
+    edge = box[0] / np.floor(box[0] / rl)
+    assert np.floor(box[0] / rl) >= 5          # a jump of 2 or 3 cells leaves the stencil
+    vb = v.copy()
+    vb[0, 0] = 2.5 * edge / w.dt              # 2.5 cell edges in one step
+    s = MDSystem(w, x, vb, "fp64", "tpa", capacity=200)
+    with pytest.raises(md.MDError) as ei:
+        md.md_step(s.state, s.pot, s.box, s.cells, s.nl, s.prec, s.kernel, w.skin, w.dt, 1, 1, 1,
+                   None, s.ws)
+    assert ei.value.code == md.MD_ERR_UNSTABLE
+    assert md.md_nlist_status(s.nl)[md.MD_ST_ERRORS] & 4
+
+
 def test_momentum_conserved_mixed():
     w = I.scaled(I.LJ_4K, 10, steps=200)
     x, v, box = I.initial_state(w)
