@@ -84,6 +84,7 @@ enum {
   MD_ST_MAXNEIGH = 1,  /* largest neighbour count of the last build (the required capacity) */
   MD_ST_BUILDS = 2,    /* number of list builds so far (md_step increments it) */
   MD_ST_REBUILD = 3,   /* internal: rebuild requested by the displacement check */
+  MD_ST_REBUILD2 = 4,  /* internal: the same for alternate steps of md_step */
   MD_STATUS_WORDS = 8
 };
 

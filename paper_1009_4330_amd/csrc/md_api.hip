@@ -324,6 +324,7 @@ WsLayout ws_layout(int64_t n, int64_t ncell) {
   L.scount = take(sizeof(int) * (size_t)(((ncell > 0 ? ncell : 1) >> kSuperShift) + 1));
   L.new_start = take(sizeof(int) * (size_t)((ncell > 0 ? ncell : 1) + 1));
   L.xq = take(sizeof(double) * 4 * nn);
+  L.xq2 = take(sizeof(double) * 4 * nn);
   L.total = o;
   return L;
 }
@@ -596,7 +597,12 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
   const double trig = 0.5 * skin;
   const double trig2 = trig * trig;
   int* status = nl->status;
-  int* gate = status + MD_ST_REBUILD;
+  // Rebuild requests alternate between two words: the drift of step t sets
+  // gates[t & 1], the rebuild before step t's forces is gated by it, and the
+  // force kernel of step t clears it while its own drift sets the other word,
+  // so no kernel clears a word that it also sets.
+  int* const gates[2] = {status + MD_ST_REBUILD2, status + MD_ST_REBUILD};
+  int* gate = gates[1];
   int* count = at<int>(ws, L.count);
   int* slot = at<int>(ws, L.slot);
   int* tmp_perm = at<int>(ws, L.tmp_perm);
@@ -611,7 +617,9 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
   int* scount = at<int>(ws, L.scount);
 
   int* new_start = at<int>(ws, L.new_start);
-  double* xq = at<double>(ws, L.xq);
+  // packed positions: the setup build and the force kernels read xq[0]
+  // first; each fused step reads one buffer and drifts into the other
+  double* const xqs[2] = {at<double>(ws, L.xq), at<double>(ws, L.xq2)};
 
   // Rebuild chain.  At setup (no gate; atoms in arbitrary order): wrap + bin +
   // count, scan, scatter, stable in-cell order with the state gathered into
@@ -621,13 +629,13 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
   // the new cell starts, list build, which also copies the new starts into
   // cells->cell_start.  Gated kernels return at once unless the rebuild flag
   // is set.
-  auto rebuild = [&](const int* g, int layout) -> md_status {
+  auto rebuild = [&](const int* g, int layout, double* xq) -> md_status {
     int* starts = g ? new_start : cells->cell_start;
     if (g) {
       MD_CK(launch_cell_count(cells->cell_start, cells->atom_cell, nc, count, scount, g, s));
       MD_CK(launch_gather_sort(cells->cell_start, new_start, count, scount, cells->atom_cell, nc,
-                               bk, cells->perm, stt->x, stt->v, stt->id, n, sx, sv, sid, status,
-                               g, s));
+                               bk, cells->perm, xq, stt->v, stt->id, n, sx, sv, sid, status, g,
+                               s));
     } else {
       MD_CK(launch_fill_int(count, ncell, 0, s));
       MD_CK(launch_bin_count(stt->x, n, bk, nc, cells->atom_cell, count, slot, s));
@@ -664,9 +672,11 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
     return MD_OK;
   };
 
-  auto forces = [&](bool ev, int kernel) -> md_status {
+  // Forces at the positions in xq; with `in`, the kernel also integrates.
+  auto forces = [&](bool ev, int kernel, const double* xq, const IntArgs* in) -> md_status {
     ForceArgs fa{};
     fa.xq = xq;
+    if (in) fa.in = *in;
     fa.n = n;
     fa.box = bk;
     fa.margin = interior_margin(p, rl);
@@ -713,7 +723,7 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
   int kernel = nl->layout;   // lanes per atom == list layout
   if (setup) {
     kernel = k == MD_KERNEL_AUTO ? MD_KERNEL_TPA : (int)k;
-    if ((st = rebuild(nullptr, kernel)) != MD_OK) return st;
+    if ((st = rebuild(nullptr, kernel, xqs[0])) != MD_OK) return st;
     for (int d = 0; d < 3; ++d) cells->nc[d] = nc[d];
     nl->layout = kernel;
     nl->rl = rl;
@@ -739,40 +749,52 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
       }
     }
     const bool ev = thermo != nullptr;
-    if ((st = forces(ev, kernel)) != MD_OK) return st;
+    if ((st = forces(ev, kernel, xqs[0], nullptr)) != MD_OK) return st;
     if (ev) {
       MD_CK(launch_ke(stt->v, n, keatom, s));
       if ((st = thermo_out(0.0)) != MD_OK) return st;
     }
   }
   const int layout = kernel;
-  BinOut bin{};
-  bin.box = bk;
-  for (int d = 0; d < 3; ++d) bin.nc[d] = nc[d];
-  bin.atom_cell = cells->atom_cell;
-  bin.xq = xq;
-  // Step s: [closing kick of s-1 +] kick + drift + check, gated rebuild,
-  // forces.  The closing kick of step s-1 is fused into step s's first kernel;
-  // the thermo row of step s-1 is summed right after it, before step s's
-  // forces overwrite the per-atom energies.  The last step's closing kick runs
-  // on its own at the end, so every call returns a full-step state.
   auto is_thermo = [&](int step) { return thermo && step >= 1 && step % thermo_every == 0; };
-  for (int step = 1; step <= nsteps; ++step) {
-    const bool th_prev = is_thermo(step - 1);
-    if (step == 1)
-      MD_CK(launch_kick_drift_check(stt->x, stt->v, stt->f, nl->x_ref, n, dtfm, dt, trig2,
-                                    status, bin, s));
-    else
-      MD_CK(launch_vv_step(stt->x, stt->v, stt->f, nl->x_ref, n, dtfm, dt, trig2,
-                           th_prev ? keatom : nullptr, status, bin, s));
-    if (th_prev && (st = thermo_out((double)(step - 1))) != MD_OK) return st;
-    if ((st = rebuild(gate, layout)) != MD_OK) return st;
-    if ((st = forces(is_thermo(step), kernel)) != MD_OK) return st;
-  }
+  // Step 1 opens with a kick and drift from the state (its forces current),
+  // into xq[1].  Then for s = 1 .. nsteps: gated rebuild of the positions in
+  // xq[s & 1], and one force kernel that also integrates -- closing kick of
+  // step s, then (s < nsteps) step s + 1's kick, drift into xq[(s + 1) & 1]
+  // and check, or (s = nsteps) the state's x and f.  The thermo row of step s
+  // is summed right after its force kernel.
   if (nsteps > 0) {
-    const bool th = is_thermo(nsteps);
-    MD_CK(launch_kick(stt->v, stt->f, n, dtfm, th ? keatom : nullptr, status, s));
-    if (th && (st = thermo_out((double)nsteps)) != MD_OK) return st;
+    BinOut bin{};
+    bin.box = bk;
+    for (int d = 0; d < 3; ++d) bin.nc[d] = nc[d];
+    bin.atom_cell = cells->atom_cell;
+    bin.xq = xqs[1];
+    bin.flag = gates[1];
+    MD_CK(launch_fill_int(gates[0], 1, 0, s));
+    MD_CK(launch_fill_int(gates[1], 1, 0, s));
+    MD_CK(launch_kick_drift_check(stt->x, stt->v, stt->f, nl->x_ref, n, dtfm, dt, trig2, status,
+                                  bin, s));
+    for (int step = 1; step <= nsteps; ++step) {
+      double* cur = xqs[step & 1];
+      gate = gates[step & 1];
+      if ((st = rebuild(gate, layout, cur)) != MD_OK) return st;
+      const bool th = is_thermo(step);
+      IntArgs in{};
+      in.mode = step < nsteps ? MD_INT_STEP : MD_INT_LAST;
+      in.v = stt->v;
+      in.xr = nl->x_ref;
+      in.x = stt->x;
+      in.keatom = th ? keatom : nullptr;
+      in.status = status;
+      in.dtfm = dtfm;
+      in.dt = dt;
+      in.trig2 = trig2;
+      in.bin = bin;
+      in.bin.xq = xqs[(step + 1) & 1];
+      in.bin.flag = gates[(step + 1) & 1];
+      if ((st = forces(th, kernel, cur, &in)) != MD_OK) return st;
+      if (th && (st = thermo_out((double)step)) != MD_OK) return st;
+    }
   }
   int words[MD_STATUS_WORDS];
   MD_CK(hipMemcpyAsync(words, status, sizeof(words), hipMemcpyDeviceToHost, s));

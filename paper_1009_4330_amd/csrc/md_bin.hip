@@ -295,17 +295,20 @@ __global__ __launch_bounds__(kCountBlock) void k_cell_count(
   }
 }
 
-// Gather member i into sorted slot p (x wrapped into the box).
-__device__ inline void put_member(int i, int p, int n, const BoxK& box, const double* __restrict__ x,
-                                  const double* __restrict__ v, const int* __restrict__ id,
-                                  int* __restrict__ perm, double* __restrict__ sx,
-                                  double* __restrict__ sv, int* __restrict__ sid) {
-  const double x0 = x[i], x1 = x[n + i], x2 = x[2 * n + i];
+// Gather member i into sorted slot p: its position from the packed records
+// (wrapped into the box), velocity and id from the state.
+__device__ inline void put_member(int i, int p, int n, const BoxK& box,
+                                  const double* __restrict__ xq, const double* __restrict__ v,
+                                  const int* __restrict__ id, int* __restrict__ perm,
+                                  double* __restrict__ sx, double* __restrict__ sv,
+                                  int* __restrict__ sid) {
+  const double2 q = *reinterpret_cast<const double2*>(xq + 4 * (size_t)i);
+  const double x2 = xq[4 * (size_t)i + 2];
   const double v0 = v[i], v1 = v[n + i], v2 = v[2 * n + i];
   const int idi = id[i];
   perm[p] = i;
-  sx[p] = wrap_coord(x0, box.L[0]);
-  sx[n + p] = wrap_coord(x1, box.L[1]);
+  sx[p] = wrap_coord(q.x, box.L[0]);
+  sx[n + p] = wrap_coord(q.y, box.L[1]);
   sx[2 * n + p] = wrap_coord(x2, box.L[2]);
   sv[p] = v0;
   sv[n + p] = v1;
@@ -326,7 +329,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_sort(
     const int* __restrict__ old_start, int* __restrict__ new_start,
     const int* __restrict__ count, const int* __restrict__ scount,
     const int* __restrict__ atom_cell, int nc0, int nc1, int nc2, BoxK box,
-    int* __restrict__ perm, const double* __restrict__ x, const double* __restrict__ v,
+    int* __restrict__ perm, const double* __restrict__ xq, const double* __restrict__ v,
     const int* __restrict__ id, int n, double* __restrict__ sx, double* __restrict__ sv,
     int* __restrict__ sid, int* __restrict__ status, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
@@ -372,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_sort(
     }
     __builtin_amdgcn_wave_barrier();   // a wavefront's LDS accesses complete in order
     if (lane < want && lane < found)
-      put_member(row[lane], base + lane, n, box, x, v, id, perm, sx, sv, sid);
+      put_member(row[lane], base + lane, n, box, xq, v, id, perm, sx, sv, sid);
   } else {
     for (int q = 0; q < S.n; ++q) {
       const int b = __builtin_amdgcn_readlane(S.b, q);
@@ -382,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_sort(
         const bool mine = t + lane < len && atom_cell[i] == cell;
         const unsigned long long m = __ballot(mine);
         const int pos = found + __popcll(m & below);
-        if (mine && pos < want) put_member(i, base + pos, n, box, x, v, id, perm, sx, sv, sid);
+        if (mine && pos < want) put_member(i, base + pos, n, box, xq, v, id, perm, sx, sv, sid);
         found += __popcll(m);
       }
     }
@@ -1096,12 +1099,12 @@ hipError_t launch_cell_sort(const int* tmp_perm, const int* cell_start, int ncel
 
 hipError_t launch_gather_sort(const int* old_start, int* new_start, const int* count,
                               const int* scount, const int* atom_cell, const int nc[3], BoxK box,
-                              int* perm, const double* x, const double* v, const int* id, int n,
+                              int* perm, const double* xq, const double* v, const int* id, int n,
                               double* sx, double* sv, int* sid, int* status, const int* gate,
                               hipStream_t s) {
   const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
   k_gather_sort<<<blocks_for(ncell * kWave), kBlock, 0, s>>>(
-      old_start, new_start, count, scount, atom_cell, nc[0], nc[1], nc[2], box, perm, x, v, id, n,
+      old_start, new_start, count, scount, atom_cell, nc[0], nc[1], nc[2], box, perm, xq, v, id, n,
       sx, sv, sid, status, gate);
   return hipGetLastError();
 }

@@ -33,6 +33,7 @@ struct FK {
   double* __restrict__ eatom;
   double* __restrict__ vatom;
   int* clear;
+  IntArgs in;
 };
 
 // Raw buffer view of the packed positions: 32-bit byte offsets (record j at
@@ -92,16 +93,19 @@ __device__ inline double group_sum(double v) {
   return v;
 }
 
-// Where this lane works: atom i, its sub-lane s, the first list entry of the
-// lane and how many entries (s, s+K, ...) it owns.
+// Where this lane works: atom i, its sub-lane s, how many list entries
+// (s, s+K, ...) it owns, and the wavefront's view of its row group: entry t of
+// this lane is the int at byte t * 256 + 4 * lane of the group, read through a
+// buffer resource with scalar row offsets (rows past the group read 0).
 template <int K>
 struct Lane {
   int i;          // atom (may be >= n for padding lanes)
   int s;          // sub-lane 0..K-1
   bool live;      // i < n
-  const int* nb;  // entry t of this lane at nb[t * 64]
   int count;      // entries owned by this lane
-  int rows;       // rows of 64 entries per atom group (ceil(cap / K))
+  int tmax;       // largest count in the wavefront (uniform)
+  __amdgpu_buffer_rsrc_t nb;   // the wavefront's row group of the list
+  unsigned voff;               // 4 * lane
   __device__ inline Lane(const FK& a) {
     const int g = xcd_block() * kBlock + threadIdx.x;   // contiguous atoms per XCD
     const int lane = g & (kWave - 1);
@@ -110,16 +114,28 @@ struct Lane {
     live = i < a.n;
     const int nn = live ? min(a.numneigh[i], a.cap) : 0;
     count = nn > s ? (nn - s + K - 1) / K : 0;
-    rows = (int)nl_rows(a.cap, K);
-    nb = a.neigh + (size_t)(g / kWave) * rows * kWave + lane;
+    int m = count;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, kWave));
+    tmax = __builtin_amdgcn_readfirstlane(m);
+    const int rows = (int)nl_rows(a.cap, K);
+    const int* base = a.neigh + (size_t)__builtin_amdgcn_readfirstlane(g / kWave) * rows * kWave;
+    nb = __builtin_amdgcn_make_buffer_rsrc(const_cast<int*>(base), (short)0, rows * kWave * 4,
+                                           kBufWord3);
+    voff = 4u * (unsigned)lane;
+  }
+  // index of this lane's entry t (0 past the group's rows)
+  __device__ inline int entry(int t) const {
+    return (int)__builtin_amdgcn_raw_buffer_load_b32(nb, (int)voff, t * kWave * 4, 0);
   }
 };
 
-// Separations of up to kUnroll entries starting at entry t: the index loads
-// are issued first (rows past the lane's count are clamped into its own rows,
-// read and masked by ok[], so no branch splits the loads), then the position
-// gathers through the buffer view, then the arithmetic.  WRAP applies the
-// minimum image; interior wavefronts skip it (see interior()).
+// Separations of kUnroll entries starting at entry t: the position gathers
+// of the batch go out first (one 32-byte record per entry through the buffer
+// view), then the next batch's index loads, then the arithmetic, so each
+// batch waits for one memory latency instead of two.  ok[] marks the lane's
+// own entries; the others use atom 0 and are masked.  WRAP applies
+// the minimum image; interior wavefronts skip it (see interior()).
 struct Batch {
   int j[kUnroll];
   bool ok[kUnroll];
@@ -132,21 +148,21 @@ struct XView {
 
 template <int K, bool WRAP>
 __device__ inline void load_batch(const FK& a, const XView& xv, const Lane<K>& ln, int t,
-                                  double xi, double yi, double zi, Batch& b) {
-#pragma unroll
-  for (int u = 0; u < kUnroll; ++u) {
-    b.ok[u] = t + u < ln.count;
-    b.j[u] = ln.nb[(size_t)min(t + u, ln.rows - 1) * kWave];
-  }
+                                  int* jn, double xi, double yi, double zi, Batch& b) {
   double xj[kUnroll], yj[kUnroll], zj[kUnroll];
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) {
+    // entries past the lane's count are never used as indices: atom 0 stands in
+    b.ok[u] = t + u < ln.count;
+    b.j[u] = b.ok[u] ? jn[u] : 0;
     const unsigned off = (unsigned)b.j[u] * 32u;
     const f64x2 xy = load_xy(xv.r, off);
     xj[u] = xy.x;
     yj[u] = xy.y;
     zj[u] = load_z(xv.r, off);
   }
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) jn[u] = ln.entry(t + kUnroll + u);
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) {
     b.dx[u] = xi - xj[u];
@@ -164,22 +180,26 @@ __device__ inline void load_batch(const FK& a, const XView& xv, const Lane<K>& l
 
 __device__ inline XView xview(const FK& a) { return XView{buffer_of(a.xq, a.n)}; }
 
-// Runs body(batch) over this lane's list entries.  The choice between the
-// plain and the minimum-image separation is uniform over the wavefront.
+// Runs body(batch) over the wavefront's list entries (a uniform loop to the
+// largest count).  The choice between the plain and the minimum-image
+// separation is uniform over the wavefront.
 template <int K, typename F>
 __device__ inline void for_each_batch(const FK& a, const Lane<K>& ln, double xi, double yi,
                                       double zi, F&& body) {
   const XView xv = xview(a);
+  int jn[kUnroll];
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) jn[u] = ln.entry(u);
   if (__all(interior(xi, yi, zi, a))) {
-    for (int t = 0; t < ln.count; t += kUnroll) {
+    for (int t = 0; t < ln.tmax; t += kUnroll) {
       Batch b;
-      load_batch<K, false>(a, xv, ln, t, xi, yi, zi, b);
+      load_batch<K, false>(a, xv, ln, t, jn, xi, yi, zi, b);
       body(b);
     }
   } else {
-    for (int t = 0; t < ln.count; t += kUnroll) {
+    for (int t = 0; t < ln.tmax; t += kUnroll) {
       Batch b;
-      load_batch<K, true>(a, xv, ln, t, xi, yi, zi, b);
+      load_batch<K, true>(a, xv, ln, t, jn, xi, yi, zi, b);
       body(b);
     }
   }
@@ -222,6 +242,10 @@ struct Acc {
     a.f[i] = fx;
     a.f[n + i] = fy;
     a.f[2 * n + i] = fz;
+    store_ev(a, i, ev, e_extra);
+  }
+  __device__ inline void store_ev(const FK& a, int i, bool ev, double e_extra) const {
+    const int n = a.n;
     if (ev) {
       if (a.eatom) a.eatom[i] = 0.5 * e + e_extra;
       if (a.vatom) {
@@ -235,6 +259,60 @@ struct Acc {
     }
   }
 };
+
+// End of a force kernel for atom i (own: this lane holds atom i's sums and
+// writes for it; every lane of the wavefront calls this).  Without fused
+// integration the force is stored; otherwise the velocity-Verlet steps of
+// IntArgs follow, with exactly the arithmetic of the separate integration
+// kernels: vh = v + dtfm f (closing kick), then v' = vh + dtfm f,
+// x' = x + dt v' and the half-skin check, or, on the last step, v = vh and
+// the state's x and f stored.
+__device__ inline void finish_atom(const FK& a, const Acc& acc, int i, bool own, double xi,
+                                   double yi, double zi, bool ev, double e_extra) {
+  const IntArgs& in = a.in;
+  if (in.mode == MD_INT_NONE) {
+    if (own) acc.store(a, i, ev, e_extra);
+    return;
+  }
+  const int n = a.n;
+  bool finite = true;
+  double xn[3] = {0.0, 0.0, 0.0}, dd[3] = {0.0, 0.0, 0.0};
+  if (own) {
+    acc.store_ev(a, i, ev, e_extra);
+    const double fq[3] = {acc.fx, acc.fy, acc.fz};
+    const double xo[3] = {xi, yi, zi};
+    double vh[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      finite = finite && isfinite(fq[d]);
+      vh[d] = in.v[d * n + i] + in.dtfm * fq[d];
+    }
+    if (in.keatom) in.keatom[i] = vh[0] * vh[0] + vh[1] * vh[1] + vh[2] * vh[2];
+    if (in.mode == MD_INT_LAST) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        in.v[d * n + i] = vh[d];
+        in.x[d * n + i] = xo[d];
+        a.f[d * n + i] = fq[d];
+      }
+    } else {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double vn = vh[d] + in.dtfm * fq[d];
+        xn[d] = xo[d] + in.dt * vn;
+        in.v[d * n + i] = vn;
+        dd[d] = xn[d] - in.xr[d * n + i];
+        finite = finite && isfinite(xn[d]);
+      }
+    }
+  }
+  if (in.mode == MD_INT_STEP) {
+    drift_flags(xn, dd, in.trig2, i, finite, own, in.status, in.bin);
+  } else {
+    const unsigned long long bad = __ballot(own && !finite);
+    if ((threadIdx.x & (kWave - 1)) == 0 && bad) atomicOr(&in.status[MD_ST_ERRORS], 2);
+  }
+}
 
 // ------------------------------------------------------------------ LJ --
 
@@ -268,19 +346,21 @@ __global__ __launch_bounds__(kBlock) void k_lj(FK a, LJK p) {
   for_each_batch<K>(a, ln, xi, yi, zi, [&](const Batch& b) {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      if (b.ok[u] && b.s[u] < p.rc2) {
-        double g, phi;
-        lj_pair<PREC>(b.s[u], p, g, phi);
-        acc.add_force(g, b.dx[u], b.dy[u], b.dz[u]);
-        if (EV) {
-          acc.e += phi - p.ecut;
-          acc.add_virial(g, b.dx[u], b.dy[u], b.dz[u]);
-        }
+      // every lane evaluates the pair function; pairs outside the cutoff or
+      // past the lane's list contribute an exact zero (a select, no branch)
+      const bool use = b.ok[u] && b.s[u] < p.rc2;
+      double g, phi;
+      lj_pair<PREC>(use ? b.s[u] : 1.0, p, g, phi);
+      g = use ? g : 0.0;
+      acc.add_force(g, b.dx[u], b.dy[u], b.dz[u]);
+      if (EV) {
+        acc.e += use ? phi - p.ecut : 0.0;
+        acc.add_virial(g, b.dx[u], b.dy[u], b.dz[u]);
       }
     }
   });
   if (K > 1) acc.reduce<K>(EV);
-  if (ln.live && ln.s == 0) acc.store(a, ln.i, EV, 0.0);
+  finish_atom(a, acc, ln.i, ln.live && ln.s == 0, xi, yi, zi, EV, 0.0);
 }
 
 // --------------------------------------------------------- Sutton-Chen --
@@ -365,12 +445,12 @@ __global__ __launch_bounds__(kBlock) void k_sc_force(FK a, SCK p,
     }
   });
   if (K > 1) acc.reduce<K>(EV);
-  if (!ln.live || ln.s != 0) return;
   // energy: eps/2 sum_j t^(n/2) is the pair repulsion share, plus the embedding
   // term pass 1 stored
-  const double emb = (EV && a.eatom) ? a.eatom[ln.i] : 0.0;
+  const bool own = ln.live && ln.s == 0;
+  const double emb = (EV && a.eatom && own) ? a.eatom[ln.i] : 0.0;
   acc.e *= p.eps;
-  acc.store(a, ln.i, EV, emb);
+  finish_atom(a, acc, ln.i, own, xi, yi, zi, EV, emb);
 }
 
 // ------------------------------------------------------------- LJ VJP --
@@ -462,6 +542,7 @@ FK make_fk(const ForceArgs& a) {
   k.eatom = a.ev.eatom;
   k.vatom = a.ev.vatom;
   k.clear = a.clear;
+  k.in = a.in;
   return k;
 }
 

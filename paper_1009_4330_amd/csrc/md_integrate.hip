@@ -5,22 +5,6 @@
 namespace md {
 namespace {
 
-// Flags of the drift: a rebuild request when |x - x_ref|^2 > (skin/2)^2 and
-// a non-finite position; one atomic per wavefront for each.  With
-// bin.atom_cell, the cell of the atom's wrapped image is recorded too (the
-// gated rebuild sorts by it); with bin.xq, the packed position.
-__device__ inline void drift_flags(const double* xn, const double* dd, double trig2, int i,
-                                   bool finite, bool live, int* status, const BinOut& bin) {
-  const double d2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
-  const unsigned long long far = __ballot(live && d2 > trig2);
-  const unsigned long long bad = __ballot(live && !finite);
-  const bool leader = (threadIdx.x & (kWave - 1)) == 0;
-  if (leader && far) atomicOr(&status[MD_ST_REBUILD], 1);
-  if (leader && bad) atomicOr(&status[MD_ST_ERRORS], 2);
-  if (live && bin.atom_cell) bin.atom_cell[i] = cell_of(xn[0], xn[1], xn[2], bin.box, bin.nc);
-  if (live && bin.xq) store_packed(bin.xq, i, xn[0], xn[1], xn[2]);
-}
-
 // v += dtfm f; x += dt v; request a rebuild when |x - x_ref|^2 > (skin/2)^2.
 // All products and sums are evaluated as written (no contraction), so the
 // trajectory arithmetic is plain IEEE double.
@@ -44,59 +28,6 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift_check(
     }
   }
   drift_flags(xn, dd, trig2, i, finite, live, status, bin);
-}
-
-// Two velocity-Verlet halves in one pass: the closing kick of step s-1
-// (v += dtfm f, optionally |v|^2 of that full-step velocity for step s-1's
-// kinetic energy), then step s's kick, drift and displacement check.  The
-// arithmetic is exactly that of k_kick followed by k_kick_drift_check.
-__global__ __launch_bounds__(kBlock) void k_vv_step(
-    double* __restrict__ x, double* __restrict__ v, const double* __restrict__ f,
-    const double* __restrict__ xr, int n, double dtfm, double dt, double trig2,
-    double* __restrict__ keatom, int* __restrict__ status, BinOut bin) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  const bool live = i < n;
-  bool finite = true;
-  double xn[3] = {0.0, 0.0, 0.0}, dd[3] = {0.0, 0.0, 0.0};
-  if (live) {
-    double vh[3];
-    for (int d = 0; d < 3; ++d) {
-      const int q = d * n + i;
-      const double fq = f[q];
-      finite = finite && isfinite(fq);
-      vh[d] = v[q] + dtfm * fq;
-    }
-    if (keatom) keatom[i] = vh[0] * vh[0] + vh[1] * vh[1] + vh[2] * vh[2];
-    for (int d = 0; d < 3; ++d) {
-      const int q = d * n + i;
-      const double vn = vh[d] + dtfm * f[q];
-      xn[d] = x[q] + dt * vn;
-      v[q] = vn;
-      x[q] = xn[d];
-      dd[d] = xn[d] - xr[q];
-      finite = finite && isfinite(xn[d]);
-    }
-  }
-  drift_flags(xn, dd, trig2, i, finite, live, status, bin);
-}
-
-// v += dtfm f; optionally the per-atom |v|^2 for the kinetic energy.
-__global__ __launch_bounds__(kBlock) void k_kick(double* __restrict__ v,
-                                                  const double* __restrict__ f, int n,
-                                                  double dtfm, double* __restrict__ keatom,
-                                                  int* __restrict__ status) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  double vv[3];
-  bool finite = true;
-  for (int d = 0; d < 3; ++d) {
-    const int q = d * n + i;
-    finite = finite && isfinite(f[q]);
-    vv[d] = v[q] + dtfm * f[q];
-    v[q] = vv[d];
-  }
-  if (keatom) keatom[i] = vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2];
-  if (!finite) atomicOr(&status[MD_ST_ERRORS], 2);
 }
 
 __global__ __launch_bounds__(kBlock) void k_ke(const double* __restrict__ v, int n,
@@ -178,19 +109,7 @@ hipError_t launch_kick_drift_check(double* x, double* v, const double* f, const 
   return hipGetLastError();
 }
 
-hipError_t launch_vv_step(double* x, double* v, const double* f, const double* xr, int n,
-                          double dtfm, double dt, double trig2, double* keatom, int* status,
-                          const BinOut& bin, hipStream_t s) {
-  k_vv_step<<<blocks_for(n), kBlock, 0, s>>>(x, v, f, xr, n, dtfm, dt, trig2, keatom, status,
-                                              bin);
-  return hipGetLastError();
-}
 
-hipError_t launch_kick(double* v, const double* f, int n, double dtfm, double* keatom,
-                       int* status, hipStream_t s) {
-  k_kick<<<blocks_for(n), kBlock, 0, s>>>(v, f, n, dtfm, keatom, status);
-  return hipGetLastError();
-}
 
 hipError_t launch_ke(const double* v, int n, double* keatom, hipStream_t s) {
   k_ke<<<blocks_for(n), kBlock, 0, s>>>(v, n, keatom);

@@ -89,7 +89,45 @@ struct BinOut {
   BoxK box;
   int nc[3];
   int* atom_cell;
-  double* xq;   // nullable: packed [n][4] copy of x
+  double* xq;    // nullable: packed [n][4] copy of x
+  int* flag;     // the rebuild-request word this drift sets
+};
+
+// Flags of a drift: a rebuild request (to bin.flag) when |x - x_ref|^2 >
+// (skin/2)^2 and a non-finite value; one atomic per wavefront for each (every lane of the
+// wavefront calls it; `live` lanes own an atom).  With bin.atom_cell, the cell
+// of the atom's wrapped image is recorded (the gated rebuild sorts by it);
+// with bin.xq, the packed position.
+__device__ inline void drift_flags(const double* xn, const double* dd, double trig2, int i,
+                                   bool finite, bool live, int* status, const BinOut& bin) {
+  const double d2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
+  const unsigned long long far = __ballot(live && d2 > trig2);
+  const unsigned long long bad = __ballot(live && !finite);
+  const bool leader = (threadIdx.x & (kWave - 1)) == 0;
+  if (leader && far) atomicOr(bin.flag, 1);
+  if (leader && bad) atomicOr(&status[MD_ST_ERRORS], 2);
+  if (live && bin.atom_cell) bin.atom_cell[i] = cell_of(xn[0], xn[1], xn[2], bin.box, bin.nc);
+  if (live && bin.xq) store_packed(bin.xq, i, xn[0], xn[1], xn[2]);
+}
+
+// Velocity-Verlet work a force kernel does for each atom once its force is
+// summed (md_step), so that no separate integration pass reads the state:
+//   MD_INT_NONE:  store f (and energy / virial) only;
+//   MD_INT_STEP:  closing kick of this step (v += dtfm f; |v|^2 to keatom when
+//                 set), the next step's kick and drift (x from the packed
+//                 positions the kernel read, the result to bin.xq, a buffer
+//                 the kernel does not read) and its displacement check;
+//   MD_INT_LAST:  closing kick only, then f and x stored in the state.
+enum { MD_INT_NONE = 0, MD_INT_STEP = 1, MD_INT_LAST = 2 };
+struct IntArgs {
+  int mode;
+  double* v;
+  const double* xr;      // x_ref of the current list
+  double* x;             // state positions (MD_INT_LAST)
+  double* keatom;        // nullable: |v|^2 of the full-step velocity
+  int* status;
+  double dtfm, dt, trig2;
+  BinOut bin;            // drift outputs (MD_INT_STEP)
 };
 
 // Lennard-Jones constants in both precisions.
@@ -130,6 +168,7 @@ struct WsLayout {
   size_t scount;     // int [ncell/16+1]  per-super-cell counts
   size_t new_start;  // int [ncell + 1]   cell starts of a rebuild in progress
   size_t xq;         // double [n][4]     packed positions (x, y, z, 0) for the force gathers
+  size_t xq2;        // double [n][4]     second packed buffer (md_step alternates the two)
   size_t total;
 };
 
@@ -165,7 +204,7 @@ hipError_t launch_cell_count(const int* old_start, const int* atom_cell, const i
                              int* count, int* scount, const int* gate, hipStream_t s);
 hipError_t launch_gather_sort(const int* old_start, int* new_start, const int* count,
                               const int* scount, const int* atom_cell, const int nc[3], BoxK box,
-                              int* perm, const double* x, const double* v, const int* id, int n,
+                              int* perm, const double* xq, const double* v, const int* id, int n,
                               double* sx, double* sv, int* sid, int* status, const int* gate,
                               hipStream_t s);
 hipError_t launch_copy_back(double* x, double* v, int* id, double* f, double* xr,
@@ -224,6 +263,7 @@ struct ForceArgs {
   EVOut ev;
   int* clear;
   hipEvent_t t0, t1;     // non-null: timed launch
+  IntArgs in;            // mode MD_INT_NONE unless md_step fuses integration
 };
 hipError_t launch_pack_positions(const double* x, int n, double* xq, hipStream_t s);
 hipError_t launch_lj(const ForceArgs& a, const LJK& p, int prec, int kernel, hipStream_t s);
@@ -236,14 +276,7 @@ hipError_t launch_lj_vjp(const ForceArgs& a, const LJK& p, int prec, int kernel,
 hipError_t launch_kick_drift_check(double* x, double* v, const double* f, const double* xr,
                                    int n, double dtfm, double dt, double trig2, int* status,
                                    const BinOut& bin, hipStream_t s);
-hipError_t launch_kick(double* v, const double* f, int n, double dtfm, double* keatom,
-                       int* status, hipStream_t s);
 hipError_t launch_ke(const double* v, int n, double* keatom, hipStream_t s);
-// Closing kick of the previous step (|v|^2 into keatom when not null) fused
-// with this step's kick, drift and displacement check.
-hipError_t launch_vv_step(double* x, double* v, const double* f, const double* xr, int n,
-                          double dtfm, double dt, double trig2, double* keatom, int* status,
-                          const BinOut& bin, hipStream_t s);
 
 // Deterministic sums: cols arrays of n doubles (col c at base[c] ) -> out[cols].
 struct SumArgs {
