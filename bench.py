@@ -7,10 +7,12 @@ plain FP64 path and the thread-per-atom kernel (K = 1) on the same workload,
 and the LJ adjoint (force VJP) throughput in atoms/s on eight 32,000-atom
 snapshots thermalised for 500 NVE steps, are reported beside it.
 
-Each "step" is one full velocity-Verlet step of md_step: kick + drift +
-displacement check, the rebuild chain when triggered (wrap, bin, sort, list),
-forces, kick, and thermo output every 100 steps.  Inputs are resident in HBM
-before the timed region starts.  Prints one JSON line on stdout.
+Each "step" is one full velocity-Verlet step of md_step: the rebuild chain
+when the half-skin check fired (count, gather-sort, list), then the force
+kernel, which also does the closing kick, the next kick, drift and check;
+thermo output every 100 steps.  Inputs are resident in HBM before the timed
+region starts.  The roofline object describes that force kernel.  Prints one
+JSON line on stdout.
 """
 from __future__ import annotations
 
@@ -37,10 +39,12 @@ def log(*a):
 
 
 def force_bytes_per_atom(mean_neigh: float) -> float:
-    """Algorithmic HBM bytes of one LJ force evaluation per atom: numneigh (4),
-    neighbour indices (4 per entry), own position (24) and force (24); the
+    """Algorithmic HBM bytes per atom of md_step's force kernel, which also
+    integrates: numneigh (4) and the neighbour indices (4 per entry), the
+    atom's packed position record (32), velocity read and written (24 + 24),
+    x_ref (24), the drifted packed record (32) and the new cell (4).  The
     neighbour positions are cache-served gathers (atoms are cell-sorted)."""
-    return 4.0 + 4.0 * mean_neigh + 24.0 + 24.0
+    return 4.0 + 4.0 * mean_neigh + 32.0 + 48.0 + 24.0 + 32.0 + 4.0
 
 
 def source_hash() -> str:
@@ -147,14 +151,13 @@ def cpu_baseline(w, x, v, target_s: float = 15.0):
                        f"state (FP64, setup excluded, {t:.1f} s)")
 
 
-def profile_force(launches: int, kernel: str):
+def profile_force(steps: int, kernel: str):
     """For hardware-counter passes: the headline state after a short warm-up,
-    then `launches` force evaluations alone, then a plain device copy of known
-    size (256 MiB read + 256 MiB written, 4 times) that calibrates the byte
-    counters."""
+    then `steps` md_step steps (their force kernels are the fused ones the
+    bench times), then a plain device copy of known size (256 MiB read + 256
+    MiB written, 4 times) that calibrates the byte counters."""
     import torch
     from paper_1009_4330_amd import inputs as I
-    from paper_1009_4330_amd import md
     from paper_1009_4330_amd.system import MDSystem
 
     w = I.LJ_256K
@@ -162,10 +165,8 @@ def profile_force(launches: int, kernel: str):
     s = MDSystem(w, x, v, "mixed", kernel)
     s.setup(thermo=False)
     s.run(20, 20)
-    f = torch.empty_like(s.state.f)
-    for _ in range(launches):
-        md.md_compute_forces(s.pot, s.state.x, s.box, s.nl, s.prec, md.MD_KERNEL_AUTO, 0, f,
-                             None, s.ws)
+    torch.cuda.synchronize()
+    s.run(steps, steps)
     torch.cuda.synchronize()
     nbytes = 256 << 20
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
@@ -173,7 +174,7 @@ def profile_force(launches: int, kernel: str):
     for _ in range(4):
         dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"force_launches": launches, "atoms": w.natoms,
+    print(json.dumps({"steps": steps, "atoms": w.natoms,
                       "mean_neighbors": s.nl.numneigh.double().mean().item(),
                       "lanes_per_atom": s.nl.layout, "copy_bytes_read": nbytes,
                       "copy_bytes_written": nbytes, "copy_launches": 4}), flush=True)
@@ -190,7 +191,7 @@ def main():
     ap.add_argument("--kernel", default="auto",
                     help="force kernel: tpa, wpa, auto or kN (N lanes per atom)")
     ap.add_argument("--profile-force", type=int, default=0, metavar="N",
-                    help="run N force-only launches and a calibration copy (for counters)")
+                    help="run N md_step steps and a calibration copy (for counters)")
     args = ap.parse_args()
     if args.profile_force:
         profile_force(args.profile_force, args.kernel)
@@ -239,7 +240,7 @@ def main():
     alg_bytes = bpa * w.natoms
     avg_s = mixed["force_ms_avg"] * 1e-3
     achieved = alg_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
-    kname = f"k_lj<MIXED, no energy/virial, K={lanes}>"
+    kname = f"k_lj<MIXED, no energy/virial, K={lanes}, fused step>"
     traffic = measured_traffic(kname, alg_bytes)
     line = {
         "metric": "atom-timesteps/s, LJ 256k atoms FP32-mixed vs FP64; adjoint HVP atoms/s",

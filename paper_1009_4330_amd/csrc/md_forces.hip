@@ -262,15 +262,17 @@ struct Acc {
 
 // End of a force kernel for atom i (own: this lane holds atom i's sums and
 // writes for it; every lane of the wavefront calls this).  Without fused
-// integration the force is stored; otherwise the velocity-Verlet steps of
-// IntArgs follow, with exactly the arithmetic of the separate integration
+// integration (FUSED false, the kernels md_compute_forces and the setup run)
+// the force is stored; otherwise the velocity-Verlet steps of IntArgs
+// (mode MD_INT_STEP or MD_INT_LAST) follow, with exactly the arithmetic of the separate integration
 // kernels: vh = v + dtfm f (closing kick), then v' = vh + dtfm f,
 // x' = x + dt v' and the half-skin check, or, on the last step, v = vh and
 // the state's x and f stored.
+template <bool FUSED>
 __device__ inline void finish_atom(const FK& a, const Acc& acc, int i, bool own, double xi,
                                    double yi, double zi, bool ev, double e_extra) {
   const IntArgs& in = a.in;
-  if (in.mode == MD_INT_NONE) {
+  if (!FUSED) {
     if (own) acc.store(a, i, ev, e_extra);
     return;
   }
@@ -334,7 +336,7 @@ __device__ inline void lj_pair(double s, const LJK& p, double& g, double& phi) {
   }
 }
 
-template <int PREC, bool EV, int K>
+template <int PREC, bool EV, int K, bool FUSED>
 __global__ __launch_bounds__(kBlock) void k_lj(FK a, LJK p) {
   if (a.clear && blockIdx.x == 0 && threadIdx.x == 0) *a.clear = 0;
   const Lane<K> ln(a);
@@ -360,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void k_lj(FK a, LJK p) {
     }
   });
   if (K > 1) acc.reduce<K>(EV);
-  finish_atom(a, acc, ln.i, ln.live && ln.s == 0, xi, yi, zi, EV, 0.0);
+  finish_atom<FUSED>(a, acc, ln.i, ln.live && ln.s == 0, xi, yi, zi, EV, 0.0);
 }
 
 // --------------------------------------------------------- Sutton-Chen --
@@ -402,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_sc_density(FK a, SCK p, double* __re
 }
 
 // Pass 2: F_ij = [n eps t^(n/2) - (m eps c / 2)(e_i + e_j) t^(m/2)] d / s, t = a^2/s.
-template <int PREC, bool EV, int K>
+template <int PREC, bool EV, int K, bool FUSED>
 __global__ __launch_bounds__(kBlock) void k_sc_force(FK a, SCK p,
                                                       const double* __restrict__ e_in) {
   if (a.clear && blockIdx.x == 0 && threadIdx.x == 0) *a.clear = 0;
@@ -450,7 +452,7 @@ __global__ __launch_bounds__(kBlock) void k_sc_force(FK a, SCK p,
   const bool own = ln.live && ln.s == 0;
   const double emb = (EV && a.eatom && own) ? a.eatom[ln.i] : 0.0;
   acc.e *= p.eps;
-  finish_atom(a, acc, ln.i, own, xi, yi, zi, EV, emb);
+  finish_atom<FUSED>(a, acc, ln.i, own, xi, yi, zi, EV, emb);
 }
 
 // ------------------------------------------------------------- LJ VJP --
@@ -596,11 +598,19 @@ hipError_t launch_lj(const ForceArgs& a, const LJK& p, int prec, int lanes, hipS
   return with_lanes(lanes, [&](auto kc) -> hipError_t {
     constexpr int K = decltype(kc)::value;
     const unsigned g = grid_for(a.n, K);
-    if (prec == MD_FP64)
-      return ev ? launch_timed(k_lj<MD_FP64, true, K>, g, s, a.t0, a.t1, k, p)
-                : launch_timed(k_lj<MD_FP64, false, K>, g, s, a.t0, a.t1, k, p);
-    return ev ? launch_timed(k_lj<MD_MIXED, true, K>, g, s, a.t0, a.t1, k, p)
-              : launch_timed(k_lj<MD_MIXED, false, K>, g, s, a.t0, a.t1, k, p);
+    const bool fused = a.in.mode != MD_INT_NONE;
+    if (prec == MD_FP64) {
+      if (fused)
+        return ev ? launch_timed(k_lj<MD_FP64, true, K, true>, g, s, a.t0, a.t1, k, p)
+                  : launch_timed(k_lj<MD_FP64, false, K, true>, g, s, a.t0, a.t1, k, p);
+      return ev ? launch_timed(k_lj<MD_FP64, true, K, false>, g, s, a.t0, a.t1, k, p)
+                : launch_timed(k_lj<MD_FP64, false, K, false>, g, s, a.t0, a.t1, k, p);
+    }
+    if (fused)
+      return ev ? launch_timed(k_lj<MD_MIXED, true, K, true>, g, s, a.t0, a.t1, k, p)
+                : launch_timed(k_lj<MD_MIXED, false, K, true>, g, s, a.t0, a.t1, k, p);
+    return ev ? launch_timed(k_lj<MD_MIXED, true, K, false>, g, s, a.t0, a.t1, k, p)
+              : launch_timed(k_lj<MD_MIXED, false, K, false>, g, s, a.t0, a.t1, k, p);
   });
 }
 
@@ -613,20 +623,20 @@ hipError_t launch_sc(const ForceArgs& a, const SCK& p, int prec, int lanes, doub
     const unsigned g = grid_for(a.n, K);
     const double* e = sc_e;
     // pass 1 (density) is not timed; the timed launch is the force pass
-    if (prec == MD_FP64) {
-      if (ev) {
-        k_sc_density<MD_FP64, true, K><<<g, kBlock, 0, s>>>(k, p, sc_e);
-        return launch_timed(k_sc_force<MD_FP64, true, K>, g, s, a.t0, a.t1, k, p, e);
-      }
-      k_sc_density<MD_FP64, false, K><<<g, kBlock, 0, s>>>(k, p, sc_e);
-      return launch_timed(k_sc_force<MD_FP64, false, K>, g, s, a.t0, a.t1, k, p, e);
-    }
-    if (ev) {
-      k_sc_density<MD_MIXED, true, K><<<g, kBlock, 0, s>>>(k, p, sc_e);
-      return launch_timed(k_sc_force<MD_MIXED, true, K>, g, s, a.t0, a.t1, k, p, e);
-    }
-    k_sc_density<MD_MIXED, false, K><<<g, kBlock, 0, s>>>(k, p, sc_e);
-    return launch_timed(k_sc_force<MD_MIXED, false, K>, g, s, a.t0, a.t1, k, p, e);
+    const bool fused = a.in.mode != MD_INT_NONE;
+    auto force = [&](auto prec_c, auto ev_c) -> hipError_t {
+      constexpr int P = decltype(prec_c)::value;
+      constexpr bool E = decltype(ev_c)::value;
+      k_sc_density<P, E, K><<<g, kBlock, 0, s>>>(k, p, sc_e);
+      return fused ? launch_timed(k_sc_force<P, E, K, true>, g, s, a.t0, a.t1, k, p, e)
+                   : launch_timed(k_sc_force<P, E, K, false>, g, s, a.t0, a.t1, k, p, e);
+    };
+    using F64 = std::integral_constant<int, MD_FP64>;
+    using MIX = std::integral_constant<int, MD_MIXED>;
+    using YES = std::integral_constant<bool, true>;
+    using NO = std::integral_constant<bool, false>;
+    if (prec == MD_FP64) return ev ? force(F64(), YES()) : force(F64(), NO());
+    return ev ? force(MIX(), YES()) : force(MIX(), NO());
   });
 }
 
