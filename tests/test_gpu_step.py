@@ -28,9 +28,12 @@ def run_both(orc, w, x, v, prec="fp64", kernel="tpa", steps=None, every=1, capac
     return ref, rows, gx, gv, gf, sysm
 
 
-@pytest.mark.parametrize("kernel", ["tpa", "wpa", "auto"])
-def test_c1_fp64_trajectory_and_rebuild_schedule(orc, kernel):
-    w = I.LJ_4K
+@pytest.mark.parametrize("kernel,ncell", [("tpa", 10), ("wpa", 10), ("auto", 10), ("k4", 12),
+                                          ("tpa", 12)])
+def test_c1_fp64_trajectory_and_rebuild_schedule(orc, kernel, ncell):
+    """C1 (10^3 fcc cells, 5 list cells per dimension) and a 12^3 box (7 list
+    cells per dimension: tagged lists, row-window forces)."""
+    w = I.LJ_4K if ncell == 10 else I.scaled(I.LJ_4K, ncell, steps=60)
     x, v, box = I.initial_state(w)
     ref, rows, gx, gv, gf, _ = run_both(orc, w, x, v, "fp64", kernel)
     # same rebuild steps: cumulative build counts after every step agree
