@@ -75,13 +75,8 @@ enum { MD_POT_LJ = 0, MD_POT_SC = 1 };
    so each row a wavefront reads is one contiguous 256-byte block.  K = 1:
    entry m of atom i at ((i / 64) * capacity + m) * 64 + i % 64; K = 64: the
    entries of atom i are consecutive.  A force kernel reads only a list of its
-   own K.  md_nlist_ints() gives the buffer size that fits every K.
-   Each entry is the neighbour's index in its low 27 bits (entry &
-   MD_NEIGH_INDEX_MASK); the 5 bits above may hold a tag of the library's own
-   (lists md_step builds mark which cell row of the atom's stencil the
-   neighbour lies in).  md_build_neighbors leaves them zero. */
+   own K.  md_nlist_ints() gives the buffer size that fits every K. */
 enum { MD_LAYOUT_TPA = 1, MD_LAYOUT_WPA = 64 };
-#define MD_NEIGH_INDEX_MASK 0x07FFFFFF
 
 /* nl->status words (device int[MD_STATUS_WORDS]). */
 enum {

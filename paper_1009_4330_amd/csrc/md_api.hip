@@ -179,7 +179,7 @@ md_status force_dispatch(const md_potential* p, const ForceArgs& fa, md_precisio
 
 // Build a list in `layout` from positions x (sorted or input order).
 md_status build_list(const double* x, int n, int sorted, const md_box* box, const int nc[3],
-                     const md_cells* cells, double rl, md_nlist* nl, int layout, int tags,
+                     const md_cells* cells, double rl, md_nlist* nl, int layout,
                      hipStream_t s) {
   BuildArgs a{};
   a.x = x;
@@ -197,7 +197,6 @@ md_status build_list(const double* x, int n, int sorted, const md_box* box, cons
   a.numneigh = nl->numneigh;
   a.x_ref = nl->x_ref;
   a.status = nl->status;
-  a.tags = tags;
   MD_CK(launch_build(a, s));
   nl->layout = layout;
   nl->rl = rl;
@@ -210,7 +209,7 @@ md_status build_list(const double* x, int n, int sorted, const md_box* box, cons
 md_status autoselect_impl(const md_potential* p, const double* x, int n, int sorted,
                           const md_box* box, const md_cells* cells, double rl, md_nlist* nl,
                           md_precision prec, int reps, md_kernel* choice, void* ws,
-                          const WsLayout& L, int tags, hipStream_t s) {
+                          const WsLayout& L, hipStream_t s) {
   int nc[3] = {cells->nc[0], cells->nc[1], cells->nc[2]};
   int before[MD_STATUS_WORDS];
   MD_CK(hipMemcpyAsync(before, nl->status, sizeof(before), hipMemcpyDeviceToHost, s));
@@ -224,7 +223,7 @@ md_status autoselect_impl(const md_potential* p, const double* x, int n, int sor
   double* xq = at<double>(ws, L.xq);
   MD_CK(launch_pack_positions(x, n, xq, s));
   for (int k = 1; k <= kWave; k *= 2) {
-    md_status st = build_list(x, n, sorted, box, nc, cells, rl, nl, k, tags, s);
+    md_status st = build_list(x, n, sorted, box, nc, cells, rl, nl, k, s);
     if (st != MD_OK) return st;
     ForceArgs fa{};
     fa.xq = xq;
@@ -258,7 +257,7 @@ md_status autoselect_impl(const md_potential* p, const double* x, int n, int sor
   MD_CK(hipEventDestroy(e0));
   MD_CK(hipEventDestroy(e1));
   if (win != kWave) {
-    md_status st = build_list(x, n, sorted, box, nc, cells, rl, nl, win, tags, s);
+    md_status st = build_list(x, n, sorted, box, nc, cells, rl, nl, win, s);
     if (st != MD_OK) return st;
   }
   MD_CK(hipMemcpyAsync(nl->status + MD_ST_BUILDS, before + MD_ST_BUILDS, sizeof(int),
@@ -441,7 +440,7 @@ md_status md_build_neighbors(const double* x, int64_t n, const md_box* box,
   if (!cell_dims(box, rl, nc, &ncell)) return MD_ERR_INVALID_ARG;
   for (int d = 0; d < 3; ++d)
     if (cells->nc[d] != nc[d]) return MD_ERR_INVALID_ARG;  // cells were binned at another rl
-  return build_list(x, (int)n, 0, box, nc, cells, rl, nl, nl->layout, 0,
+  return build_list(x, (int)n, 0, box, nc, cells, rl, nl, nl->layout,
                     static_cast<hipStream_t>(stream));
 }
 
@@ -560,7 +559,7 @@ md_status md_autoselect(const md_potential* p, const double* x, int64_t n, const
     if (cells->nc[d] != nc[d]) return MD_ERR_INVALID_ARG;
   const WsLayout L = ws_layout(n, ncell);
   if ((st = check_ws(ws, ws_bytes, L)) != MD_OK) return st;
-  return autoselect_impl(p, x, (int)n, 0, box, cells, rl, nl, prec, reps, choice, ws, L, 0,
+  return autoselect_impl(p, x, (int)n, 0, box, cells, rl, nl, prec, reps, choice, ws, L,
                          static_cast<hipStream_t>(stream));
 }
 
@@ -618,9 +617,6 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
   int* scount = at<int>(ws, L.scount);
 
   int* new_start = at<int>(ws, L.new_start);
-  // entries carry row tags for the windowed force kernel when every x-row
-  // segment's window holds distinct cells
-  const int tags = nc[0] >= kRowCells + 2 ? 1 : 0;
   // packed positions: the setup build and the force kernels read xq[0]
   // first; each fused step reads one buffer and drifts into the other
   double* const xqs[2] = {at<double>(ws, L.xq), at<double>(ws, L.xq2)};
@@ -666,7 +662,6 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
     a.x_ref = nl->x_ref;
     a.status = status;
     a.xq_out = xq;
-    a.tags = tags;
     a.x_out = stt->x;
     a.v_out = stt->v;
     a.v_in = sv;
@@ -739,7 +734,7 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
       int lanes = 0;
       if (cached_choice(p, prec, words[MD_ST_MAXNEIGH], &lanes)) {
         if (lanes != kernel) {
-          st = build_list(stt->x, n, 1, box, nc, cells, rl, nl, lanes, tags, s);
+          st = build_list(stt->x, n, 1, box, nc, cells, rl, nl, lanes, s);
           if (st != MD_OK) return st;
           MD_CK(hipMemcpyAsync(status + MD_ST_BUILDS, words + MD_ST_BUILDS, sizeof(int),
                                hipMemcpyHostToDevice, s));
@@ -748,8 +743,7 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
         kernel = lanes;
       } else {
         md_kernel choice = MD_KERNEL_TPA;
-        st = autoselect_impl(p, stt->x, n, 1, box, cells, rl, nl, prec, 5, &choice, ws, L, tags,
-                             s);
+        st = autoselect_impl(p, stt->x, n, 1, box, cells, rl, nl, prec, 5, &choice, ws, L, s);
         if (st != MD_OK) return st;
         kernel = (int)choice;
       }

@@ -481,12 +481,10 @@ struct CandSegs {
 // address space per instantiation, so no access goes through a flat
 // pointer, which would make LDS waits wait for global memory too).  FIRST:
 // the lists start empty, else they continue from hcnt / numneigh.  Each home
-// atom's count goes to numneigh and, for the first 256, to hcnt.  Staged
-// indices carry their row tag (zero without tags); a home atom's own entry
-// is its index with self_tag.
+// atom's count goes to numneigh and, for the first 256, to hcnt.
 template <bool WRAP, bool HOME_LDS, bool FIRST>
 __device__ inline void build_home(const BuildArgs& a, const BuildLds& L, const CandSegs& cs,
-                                  int hl, int hb, int he, int self_tag, int lane, int wave) {
+                                  int hl, int hb, int he, int lane, int wave) {
   const int n = a.n;
   const double* __restrict__ x = a.x;
   const bool sorted = a.sorted != 0;
@@ -506,8 +504,6 @@ __device__ inline void build_home(const BuildArgs& a, const BuildLds& L, const C
     const int i0 = sorted ? h : a.perm[h];
     const int i1 = two ? (sorted ? h + 1 : a.perm[h + 1]) : -1;
     const int k1 = two ? i1 : i0;   // a valid index for the address arithmetic
-    // staged entries carry their row tag; the home atoms' own entries carry self_tag
-    const int s0 = i0 | self_tag, s1 = two ? (i1 | self_tag) : -1;
     double x0, y0, z0, x1, y1, z1;
     if (HOME_LDS) {
       const int q0 = hl + (h - hb);
@@ -555,13 +551,13 @@ __device__ inline void build_home(const BuildArgs& a, const BuildLds& L, const C
         }
         const double ra = ax * ax + ay * ay + az * az;
         const double rb = bx * bx + by * by + bz * bz;
-        const bool ta = (ra < rl2) & (j != s0);
-        const bool tb = (rb < rl2) & (j != s1);
+        const bool ta = (ra < rl2) & (j != i0);
+        const bool tb = (rb < rl2) & (j != i1);
         // each ballot taken straight from one compare (no mask materialised in VGPRs)
         const unsigned long long ma =
-            __builtin_amdgcn_ballot_w64(ra < rl2) & __builtin_amdgcn_ballot_w64(j != s0);
+            __builtin_amdgcn_ballot_w64(ra < rl2) & __builtin_amdgcn_ballot_w64(j != i0);
         const unsigned long long mb =
-            __builtin_amdgcn_ballot_w64(rb < rl2) & __builtin_amdgcn_ballot_w64(j != s1);
+            __builtin_amdgcn_ballot_w64(rb < rl2) & __builtin_amdgcn_ballot_w64(j != i1);
         const int pa = cnt0 + __builtin_amdgcn_mbcnt_hi(
                                   (unsigned)(ma >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)ma, 0u));
         const int pb = cnt1 + __builtin_amdgcn_mbcnt_hi(
@@ -613,18 +609,17 @@ __device__ inline bool cell_wraps(int cx, int cy, int cz, const int* nc) {
 // build_home for the per-cell path's runtime cases.
 template <bool WRAP>
 __device__ inline void build_home_any(const BuildArgs& a, const BuildLds& L, const CandSegs& cs,
-                                      bool first, int hl, int hb, int he, int self_tag, int lane,
-                                      int wave) {
+                                      bool first, int hl, int hb, int he, int lane, int wave) {
   if (first) {
     if (hl >= 0)
-      build_home<WRAP, true, true>(a, L, cs, hl, hb, he, self_tag, lane, wave);
+      build_home<WRAP, true, true>(a, L, cs, hl, hb, he, lane, wave);
     else
-      build_home<WRAP, false, true>(a, L, cs, hl, hb, he, self_tag, lane, wave);
+      build_home<WRAP, false, true>(a, L, cs, hl, hb, he, lane, wave);
   } else {
     if (hl >= 0)
-      build_home<WRAP, true, false>(a, L, cs, hl, hb, he, self_tag, lane, wave);
+      build_home<WRAP, true, false>(a, L, cs, hl, hb, he, lane, wave);
     else
-      build_home<WRAP, false, false>(a, L, cs, hl, hb, he, self_tag, lane, wave);
+      build_home<WRAP, false, false>(a, L, cs, hl, hb, he, lane, wave);
   }
 }
 
@@ -719,7 +714,7 @@ static_assert(2 * kStageHalf * (kBlock / kWave) >= 27, "staging covers the stenc
 // the first 64 in-chunk atoms of each with all loads in flight together.
 __device__ inline void stage_entries(const BuildArgs& a, const BuildLds& L, int k0, int c0,
                                      int clen, int nst, const int* st_start, const int* st_off,
-                                     const int* st_tag, int lane, int wave) {
+                                     int lane, int wave) {
   const int n = a.n;
   const double* __restrict__ x = a.x;
   const bool sorted = a.sorted != 0;
@@ -737,17 +732,15 @@ __device__ inline void stage_entries(const BuildArgs& a, const BuildLds& L, int 
         const int sl = st_start[e] + (q - st_off[e]);
         sq[k] = q - c0;
         sj[k] = sorted ? sl : a.perm[sl];
-        sj[k] |= st_tag[e];
       }
     }
   }
 #pragma unroll
   for (int k = 0; k < kStageHalf; ++k) {
     if (sq[k] >= 0) {
-      const int j = sj[k] & kIndexMask;
-      sx[k] = x[j];
-      sy[k] = x[n + j];
-      sz[k] = x[2 * n + j];
+      sx[k] = x[sj[k]];
+      sy[k] = x[n + sj[k]];
+      sz[k] = x[2 * n + sj[k]];
     }
   }
 #pragma unroll
@@ -775,7 +768,7 @@ __device__ inline void pad_slots(const BuildLds& L, int from, int to, int tid) {
 // kBuildChunk.  Every thread of the workgroup calls it.  Returns this
 // thread's largest list length; copies cell_start into cell_start_out.
 __device__ inline int build_cell(const BuildArgs& a, const BuildLds& L, int cell, int* st_start,
-                                 int* st_off, int* st_tag, int* st_meta) {
+                                 int* st_off, int* st_meta) {
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1), wave = tid / kWave;
   const int hb = a.cell_start[cell], he = a.cell_start[cell + 1];
@@ -803,17 +796,6 @@ __device__ inline int build_cell(const BuildArgs& a, const BuildLds& L, int cell
       st_start[pos] = b;
       st_off[pos] = inc - cnt;
       if (c2 == cell) st_meta[1] = pos;
-      // row tag of this entry within the home cell's stencil (see entry_tag)
-      int tag = 0;
-      if (a.tags) {
-        const int nc0 = a.nc[0], nc1 = a.nc[1], nc2 = a.nc[2];
-        const int hx = cell % nc0, hy = (cell / nc0) % nc1, hz = cell / (nc0 * nc1);
-        const int wx = c2 % nc0, wy = (c2 / nc0) % nc1, wz = c2 / (nc0 * nc1);
-        const int cx0 = hx / kRowCells * kRowCells, nh = min(kRowCells, nc0 - cx0);
-        const int row = rank_in(wz, hz, nc2) * min(nc1, 3) + rank_in(wy, hy, nc1);
-        tag = entry_tag(row, wx < cx0 - 1 || wx > cx0 + nh ? 1 : 0);
-      }
-      st_tag[pos] = tag;
     }
     if (lane == kWave - 1) {
       st_meta[0] = __popcll(km);
@@ -835,14 +817,14 @@ __device__ inline int build_cell(const BuildArgs& a, const BuildLds& L, int cell
   for (int c0 = 0; c0 < total; c0 += kBuildChunk) {
     const int clen = min(kBuildChunk, total - c0);
     const int cpad = (clen + kWave - 1) & ~(kWave - 1);
-    stage_entries(a, L, 0, c0, clen, nst, st_start, st_off, st_tag, lane, wave);
-    stage_entries(a, L, kStageHalf, c0, clen, nst, st_start, st_off, st_tag, lane, wave);
+    stage_entries(a, L, 0, c0, clen, nst, st_start, st_off, lane, wave);
+    stage_entries(a, L, kStageHalf, c0, clen, nst, st_start, st_off, lane, wave);
     for (int e = wave; e < nst; e += kBlock / kWave) {
       const int lo = max(st_off[e], c0), hi = min(st_off[e + 1], c0 + clen);
       for (int q = lo + kWave + lane; q < hi; q += kWave) {
         const int sl = st_start[e] + (q - st_off[e]);
         const int j = a.sorted ? sl : a.perm[sl];
-        L.cjs[q - c0] = j | st_tag[e];
+        L.cjs[q - c0] = j;
         L.cxs[q - c0] = a.x[j];
         L.cys[q - c0] = a.x[a.n + j];
         L.czs[q - c0] = a.x[2 * a.n + j];
@@ -855,11 +837,10 @@ __device__ inline int build_cell(const BuildArgs& a, const BuildLds& L, int cell
     cs.n = 1;
     cs.base[0] = 0;
     cs.pad[0] = cpad;
-    const int self_tag = st_tag[st_meta[1]];
     if (wrap)
-      build_home_any<true>(a, L, cs, c0 == 0, hl, hb, he, self_tag, lane, wave);
+      build_home_any<true>(a, L, cs, c0 == 0, hl, hb, he, lane, wave);
     else
-      build_home_any<false>(a, L, cs, c0 == 0, hl, hb, he, self_tag, lane, wave);
+      build_home_any<false>(a, L, cs, c0 == 0, hl, hb, he, lane, wave);
     __syncthreads();
     hl_last = hl;
   }
@@ -897,12 +878,12 @@ __global__ __launch_bounds__(kBlock) void k_build(BuildArgs a) {
   __shared__ int cjs[kBuildChunk];
   __shared__ int hcnt[kBlock];
   __shared__ int lbuf[(kBlock / kWave) * kListRow];
-  __shared__ int st_start[27], st_off[28], st_tag[27], st_meta[2];
+  __shared__ int st_start[27], st_off[28], st_meta[2];
   __shared__ int red[kBlock / kWave];
   const BuildLds L{cxs, cys, czs, cjs, hcnt, lbuf};
   const int cell = xcd_block();
   if (cell == 0 && threadIdx.x == 0) atomicAdd(&a.status[MD_ST_BUILDS], 1);
-  const int mx = build_cell(a, L, cell, st_start, st_off, st_tag, st_meta);
+  const int mx = build_cell(a, L, cell, st_start, st_off, st_meta);
   report_max(a, mx, red);
 }
 
@@ -912,34 +893,28 @@ __global__ __launch_bounds__(kBlock) void k_build(BuildArgs a) {
 // to[ncs] the slab's length).
 struct SlabRegs {
   double x[kSlabRounds], y[kSlabRounds], z[kSlabRounds];
-  int j[kSlabRounds];      // tagged index
-  bool ok[kSlabRounds];    // this thread holds candidate tid + r * kBlock
+  int j[kSlabRounds];
 };
 
-// Slab cell e's entries carry entry_tag(e, part) when tags are on (part: the
-// slab lies across the x boundary from the row segment).
 __device__ inline void slab_load(const BuildArgs& a, const int* ts, const int* to, int ncs,
-                                 int part, int tid, SlabRegs& R) {
+                                 int tid, SlabRegs& R) {
   const int len = to[ncs];
 #pragma unroll
   for (int r = 0; r < kSlabRounds; ++r) {
     const int q = tid + r * kBlock;
-    R.j[r] = 0;
-    R.ok[r] = q < len;
+    R.j[r] = -1;
     if (q < len) {
       int e = 0;
       for (int k = 1; k < ncs; ++k) e += q >= to[k] ? 1 : 0;
       R.j[r] = ts[e] + (q - to[e]);
-      if (a.tags) R.j[r] |= entry_tag(e, part);
     }
   }
 #pragma unroll
   for (int r = 0; r < kSlabRounds; ++r) {
-    if (R.ok[r]) {
-      const int j = R.j[r] & kIndexMask;
-      R.x[r] = a.x[j];
-      R.y[r] = a.x[a.n + j];
-      R.z[r] = a.x[2 * a.n + j];
+    if (R.j[r] >= 0) {
+      R.x[r] = a.x[R.j[r]];
+      R.y[r] = a.x[a.n + R.j[r]];
+      R.z[r] = a.x[2 * a.n + R.j[r]];
     }
   }
 }
@@ -949,7 +924,7 @@ __device__ inline void slab_store(const BuildLds& L, int base, int len, int tid,
 #pragma unroll
   for (int r = 0; r < kSlabRounds; ++r) {
     const int q = tid + r * kBlock;
-    if (R.ok[r]) {
+    if (R.j[r] >= 0) {
       L.cjs[base + q] = R.j[r];
       L.cxs[base + q] = R.x[r];
       L.cys[base + q] = R.y[r];
@@ -973,6 +948,7 @@ __device__ inline int self_rank(int c, int nc) {
 // the current cell's lists are built.  A home cell's candidates are the three
 // slots (each padded to a multiple of 64), its home atoms the middle slab's
 // home cell.  Runs with a slab over kSlabCap atoms take the per-cell path.
+constexpr int kRowCells = 4;
 constexpr int kMaxSlabs = kRowCells + 2;
 
 __global__ __launch_bounds__(kBlock) void k_build_rows(BuildArgs a) {
@@ -982,7 +958,7 @@ __global__ __launch_bounds__(kBlock) void k_build_rows(BuildArgs a) {
   __shared__ int hcnt[kBlock];
   __shared__ int lbuf[(kBlock / kWave) * kListRow];
   __shared__ int t_start[kMaxSlabs * 9], t_off[kMaxSlabs * 10];
-  __shared__ int st_start[27], st_off[28], st_tag[27], st_meta[2];
+  __shared__ int st_start[27], st_off[28], st_meta[2];
   __shared__ int red[kBlock / kWave];
   __shared__ int big;
   const BuildLds L{cxs, cys, czs, cjs, hcnt, lbuf};
@@ -1032,18 +1008,14 @@ __global__ __launch_bounds__(kBlock) void k_build_rows(BuildArgs a) {
   int mx = 0;
   if (big) {
     for (int k = 0; k < nh; ++k)
-      mx = max(mx, build_cell(a, L, (cz * nc1 + cy) * nc0 + cx0 + k, st_start, st_off, st_tag,
-                              st_meta));
+      mx = max(mx, build_cell(a, L, (cz * nc1 + cy) * nc0 + cx0 + k, st_start, st_off, st_meta));
   } else {
     const int eh = self_rank(cz, nc2) * ny + self_rank(cy, nc1);   // home cell within a slab
-    // slab u lies across the x boundary from this segment when cx0 - 1 + u is
-    // outside [0, nc0)
-    auto part_of = [&](int u) { return cx0 - 1 + u < 0 || cx0 - 1 + u >= nc0 ? 1 : 0; };
     {
       SlabRegs R0, R1, R2;
-      slab_load(a, &t_start[0], &t_off[0], ncs, part_of(0), tid, R0);
-      slab_load(a, &t_start[9], &t_off[10], ncs, part_of(1), tid, R1);
-      slab_load(a, &t_start[18], &t_off[20], ncs, part_of(2), tid, R2);
+      slab_load(a, &t_start[0], &t_off[0], ncs, tid, R0);
+      slab_load(a, &t_start[9], &t_off[10], ncs, tid, R1);
+      slab_load(a, &t_start[18], &t_off[20], ncs, tid, R2);
       slab_store(L, 0, t_off[ncs], tid, R0);
       slab_store(L, kSlabCap, t_off[10 + ncs], tid, R1);
       slab_store(L, 2 * kSlabCap, t_off[20 + ncs], tid, R2);
@@ -1059,8 +1031,7 @@ __global__ __launch_bounds__(kBlock) void k_build_rows(BuildArgs a) {
       P.load(a, hb, he, tid);
       SlabRegs N;
       const bool more = k + 3 < nslab;
-      if (more)
-        slab_load(a, &t_start[(k + 3) * 9], &t_off[(k + 3) * 10], ncs, part_of(k + 3), tid, N);
+      if (more) slab_load(a, &t_start[(k + 3) * 9], &t_off[(k + 3) * 10], ncs, tid, N);
       CandSegs cs;
       cs.n = 3;
 #pragma unroll
@@ -1069,11 +1040,10 @@ __global__ __launch_bounds__(kBlock) void k_build_rows(BuildArgs a) {
         cs.base[m] = ((k + m) % 3) * kSlabCap;
         cs.pad[m] = (len + kWave - 1) & ~(kWave - 1);
       }
-      const int self_tag = a.tags ? entry_tag(eh, 0) : 0;
       if (cell_wraps(cx0 + k, cy, cz, a.nc))
-        build_home<true, true, true>(a, L, cs, hl, hb, he, self_tag, lane, wave);
+        build_home<true, true, true>(a, L, cs, hl, hb, he, lane, wave);
       else
-        build_home<false, true, true>(a, L, cs, hl, hb, he, self_tag, lane, wave);
+        build_home<false, true, true>(a, L, cs, hl, hb, he, lane, wave);
       __syncthreads();
       mx = max(mx, finish_home<true>(a, L, hl, hb, he, tid, P.pre, P.pi, P.v0, P.v1, P.v2, P.pid));
       if (tid == 0 && a.cell_start_out) {

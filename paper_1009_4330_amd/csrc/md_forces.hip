@@ -154,7 +154,7 @@ __device__ inline void load_batch(const FK& a, const XView& xv, const Lane<K>& l
   for (int u = 0; u < kUnroll; ++u) {
     // entries past the lane's count are never used as indices: atom 0 stands in
     b.ok[u] = t + u < ln.count;
-    b.j[u] = b.ok[u] ? (jn[u] & kIndexMask) : 0;   // drop the row tag
+    b.j[u] = b.ok[u] ? jn[u] : 0;
     const unsigned off = (unsigned)b.j[u] * 32u;
     const f64x2 xy = load_xy(xv.r, off);
     xj[u] = xy.x;

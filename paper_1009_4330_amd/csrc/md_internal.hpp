@@ -33,27 +33,6 @@ __host__ __device__ inline size_t nl_index(int i, int m, int cap, int k) {
 }
 inline bool lanes_ok(int k) { return k >= 1 && k <= 64 && (k & (k - 1)) == 0; }
 
-// List entries: neighbour index in the low 27 bits, and in lists md_step
-// builds a tag above them -- the neighbour's cell row within the home atom's
-// stencil (0..8, distinct (z, y) rows in increasing order) times 2 plus 1 if
-// its cell lies across the x periodic boundary from the home atom's row
-// segment (kRowCells consecutive cells along x).  The windowed force kernel
-// maps (tag, index) to the LDS slot where it staged that row.
-constexpr int kIndexBits = 27;
-constexpr int kIndexMask = MD_NEIGH_INDEX_MASK;
-constexpr int kRowCells = 4;   // cells per x-row segment (list build and windowed forces)
-__host__ __device__ inline int entry_tag(int row, int part) {
-  return (int)((unsigned)(row * 2 + part) << kIndexBits);
-}
-// Rank of w among the distinct cells {c - 1, c, c + 1} of a periodic
-// dimension of nc cells, in increasing order.
-__host__ __device__ inline int rank_in(int w, int c, int nc) {
-  if (nc < 3) return w;
-  if (c == 0) return w == nc - 1 ? 2 : w;
-  if (c == nc - 1) return w == 0 ? 0 : w - (nc - 3);
-  return w - (c - 1);
-}
-
 // MI355X spreads the workgroups of a dispatch round-robin over its 8 XCDs, each
 // with its own L2.  Renumbering so that XCD x runs one contiguous range of
 // logical blocks keeps each XCD's gathers (neighbour positions of cell-sorted
@@ -258,7 +237,6 @@ struct BuildArgs {
   double* x_ref;
   int* status;
   double* xq_out;        // nullable: packed [n][4] copy of the home atoms' positions
-  int tags;              // nonzero: entries carry row tags (sorted, nc[0] >= kRowCells + 2)
   // md_step extras
   double* x_out;
   double* v_out;

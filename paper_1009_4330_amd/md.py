@@ -18,7 +18,6 @@ MD_OK, MD_ERR_INVALID_ARG, MD_ERR_BOX_TOO_SMALL, MD_ERR_NLIST_OVERFLOW = 0, 1, 2
 MD_ERR_NONFINITE, MD_ERR_UNSUPPORTED, MD_ERR_HIP, MD_ERR_WORKSPACE = 4, 5, 6, 7
 MD_ERR_UNSTABLE = 8
 MD_MAX_ATOMS = 134217727          # md.h: largest atom count
-MD_NEIGH_INDEX_MASK = 0x07FFFFFF  # md.h: index bits of a list entry
 MD_FP64, MD_MIXED = 0, 1
 MD_KERNEL_AUTO, MD_KERNEL_TPA, MD_KERNEL_WPA = 0, 1, 64
 LANES = (1, 2, 4, 8, 16, 32, 64)
@@ -192,7 +191,7 @@ class NList:
 
     def rows(self) -> torch.Tensor:
         """The list as an [n][capacity] tensor (row i = neighbours of atom i),
-        gathered through the layout-K index of include/md.h, tags removed."""
+        gathered through the layout-K index of include/md.h."""
         n, cap, k = self.numneigh.numel(), self.c.capacity, self.c.layout
         dev = self.neigh.device
         i = torch.arange(n, device=dev, dtype=torch.int64)[:, None]
@@ -200,7 +199,7 @@ class NList:
         g = 64 // k
         rows = (cap + k - 1) // k
         idx = ((i // g) * rows + m // k) * 64 + (i % g) * k + m % k
-        return self.neigh[idx] & MD_NEIGH_INDEX_MASK
+        return self.neigh[idx]
 
 
 class State:

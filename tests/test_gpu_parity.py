@@ -93,24 +93,6 @@ def test_neighbor_pairs_bit_exact(orc, case, layout, kernel):
     assert words[md.MD_ST_ERRORS] == 0 and words[md.MD_ST_MAXNEIGH] == ref.max_count
 
 
-def expected_tags(oc, box, rl, row_cells=4):
-    """Row tag of every (i, j) entry of a list md_step builds (indices in cell
-    order): the neighbour's (z, y) row rank within i's stencil times 2, plus 1
-    when its x cell lies outside i's x-row segment window
-    [cx0 - 1, cx0 + nh] taken as plain integers."""
-    nc = np.array(oc.nc)
-    cell = np.asarray(oc.atom_cell)[np.asarray(oc.perm)]          # cell of sorted atom k
-    cx, cy, cz = cell % nc[0], (cell // nc[0]) % nc[1], cell // (nc[0] * nc[1])
-
-    def rank(w, c, n):
-        w, c = np.asarray(w), np.asarray(c)
-        if n < 3:
-            return w
-        return np.where(c == 0, np.where(w == n - 1, 2, w),
-                        np.where(c == n - 1, np.where(w == 0, 0, w - (n - 3)), w - (c - 1)))
-    return cx, cy, cz, rank
-
-
 @pytest.mark.parametrize("case", ["liquid4k_nc5", "jitter864_nc3", "liquid4k_rc5",
                                   "liquid6912_nc7"])
 def test_step_setup_list_bit_exact(orc, case):
@@ -146,34 +128,6 @@ def test_step_setup_list_bit_exact(orc, case):
     assert np.array_equal(s.nl.numneigh.cpu().numpy(), ref.numneigh)
     words = md.md_nlist_status(s.nl)
     assert words[md.MD_ST_ERRORS] == 0 and words[md.MD_ST_MAXNEIGH] == ref.max_count
-    # row tags (lists md_step builds with at least 6 cells along x), exact
-    raw = rows_raw(s.nl)
-    cnt = s.nl.numneigh.cpu().numpy()
-    mask = np.arange(s.nl.capacity)[None, :] < cnt[:, None]
-    tag = (raw.astype(np.int64) & 0xFFFFFFFF) >> 27
-    nc = np.array(oc.nc)
-    if nc[0] < 6:
-        assert np.all(tag[mask] == 0)
-        return
-    cx, cy, cz, rank = expected_tags(oc, box, rl)
-    i = np.repeat(np.arange(len(cnt)), cnt)
-    j = (raw[mask].astype(np.int64) & 0x07FFFFFF)
-    ny = min(nc[1], 3)
-    row = rank(cz[j], cz[i], nc[2]) * ny + rank(cy[j], cy[i], nc[1])
-    cx0 = cx[i] // 4 * 4
-    nh = np.minimum(4, nc[0] - cx0)
-    part = ((cx[j] < cx0 - 1) | (cx[j] > cx0 + nh)).astype(np.int64)
-    assert np.array_equal(tag[mask], row * 2 + part)
-
-
-def rows_raw(nl):
-    """List entries with their tag bits, as an [n][capacity] numpy array."""
-    n, cap, k = nl.numneigh.numel(), nl.capacity, nl.layout
-    i = np.arange(n)[:, None]
-    m = np.arange(cap)[None, :]
-    g, rows = 64 // k, (cap + k - 1) // k
-    idx = ((i // g) * rows + m // k) * 64 + (i % g) * k + m % k
-    return nl.neigh.cpu().numpy()[idx]
 
 
 def test_neighbor_overflow_reports_required_capacity(orc):

@@ -32,7 +32,7 @@ def run_both(orc, w, x, v, prec="fp64", kernel="tpa", steps=None, every=1, capac
                                           ("tpa", 12)])
 def test_c1_fp64_trajectory_and_rebuild_schedule(orc, kernel, ncell):
     """C1 (10^3 fcc cells, 5 list cells per dimension) and a 12^3 box (7 list
-    cells per dimension: tagged lists, row-window forces)."""
+    cells per dimension, several row segments per x row)."""
     w = I.LJ_4K if ncell == 10 else I.scaled(I.LJ_4K, ncell, steps=60)
     x, v, box = I.initial_state(w)
     ref, rows, gx, gv, gf, _ = run_both(orc, w, x, v, "fp64", kernel)
