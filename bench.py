@@ -180,6 +180,127 @@ def profile_force(steps: int, kernel: str):
                       "copy_bytes_written": nbytes, "copy_launches": 4}), flush=True)
 
 
+def copy_peak(nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """Device-to-device copy bandwidth (read + write bytes / s) of a plain
+    torch copy: the measured stream peak the roofline is also compared with."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return 2.0 * nbytes * reps / (time.perf_counter() - t0) / 1e9
+
+
+def fit_timing(iters: int = 3):
+    """Force matching on the eight thermalised 32k snapshots (sum of the mean
+    squared force errors): L-BFGS over (eps, sigma) from (1, 1) towards forces
+    generated at the target parameters; wall time of the fit."""
+    import torch
+    from paper_1009_4330_amd import autograd as AG
+    from paper_1009_4330_amd import inputs as I
+    from paper_1009_4330_amd import md
+    from paper_1009_4330_amd.system import MDSystem
+
+    w = I.LJ_FM_32K
+    snaps = []
+    for seed in I.FM_SEEDS:
+        x, v, box = I.initial_state(w, seed)
+        s = MDSystem(w, x, v, "fp64", "tpa")
+        s.setup(thermo=False)
+        s.run(w.steps, w.steps)
+        pot = md.lj_potential(w.rc, I.FM_TARGET[0], I.FM_TARGET[1], 0)
+        f = torch.empty_like(s.state.f)
+        md.md_compute_forces(pot, s.state.x, s.box, s.nl, md.MD_FP64, md.MD_KERNEL_AUTO, 0, f,
+                             None, s.ws)
+        snaps.append((s, f))
+    out = {}
+    for prec_name, prec in (("mixed", md.MD_MIXED), ("fp64", md.MD_FP64)):
+        eps = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+        sig = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+        opt = torch.optim.LBFGS([eps, sig], lr=1.0, max_iter=60, tolerance_grad=1e-15,
+                                tolerance_change=1e-18, line_search_fn="strong_wolfe")
+        calls = [0]
+
+        def closure():
+            opt.zero_grad()
+            loss = 0.0
+            for s, target in snaps:
+                f = AG.lj_forces(s.state.x, eps, sig, s.box, s.nl, w.rc, prec, s.ws)
+                loss = loss + ((f - target) ** 2).mean()
+            loss.backward()
+            calls[0] += 1
+            return loss
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            loss = opt.step(closure)
+        torch.cuda.synchronize()
+        out[prec_name] = dict(seconds=time.perf_counter() - t0, evaluations=calls[0],
+                              eps=eps.item(), sigma=sig.item(), loss=float(loss))
+    return out
+
+
+def oracle_one_thread(w, x, v, steps: int = 10):
+    """The oracle at one host thread, in a child process (OMP_NUM_THREADS=1)."""
+    import subprocess
+    code = ("import sys, time, numpy as np; sys.path.insert(0, %r); import oracle; "
+            "from paper_1009_4330_amd import inputs as I; w = I.WORKLOADS[%r]; "
+            "x, v, _ = I.initial_state(w); p = oracle.params_for(w); "
+            "t0 = time.perf_counter(); oracle.md_run(p, x, v, w.box, 0, 1); ts = time.perf_counter() - t0; "
+            "t0 = time.perf_counter(); oracle.md_run(p, x, v, w.box, %d, %d); t = time.perf_counter() - t0 - ts; "
+            "print(%d * w.natoms / t, oracle.num_threads())") % (ROOT, w.name, steps, steps, steps)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                         timeout=600)
+    rate, threads = res.stdout.split()
+    return dict(value=float(rate), unit="atom-timesteps/s", cores=int(threads), kind="oracle",
+                sample=f"{steps} NVE steps of {w.name}, setup excluded")
+
+
+def suite(steps: int):
+    """The other configurations of the measurement plan; one JSON line each."""
+    import torch
+    from paper_1009_4330_amd import inputs as I
+
+    def emit(d):
+        print(json.dumps(d), flush=True)
+
+    emit({"item": "copy_peak_GBps", "value": copy_peak()})
+    w = I.LJ_HI_108K
+    x, v, _ = I.initial_state(w)
+    for prec in ("fp64", "mixed"):
+        for kern in ("tpa", "wpa", "auto"):
+            r = run_md(w, x, v, prec, kern, steps, 10)
+            emit({"item": "C3", "workload": w.name, "precision": prec, "kernel": kern,
+                  "lanes_per_atom": r["kernel"], "atom_steps_per_s": steps * w.natoms / r["elapsed"],
+                  "force_us": 1e3 * r["force_ms_avg"], "rebuilds": r["rebuilds"],
+                  "mean_neighbors": r["mean_neigh"], "steps": steps})
+    w = I.SC_500K
+    x, v, _ = I.initial_state(w)
+    for prec in ("fp64", "mixed"):
+        r = run_md(w, x, v, prec, "auto", steps, 10)
+        emit({"item": "C4", "workload": w.name, "precision": prec, "kernel": "auto",
+              "lanes_per_atom": r["kernel"], "atom_steps_per_s": steps * w.natoms / r["elapsed"],
+              "force_us": 1e3 * r["force_ms_avg"], "rebuilds": r["rebuilds"],
+              "mean_neighbors": r["mean_neigh"], "steps": steps})
+    emit({"item": "C5_fit", **{k: v for k, v in fit_timing().items()}})
+    for nc in (10, 20, 30, 40, 60, 80):
+        w = I.scaled(I.LJ_256K, nc)
+        x, v, _ = I.initial_state(w)
+        r = run_md(w, x, v, "mixed", "auto", steps, 10)
+        emit({"item": "sweep", "atoms": w.natoms, "precision": "mixed", "kernel": "auto",
+              "lanes_per_atom": r["kernel"], "atom_steps_per_s": steps * w.natoms / r["elapsed"],
+              "force_us": 1e3 * r["force_ms_avg"], "rebuilds": r["rebuilds"], "steps": steps})
+    w = I.LJ_256K
+    x, v, _ = I.initial_state(w)
+    emit({"item": "oracle_one_thread", **oracle_one_thread(w, x, v)})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,9 +313,15 @@ def main():
                     help="force kernel: tpa, wpa, auto or kN (N lanes per atom)")
     ap.add_argument("--profile-force", type=int, default=0, metavar="N",
                     help="run N md_step steps and a calibration copy (for counters)")
+    ap.add_argument("--suite", action="store_true",
+                    help="the other configurations (rc 5.0 LJ, Sutton-Chen, the force-matching "
+                         "fit, a size sweep, copy peak, one-thread oracle); JSON lines")
     args = ap.parse_args()
     if args.profile_force:
         profile_force(args.profile_force, args.kernel)
+        return
+    if args.suite:
+        suite(args.steps if args.steps != 1000 else 200)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "

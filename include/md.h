@@ -225,8 +225,9 @@ md_status md_force_vjp(const md_potential* p, const double* x, int64_t n, const 
 /* Mini-benchmark (the paper's setup-time TpA/BpA selection, over every K):
    for K = 1, 2, 4, ..., 64 build the list in layout K from x and time `reps`
    force launches; *choice [host] gets the fastest K.  The list is left in
-   that layout.  Synchronises.  The winner is cached per (potential type,
-   precision, neighbour-count bucket) and md_step's AUTO reuses it. */
+   that layout.  Synchronises.  The winner is cached per (device, potential
+   type, precision, power-of-two bucket of the largest neighbour count,
+   power-of-two bucket of n) and md_step's AUTO reuses it. */
 md_status md_autoselect(const md_potential* p, const double* x, int64_t n, const md_box* box,
                         const md_cells* cells, double skin, md_nlist* nl, md_precision prec,
                         int reps, md_kernel* choice, void* ws, size_t ws_bytes, void* stream);

@@ -158,13 +158,23 @@ void timing_events(hipEvent_t* t0, hipEvent_t* t1) {
 
 // ------------------------------------------------------ AUTO selection --
 
+// Key: device, potential kind, precision, log2 buckets of the largest
+// neighbour count and of the atom count (the winner moves with both: a small
+// system needs more lanes per atom to fill the chip).
+using AutoKey = std::tuple<int, int, int, int, int>;
 std::mutex g_auto_mu;
-std::map<std::tuple<int, int, int>, md_kernel> g_auto_cache;
+std::map<AutoKey, md_kernel> g_auto_cache;
 
 int count_bucket(int maxcount) {
   int b = 0;
   while ((1 << b) < maxcount && b < 30) ++b;
   return b;
+}
+
+AutoKey auto_key(const md_potential* p, md_precision prec, int maxcount, int n) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  return std::make_tuple(dev, p->kind, (int)prec, count_bucket(maxcount), count_bucket(n));
 }
 
 md_status force_dispatch(const md_potential* p, const ForceArgs& fa, md_precision prec,
@@ -265,16 +275,16 @@ md_status autoselect_impl(const md_potential* p, const double* x, int n, int sor
   MD_CK(hipStreamSynchronize(s));
   {
     std::lock_guard<std::mutex> lk(g_auto_mu);
-    g_auto_cache[std::make_tuple(p->kind, (int)prec, count_bucket(maxcount))] = (md_kernel)win;
+    g_auto_cache[auto_key(p, prec, maxcount, n)] = (md_kernel)win;
   }
   *choice = (md_kernel)win;
   return MD_OK;
 }
 
-// Cached AUTO winner for this potential, precision and neighbour-count bucket.
-bool cached_choice(const md_potential* p, md_precision prec, int maxcount, int* lanes) {
+// Cached AUTO winner for this device, potential, precision and size buckets.
+bool cached_choice(const md_potential* p, md_precision prec, int maxcount, int n, int* lanes) {
   std::lock_guard<std::mutex> lk(g_auto_mu);
-  auto it = g_auto_cache.find(std::make_tuple(p->kind, (int)prec, count_bucket(maxcount)));
+  auto it = g_auto_cache.find(auto_key(p, prec, maxcount, n));
   if (it == g_auto_cache.end()) return false;
   *lanes = (int)it->second;
   return true;
@@ -732,7 +742,7 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
       MD_CK(hipMemcpyAsync(words, status, sizeof(words), hipMemcpyDeviceToHost, s));
       MD_CK(hipStreamSynchronize(s));
       int lanes = 0;
-      if (cached_choice(p, prec, words[MD_ST_MAXNEIGH], &lanes)) {
+      if (cached_choice(p, prec, words[MD_ST_MAXNEIGH], n, &lanes)) {
         if (lanes != kernel) {
           st = build_list(stt->x, n, 1, box, nc, cells, rl, nl, lanes, s);
           if (st != MD_OK) return st;
