@@ -92,7 +92,45 @@ def run_md(w, x, v, prec, kernel, steps, warmup):
     return dict(elapsed=elapsed, rows=rows, force_launches=launches,
                 force_ms_avg=ms / max(launches, 1), rebuilds=words[md.MD_ST_BUILDS] - builds0,
                 mean_neigh=nn, max_neigh=words[md.MD_ST_MAXNEIGH], n=w.natoms,
-                kernel=sysm.kernel)
+                kernel=sysm.kernel, system=sysm)
+
+
+def nve_drift(rows, n: int, dt: float):
+    """Total-energy drift over the thermo rows of a timed run: largest
+    |E - E0| / |E0| and the least-squares slope of E/N per time unit."""
+    e = rows[:, 3]
+    t = rows[:, 0] * dt
+    slope = float(np.polyfit(t, e / n, 1)[0]) if len(e) > 1 else 0.0
+    return {"max_rel": float(np.max(np.abs(e - e[0])) / abs(e[0])), "slope_per_tau": slope,
+            "rows": int(len(e))}
+
+
+def mixed_force_error(sysm) -> float:
+    """rel-RMS of the MIXED forces against the library's FP64 forces on the
+    final state of a run (same list)."""
+    import torch
+    from paper_1009_4330_amd import md
+    out = {}
+    for prec in (md.MD_FP64, md.MD_MIXED):
+        f = torch.empty_like(sysm.state.f)
+        md.md_compute_forces(sysm.pot, sysm.state.x, sysm.box, sysm.nl, prec, sysm.nl.layout, 0, f,
+                             None, sysm.ws)
+        out[prec] = f
+    d = out[md.MD_MIXED] - out[md.MD_FP64]
+    return float(torch.sqrt((d * d).sum() / (out[md.MD_FP64] ** 2).sum()))
+
+
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count(), "model": model}
 
 
 def bench_vjp(reps: int):
@@ -356,6 +394,7 @@ def main():
         vjp = bench_vjp(reps=20)
         log(f"[bench] vjp atoms/s: {vjp}")
         extras = {"fp64_atom_timesteps_per_s": v64, "mixed_over_fp64": value / v64,
+                  "nve_drift_fp64": nve_drift(fp64["rows"], w.natoms, w.dt),
                   "fp64_force_kernel_us": 1e3 * fp64["force_ms_avg"],
                   "fp64_lanes_per_atom": fp64["kernel"],
                   "mixed_tpa_atom_timesteps_per_s": vt,
@@ -393,11 +432,14 @@ def main():
                      "timed_launches": mixed["force_launches"]},
         "rebuilds": mixed["rebuilds"],
         "mean_neighbors": mixed["mean_neigh"],
+        "nve_drift_mixed": nve_drift(mixed["rows"], w.natoms, w.dt),
+        "mixed_force_rel_rms_vs_fp64": mixed_force_error(mixed["system"]),
         **extras,
     }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(w, x, v)
+        line["cpu_baseline"]["host"] = host_info()
     print(json.dumps(line), flush=True)
 
 

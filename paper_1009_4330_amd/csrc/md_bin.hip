@@ -2,6 +2,8 @@
 // list build (the cell machinery of the paper's section "Cell list approach",
 // used here only to find neighbours; the list itself is what the kernels of
 // its "Neighbor list approach" read).
+#include <algorithm>
+
 #include "md_internal.hpp"
 
 namespace md {
@@ -252,18 +254,17 @@ __device__ inline void seg_cells(const Segs& S, int lane, const int* __restrict_
   }
 }
 
-// One wavefront per new cell, 16 per workgroup (one super-cell): the number
-// of atoms of the surrounding old ranges whose new cell this is, and the
-// super-cell's total.  Plain stores only.
+// One wavefront per new cell, 16 per workgroup (one super-cell at a time,
+// a resident grid looping over them): the number of atoms of the surrounding
+// old ranges whose new cell this is, and the super-cell's total.  Plain
+// stores only.
 constexpr int kCountBlock = kWave * kSuperCells;
 
-__global__ __launch_bounds__(kCountBlock) void k_cell_count(
-    const int* __restrict__ old_start, const int* __restrict__ atom_cell, int nc0, int nc1,
-    int nc2, int* __restrict__ count, int* __restrict__ scount, const int* __restrict__ gate) {
-  if (gate && *gate == 0) return;
-  __shared__ int part[kSuperCells];
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int sc = xcd_block();
+// Counts of the 16 cells of super-cell sc (one wavefront per cell) and their total.
+__device__ inline void cell_count_super(const int* __restrict__ old_start,
+                                        const int* __restrict__ atom_cell, int nc0, int nc1,
+                                        int nc2, int* __restrict__ count, int* __restrict__ scount,
+                                        int sc, int lane, int wave, int* part) {
   const int cell = __builtin_amdgcn_readfirstlane(sc * kSuperCells + wave);
   const int nc[3] = {nc0, nc1, nc2};
   int cnt = 0;
@@ -293,6 +294,19 @@ __global__ __launch_bounds__(kCountBlock) void k_cell_count(
     for (int w = 0; w < kSuperCells; ++w) tot += part[w];
     scount[sc] = tot;
   }
+  __syncthreads();   // part is reused by the next super-cell
+}
+
+__global__ __launch_bounds__(kCountBlock) void k_cell_count(
+    const int* __restrict__ old_start, const int* __restrict__ atom_cell, int nc0, int nc1,
+    int nc2, int* __restrict__ count, int* __restrict__ scount, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  __shared__ int part[kSuperCells];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int ncell = nc0 * nc1 * nc2;
+  const BlockRange br = xcd_range((ncell + kSuperCells - 1) / kSuperCells);
+  for (int sc = br.first; sc < br.end; sc += br.step)
+    cell_count_super(old_start, atom_cell, nc0, nc1, nc2, count, scount, sc, lane, wave, part);
 }
 
 // Gather member i into sorted slot p: its position from the packed records
@@ -325,19 +339,14 @@ __device__ inline void put_member(int i, int p, int n, const BoxK& box,
 // count of all earlier cells: the super-cell totals before its super-cell
 // plus the counts of the earlier cells of its own; it is written to
 // new_start.  If the counts do not add up to n, status bit 2 is set.
-__global__ __launch_bounds__(kBlock) void k_gather_sort(
+__device__ inline void gather_cell(
     const int* __restrict__ old_start, int* __restrict__ new_start,
     const int* __restrict__ count, const int* __restrict__ scount,
-    const int* __restrict__ atom_cell, int nc0, int nc1, int nc2, BoxK box,
+    const int* __restrict__ atom_cell, int nc0, int nc1, int nc2, const BoxK& box,
     int* __restrict__ perm, const double* __restrict__ xq, const double* __restrict__ v,
     const int* __restrict__ id, int n, double* __restrict__ sx, double* __restrict__ sv,
-    int* __restrict__ sid, int* __restrict__ status, const int* __restrict__ gate) {
-  if (gate && *gate == 0) return;
-  __shared__ int members[kBlock];
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int cell = __builtin_amdgcn_readfirstlane((xcd_block() * kBlock + threadIdx.x) / kWave);
+    int* __restrict__ sid, int* __restrict__ status, int cell, int lane, int* row) {
   const int ncell = nc0 * nc1 * nc2;
-  if (cell >= ncell) return;
   const int nc[3] = {nc0, nc1, nc2};
   const Segs S = old_segments(cell, lane, nc, old_start);
   const int sc = cell >> kSuperShift;
@@ -361,7 +370,6 @@ __global__ __launch_bounds__(kBlock) void k_gather_sort(
     // member indices in order into this wave's LDS row, then one gather
     int cid[kMaxSegs][2], sb[kMaxSegs];
     seg_cells(S, lane, atom_cell, cid, sb);
-    int* row = members + wave * kWave;
 #pragma unroll
     for (int q = 0; q < kMaxSegs; ++q) {
 #pragma unroll
@@ -391,6 +399,28 @@ __global__ __launch_bounds__(kBlock) void k_gather_sort(
     }
   }
   if (lane == 0 && found != want) atomicOr(&status[MD_ST_ERRORS], 4);
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_sort(
+    const int* __restrict__ old_start, int* __restrict__ new_start,
+    const int* __restrict__ count, const int* __restrict__ scount,
+    const int* __restrict__ atom_cell, int nc0, int nc1, int nc2, BoxK box,
+    int* __restrict__ perm, const double* __restrict__ xq, const double* __restrict__ v,
+    const int* __restrict__ id, int n, double* __restrict__ sx, double* __restrict__ sv,
+    int* __restrict__ sid, int* __restrict__ status, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  __shared__ int members[kBlock];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int ncell = nc0 * nc1 * nc2;
+  constexpr int kCells = kBlock / kWave;   // cells per logical block
+  const BlockRange br = xcd_range((ncell + kCells - 1) / kCells);
+  for (int lb = br.first; lb < br.end; lb += br.step) {
+    const int cell = lb * kCells + wave;
+    if (cell < ncell)
+      gather_cell(old_start, new_start, count, scount, atom_cell, nc0, nc1, nc2, box, perm, xq,
+                  v, id, n, sx, sv, sid, status, cell, lane, members + wave * kWave);
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_copy_back(double* __restrict__ x,
@@ -448,6 +478,14 @@ __device__ inline int wave_max(int v) {
 // row0 (K = 2^lk lanes per atom: entry pos sits in row pos / K, column pos % K).
 __device__ inline void put_entry(int* __restrict__ row0, int pos, int lk, int j) {
   row0[((pos >> lk) << 6) + (pos & ((1 << lk) - 1))] = j;
+}
+
+// put_entry as a relaxed atomic store: the same global store, but an
+// operation the compiler does not merge with the LDS stores it sits beside
+// (a merged store would go through a flat pointer).
+__device__ inline void put_entry_apart(int* __restrict__ row0, int pos, int lk, int j) {
+  __hip_atomic_store(row0 + ((pos >> lk) << 6) + (pos & ((1 << lk) - 1)), j, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // LDS of the list-build kernels.
@@ -528,8 +566,15 @@ __device__ inline void build_home(const BuildArgs& a, const BuildLds& L, const C
         a.neigh + (size_t)(k1 >> gs) * rows * kWave + ((k1 & ((1 << gs) - 1)) << lk);
     int base0 = 0, base1 = 0;
     if (!FIRST) {
-      base0 = h - hb < kBlock ? L.hcnt[h - hb] : a.numneigh[i0];
-      if (two) base1 = h + 1 - hb < kBlock ? L.hcnt[h + 1 - hb] : a.numneigh[k1];
+      // LDS copy for the first kBlock home atoms, else the global count (an
+      // atomic load, so that the two loads never share one flat access)
+      base0 = h - hb < kBlock ? L.hcnt[h - hb]
+                              : __hip_atomic_load(&a.numneigh[i0], __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+      if (two)
+        base1 = h + 1 - hb < kBlock ? L.hcnt[h + 1 - hb]
+                                    : __hip_atomic_load(&a.numneigh[k1], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
     }
     // entries of this pass, relative to base0 / base1
     int cnt0 = 0, cnt1 = 0;
@@ -703,10 +748,8 @@ struct HomePrefetch {
   }
 };
 
-constexpr int kSlabCap = 256;                  // candidates per slab slot (9 cells), a multiple of 64
-constexpr int kSlabRounds = (kSlabCap + kBlock - 1) / kBlock;   // slab candidates per thread
-static_assert(kSlabCap % 64 == 0, "a padded slab stays inside its slot");
-constexpr int kBuildChunk = 3 * kSlabCap;      // candidates per pass of the per-cell path
+constexpr int kBuildChunk = 768;   // candidates per pass of the per-cell path, a multiple of 64
+static_assert(kBuildChunk % 64 == 0, "a padded chunk stays inside the arrays");
 constexpr int kStageHalf = 4;   // stencil entries per wave staged together (two halves cover 27)
 static_assert(2 * kStageHalf * (kBlock / kWave) >= 27, "staging covers the stencil");
 
@@ -887,51 +930,145 @@ __global__ __launch_bounds__(kBlock) void k_build(BuildArgs a) {
   report_max(a, mx, red);
 }
 
-// Slab u of a row segment: the (up to 9) cells (wy, wz) around the row at one
-// x index, their atoms contiguous in the slab in increasing cell order.  Slab
-// tables hold each cell's first slot (ts) and its offset in the slab (to, with
-// to[ncs] the slab's length).
-struct SlabRegs {
-  double x[kSlabRounds], y[kSlabRounds], z[kSlabRounds];
-  int j[kSlabRounds];
-};
+// Row path.  A workgroup takes a run of up to kRowCells consecutive cells of
+// one x row.  Slab u is the (up to 9) cells (wy, wz) around the row at x index
+// cx0 - 1 + u, in increasing cell order; all kRowCells + 2 slabs of the run
+// sit back to back in LDS, so the 27-cell stencil of home cell k is the one
+// contiguous candidate range slabs k .. k + 2.  Candidate order: slab x - 1,
+// x, x + 1, cells in increasing order inside a slab, slot order inside a cell.
+constexpr int kRowCells = 4;
+constexpr int kMaxSlabs = kRowCells + 2;
+constexpr int kRowCells9 = kMaxSlabs * 9;   // (slab, cell) entries of a run
+constexpr int kRowCap = 1408;               // candidates of a run held in LDS
+// The last iteration of a pair's loop prefetches one row of 64 slots past its
+// range: the arrays extend two rows past kRowCap.
+constexpr int kRowSlots = kRowCap + 2 * kWave;
+static_assert(kRowSlots >= kBuildChunk, "the per-cell fallback fits the row arrays");
 
-__device__ inline void slab_load(const BuildArgs& a, const int* ts, const int* to, int ncs,
-                                 int tid, SlabRegs& R) {
-  const int len = to[ncs];
-#pragma unroll
-  for (int r = 0; r < kSlabRounds; ++r) {
-    const int q = tid + r * kBlock;
-    R.j[r] = -1;
-    if (q < len) {
-      int e = 0;
-      for (int k = 1; k < ncs; ++k) e += q >= to[k] ? 1 : 0;
-      R.j[r] = ts[e] + (q - to[e]);
+// Minimum image along the dimensions set in WM (home cells touching a box face
+// there, or fewer than 3 cells); along the others the candidates are the
+// unwrapped neighbours and the plain difference is the minimum image of every
+// accepted pair, bit for bit (see cell_wraps).
+template <int WM>
+__device__ inline void pair_image(double& dx, double& dy, double& dz, const BoxK& box) {
+  if (WM & 1) dx = min_image(dx, box.L[0], box.inv[0]);
+  if (WM & 2) dy = min_image(dy, box.L[1], box.inv[1]);
+  if (WM & 4) dz = min_image(dz, box.L[2], box.inv[2]);
+}
+
+// Lists of home atoms i0 and (when two) i0 + 1, staged at LDS slots s0 and
+// s0 + 1, against the candidates in LDS slots [c0, c1).  64 candidates per
+// iteration, tested against both atoms; the next 64 are read from LDS while
+// these are tested.  Past c1 (last iteration) and at the home atoms' own slots
+// a scalar lane mask drops the candidate.  Accepted ones go, in candidate
+// order, through a ballot prefix count into the wavefront's LDS buffer
+// (anything past kListBuf straight into the list) and are copied into the
+// list layout when the pair is done.  hidx: index of i0 among the
+// workgroup's home atoms (for hcnt).
+template <int WM>
+__device__ inline void build_pair(const BuildArgs& a, const BuildLds& L, int c0, int c1, int s0,
+                                  int i0, bool two, int hidx, int lane, int wave) {
+  const int lk = __ffs(a.layout) - 1;
+  const int gs = 6 - lk;
+  const size_t rows = nl_rows(a.cap, a.layout);
+  const double rl2 = a.rl2;
+  const BoxK box = a.box;
+  int* __restrict__ lrow = L.lbuf + wave * kListRow;
+  const int k1 = two ? i0 + 1 : i0;
+  const double x0 = L.cxs[s0], y0 = L.cys[s0], z0 = L.czs[s0];
+  double x1 = L.cxs[s0 + 1], y1 = L.cys[s0 + 1], z1 = L.czs[s0 + 1];
+  if (!two) x1 = y1 = z1 = __builtin_nan("");
+  int* __restrict__ r0 =
+      a.neigh + (size_t)(i0 >> gs) * rows * kWave + ((i0 & ((1 << gs) - 1)) << lk);
+  int* __restrict__ r1 =
+      a.neigh + (size_t)(k1 >> gs) * rows * kWave + ((k1 & ((1 << gs) - 1)) << lk);
+  const int total = c1 - c0;
+  const int ks = s0 - c0;   // candidate index of i0 itself (i0 + 1 follows it)
+  int cnt0 = 0, cnt1 = 0;
+  // Test the 64 candidates (j, cx, cy, cz) of iteration t against both atoms.
+  auto test = [&](int t, int j, double cx, double cy, double cz) {
+    double ax = x0 - cx, ay = y0 - cy, az = z0 - cz;
+    double bx = x1 - cx, by = y1 - cy, bz = z1 - cz;
+    pair_image<WM>(ax, ay, az, box);
+    pair_image<WM>(bx, by, bz, box);
+    const double ra = ax * ax + ay * ay + az * az;
+    const double rb = bx * bx + by * by + bz * bz;
+    // scalar masks: lanes inside the range, minus each home atom's own slot
+    const int rem = total - t;
+    const unsigned long long vm = rem >= kWave ? ~0ull : (1ull << rem) - 1ull;
+    const int d = ks - t;
+    const unsigned long long self0 = (unsigned)d < (unsigned)kWave ? 1ull << d : 0ull;
+    const unsigned long long self1 =
+        (unsigned)(d + 1) < (unsigned)kWave ? 1ull << (d + 1) : 0ull;
+    const unsigned long long ma = __builtin_amdgcn_ballot_w64(ra < rl2) & (vm & ~self0);
+    const unsigned long long mb = __builtin_amdgcn_ballot_w64(rb < rl2) & (vm & ~self1);
+    const bool ta = __builtin_amdgcn_inverse_ballot_w64(ma);
+    const bool tb = __builtin_amdgcn_inverse_ballot_w64(mb);
+    // rank among this iteration's accepted candidates
+    const int la = __builtin_amdgcn_mbcnt_hi((unsigned)(ma >> 32),
+                                             __builtin_amdgcn_mbcnt_lo((unsigned)ma, 0u));
+    const int lb = __builtin_amdgcn_mbcnt_hi((unsigned)(mb >> 32),
+                                             __builtin_amdgcn_mbcnt_lo((unsigned)mb, 0u));
+    const int na = __popcll(ma), nb = __popcll(mb);
+    // accepted lanes append to the atom's LDS buffer at cnt + rank; past
+    // kListBuf (wave-uniform, long lists only) entries go to the list itself
+    if (cnt0 + na <= kListBuf && cnt1 + nb <= kListBuf) {
+      if (ta) lrow[cnt0 + la] = j;
+      if (tb) lrow[kListBuf + cnt1 + lb] = j;
+    } else {
+      const int pa = cnt0 + la, pb = cnt1 + lb;
+      if (ta && pa < kListBuf) lrow[pa] = j;
+      if (tb && pb < kListBuf) lrow[kListBuf + pb] = j;
+      if (ta && pa >= kListBuf && pa < a.cap) put_entry_apart(r0, pa, lk, j);
+      if (tb && pb >= kListBuf && pb < a.cap) put_entry_apart(r1, pb, lk, j);
     }
+    cnt0 += na;
+    cnt1 += nb;
+  };
+  // two register sets alternate: the next 64 candidates are read while the
+  // current ones are tested
+  int q = c0 + lane;
+  int ja = L.cjs[q];
+  double xa = L.cxs[q], ya = L.cys[q], za = L.czs[q];
+  for (int t = 0; t < total; t += 2 * kWave) {
+    const int jb = L.cjs[q + kWave];
+    const double xb = L.cxs[q + kWave], yb = L.cys[q + kWave], zb = L.czs[q + kWave];
+    __builtin_amdgcn_sched_barrier(0);
+    test(t, ja, xa, ya, za);
+    if (t + kWave >= total) break;
+    q += 2 * kWave;
+    ja = L.cjs[q];
+    xa = L.cxs[q];
+    ya = L.cys[q];
+    za = L.czs[q];
+    __builtin_amdgcn_sched_barrier(0);
+    test(t + kWave, jb, xb, yb, zb);
   }
-#pragma unroll
-  for (int r = 0; r < kSlabRounds; ++r) {
-    if (R.j[r] >= 0) {
-      R.x[r] = a.x[R.j[r]];
-      R.y[r] = a.x[a.n + R.j[r]];
-      R.z[r] = a.x[2 * a.n + R.j[r]];
+  // copy the buffered entries into the list layout (this wave's own LDS
+  // rows; a wavefront's LDS accesses complete in order)
+  __builtin_amdgcn_wave_barrier();
+  const int lim0 = min(min(cnt0, kListBuf), a.cap);
+  const int lim1 = min(min(cnt1, kListBuf), a.cap);
+  for (int m = lane; m < lim0; m += kWave) put_entry(r0, m, lk, lrow[m]);
+  for (int m = lane; m < lim1; m += kWave) put_entry(r1, m, lk, lrow[kListBuf + m]);
+  __builtin_amdgcn_wave_barrier();
+  if (lane == 0) {
+    a.numneigh[i0] = cnt0;
+    if (hidx < kBlock) L.hcnt[hidx] = cnt0;
+    if (two) {
+      a.numneigh[i0 + 1] = cnt1;
+      if (hidx + 1 < kBlock) L.hcnt[hidx + 1] = cnt1;
     }
   }
 }
 
-__device__ inline void slab_store(const BuildLds& L, int base, int len, int tid,
-                                  const SlabRegs& R) {
-#pragma unroll
-  for (int r = 0; r < kSlabRounds; ++r) {
-    const int q = tid + r * kBlock;
-    if (R.j[r] >= 0) {
-      L.cjs[base + q] = R.j[r];
-      L.cxs[base + q] = R.x[r];
-      L.cys[base + q] = R.y[r];
-      L.czs[base + q] = R.z[r];
-    }
-  }
-  pad_slots(L, base + len, base + ((len + kWave - 1) & ~(kWave - 1)), tid);
+template <int WM>
+__device__ inline void build_cell_pairs(const BuildArgs& a, const BuildLds& L, int c0, int c1,
+                                        int slot, int hb, int nhome, int hidx, int first,
+                                        int lane, int wave) {
+  for (int p = first; 2 * p < nhome; p += kBlock / kWave)
+    build_pair<WM>(a, L, c0, c1, slot + 2 * p, hb + 2 * p, 2 * p + 1 < nhome, hidx + 2 * p,
+                   lane, wave);
 }
 
 // Rank of c among the distinct cells {c - 1, c, c + 1} in increasing order
@@ -941,45 +1078,32 @@ __device__ inline int self_rank(int c, int nc) {
   return c == 0 ? 0 : (c == nc - 1 ? 2 : 1);
 }
 
-// Sorted atoms, at least 3 cells along x: one workgroup per run of up to
-// kRowCells consecutive cells of an x row.  Moving one cell along x drops one
-// slab of 9 cells from the 27-cell stencil and adds one, so the workgroup
-// keeps three slab slots in LDS and loads the next slab into registers while
-// the current cell's lists are built.  A home cell's candidates are the three
-// slots (each padded to a multiple of 64), its home atoms the middle slab's
-// home cell.  Runs with a slab over kSlabCap atoms take the per-cell path.
-constexpr int kRowCells = 4;
-constexpr int kMaxSlabs = kRowCells + 2;
-
-__global__ __launch_bounds__(kBlock) void k_build_rows(BuildArgs a) {
-  if (a.gate && *a.gate == 0) return;
-  __shared__ double cxs[kBuildChunk], cys[kBuildChunk], czs[kBuildChunk];
-  __shared__ int cjs[kBuildChunk];
-  __shared__ int hcnt[kBlock];
-  __shared__ int lbuf[(kBlock / kWave) * kListRow];
-  __shared__ int t_start[kMaxSlabs * 9], t_off[kMaxSlabs * 10];
-  __shared__ int st_start[27], st_off[28], st_meta[2];
-  __shared__ int red[kBlock / kWave];
-  __shared__ int big;
-  const BuildLds L{cxs, cys, czs, cjs, hcnt, lbuf};
+// Row segment wg (a run of up to kRowCells consecutive cells of an x row) of
+// the row path; every thread of the workgroup calls it.  The run's slabs are
+// staged once; the home atoms of all its cells, two per work item, are dealt
+// to the wavefronts in turn with no barrier between cells.  Runs whose slabs
+// hold more than kRowCap atoms take the per-cell path.  Returns this
+// thread's largest list length.
+__device__ inline int build_row_segment(const BuildArgs& a, const BuildLds& L, int wg,
+                                        int* g_off, int* g_start, int* st_start, int* st_off,
+                                        int* st_meta, int* big) {
   const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1), wave = tid / kWave;
+  const int lane = tid & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
   const int nc0 = a.nc[0], nc1 = a.nc[1], nc2 = a.nc[2];
   const int spr = (nc0 + kRowCells - 1) / kRowCells;   // row segments per row
-  const int wg = xcd_block();
   const int row = wg / spr, seg = wg % spr;
   const int cy = row % nc1, cz = row / nc1;
   const int cx0 = seg * kRowCells;
   const int nh = min(kRowCells, nc0 - cx0);
   const int nslab = nh + 2;
   const int ny = min(nc1, 3), nz = min(nc2, 3), ncs = ny * nz;
+  const int ne = nslab * ncs;   // (slab, cell) entries, entry u * ncs + e
   if (wg == 0 && tid == 0) atomicAdd(&a.status[MD_ST_BUILDS], 1);
   if (wave == 0) {
-    // slab u = lane / ncs (x index cx0 - 1 + u), cell e = lane % ncs of it
     const int u = lane / ncs, e = lane % ncs;
-    const bool ok = lane < nslab * ncs;
     int b = 0, cnt = 0;
-    if (ok) {
+    if (lane < ne) {
       int sx = cx0 - 1 + u;
       sx = sx < 0 ? sx + nc0 : (sx >= nc0 ? sx - nc0 : sx);
       const int c = (nbr_sorted(cz, nc2, e / ny) * nc1 + nbr_sorted(cy, nc1, e % ny)) * nc0 + sx;
@@ -992,74 +1116,165 @@ __global__ __launch_bounds__(kBlock) void k_build_rows(BuildArgs a) {
       const int y = __shfl_up(inc, off, kWave);
       if (lane >= off) inc += y;
     }
-    const int first = u * ncs;
-    const int before = __shfl(inc, first > 0 ? first - 1 : 0, kWave);
-    const int sbase = first > 0 ? before : 0;
-    const bool last = ok && e == ncs - 1;
-    if (ok) {
-      t_start[u * 9 + e] = b;
-      t_off[u * 10 + e] = inc - cnt - sbase;
-      if (last) t_off[u * 10 + ncs] = inc - sbase;
+    if (lane < ne) {
+      g_start[lane] = b;
+      g_off[lane] = inc - cnt;
+      if (lane == ne - 1) {
+        g_off[ne] = inc;
+        *big = inc > kRowCap;
+      }
     }
-    const unsigned long long over = __ballot(last && inc - sbase > kSlabCap);
-    if (lane == 0) big = over != 0ull;
   }
   __syncthreads();
   int mx = 0;
-  if (big) {
+  if (*big) {
     for (int k = 0; k < nh; ++k)
       mx = max(mx, build_cell(a, L, (cz * nc1 + cy) * nc0 + cx0 + k, st_start, st_off, st_meta));
-  } else {
-    const int eh = self_rank(cz, nc2) * ny + self_rank(cy, nc1);   // home cell within a slab
-    {
-      SlabRegs R0, R1, R2;
-      slab_load(a, &t_start[0], &t_off[0], ncs, tid, R0);
-      slab_load(a, &t_start[9], &t_off[10], ncs, tid, R1);
-      slab_load(a, &t_start[18], &t_off[20], ncs, tid, R2);
-      slab_store(L, 0, t_off[ncs], tid, R0);
-      slab_store(L, kSlabCap, t_off[10 + ncs], tid, R1);
-      slab_store(L, 2 * kSlabCap, t_off[20 + ncs], tid, R2);
-    }
     __syncthreads();
-    for (int k = 0; k < nh; ++k) {
-      const int cell = (cz * nc1 + cy) * nc0 + cx0 + k;
-      const int* to = &t_off[(k + 1) * 10];
-      const int hb = t_start[(k + 1) * 9 + eh];
-      const int he = hb + (to[eh + 1] - to[eh]);
-      const int hl = ((k + 1) % 3) * kSlabCap + to[eh];
-      HomePrefetch P;
-      P.load(a, hb, he, tid);
-      SlabRegs N;
-      const bool more = k + 3 < nslab;
-      if (more) slab_load(a, &t_start[(k + 3) * 9], &t_off[(k + 3) * 10], ncs, tid, N);
-      CandSegs cs;
-      cs.n = 3;
+    return mx;
+  }
+  const int eh = self_rank(cz, nc2) * ny + self_rank(cy, nc1);   // home cell within a slab
+  const int hb0 = __builtin_amdgcn_readfirstlane(g_start[ncs + eh]);   // first home atom of the run
+  const int hend = g_start[nh * ncs + eh] + (g_off[nh * ncs + eh + 1] - g_off[nh * ncs + eh]);
+  HomePrefetch P;
+  P.load(a, hb0, hend, tid);
+  {
+    // stage the slabs: slot q holds the atom at sorted index g_start[c] + q -
+    // g_off[c], c the last entry with g_off[c] <= q (a binary search; empty
+    // cells share their offset with the next entry and are skipped by it)
+    const int total = g_off[ne];
+    constexpr int kRounds = 3;
+    for (int q0 = 0; q0 < total; q0 += kRounds * kBlock) {
+      int jr[kRounds];
+      double xr[kRounds], yr[kRounds], zr[kRounds];
 #pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        const int len = t_off[(k + m) * 10 + ncs];
-        cs.base[m] = ((k + m) % 3) * kSlabCap;
-        cs.pad[m] = (len + kWave - 1) & ~(kWave - 1);
+      for (int r = 0; r < kRounds; ++r) {
+        const int q = q0 + r * kBlock + tid;
+        jr[r] = -1;
+        if (q < total) {
+          int lo = 0, hi = ne;
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (g_off[mid] <= q) lo = mid; else hi = mid;
+          }
+          jr[r] = g_start[lo] + (q - g_off[lo]);
+        }
       }
-      if (cell_wraps(cx0 + k, cy, cz, a.nc))
-        build_home<true, true, true>(a, L, cs, hl, hb, he, lane, wave);
-      else
-        build_home<false, true, true>(a, L, cs, hl, hb, he, lane, wave);
-      __syncthreads();
-      mx = max(mx, finish_home<true>(a, L, hl, hb, he, tid, P.pre, P.pi, P.v0, P.v1, P.v2, P.pid));
-      if (tid == 0 && a.cell_start_out) {
-        a.cell_start_out[cell] = hb;
-        if (cell == nc0 * nc1 * nc2 - 1) a.cell_start_out[cell + 1] = he;
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) {
+        if (jr[r] >= 0) {
+          xr[r] = a.x[jr[r]];
+          yr[r] = a.x[a.n + jr[r]];
+          zr[r] = a.x[2 * a.n + jr[r]];
+        }
       }
-      if (more) slab_store(L, (k % 3) * kSlabCap, t_off[(k + 3) * 10 + ncs], tid, N);
-      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) {
+        const int q = q0 + r * kBlock + tid;
+        if (jr[r] >= 0) {
+          L.cjs[q] = jr[r];
+          L.cxs[q] = xr[r];
+          L.cys[q] = yr[r];
+          L.czs[q] = zr[r];
+        }
+      }
     }
   }
+  __syncthreads();
+  // work items: pair p of home cell k is item g = (pairs before cell k) + p,
+  // taken by wavefront g % 4
+  int g0 = 0;
+  const bool ywrap = nc1 < 3 || cy == 0 || cy == nc1 - 1;
+  const bool zwrap = nc2 < 3 || cz == 0 || cz == nc2 - 1;
+  for (int k = 0; k < nh; ++k) {
+    // LDS values the whole workgroup shares: kept in scalar registers
+    const int eo = (k + 1) * ncs + eh;
+    const int slot = __builtin_amdgcn_readfirstlane(g_off[eo]);
+    const int hb = __builtin_amdgcn_readfirstlane(g_start[eo]);
+    const int nhome = __builtin_amdgcn_readfirstlane(g_off[eo + 1]) - slot;
+    const int c0 = __builtin_amdgcn_readfirstlane(g_off[k * ncs]);
+    const int c1 = __builtin_amdgcn_readfirstlane(g_off[(k + 3) * ncs]);
+    const int first = (wave - g0) & (kBlock / kWave - 1);
+    const int cx = cx0 + k;
+    const int wm = (cx == 0 || cx == nc0 - 1 ? 1 : 0) | (ywrap ? 2 : 0) | (zwrap ? 4 : 0);
+    const int hidx = hb - hb0;
+    switch (wm) {
+      case 0: build_cell_pairs<0>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
+      case 1: build_cell_pairs<1>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
+      case 2: build_cell_pairs<2>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
+      case 3: build_cell_pairs<3>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
+      case 4: build_cell_pairs<4>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
+      case 5: build_cell_pairs<5>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
+      case 6: build_cell_pairs<6>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
+      default: build_cell_pairs<7>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
+    }
+    g0 += (nhome + 1) >> 1;
+    if (tid == 0 && a.cell_start_out) {
+      const int cell = (cz * nc1 + cy) * nc0 + cx;
+      a.cell_start_out[cell] = hb;
+      if (cell == nc0 * nc1 * nc2 - 1) a.cell_start_out[cell + 1] = hb + nhome;
+    }
+  }
+  __syncthreads();
+  // copies of the home atoms' state (home atom h - hb0 of the run: its cell k
+  // found by the run's cell boundaries, its LDS slot from the cell's)
+  for (int h = hb0 + tid; h < hend; h += kBlock) {
+    int k = 0;
+    while (k + 1 < nh && h >= g_start[(k + 2) * ncs + eh]) ++k;
+    const int eo = (k + 1) * ncs + eh;
+    const int slot = g_off[eo] + (h - g_start[eo]);
+    const int t = h - hb0;
+    mx = max(mx, t < kBlock ? L.hcnt[t]
+                            : __hip_atomic_load(&a.numneigh[h], __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT));
+    const bool mine = P.pre && t == tid;
+    finish_one<true>(a, L, slot, 0, h, mine, P.v0, P.v1, P.v2, P.pid);
+  }
+  __syncthreads();   // LDS tables and slabs are reused by the next segment
+  return mx;
+}
+
+// Sorted atoms, at least 3 cells along x: a resident grid working through
+// the row segments (build_row_segment).
+__global__ __launch_bounds__(kBlock) void k_build_rows(BuildArgs a) {
+  if (a.gate && *a.gate == 0) return;
+  __shared__ double cxs[kRowSlots], cys[kRowSlots], czs[kRowSlots];
+  __shared__ int cjs[kRowSlots];
+  __shared__ int hcnt[kBlock];
+  __shared__ int lbuf[(kBlock / kWave) * kListRow];
+  __shared__ int g_off[kRowCells9 + 1], g_start[kRowCells9];
+  __shared__ int st_start[27], st_off[28], st_meta[2];
+  __shared__ int red[kBlock / kWave];
+  __shared__ int big;
+  const BuildLds L{cxs, cys, czs, cjs, hcnt, lbuf};
+  const int nc0 = a.nc[0], nc1 = a.nc[1], nc2 = a.nc[2];
+  const int spr = (nc0 + kRowCells - 1) / kRowCells;   // row segments per row
+  const BlockRange br = xcd_range(spr * nc1 * nc2);
+  int mx = 0;
+  for (int wg = br.first; wg < br.end; wg += br.step)
+    mx = max(mx, build_row_segment(a, L, wg, g_off, g_start, st_start, st_off, st_meta, &big));
   report_max(a, mx, red);
 }
 
 inline unsigned blocks_for(int64_t n, int per = kBlock) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
+
+unsigned resident_grid(int per_cu, int64_t need) {
+  // compute-unit count per device, looked up once
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (cus[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        v <= 0)
+      v = 256;
+    cus[dev] = v;
+  }
+  const int64_t g = ((int64_t)cus[dev] * per_cu + kXcds - 1) / kXcds * kXcds;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, need));
+}
 
 hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t s) {
   if (count <= 0) return hipSuccess;
@@ -1077,7 +1292,7 @@ hipError_t launch_bin_count(double* x, int n, BoxK box, const int nc[3], int* at
 hipError_t launch_cell_count(const int* old_start, const int* atom_cell, const int nc[3],
                              int* count, int* scount, const int* gate, hipStream_t s) {
   const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
-  k_cell_count<<<blocks_for(ncell, kSuperCells), kCountBlock, 0, s>>>(
+  k_cell_count<<<resident_grid(2, blocks_for(ncell, kSuperCells)), kCountBlock, 0, s>>>(
       old_start, atom_cell, nc[0], nc[1], nc[2], count, scount, gate);
   return hipGetLastError();
 }
@@ -1103,7 +1318,7 @@ hipError_t launch_gather_sort(const int* old_start, int* new_start, const int* c
                               double* sx, double* sv, int* sid, int* status, const int* gate,
                               hipStream_t s) {
   const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
-  k_gather_sort<<<blocks_for(ncell * kWave), kBlock, 0, s>>>(
+  k_gather_sort<<<resident_grid(8, blocks_for(ncell * kWave)), kBlock, 0, s>>>(
       old_start, new_start, count, scount, atom_cell, nc[0], nc[1], nc[2], box, perm, xq, v, id, n,
       sx, sv, sid, status, gate);
   return hipGetLastError();
@@ -1134,8 +1349,8 @@ hipError_t launch_gather_int(const int* perm, int n, const int* src, int* dst, h
 
 hipError_t launch_build(const BuildArgs& a, hipStream_t s) {
   if (a.sorted && a.nc[0] >= 3) {
-    const unsigned segs = (unsigned)((a.nc[0] + kRowCells - 1) / kRowCells * a.nc[1] * a.nc[2]);
-    k_build_rows<<<segs, kBlock, 0, s>>>(a);
+    const int64_t segs = (int64_t)((a.nc[0] + kRowCells - 1) / kRowCells) * a.nc[1] * a.nc[2];
+    k_build_rows<<<resident_grid(3, segs), kBlock, 0, s>>>(a);
   } else {
     const unsigned ncell = (unsigned)(a.nc[0] * a.nc[1] * a.nc[2]);
     k_build<<<ncell, kBlock, 0, s>>>(a);

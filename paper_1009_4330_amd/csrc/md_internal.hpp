@@ -44,6 +44,22 @@ __device__ inline int xcd_block() {
   const int xcd = b % kXcds, local = b / kXcds;
   return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
 }
+// Logical blocks [0, nb) worked through by a grid of any size (a resident
+// grid looping over its share): the blocks of XCD x (physical blocks
+// x, x + 8, ...) take the contiguous chunk x of the logical range in strides
+// of their own count, so neighbouring logical blocks still share an L2.
+struct BlockRange {
+  int first, end, step;
+};
+__device__ inline BlockRange xcd_range(int nb) {
+  const int p = blockIdx.x, g = gridDim.x;
+  const int xcd = p % kXcds, local = p / kXcds;
+  const int phys = g / kXcds + (xcd < g % kXcds ? 1 : 0);   // physical blocks on this XCD
+  const int q = nb / kXcds, r = nb % kXcds;
+  const int lo = xcd * q + (xcd < r ? xcd : r);
+  return BlockRange{lo + local, lo + q + (xcd < r ? 1 : 0), phys};
+}
+
 constexpr int kSuperShift = 4;       // 16 cells per super-cell for the two-level cell scan
 constexpr int kSuperCells = 1 << kSuperShift;
 
@@ -182,6 +198,10 @@ WsLayout ws_layout(int64_t n, int64_t ncell);
 // (zero on entry) and records each atom's arrival slot in its cell.
 // launch_scan_cells turns the counts into cell_start.
 hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t s);
+// Workgroups that fit on the current device at once with `per_cu` of them per
+// compute unit (a multiple of 8), capped at `need`.
+unsigned resident_grid(int per_cu, int64_t need);
+
 hipError_t launch_bin_count(double* x, int n, BoxK box, const int nc[3], int* atom_cell,
                             int* count, int* slot, hipStream_t s);
 hipError_t launch_scan_cells(const int* count, int ncell, int* cell_start, hipStream_t s);
