@@ -956,74 +956,95 @@ __device__ inline void pair_image(double& dx, double& dy, double& dz, const BoxK
   if (WM & 4) dz = min_image(dz, box.L[2], box.inv[2]);
 }
 
-// Lists of home atoms i0 and (when two) i0 + 1, staged at LDS slots s0 and
-// s0 + 1, against the candidates in LDS slots [c0, c1).  64 candidates per
-// iteration, tested against both atoms; the next 64 are read from LDS while
-// these are tested.  Past c1 (last iteration) and at the home atoms' own slots
-// a scalar lane mask drops the candidate.  Accepted ones go, in candidate
-// order, through a ballot prefix count into the wavefront's LDS buffer
-// (anything past kListBuf straight into the list) and are copied into the
-// list layout when the pair is done.  hidx: index of i0 among the
-// workgroup's home atoms (for hcnt).
+// Home atoms tested together per candidate batch in the row path: each batch
+// of 64 candidates read from LDS serves kGroup independent distance chains.
+constexpr int kGroup = 4;
+constexpr int kGroupRow = kGroup * kListBuf;   // per wavefront: one buffer per home atom
+constexpr int kLbufRow = kGroupRow > kListRow ? kGroupRow : kListRow;
+
+// Lists of the nh (<= kGroup) consecutive home atoms i0, i0 + 1, ... staged
+// at LDS slots s0, s0 + 1, ..., against the candidates in LDS slots [c0, c1).
+// 64 candidates per iteration, tested against every atom of the group; the
+// next 64 are read from LDS while these are tested.  Past c1 (last
+// iteration) and at the home atoms' own slots a scalar lane mask drops the
+// candidate.  Accepted ones go, in candidate order, through a ballot prefix
+// count into the atom's LDS buffer (anything past kListBuf straight into the
+// list) and are copied into the list layout when the group is done.  hidx:
+// index of i0 among the workgroup's home atoms (for hcnt).
 template <int WM>
-__device__ inline void build_pair(const BuildArgs& a, const BuildLds& L, int c0, int c1, int s0,
-                                  int i0, bool two, int hidx, int lane, int wave) {
+__device__ inline void build_group(const BuildArgs& a, const BuildLds& L, int c0, int c1, int s0,
+                                   int i0, int nh, int hidx, int lane, int wave) {
   const int lk = __ffs(a.layout) - 1;
   const int gs = 6 - lk;
   const size_t rows = nl_rows(a.cap, a.layout);
   const double rl2 = a.rl2;
   const BoxK box = a.box;
-  int* __restrict__ lrow = L.lbuf + wave * kListRow;
-  const int k1 = two ? i0 + 1 : i0;
-  const double x0 = L.cxs[s0], y0 = L.cys[s0], z0 = L.czs[s0];
-  double x1 = L.cxs[s0 + 1], y1 = L.cys[s0 + 1], z1 = L.czs[s0 + 1];
-  if (!two) x1 = y1 = z1 = __builtin_nan("");
-  int* __restrict__ r0 =
-      a.neigh + (size_t)(i0 >> gs) * rows * kWave + ((i0 & ((1 << gs) - 1)) << lk);
-  int* __restrict__ r1 =
-      a.neigh + (size_t)(k1 >> gs) * rows * kWave + ((k1 & ((1 << gs) - 1)) << lk);
+  int* __restrict__ lrow = L.lbuf + wave * kLbufRow;
+  double hx[kGroup], hy[kGroup], hz[kGroup];
+  int* r[kGroup];
+  int cnt[kGroup];
+#pragma unroll
+  for (int g = 0; g < kGroup; ++g) {
+    // an atom past nh keeps NaN coordinates: it accepts nothing
+    hx[g] = g < nh ? L.cxs[s0 + g] : __builtin_nan("");
+    hy[g] = g < nh ? L.cys[s0 + g] : __builtin_nan("");
+    hz[g] = g < nh ? L.czs[s0 + g] : __builtin_nan("");
+    const int ig = g < nh ? i0 + g : i0;
+    r[g] = a.neigh + (size_t)(ig >> gs) * rows * kWave + ((ig & ((1 << gs) - 1)) << lk);
+    cnt[g] = 0;
+  }
   const int total = c1 - c0;
-  const int ks = s0 - c0;   // candidate index of i0 itself (i0 + 1 follows it)
-  int cnt0 = 0, cnt1 = 0;
-  // Test the 64 candidates (j, cx, cy, cz) of iteration t against both atoms.
+  const int ks = s0 - c0;   // candidate index of i0 itself (the others follow it)
+  // Test the 64 candidates (j, cx, cy, cz) of iteration t against the group.
   auto test = [&](int t, int j, double cx, double cy, double cz) {
-    double ax = x0 - cx, ay = y0 - cy, az = z0 - cz;
-    double bx = x1 - cx, by = y1 - cy, bz = z1 - cz;
-    pair_image<WM>(ax, ay, az, box);
-    pair_image<WM>(bx, by, bz, box);
-    const double ra = ax * ax + ay * ay + az * az;
-    const double rb = bx * bx + by * by + bz * bz;
-    // scalar masks: lanes inside the range, minus each home atom's own slot
+    unsigned long long m[kGroup];
+#pragma unroll
+    for (int g = 0; g < kGroup; ++g) {
+      double dx = hx[g] - cx, dy = hy[g] - cy, dz = hz[g] - cz;
+      pair_image<WM>(dx, dy, dz, box);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      m[g] = __builtin_amdgcn_ballot_w64(r2 < rl2);
+    }
+    // scalar masks, only in the (one or two) iterations that need them: lanes
+    // past the range, and each home atom's own slot
     const int rem = total - t;
-    const unsigned long long vm = rem >= kWave ? ~0ull : (1ull << rem) - 1ull;
     const int d = ks - t;
-    const unsigned long long self0 = (unsigned)d < (unsigned)kWave ? 1ull << d : 0ull;
-    const unsigned long long self1 =
-        (unsigned)(d + 1) < (unsigned)kWave ? 1ull << (d + 1) : 0ull;
-    const unsigned long long ma = __builtin_amdgcn_ballot_w64(ra < rl2) & (vm & ~self0);
-    const unsigned long long mb = __builtin_amdgcn_ballot_w64(rb < rl2) & (vm & ~self1);
-    const bool ta = __builtin_amdgcn_inverse_ballot_w64(ma);
-    const bool tb = __builtin_amdgcn_inverse_ballot_w64(mb);
-    // rank among this iteration's accepted candidates
-    const int la = __builtin_amdgcn_mbcnt_hi((unsigned)(ma >> 32),
-                                             __builtin_amdgcn_mbcnt_lo((unsigned)ma, 0u));
-    const int lb = __builtin_amdgcn_mbcnt_hi((unsigned)(mb >> 32),
-                                             __builtin_amdgcn_mbcnt_lo((unsigned)mb, 0u));
-    const int na = __popcll(ma), nb = __popcll(mb);
+    if (rem < kWave || (unsigned)(d + kGroup - 1) < (unsigned)(kWave + kGroup - 1)) {
+      const unsigned long long vm = rem >= kWave ? ~0ull : (1ull << rem) - 1ull;
+#pragma unroll
+      for (int g = 0; g < kGroup; ++g) {
+        const unsigned long long self =
+            (unsigned)(d + g) < (unsigned)kWave ? 1ull << (d + g) : 0ull;
+        m[g] &= vm & ~self;
+      }
+    }
+    int n[kGroup], rk[kGroup];
+    bool fits = true;
+#pragma unroll
+    for (int g = 0; g < kGroup; ++g) {
+      n[g] = __popcll(m[g]);
+      // rank among this iteration's accepted candidates
+      rk[g] = __builtin_amdgcn_mbcnt_hi((unsigned)(m[g] >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((unsigned)m[g], 0u));
+      fits = fits && cnt[g] + n[g] <= kListBuf;
+    }
     // accepted lanes append to the atom's LDS buffer at cnt + rank; past
     // kListBuf (wave-uniform, long lists only) entries go to the list itself
-    if (cnt0 + na <= kListBuf && cnt1 + nb <= kListBuf) {
-      if (ta) lrow[cnt0 + la] = j;
-      if (tb) lrow[kListBuf + cnt1 + lb] = j;
+    if (fits) {
+#pragma unroll
+      for (int g = 0; g < kGroup; ++g)
+        if (__builtin_amdgcn_inverse_ballot_w64(m[g])) lrow[g * kListBuf + cnt[g] + rk[g]] = j;
     } else {
-      const int pa = cnt0 + la, pb = cnt1 + lb;
-      if (ta && pa < kListBuf) lrow[pa] = j;
-      if (tb && pb < kListBuf) lrow[kListBuf + pb] = j;
-      if (ta && pa >= kListBuf && pa < a.cap) put_entry_apart(r0, pa, lk, j);
-      if (tb && pb >= kListBuf && pb < a.cap) put_entry_apart(r1, pb, lk, j);
+#pragma unroll
+      for (int g = 0; g < kGroup; ++g) {
+        const bool t = __builtin_amdgcn_inverse_ballot_w64(m[g]);
+        const int p = cnt[g] + rk[g];
+        if (t && p < kListBuf) lrow[g * kListBuf + p] = j;
+        if (t && p >= kListBuf && p < a.cap) put_entry_apart(r[g], p, lk, j);
+      }
     }
-    cnt0 += na;
-    cnt1 += nb;
+#pragma unroll
+    for (int g = 0; g < kGroup; ++g) cnt[g] += n[g];
   };
   // two register sets alternate: the next 64 candidates are read while the
   // current ones are tested
@@ -1047,28 +1068,30 @@ __device__ inline void build_pair(const BuildArgs& a, const BuildLds& L, int c0,
   // copy the buffered entries into the list layout (this wave's own LDS
   // rows; a wavefront's LDS accesses complete in order)
   __builtin_amdgcn_wave_barrier();
-  const int lim0 = min(min(cnt0, kListBuf), a.cap);
-  const int lim1 = min(min(cnt1, kListBuf), a.cap);
-  for (int m = lane; m < lim0; m += kWave) put_entry(r0, m, lk, lrow[m]);
-  for (int m = lane; m < lim1; m += kWave) put_entry(r1, m, lk, lrow[kListBuf + m]);
+#pragma unroll
+  for (int g = 0; g < kGroup; ++g) {
+    const int lim = g < nh ? min(min(cnt[g], kListBuf), a.cap) : 0;
+    for (int mm = lane; mm < lim; mm += kWave) put_entry(r[g], mm, lk, lrow[g * kListBuf + mm]);
+  }
   __builtin_amdgcn_wave_barrier();
   if (lane == 0) {
-    a.numneigh[i0] = cnt0;
-    if (hidx < kBlock) L.hcnt[hidx] = cnt0;
-    if (two) {
-      a.numneigh[i0 + 1] = cnt1;
-      if (hidx + 1 < kBlock) L.hcnt[hidx + 1] = cnt1;
+#pragma unroll
+    for (int g = 0; g < kGroup; ++g) {
+      if (g < nh) {
+        a.numneigh[i0 + g] = cnt[g];
+        if (hidx + g < kBlock) L.hcnt[hidx + g] = cnt[g];
+      }
     }
   }
 }
 
 template <int WM>
-__device__ inline void build_cell_pairs(const BuildArgs& a, const BuildLds& L, int c0, int c1,
-                                        int slot, int hb, int nhome, int hidx, int first,
-                                        int lane, int wave) {
-  for (int p = first; 2 * p < nhome; p += kBlock / kWave)
-    build_pair<WM>(a, L, c0, c1, slot + 2 * p, hb + 2 * p, 2 * p + 1 < nhome, hidx + 2 * p,
-                   lane, wave);
+__device__ inline void build_cell_groups(const BuildArgs& a, const BuildLds& L, int c0, int c1,
+                                         int slot, int hb, int nhome, int hidx, int first,
+                                         int lane, int wave) {
+  for (int p = first; kGroup * p < nhome; p += kBlock / kWave)
+    build_group<WM>(a, L, c0, c1, slot + kGroup * p, hb + kGroup * p,
+                    min(kGroup, nhome - kGroup * p), hidx + kGroup * p, lane, wave);
 }
 
 // Rank of c among the distinct cells {c - 1, c, c + 1} in increasing order
@@ -1181,8 +1204,8 @@ __device__ inline int build_row_segment(const BuildArgs& a, const BuildLds& L, i
     }
   }
   __syncthreads();
-  // work items: pair p of home cell k is item g = (pairs before cell k) + p,
-  // taken by wavefront g % 4
+  // work items: group p (kGroup home atoms) of home cell k is item
+  // g = (groups before cell k) + p, taken by wavefront g % 4
   int g0 = 0;
   const bool ywrap = nc1 < 3 || cy == 0 || cy == nc1 - 1;
   const bool zwrap = nc2 < 3 || cz == 0 || cz == nc2 - 1;
@@ -1199,16 +1222,16 @@ __device__ inline int build_row_segment(const BuildArgs& a, const BuildLds& L, i
     const int wm = (cx == 0 || cx == nc0 - 1 ? 1 : 0) | (ywrap ? 2 : 0) | (zwrap ? 4 : 0);
     const int hidx = hb - hb0;
     switch (wm) {
-      case 0: build_cell_pairs<0>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
-      case 1: build_cell_pairs<1>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
-      case 2: build_cell_pairs<2>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
-      case 3: build_cell_pairs<3>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
-      case 4: build_cell_pairs<4>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
-      case 5: build_cell_pairs<5>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
-      case 6: build_cell_pairs<6>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
-      default: build_cell_pairs<7>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
+      case 0: build_cell_groups<0>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
+      case 1: build_cell_groups<1>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
+      case 2: build_cell_groups<2>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
+      case 3: build_cell_groups<3>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
+      case 4: build_cell_groups<4>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
+      case 5: build_cell_groups<5>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
+      case 6: build_cell_groups<6>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
+      default: build_cell_groups<7>(a, L, c0, c1, slot, hb, nhome, hidx, first, lane, wave); break;
     }
-    g0 += (nhome + 1) >> 1;
+    g0 += (nhome + kGroup - 1) / kGroup;
     if (tid == 0 && a.cell_start_out) {
       const int cell = (cz * nc1 + cy) * nc0 + cx;
       a.cell_start_out[cell] = hb;
@@ -1241,7 +1264,7 @@ __global__ __launch_bounds__(kBlock) void k_build_rows(BuildArgs a) {
   __shared__ double cxs[kRowSlots], cys[kRowSlots], czs[kRowSlots];
   __shared__ int cjs[kRowSlots];
   __shared__ int hcnt[kBlock];
-  __shared__ int lbuf[(kBlock / kWave) * kListRow];
+  __shared__ int lbuf[(kBlock / kWave) * kLbufRow];
   __shared__ int g_off[kRowCells9 + 1], g_start[kRowCells9];
   __shared__ int st_start[27], st_off[28], st_meta[2];
   __shared__ int red[kBlock / kWave];
