@@ -44,13 +44,18 @@ __device__ inline __amdgpu_buffer_rsrc_t buffer_of(const double* p, int n_record
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), (short)0,
                                            (int)((unsigned)n_records * 32u), kBufWord3);
 }
-// x and y of a record (one 16-byte load), z (8 bytes at +16).
-__device__ inline f64x2 load_xy(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+// 16 bytes of the packed records: (x, y) at +0, (z, pad) at +16.
+__device__ inline f64x2 load16(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
   return __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)byte_off, 0, 0));
 }
-__device__ inline double load_z(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
-  return __builtin_bit_cast(double,
-                            __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 16, 0));
+
+// Value of the partner lane (lane ^ 1): a quad permute [1, 0, 3, 2].
+__device__ inline int swap_pair(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+}
+__device__ inline double swap_pair(double v) {
+  const int2 w = __builtin_bit_cast(int2, v);
+  return __builtin_bit_cast(double, make_int2(swap_pair(w.x), swap_pair(w.y)));
 }
 // Home atom position (plain loads).
 __device__ inline void home_pos(const FK& a, int i, double& x, double& y, double& z) {
@@ -146,20 +151,42 @@ struct XView {
   __amdgpu_buffer_rsrc_t r;   // the packed [n][4] positions
 };
 
-template <int K, bool WRAP>
+// PAIRED: lanes 2m and 2m + 1 fetch their two records together.  In each
+// 16-byte load both lanes of the pair read the same record (one cache-line
+// lookup instead of two), the even lane's record first, then the odd lane's;
+// each lane then holds its own (x, y) and its partner's z, and one lane swap
+// hands every lane its own z.  That trades L1 tag lookups for 8 more bytes
+// per entry and a few vector instructions: a gain where the pair arithmetic
+// leaves the vector ALUs room (FP32-mixed), a loss in FP64.  Otherwise each
+// lane reads (x, y) and z of its own record with a 16- and an 8-byte load.
+template <int K, bool WRAP, bool PAIRED>
 __device__ inline void load_batch(const FK& a, const XView& xv, const Lane<K>& ln, int t,
                                   int* jn, double xi, double yi, double zi, Batch& b) {
   double xj[kUnroll], yj[kUnroll], zj[kUnroll];
+  const bool odd = (threadIdx.x & 1) != 0;
+  const unsigned half = odd ? 16u : 0u;
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) {
     // entries past the lane's count are never used as indices: atom 0 stands in
     b.ok[u] = t + u < ln.count;
     b.j[u] = b.ok[u] ? jn[u] : 0;
-    const unsigned off = (unsigned)b.j[u] * 32u;
-    const f64x2 xy = load_xy(xv.r, off);
-    xj[u] = xy.x;
-    yj[u] = xy.y;
-    zj[u] = load_z(xv.r, off);
+    if (PAIRED) {
+      const int pj = swap_pair(b.j[u]);
+      const unsigned je = (unsigned)(odd ? pj : b.j[u]);   // the even lane's entry
+      const unsigned jo = (unsigned)(odd ? b.j[u] : pj);   // the odd lane's entry
+      const f64x2 p = load16(xv.r, je * 32u + half);         // even: x, y of je; odd: z of je
+      const f64x2 q = load16(xv.r, jo * 32u + (16u - half));  // even: z of jo; odd: x, y of jo
+      zj[u] = swap_pair(odd ? p.x : q.x);
+      xj[u] = odd ? q.x : p.x;
+      yj[u] = odd ? q.y : p.y;
+    } else {
+      const unsigned off = (unsigned)b.j[u] * 32u;
+      const f64x2 xy = load16(xv.r, off);
+      xj[u] = xy.x;
+      yj[u] = xy.y;
+      zj[u] = __builtin_bit_cast(double,
+                                 __builtin_amdgcn_raw_buffer_load_b64(xv.r, (int)off, 16, 0));
+    }
   }
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) jn[u] = ln.entry(t + kUnroll + u);
@@ -183,7 +210,7 @@ __device__ inline XView xview(const FK& a) { return XView{buffer_of(a.xq, a.n)};
 // Runs body(batch) over the wavefront's list entries (a uniform loop to the
 // largest count).  The choice between the plain and the minimum-image
 // separation is uniform over the wavefront.
-template <int K, typename F>
+template <int K, bool PAIRED, typename F>
 __device__ inline void for_each_batch(const FK& a, const Lane<K>& ln, double xi, double yi,
                                       double zi, F&& body) {
   const XView xv = xview(a);
@@ -193,13 +220,13 @@ __device__ inline void for_each_batch(const FK& a, const Lane<K>& ln, double xi,
   if (__all(interior(xi, yi, zi, a))) {
     for (int t = 0; t < ln.tmax; t += kUnroll) {
       Batch b;
-      load_batch<K, false>(a, xv, ln, t, jn, xi, yi, zi, b);
+      load_batch<K, false, PAIRED>(a, xv, ln, t, jn, xi, yi, zi, b);
       body(b);
     }
   } else {
     for (int t = 0; t < ln.tmax; t += kUnroll) {
       Batch b;
-      load_batch<K, true>(a, xv, ln, t, jn, xi, yi, zi, b);
+      load_batch<K, true, PAIRED>(a, xv, ln, t, jn, xi, yi, zi, b);
       body(b);
     }
   }
@@ -345,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_lj(FK a, LJK p) {
   double xi, yi, zi;
   home_pos(a, io, xi, yi, zi);
   Acc acc;
-  for_each_batch<K>(a, ln, xi, yi, zi, [&](const Batch& b) {
+  for_each_batch<K, PREC == MD_MIXED>(a, ln, xi, yi, zi, [&](const Batch& b) {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       // every lane evaluates the pair function; pairs outside the cutoff or
@@ -386,7 +413,7 @@ __global__ __launch_bounds__(kBlock) void k_sc_density(FK a, SCK p, double* __re
   double xi, yi, zi;
   home_pos(a, io, xi, yi, zi);
   double rho = 0.0;
-  for_each_batch<K>(a, ln, xi, yi, zi, [&](const Batch& b) {
+  for_each_batch<K, PREC == MD_MIXED>(a, ln, xi, yi, zi, [&](const Batch& b) {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       if (b.ok[u] && b.s[u] < p.rc2) {
@@ -415,7 +442,7 @@ __global__ __launch_bounds__(kBlock) void k_sc_force(FK a, SCK p,
   home_pos(a, io, xi, yi, zi);
   const double ei = e_in[io];
   Acc acc;
-  for_each_batch<K>(a, ln, xi, yi, zi, [&](const Batch& b) {
+  for_each_batch<K, PREC == MD_MIXED>(a, ln, xi, yi, zi, [&](const Batch& b) {
     double ej[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) ej[u] = e_in[b.j[u]];
@@ -471,7 +498,7 @@ __global__ __launch_bounds__(kBlock) void k_lj_vjp(FK a, LJK p, const double* __
   home_pos(a, io, xi, yi, zi);
   const double uxi = u[io], uyi = u[n + io], uzi = u[2 * n + io];
   double gxa = 0, gya = 0, gza = 0, fx = 0, fy = 0, fz = 0, dsig = 0;
-  for_each_batch<K>(a, ln, xi, yi, zi, [&](const Batch& b) {
+  for_each_batch<K, PREC == MD_MIXED>(a, ln, xi, yi, zi, [&](const Batch& b) {
     double ux[kUnroll], uy[kUnroll], uz[kUnroll];
 #pragma unroll
     for (int q = 0; q < kUnroll; ++q) {
