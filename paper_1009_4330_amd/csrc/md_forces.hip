@@ -49,10 +49,18 @@ __device__ inline f64x2 load16(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
   return __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)byte_off, 0, 0));
 }
 
+// 12 bytes of the packed records: bytes [0, 12) are x and the low word of y,
+// bytes [12, 24) the high word of y and z.
+using u32x3 = unsigned __attribute__((ext_vector_type(3)));
+__device__ inline u32x3 load12(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+  return __builtin_bit_cast(u32x3, __builtin_amdgcn_raw_buffer_load_b96(r, (int)byte_off, 0, 0));
+}
+
 // Value of the partner lane (lane ^ 1): a quad permute [1, 0, 3, 2].
 __device__ inline int swap_pair(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
 }
+__device__ inline unsigned swap_pair(unsigned v) { return (unsigned)swap_pair((int)v); }
 __device__ inline double swap_pair(double v) {
   const int2 w = __builtin_bit_cast(int2, v);
   return __builtin_bit_cast(double, make_int2(swap_pair(w.x), swap_pair(w.y)));
@@ -152,19 +160,18 @@ struct XView {
 };
 
 // PAIRED: lanes 2m and 2m + 1 fetch their two records together.  In each
-// 16-byte load both lanes of the pair read the same record (one cache-line
-// lookup instead of two), the even lane's record first, then the odd lane's;
-// each lane then holds its own (x, y) and its partner's z, and one lane swap
-// hands every lane its own z.  That trades L1 tag lookups for 8 more bytes
-// per entry and a few vector instructions: a gain where the pair arithmetic
-// leaves the vector ALUs room (FP32-mixed), a loss in FP64.  Otherwise each
-// lane reads (x, y) and z of its own record with a 16- and an 8-byte load.
+// 12-byte load both lanes of the pair read one record (one cache-line lookup
+// instead of two, and the 24 bytes the record holds), the even lane's record
+// first, then the odd lane's; each lane then holds the first half of its own
+// record and the second half of its partner's, and a three-word lane swap
+// completes every lane's record.  Otherwise each lane reads (x, y) and z of
+// its own record with a 16- and an 8-byte load.
 template <int K, bool WRAP, bool PAIRED>
 __device__ inline void load_batch(const FK& a, const XView& xv, const Lane<K>& ln, int t,
                                   int* jn, double xi, double yi, double zi, Batch& b) {
   double xj[kUnroll], yj[kUnroll], zj[kUnroll];
   const bool odd = (threadIdx.x & 1) != 0;
-  const unsigned half = odd ? 16u : 0u;
+  const unsigned half = odd ? 12u : 0u;
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) {
     // entries past the lane's count are never used as indices: atom 0 stands in
@@ -174,11 +181,16 @@ __device__ inline void load_batch(const FK& a, const XView& xv, const Lane<K>& l
       const int pj = swap_pair(b.j[u]);
       const unsigned je = (unsigned)(odd ? pj : b.j[u]);   // the even lane's entry
       const unsigned jo = (unsigned)(odd ? b.j[u] : pj);   // the odd lane's entry
-      const f64x2 p = load16(xv.r, je * 32u + half);         // even: x, y of je; odd: z of je
-      const f64x2 q = load16(xv.r, jo * 32u + (16u - half));  // even: z of jo; odd: x, y of jo
-      zj[u] = swap_pair(odd ? p.x : q.x);
-      xj[u] = odd ? q.x : p.x;
-      yj[u] = odd ? q.y : p.y;
+      // first halves (x, low word of y) to the owner, second halves (high
+      // word of y, z) to the partner, which hands them back with one swap
+      const u32x3 p = load12(xv.r, je * 32u + half);          // even: first half of je
+      const u32x3 q = load12(xv.r, jo * 32u + (12u - half));  // even: second half of jo
+      const u32x3 own = odd ? q : p;
+      const u32x3 give = odd ? p : q;
+      const unsigned r0 = swap_pair(give.x), r1 = swap_pair(give.y), r2 = swap_pair(give.z);
+      xj[u] = __builtin_bit_cast(double, make_uint2(own.x, own.y));
+      yj[u] = __builtin_bit_cast(double, make_uint2(own.z, r0));
+      zj[u] = __builtin_bit_cast(double, make_uint2(r1, r2));
     } else {
       const unsigned off = (unsigned)b.j[u] * 32u;
       const f64x2 xy = load16(xv.r, off);
