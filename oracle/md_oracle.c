@@ -18,8 +18,9 @@
  *   - a full Verlet list: every ordered pair (i, j), i != j, whose minimum-
  *     image separation satisfies r^2 < r_l^2, r_l = r_c + skin (the per-atom
  *     neighbor loop of the TpA/BpA listings reads such a list);
- *   - 12-6 Lennard-Jones (lj/cut of Appendix A) and analytic Sutton-Chen
- *     (standing in for the EAM system of Appendix A) forces, energy, virial;
+ *   - 12-6 Lennard-Jones (lj/cut of Appendix A), analytic Sutton-Chen
+ *     (standing in for the EAM system of Appendix A) and Buckingham + cut
+ *     Coulomb (the silicate system of Appendix A) forces, energy, virial;
  *   - velocity-Verlet NVE integration ("NVE integrator", section "Design
  *     objectives") with a rebuild of the list whenever an atom moved more than
  *     skin/2 since the last build;
@@ -239,6 +240,71 @@ int orc_lj_forces(int64_t n, const double* x, const double* L, const int* numnei
   return ORC_OK;
 }
 
+/* ------------------------------------------ Buckingham + cut Coulomb -- */
+
+/* Buckingham with a plain cut Coulomb term (buck/coul/cut, the potential of
+   Appendix A's silicate system), one cutoff rc for both terms:
+     phi_ab(r) = A_ab exp(-r / rho_ab) - C_ab / r^6 + qqr2e q_a q_b / r,  r < rc,
+   a = type[i], b = type[j] (species 0..3; tables indexed a * 4 + b).  With
+     dphi/dr = -(A_ab / rho_ab) exp(-r / rho_ab) + 6 C_ab / r^7 - qqr2e q_a q_b / r^2
+   the force on i from j is F_ij = -(dphi/dr) d / r, d = x_i - x_j (minimum
+   image).  No energy shift at rc.  Outputs as for LJ. */
+int orc_buck_forces(int64_t n, const double* x, const double* L, const int* numneigh,
+                    const int* neigh, int cap, double rc, const int* type, const double* A,
+                    const double* rho, const double* C, const double* q, double qqr2e,
+                    double* f, double* eatom, double* vatom, double* energy, double* virial) {
+  if (n <= 0 || !x || !numneigh || !neigh || !f || !type || !A || !rho || !C || !q)
+    return ORC_EINVAL;
+  for (int64_t i = 0; i < n; ++i)
+    if (type[i] < 0 || type[i] > 3) return ORC_EINVAL;
+  const double rc2 = rc * rc;
+  double* ea = (double*)calloc((size_t)n, sizeof(double));
+  double* va = (double*)calloc((size_t)n * 6, sizeof(double));
+  if (!ea || !va) { free(ea); free(va); return ORC_EINVAL; }
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double fi[3] = {0.0, 0.0, 0.0}, ei = 0.0, wi[6] = {0, 0, 0, 0, 0, 0};
+    int cnt = numneigh[i] < cap ? numneigh[i] : cap;
+    for (int k = 0; k < cnt; ++k) {
+      int64_t j = neigh[i * (int64_t)cap + k];
+      double d[3];
+      double s = dist2(x, n, L, i, j, d);
+      if (!(s < rc2)) continue;
+      int ab = type[i] * 4 + type[j];
+      double r = sqrt(s);
+      double ex = A[ab] * exp(-r / rho[ab]);
+      double r6 = s * s * s;
+      double qq = qqr2e * q[type[i]] * q[type[j]];
+      double phi = ex - C[ab] / r6 + qq / r;
+      double dphidr = -ex / rho[ab] + 6.0 * C[ab] / (r6 * r) - qq / s;
+      double g = -dphidr / r;
+      for (int c = 0; c < 3; ++c) fi[c] += g * d[c];
+      ei += 0.5 * phi;
+      wi[0] += 0.5 * d[0] * d[0] * g;
+      wi[1] += 0.5 * d[1] * d[1] * g;
+      wi[2] += 0.5 * d[2] * d[2] * g;
+      wi[3] += 0.5 * d[0] * d[1] * g;
+      wi[4] += 0.5 * d[0] * d[2] * g;
+      wi[5] += 0.5 * d[1] * d[2] * g;
+    }
+    for (int c = 0; c < 3; ++c) f[c * n + i] = fi[c];
+    ea[i] = ei;
+    for (int c = 0; c < 6; ++c) va[c * n + i] = wi[c];
+  }
+  double et = 0.0, vt[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t i = 0; i < n; ++i) {
+    et += ea[i];
+    for (int c = 0; c < 6; ++c) vt[c] += va[c * n + i];
+  }
+  if (eatom) memcpy(eatom, ea, sizeof(double) * (size_t)n);
+  if (vatom) memcpy(vatom, va, sizeof(double) * (size_t)n * 6);
+  if (energy) *energy = et;
+  if (virial) for (int c = 0; c < 6; ++c) virial[c] = vt[c];
+  free(ea);
+  free(va);
+  return ORC_OK;
+}
+
 /* --------------------------------------------------------- Sutton-Chen -- */
 
 /* Sutton-Chen (Phil. Mag. Lett. 61, 139 (1990)), truncated at rc:
@@ -375,13 +441,15 @@ int orc_lj_vjp(int64_t n, const double* x, const double* L, const int* numneigh,
 /* ------------------------------------------------------ NVE integration -- */
 
 typedef struct {
-  int kind;                      /* 0 = Lennard-Jones, 1 = Sutton-Chen */
+  int kind;                      /* 0 = Lennard-Jones, 1 = Sutton-Chen, 2 = Buckingham + Coulomb */
   double rc, skin;
   double lj_eps, lj_sigma;
   int lj_shift;
   double sc_eps, sc_a, sc_c;
   int sc_n, sc_m;
   double mass, dt, ftm2v, mvv2e, boltz;
+  double buck_A[16], buck_rho[16], buck_C[16], q[4], qqr2e;
+  const int* type;               /* kind 2: species per atom, input order */
 } orc_params;
 
 typedef struct {                 /* per-run working storage */
@@ -411,6 +479,9 @@ static int forces(const orc_params* p, int64_t n, const double* x, const double*
   if (p->kind == 0)
     return orc_lj_forces(n, x, L, w->numneigh, w->neigh, w->cap, p->rc, p->lj_eps,
                          p->lj_sigma, p->lj_shift, f, NULL, NULL, pe, vir);
+  if (p->kind == 2)
+    return orc_buck_forces(n, x, L, w->numneigh, w->neigh, w->cap, p->rc, p->type, p->buck_A,
+                           p->buck_rho, p->buck_C, p->q, p->qqr2e, f, NULL, NULL, pe, vir);
   return orc_sc_forces(n, x, L, w->numneigh, w->neigh, w->cap, p->rc, p->sc_eps, p->sc_a,
                        p->sc_c, p->sc_n, p->sc_m, f, NULL, NULL, NULL, pe, vir);
 }

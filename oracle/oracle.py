@@ -88,7 +88,10 @@ class Params(ctypes.Structure):
                 ("sc_a", ctypes.c_double), ("sc_c", ctypes.c_double), ("sc_n", ctypes.c_int),
                 ("sc_m", ctypes.c_int), ("mass", ctypes.c_double), ("dt", ctypes.c_double),
                 ("ftm2v", ctypes.c_double), ("mvv2e", ctypes.c_double),
-                ("boltz", ctypes.c_double)]
+                ("boltz", ctypes.c_double), ("buck_A", ctypes.c_double * 16),
+                ("buck_rho", ctypes.c_double * 16), ("buck_C", ctypes.c_double * 16),
+                ("q", ctypes.c_double * 4), ("qqr2e", ctypes.c_double),
+                ("type", ctypes.c_void_p)]
 
 
 def _declare(L):
@@ -104,12 +107,15 @@ def _declare(L):
     L.orc_sc_forces.argtypes = [_i64, _dp, _dp, _ip, _ip, ctypes.c_int, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_buck_forces.argtypes = [_i64, _dp, _dp, _ip, _ip, ctypes.c_int, ctypes.c_double,
+                                  _ip, _dp, _dp, _dp, _dp, ctypes.c_double, _dp, _dp, _dp,
+                                  _dp, _dp]
     L.orc_lj_vjp.argtypes = [_i64, _dp, _dp, _ip, _ip, ctypes.c_int, ctypes.c_double,
                              ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
     L.orc_md_run.argtypes = [ctypes.POINTER(Params), _i64, _dp, _dp, _dp, ctypes.c_int,
                              ctypes.c_int, ctypes.c_int, _dp, _ip, _dp]
     for name in ("orc_cell_dims", "orc_bin", "orc_build_nlist", "orc_lj_forces",
-                 "orc_sc_forces", "orc_lj_vjp", "orc_md_run"):
+                 "orc_sc_forces", "orc_buck_forces", "orc_lj_vjp", "orc_md_run"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -254,6 +260,36 @@ def sc_forces(x, box, nl: NList, rc, eps, a, c, nexp, mexp) -> ForceResult:
     return ForceResult(f, float(e[0]), w, ea, va, rho)
 
 
+def buck_tables(pairs):
+    """Symmetric 4 x 4 table (flattened a * 4 + b) from ((a, b), value) pairs."""
+    t = np.zeros(16)
+    for (a, b), val in pairs:
+        t[a * 4 + b] = val
+        t[b * 4 + a] = val
+    return t
+
+
+def buck_forces(x, box, nl: NList, rc, types, A, rho, C, q, qqr2e) -> ForceResult:
+    """Buckingham + cut Coulomb; A, rho, C: 16-entry tables (a * 4 + b), q: 4
+    charges per species, types: species per atom.  Entries of rho for pairs
+    that never occur may be anything nonzero."""
+    x = _f64(x)
+    n = x.shape[1]
+    types = np.ascontiguousarray(types, dtype=np.int32)
+    rho = np.where(np.asarray(rho, float) == 0.0, 1.0, np.asarray(rho, float))
+    f = np.zeros((3, n))
+    ea = np.zeros(n)
+    va = np.zeros((6, n))
+    e = np.zeros(1)
+    w = np.zeros(6)
+    st = lib().orc_buck_forces(n, _d(x), _d(_f64(box)), _i(nl.numneigh), _i(nl.neigh), nl.cap,
+                               rc, _i(types), _d(_f64(A)), _d(_f64(rho)), _d(_f64(C)),
+                               _d(_f64(q)), qqr2e, _d(f), _d(ea), _d(va), _d(e), _d(w))
+    if st:
+        raise OracleError(st, "buck_forces")
+    return ForceResult(f, float(e[0]), w, ea, va)
+
+
 def lj_vjp(x, box, nl: NList, rc, eps, sigma, u):
     """Returns (gx [3][N], gparam [2] = dL/deps, dL/dsigma)."""
     x = _f64(x)
@@ -268,12 +304,26 @@ def lj_vjp(x, box, nl: NList, rc, eps, sigma, u):
     return gx, gp
 
 
+_KIND = {"lj": 0, "sc": 1, "buck": 2}
+
+
 def params_for(w, **over) -> Params:
-    """orc_params for a Workload (paper_1009_4330_amd.inputs.Workload)."""
-    p = Params(kind=0 if w.potential == "lj" else 1, rc=w.rc, skin=w.skin, lj_eps=w.lj_eps,
+    """orc_params for a Workload (paper_1009_4330_amd.inputs.Workload).  For
+    the Buckingham workload the species array (input order) is kept alive on
+    the returned object."""
+    p = Params(kind=_KIND[w.potential], rc=w.rc, skin=w.skin, lj_eps=w.lj_eps,
                lj_sigma=w.lj_sigma, lj_shift=w.lj_shift, sc_eps=w.sc_eps, sc_a=w.sc_a,
                sc_c=w.sc_c, sc_n=w.sc_n, sc_m=w.sc_m, mass=w.mass, dt=w.dt,
                ftm2v=w.units.ftm2v, mvv2e=w.units.mvv2e, boltz=w.units.boltz)
+    if w.potential == "buck":
+        p.buck_A[:] = buck_tables(w.buck_A)
+        rho = buck_tables(w.buck_rho)
+        p.buck_rho[:] = np.where(rho == 0.0, 1.0, rho)
+        p.buck_C[:] = buck_tables(w.buck_C)
+        p.q[:] = list(w.charges) + [0.0] * (4 - len(w.charges))
+        p.qqr2e = w.qqr2e
+        p._types = np.ascontiguousarray(w.species(), dtype=np.int32)
+        p.type = p._types.ctypes.data
     for k, v in over.items():
         setattr(p, k, v)
     return p

@@ -45,9 +45,9 @@ METAL_UNITS = Units(METAL_FTM2V, METAL_MVV2E, METAL_BOLTZ)
 class Workload:
     """One synthetic MD system: lattice, potential and run parameters."""
     name: str
-    ncell: int                 # fcc unit cells per box edge
+    ncell: int                 # cubic unit cells per box edge
     a: float                   # lattice constant
-    potential: str             # "lj" or "sc"
+    potential: str             # "lj", "sc" or "buck"
     rc: float
     skin: float
     dt: float
@@ -66,10 +66,24 @@ class Workload:
     sc_c: float = 0.0
     sc_n: int = 0
     sc_m: int = 0
+    # Buckingham + cut Coulomb: {(a, b): value} per species pair, charges per
+    # species, the Coulomb constant in the workload's units
+    lattice: str = "fcc"       # "fcc" (4 atoms per cell) or "rocksalt" (8, two species)
+    buck_A: tuple = ()
+    buck_rho: tuple = ()
+    buck_C: tuple = ()
+    charges: tuple = ()
+    qqr2e: float = 0.0
 
     @property
     def natoms(self) -> int:
-        return 4 * self.ncell ** 3
+        return (8 if self.lattice == "rocksalt" else 4) * self.ncell ** 3
+
+    def species(self) -> np.ndarray:
+        """Species per atom in the order of initial_state's positions."""
+        if self.lattice != "rocksalt":
+            return np.zeros(self.natoms, np.int32)
+        return np.tile(np.array([0, 0, 0, 0, 1, 1, 1, 1], np.int32), self.ncell ** 3)
 
     @property
     def box(self) -> tuple:
@@ -96,10 +110,32 @@ SC_500K = Workload("sc_cu_500k", 50, 3.61, "sc", 7.22, 1.0, 0.001, 200, 600.0, 5
                    mass=63.55, units=METAL_UNITS, sc_eps=1.2382e-2, sc_a=3.61,
                    sc_c=39.432, sc_n=9, sc_m=6)
 LJ_FM_32K = Workload("lj_fm_32k", 20, A_LJ, "lj", 2.5, 0.3, 0.005, 500, 1.5, 1)
+
+# The paper's second system (Appendix A "Silicate (cutoff)") uses Buckingham +
+# cut Coulomb at 15 A cutoff, number density 0.09 A^-3 and 600 K, with
+# parameters it does not print.  Stand-in: a two-species rocksalt ionic
+# crystal at that density (a = (8 / 0.09)^(1/3) A), charges +-2 e and
+# Buckingham terms of magnitudes typical of oxide models; one mass for both
+# species (the kernels assume uniform mass).  All values are synthetic.  At
+# 26^3 cells the box holds 140,608 atoms, about the paper's 139,968.
+# The lattice constant puts the 15 A cutoff between two shells of the ion
+# lattice (spacing a/2: shells at a/2 sqrt(46) = 14.85 A and a/2 sqrt(48) =
+# 15.16 A), so that thermal motion seldom carries a pair across it (with a
+# plain cut Coulomb every crossing changes the energy by qqr2e q_a q_b / rc);
+# number density 8 / a^3 = 0.0954 A^-3, close to the paper's 0.09.
+A_BUCK = 4.377
+QQR2E_METAL = 14.399645        # e^2 / (4 pi eps0) in eV A
+BUCK_KW = dict(mass=20.0, units=METAL_UNITS, lattice="rocksalt",
+               buck_A=(((0, 1), 1500.0), ((1, 1), 20000.0)),
+               buck_rho=(((0, 1), 0.30), ((1, 1), 0.15)),
+               buck_C=(((1, 1), 30.0),),
+               charges=(2.0, -2.0), qqr2e=QQR2E_METAL)
+BUCK_141K = Workload("buck_coul_141k", 26, A_BUCK, "buck", 15.0, 2.0, 0.001, 100, 600.0,
+                     140608, **BUCK_KW)
 FM_SEEDS = tuple(range(1, 9))
 FM_TARGET = (1.1, 1.05)        # (eps, sigma) that generate the target forces
 
-WORKLOADS = {w.name: w for w in (LJ_4K, LJ_256K, LJ_HI_108K, SC_500K, LJ_FM_32K)}
+WORKLOADS = {w.name: w for w in (LJ_4K, LJ_256K, LJ_HI_108K, SC_500K, LJ_FM_32K, BUCK_141K)}
 
 
 def scaled(w: Workload, ncell: int, **kw) -> Workload:
@@ -146,9 +182,32 @@ def random_unit_vectors(n: int, seed: int) -> np.ndarray:
     return np.ascontiguousarray(rng.standard_normal((3, n)))
 
 
+def rocksalt_positions(ncell: int, a: float) -> np.ndarray:
+    """Rocksalt lattice, SoA float64 [3][N]: per cubic cell the four fcc
+    sites (species 0) then the same sites shifted by a/2 along x (species 1)."""
+    idx = np.arange(ncell, dtype=np.float64)
+    cz, cy, cx = np.meshgrid(idx, idx, idx, indexing="ij")
+    out = np.empty((3, ncell, ncell, ncell, 8), dtype=np.float64)
+    for s, shift in enumerate((0.0, 0.5)):
+        for b, (bx, by, bz) in enumerate(FCC_BASIS):
+            out[0, ..., 4 * s + b] = (cx + bx + shift) * a
+            out[1, ..., 4 * s + b] = (cy + by) * a
+            out[2, ..., 4 * s + b] = (cz + bz) * a
+    return np.ascontiguousarray(out.reshape(3, -1))
+
+
+def pair_table(w: Workload, which: str) -> np.ndarray:
+    """Symmetric 4 x 4 table (flattened a * 4 + b) of a Buckingham parameter."""
+    t = np.zeros(16)
+    for (a, b), val in getattr(w, which):
+        t[a * 4 + b] = val
+        t[b * 4 + a] = val
+    return t
+
+
 def initial_state(w: Workload, seed: Optional[int] = None):
     """(x, v, box) for a workload: perfect lattice + Gaussian velocities."""
-    x = fcc_positions(w.ncell, w.a)
+    x = rocksalt_positions(w.ncell, w.a) if w.lattice == "rocksalt" else fcc_positions(w.ncell, w.a)
     v = gaussian_velocities(w.natoms, w.temp, w.mass, w.units,
                             w.seed if seed is None else seed)
     return x, v, w.box
