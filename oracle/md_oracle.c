@@ -263,7 +263,7 @@ int orc_buck_forces(int64_t n, const double* x, const double* L, const int* numn
   if (!ea || !va) { free(ea); free(va); return ORC_EINVAL; }
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
-    double fi[3] = {0.0, 0.0, 0.0}, ei = 0.0, wi[6] = {0, 0, 0, 0, 0, 0};
+    double fb[3] = {0.0, 0.0, 0.0}, eb = 0.0, wb[6] = {0, 0, 0, 0, 0, 0};
     int cnt = numneigh[i] < cap ? numneigh[i] : cap;
     for (int k = 0; k < cnt; ++k) {
       int64_t j = neigh[i * (int64_t)cap + k];
@@ -278,18 +278,18 @@ int orc_buck_forces(int64_t n, const double* x, const double* L, const int* numn
       double phi = ex - C[ab] / r6 + qq / r;
       double dphidr = -ex / rho[ab] + 6.0 * C[ab] / (r6 * r) - qq / s;
       double g = -dphidr / r;
-      for (int c = 0; c < 3; ++c) fi[c] += g * d[c];
-      ei += 0.5 * phi;
-      wi[0] += 0.5 * d[0] * d[0] * g;
-      wi[1] += 0.5 * d[1] * d[1] * g;
-      wi[2] += 0.5 * d[2] * d[2] * g;
-      wi[3] += 0.5 * d[0] * d[1] * g;
-      wi[4] += 0.5 * d[0] * d[2] * g;
-      wi[5] += 0.5 * d[1] * d[2] * g;
+      for (int c = 0; c < 3; ++c) fb[c] += g * d[c];
+      eb += 0.5 * phi;
+      wb[0] += 0.5 * d[0] * d[0] * g;
+      wb[1] += 0.5 * d[1] * d[1] * g;
+      wb[2] += 0.5 * d[2] * d[2] * g;
+      wb[3] += 0.5 * d[0] * d[1] * g;
+      wb[4] += 0.5 * d[0] * d[2] * g;
+      wb[5] += 0.5 * d[1] * d[2] * g;
     }
-    for (int c = 0; c < 3; ++c) f[c * n + i] = fi[c];
-    ea[i] = ei;
-    for (int c = 0; c < 6; ++c) va[c * n + i] = wi[c];
+    for (int c = 0; c < 3; ++c) f[c * n + i] = fb[c];
+    ea[i] = eb;
+    for (int c = 0; c < 6; ++c) va[c * n + i] = wb[c];
   }
   double et = 0.0, vt[6] = {0, 0, 0, 0, 0, 0};
   for (int64_t i = 0; i < n; ++i) {

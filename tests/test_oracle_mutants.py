@@ -8,6 +8,8 @@ import tempfile
 import pytest
 
 import test_oracle as T
+import test_oracle_buck as TB
+from paper_1009_4330_amd import inputs as I
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle",
                    "md_oracle.c")
@@ -37,7 +39,19 @@ MUTANTS = {
                              "double ke = p->mvv2e * p->mass * sv;", ["temperature"]),
     "cell_index_scale": ("int c = (int)((r * (double)nc) / L);",
                          "int c = (int)((r * (double)(nc - 1)) / L);", ["bin_sort", "brute_list"]),
+    "buck_species_pair": ("int ab = type[i] * 4 + type[j];", "int ab = type[i] * 4 + type[i];",
+                          ["buck_brute_bm", "buck_symmetry"]),
+    "buck_coulomb_force_power": ("- qq / s;", "- qq / r;", ["buck_fd", "buck_brute_coul"]),
+    "buck_dispersion_factor": ("6.0 * C[ab] / (r6 * r)", "C[ab] / (r6 * r)",
+                               ["buck_fd", "buck_brute_disp"]),
+    "buck_energy_half_dropped": ("eb += 0.5 * phi;", "eb += phi;",
+                                 ["buck_lattice", "buck_brute_disp"]),
 }
+
+
+def _jittered():
+    x, _, box = I.initial_state(TB.W8)
+    return I.jitter(x, 0.08, 11), box
 
 PINS = {
     "lattice": lambda o: T.test_lj_perfect_lattice_closed_form(o, 2.5),
@@ -55,6 +69,13 @@ PINS = {
     "schedule": lambda o: T.test_rebuild_schedule_follows_half_skin(o),
     "temperature": lambda o: T.test_initial_temperature_and_momentum(o),
     "bin_sort": lambda o: T.test_bin_is_stable_counting_sort(o, 4, 1),
+    "buck_symmetry": lambda o: TB.test_perfect_crystal_forces_vanish(o),
+    "buck_brute_bm": lambda o: TB.test_each_term_against_brute_force(o, _jittered(), "born_mayer"),
+    "buck_brute_disp": lambda o: TB.test_each_term_against_brute_force(o, _jittered(),
+                                                                       "dispersion"),
+    "buck_brute_coul": lambda o: TB.test_each_term_against_brute_force(o, _jittered(), "coulomb"),
+    "buck_fd": lambda o: TB.test_forces_are_minus_energy_gradient(o, _jittered()),
+    "buck_lattice": lambda o: TB.test_dispersion_lattice_sum(o),
 }
 
 
