@@ -326,6 +326,14 @@ def suite(steps: int):
               "lanes_per_atom": r["kernel"], "atom_steps_per_s": steps * w.natoms / r["elapsed"],
               "force_us": 1e3 * r["force_ms_avg"], "rebuilds": r["rebuilds"],
               "mean_neighbors": r["mean_neigh"], "steps": steps})
+    w = I.BUCK_141K
+    x, v, _ = I.initial_state(w)
+    for prec in ("fp64", "mixed"):
+        r = run_md(w, x, v, prec, "auto", steps, 10)
+        emit({"item": "buck_coul", "workload": w.name, "precision": prec, "kernel": "auto",
+              "lanes_per_atom": r["kernel"], "atom_steps_per_s": steps * w.natoms / r["elapsed"],
+              "force_us": 1e3 * r["force_ms_avg"], "rebuilds": r["rebuilds"],
+              "mean_neighbors": r["mean_neigh"], "steps": steps})
     emit({"item": "C5_fit", **{k: v for k, v in fit_timing().items()}})
     for nc in (10, 20, 30, 40, 60, 80):
         w = I.scaled(I.LJ_256K, nc)
@@ -337,6 +345,26 @@ def suite(steps: int):
     w = I.LJ_256K
     x, v, _ = I.initial_state(w)
     emit({"item": "oracle_one_thread", **oracle_one_thread(w, x, v)})
+
+
+def one_workload(name: str, kernel: str, steps: int, warmup: int):
+    """Time one named workload in FP64 and FP32-mixed; one JSON line each."""
+    from paper_1009_4330_amd import inputs as I
+
+    if name not in I.WORKLOADS:
+        print(f"unknown workload {name}; one of {sorted(I.WORKLOADS)}", file=sys.stderr)
+        sys.exit(2)
+    w = I.WORKLOADS[name]
+    x, v, _ = I.initial_state(w)
+    for prec in ("fp64", "mixed"):
+        log(f"[bench] {w.name}: {w.natoms} atoms, {prec}, kernel {kernel}")
+        r = run_md(w, x, v, prec, kernel, steps, warmup)
+        print(json.dumps({"item": "workload", "workload": w.name, "precision": prec,
+                          "kernel": kernel, "lanes_per_atom": r["kernel"],
+                          "atom_steps_per_s": steps * w.natoms / r["elapsed"],
+                          "ms_per_step": 1e3 * r["elapsed"] / steps,
+                          "force_us": 1e3 * r["force_ms_avg"], "rebuilds": r["rebuilds"],
+                          "mean_neighbors": r["mean_neigh"], "steps": steps}), flush=True)
 
 
 def main():
@@ -351,15 +379,23 @@ def main():
                     help="force kernel: tpa, wpa, auto or kN (N lanes per atom)")
     ap.add_argument("--profile-force", type=int, default=0, metavar="N",
                     help="run N md_step steps and a calibration copy (for counters)")
+    ap.add_argument("--workload", default="",
+                    help="time one other workload by name (e.g. buck_coul_141k, sc_cu_500k) in "
+                         "both precisions with --kernel; one JSON line per precision")
     ap.add_argument("--suite", action="store_true",
-                    help="the other configurations (rc 5.0 LJ, Sutton-Chen, the force-matching "
-                         "fit, a size sweep, copy peak, one-thread oracle); JSON lines")
+                    help="the other configurations (rc 5.0 LJ, Sutton-Chen, Buckingham + Coulomb, "
+                         "the force-matching fit, a size sweep, copy peak, one-thread oracle); "
+                         "JSON lines")
     args = ap.parse_args()
     if args.profile_force:
         profile_force(args.profile_force, args.kernel)
         return
     if args.suite:
         suite(args.steps if args.steps != 1000 else 200)
+        return
+    if args.workload:
+        one_workload(args.workload, args.kernel, args.steps if args.steps != 1000 else 200,
+                     args.warmup)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "

@@ -67,7 +67,7 @@ typedef enum { MD_FP64 = 0, MD_MIXED = 1 } md_precision;
    mini-benchmark (md_autoselect). */
 typedef enum { MD_KERNEL_AUTO = 0, MD_KERNEL_TPA = 1, MD_KERNEL_WPA = 64 } md_kernel;
 enum { MD_EFLAG = 1, MD_VFLAG = 2 };
-enum { MD_POT_LJ = 0, MD_POT_SC = 1 };
+enum { MD_POT_LJ = 0, MD_POT_SC = 1, MD_POT_BUCK = 2 };
 
 /* Neighbour-list layout K (lanes per atom, as above): groups of G = 64 / K
    consecutive atoms share rows of 64 ints, and entry m of atom i lives at
@@ -94,14 +94,26 @@ typedef struct { double L[3]; } md_box; /* [host] */
    (lj/cut, the paper's Appendix A "LJ"); lj_shift != 0 subtracts phi(rc) from
    the reported energy (forces unchanged).  SC (Sutton-Chen, standing in for the
    paper's EAM benchmark): E = eps sum_i [1/2 sum_j (a/r_ij)^n - c sqrt(rho_i)],
-   rho_i = sum_j (a/r_ij)^m, both sums truncated at rc. */
+   rho_i = sum_j (a/r_ij)^m, both sums truncated at rc.  BUCK (Buckingham + cut
+   Coulomb, the paper's Appendix A "Silicate (cutoff)" system):
+     phi_ab(r) = A_ab exp(-r / rho_ab) - C_ab / r^6 + qqr2e q_a q_b / r,  r < rc,
+   a, b the species of the two atoms (0..3), tables indexed a * 4 + b and
+   symmetric; no shift at rc.  `type` [device, int per atom] gives the
+   species in the order of the positions a call works on: md_compute_forces
+   and md_autoselect read it in the order of their x; md_step reads it in the
+   state's order and permutes it along with the atoms (like st->id).  Pairs
+   with A_ab = 0 ignore rho_ab. */
 typedef struct {
-  int kind;          /* MD_POT_LJ or MD_POT_SC */
+  int kind;          /* MD_POT_LJ, MD_POT_SC or MD_POT_BUCK */
   double rc;         /* force cutoff */
   double lj_eps, lj_sigma;
   int lj_shift;
   double sc_eps, sc_a, sc_c;
   int sc_n, sc_m;
+  double buck_A[16], buck_rho[16], buck_C[16];
+  double q[4];       /* charge per species */
+  double qqr2e;      /* Coulomb constant in the run's units */
+  int* type;         /* BUCK: species per atom (see above); unused otherwise */
 } md_potential;
 
 /* Cell grid: nc_d = floor(L_d / rl) cells per dimension (edge >= rl), linear

@@ -78,7 +78,46 @@ md_status check_pot(const md_potential* p) {
       return MD_ERR_INVALID_ARG;
     return MD_OK;
   }
+  if (p->kind == MD_POT_BUCK) {
+    if (!p->type || !finite_pos(p->qqr2e)) return MD_ERR_INVALID_ARG;
+    for (int q = 0; q < 4; ++q)
+      if (!std::isfinite(p->q[q])) return MD_ERR_INVALID_ARG;
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        const int ab = 4 * a + b, ba = 4 * b + a;
+        const double A = p->buck_A[ab], rho = p->buck_rho[ab], C = p->buck_C[ab];
+        if (!(A >= 0.0) || !std::isfinite(A) || !(C >= 0.0) || !std::isfinite(C))
+          return MD_ERR_INVALID_ARG;
+        if (A > 0.0 && !finite_pos(rho)) return MD_ERR_INVALID_ARG;
+        if (A != p->buck_A[ba] || C != p->buck_C[ba] ||
+            (A > 0.0 && rho != p->buck_rho[ba]))
+          return MD_ERR_INVALID_ARG;
+      }
+    return MD_OK;
+  }
   return MD_ERR_INVALID_ARG;
+}
+
+// Species of the atoms a call works on (Buckingham only; the other kinds
+// ignore species and read none).
+const int* species(const md_potential* p) { return p->kind == MD_POT_BUCK ? p->type : nullptr; }
+
+BuckK make_buck(const md_potential* p) {
+  BuckK k;
+  k.rc2 = p->rc * p->rc;
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      const int ab = 4 * a + b;
+      const double A = p->buck_A[ab];
+      const double irho = A > 0.0 ? 1.0 / p->buck_rho[ab] : 0.0;
+      const double row[6] = {A, A * irho, irho, p->buck_C[ab], 6.0 * p->buck_C[ab],
+                             p->qqr2e * p->q[a] * p->q[b]};
+      for (int c = 0; c < 6; ++c) {
+        k.row[ab][c] = row[c];
+        k.rowf[ab][c] = (float)row[c];
+      }
+    }
+  return k;
 }
 
 LJK make_lj(const md_potential* p) {
@@ -182,6 +221,8 @@ md_status force_dispatch(const md_potential* p, const ForceArgs& fa, md_precisio
   hipError_t e;
   if (p->kind == MD_POT_LJ)
     e = launch_lj(fa, make_lj(p), prec, kernel, s);
+  else if (p->kind == MD_POT_BUCK)
+    e = launch_buck(fa, make_buck(p), prec, kernel, s);
   else
     e = launch_sc(fa, make_sc(p), prec, kernel, sc_e, s);
   return e == hipSuccess ? MD_OK : MD_ERR_HIP;
@@ -231,7 +272,7 @@ md_status autoselect_impl(const md_potential* p, const double* x, int n, int sor
   int win = MD_KERNEL_TPA;
   int maxcount = 0;
   double* xq = at<double>(ws, L.xq);
-  MD_CK(launch_pack_positions(x, n, xq, s));
+  MD_CK(launch_pack_positions(x, n, xq, species(p), s));
   for (int k = 1; k <= kWave; k *= 2) {
     md_status st = build_list(x, n, sorted, box, nc, cells, rl, nl, k, s);
     if (st != MD_OK) return st;
@@ -325,6 +366,7 @@ WsLayout ws_layout(int64_t n, int64_t ncell) {
   L.tmp_v = take(sizeof(double) * 3 * nn);
   L.tmp_f = take(sizeof(double) * 3 * nn);
   L.tmp_id = take(sizeof(int) * nn);
+  L.tmp_type = take(sizeof(int) * nn);
   L.eatom = take(sizeof(double) * nn);
   L.vatom = take(sizeof(double) * 6 * nn);
   L.keatom = take(sizeof(double) * nn);
@@ -403,8 +445,8 @@ md_status md_bin_cells(double* x, int64_t n, const md_box* box, double rl, md_ce
   MD_CK(launch_scatter(cells->atom_cell, at<int>(ws, L.slot), cells->cell_start, ni,
                        at<int>(ws, L.tmp_perm), nullptr, s));
   MD_CK(launch_cell_sort(at<int>(ws, L.tmp_perm), cells->cell_start, (int)ncell, cells->perm,
-                         nullptr, nullptr, nullptr, nullptr, ni, nullptr, nullptr, nullptr,
-                         nullptr, nullptr, s));
+                         nullptr, nullptr, nullptr, nullptr, nullptr, ni, nullptr, nullptr,
+                         nullptr, nullptr, nullptr, nullptr, s));
   for (int d = 0; d < 3; ++d) cells->nc[d] = nc[d];
   return MD_OK;
 }
@@ -471,7 +513,7 @@ md_status md_compute_forces(const md_potential* p, const double* x, int64_t n,
   if ((st = check_ws(ws, ws_bytes, L)) != MD_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   double* xq = at<double>(ws, L.xq);
-  MD_CK(launch_pack_positions(x, (int)n, xq, s));
+  MD_CK(launch_pack_positions(x, (int)n, xq, species(p), s));
   ForceArgs fa{};
   fa.xq = xq;
   fa.n = (int)n;
@@ -514,7 +556,7 @@ md_status md_force_vjp(const md_potential* p, const double* x, int64_t n, const 
   if ((st = check_ws(ws, ws_bytes, L)) != MD_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   double* xq = at<double>(ws, L.xq);
-  MD_CK(launch_pack_positions(x, (int)n, xq, s));
+  MD_CK(launch_pack_positions(x, (int)n, xq, species(p), s));
   ForceArgs fa{};
   fa.xq = xq;
   fa.n = (int)n;
@@ -619,6 +661,9 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
   double* sx = at<double>(ws, L.tmp_x);
   double* sv = at<double>(ws, L.tmp_v);
   int* sid = at<int>(ws, L.tmp_id);
+  // species travel with the atoms through every rebuild (Buckingham only)
+  int* const type = const_cast<int*>(species(p));
+  int* stype = at<int>(ws, L.tmp_type);
   double* eatom = at<double>(ws, L.eatom);
   double* vatom = at<double>(ws, L.vatom);
   double* keatom = at<double>(ws, L.keatom);
@@ -644,15 +689,15 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
     if (g) {
       MD_CK(launch_cell_count(cells->cell_start, cells->atom_cell, nc, count, scount, g, s));
       MD_CK(launch_gather_sort(cells->cell_start, new_start, count, scount, cells->atom_cell, nc,
-                               bk, cells->perm, xq, stt->v, stt->id, n, sx, sv, sid, status, g,
-                               s));
+                               bk, cells->perm, xq, stt->v, stt->id, type, n, sx, sv, sid, stype,
+                               status, g, s));
     } else {
       MD_CK(launch_fill_int(count, ncell, 0, s));
       MD_CK(launch_bin_count(stt->x, n, bk, nc, cells->atom_cell, count, slot, s));
       MD_CK(launch_scan_cells(count, (int)ncell, starts, s));
       MD_CK(launch_scatter(cells->atom_cell, slot, starts, n, tmp_perm, g, s));
       MD_CK(launch_cell_sort(tmp_perm, starts, (int)ncell, cells->perm, stt->x, stt->v, stt->id,
-                             nullptr, n, sx, sv, sid, nullptr, g, s));
+                             nullptr, type, n, sx, sv, sid, nullptr, stype, g, s));
     }
     BuildArgs a{};
     a.x = sx;
@@ -677,6 +722,8 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
     a.v_in = sv;
     a.id_out = stt->id;
     a.id_in = sid;
+    a.type_out = type;
+    a.type_in = type ? stype : nullptr;
     a.gate = g;
     MD_CK(launch_build(a, s));
     return MD_OK;
@@ -780,6 +827,7 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
     bin.atom_cell = cells->atom_cell;
     bin.xq = xqs[1];
     bin.flag = gates[1];
+    bin.type = type;
     MD_CK(launch_fill_int(gates[0], 1, 0, s));
     MD_CK(launch_fill_int(gates[1], 1, 0, s));
     MD_CK(launch_kick_drift_check(stt->x, stt->v, stt->f, nl->x_ref, n, dtfm, dt, trig2, status,

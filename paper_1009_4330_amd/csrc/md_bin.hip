@@ -118,9 +118,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const int* __restrict__ atom
 __global__ __launch_bounds__(kBlock) void k_cell_sort(
     const int* __restrict__ tmp_perm, const int* __restrict__ cell_start, int ncell,
     int* __restrict__ perm, const double* __restrict__ x, const double* __restrict__ v,
-    const int* __restrict__ id, const double* __restrict__ f, int n, double* __restrict__ sx,
-    double* __restrict__ sv, int* __restrict__ sid, double* __restrict__ sf,
-    const int* __restrict__ gate) {
+    const int* __restrict__ id, const double* __restrict__ f, const int* __restrict__ type,
+    int n, double* __restrict__ sx, double* __restrict__ sv, int* __restrict__ sid,
+    double* __restrict__ sf, int* __restrict__ stype, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
   const int lane = threadIdx.x & (kWave - 1);
   const int cell = (blockIdx.x * kBlock + threadIdx.x) / kWave;
@@ -144,6 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_sort(
       sv[2 * n + p] = v[2 * n + key];
     }
     if (sid) sid[p] = id[key];
+    if (stype) stype[p] = type[key];
     if (sf) {
       sf[p] = f[key];
       sf[n + p] = f[n + key];
@@ -313,9 +314,10 @@ __global__ __launch_bounds__(kCountBlock) void k_cell_count(
 // (wrapped into the box), velocity and id from the state.
 __device__ inline void put_member(int i, int p, int n, const BoxK& box,
                                   const double* __restrict__ xq, const double* __restrict__ v,
-                                  const int* __restrict__ id, int* __restrict__ perm,
-                                  double* __restrict__ sx, double* __restrict__ sv,
-                                  int* __restrict__ sid) {
+                                  const int* __restrict__ id, const int* __restrict__ type,
+                                  int* __restrict__ perm, double* __restrict__ sx,
+                                  double* __restrict__ sv, int* __restrict__ sid,
+                                  int* __restrict__ stype) {
   const double2 q = *reinterpret_cast<const double2*>(xq + 4 * (size_t)i);
   const double x2 = xq[4 * (size_t)i + 2];
   const double v0 = v[i], v1 = v[n + i], v2 = v[2 * n + i];
@@ -328,6 +330,7 @@ __device__ inline void put_member(int i, int p, int n, const BoxK& box,
   sv[n + p] = v1;
   sv[2 * n + p] = v2;
   sid[p] = idi;
+  if (stype) stype[p] = type[i];
 }
 
 // Rebuild-time sort of atoms that are already in the previous build's cell
@@ -344,8 +347,9 @@ __device__ inline void gather_cell(
     const int* __restrict__ count, const int* __restrict__ scount,
     const int* __restrict__ atom_cell, int nc0, int nc1, int nc2, const BoxK& box,
     int* __restrict__ perm, const double* __restrict__ xq, const double* __restrict__ v,
-    const int* __restrict__ id, int n, double* __restrict__ sx, double* __restrict__ sv,
-    int* __restrict__ sid, int* __restrict__ status, int cell, int lane, int* row) {
+    const int* __restrict__ id, const int* __restrict__ type, int n, double* __restrict__ sx,
+    double* __restrict__ sv, int* __restrict__ sid, int* __restrict__ stype,
+    int* __restrict__ status, int cell, int lane, int* row) {
   const int ncell = nc0 * nc1 * nc2;
   const int nc[3] = {nc0, nc1, nc2};
   const Segs S = old_segments(cell, lane, nc, old_start);
@@ -383,7 +387,7 @@ __device__ inline void gather_cell(
     }
     __builtin_amdgcn_wave_barrier();   // a wavefront's LDS accesses complete in order
     if (lane < want && lane < found)
-      put_member(row[lane], base + lane, n, box, xq, v, id, perm, sx, sv, sid);
+      put_member(row[lane], base + lane, n, box, xq, v, id, type, perm, sx, sv, sid, stype);
   } else {
     for (int q = 0; q < S.n; ++q) {
       const int b = __builtin_amdgcn_readlane(S.b, q);
@@ -393,7 +397,8 @@ __device__ inline void gather_cell(
         const bool mine = t + lane < len && atom_cell[i] == cell;
         const unsigned long long m = __ballot(mine);
         const int pos = found + __popcll(m & below);
-        if (mine && pos < want) put_member(i, base + pos, n, box, xq, v, id, perm, sx, sv, sid);
+        if (mine && pos < want)
+          put_member(i, base + pos, n, box, xq, v, id, type, perm, sx, sv, sid, stype);
         found += __popcll(m);
       }
     }
@@ -406,8 +411,9 @@ __global__ __launch_bounds__(kBlock) void k_gather_sort(
     const int* __restrict__ count, const int* __restrict__ scount,
     const int* __restrict__ atom_cell, int nc0, int nc1, int nc2, BoxK box,
     int* __restrict__ perm, const double* __restrict__ xq, const double* __restrict__ v,
-    const int* __restrict__ id, int n, double* __restrict__ sx, double* __restrict__ sv,
-    int* __restrict__ sid, int* __restrict__ status, const int* __restrict__ gate) {
+    const int* __restrict__ id, const int* __restrict__ type, int n, double* __restrict__ sx,
+    double* __restrict__ sv, int* __restrict__ sid, int* __restrict__ stype,
+    int* __restrict__ status, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
   __shared__ int members[kBlock];
   const int lane = threadIdx.x & (kWave - 1);
@@ -419,7 +425,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_sort(
     const int cell = lb * kCells + wave;
     if (cell < ncell)
       gather_cell(old_start, new_start, count, scount, atom_cell, nc0, nc1, nc2, box, perm, xq,
-                  v, id, n, sx, sv, sid, status, cell, lane, members + wave * kWave);
+                  v, id, type, n, sx, sv, sid, stype, status, cell, lane,
+                  members + wave * kWave);
   }
 }
 
@@ -693,7 +700,9 @@ __device__ inline void finish_one(const BuildArgs& a, const BuildLds& L, int hl,
     a.x_ref[n + i] = yi;
     a.x_ref[2 * n + i] = zi;
   }
-  if (a.xq_out) store_packed(a.xq_out, i, xi, yi, zi);
+  const int ti = a.type_in ? a.type_in[i] : 0;
+  if (a.xq_out) store_packed(a.xq_out, i, xi, yi, zi, ti);
+  if (a.type_out) a.type_out[i] = ti;
   if (a.x_out) {
     a.x_out[i] = xi;
     a.x_out[n + i] = yi;
@@ -806,55 +815,15 @@ __device__ inline void pad_slots(const BuildLds& L, int from, int to, int tid) {
   }
 }
 
-// The list of one cell, general path: the (up to) 27 stencil entries, in
-// stencil order and slot order inside a cell, staged in chunks of
-// kBuildChunk.  Every thread of the workgroup calls it.  Returns this
-// thread's largest list length; copies cell_start into cell_start_out.
-__device__ inline int build_cell(const BuildArgs& a, const BuildLds& L, int cell, int* st_start,
-                                 int* st_off, int* st_meta) {
-  const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1), wave = tid / kWave;
-  const int hb = a.cell_start[cell], he = a.cell_start[cell + 1];
+// Home atoms [hb, he) of one cell against its staged stencil (general path):
+// the candidates in chunks of kBuildChunk, then the copies of the home atoms'
+// state.  home_off is the candidate offset of atom hb within the stencil.
+__device__ inline int build_piece(const BuildArgs& a, const BuildLds& L, int hb, int he,
+                                  int home_off, int total, int nst, bool wrap,
+                                  const int* st_start, const int* st_off, int lane, int wave,
+                                  int tid) {
   HomePrefetch P;
   P.load(a, hb, he, tid);
-  if (wave == 0) {
-    // Stencil entry (oz, oy, ox) = lane, all 27 looked up at once; the kept
-    // entries keep the z, y, x offset order, their offsets by a wave scan.
-    bool kept;
-    const int c2 = stencil_lane(cell, lane, a.nc, &kept);
-    const unsigned long long km = __ballot(kept);
-    int b = 0, cnt = 0;
-    if (kept) {
-      b = a.cell_start[c2];
-      cnt = a.cell_start[c2 + 1] - b;
-    }
-    int inc = cnt;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      const int y = __shfl_up(inc, off, kWave);
-      if (lane >= off) inc += y;
-    }
-    if (kept) {
-      const int pos = __popcll(km & ((1ull << lane) - 1));
-      st_start[pos] = b;
-      st_off[pos] = inc - cnt;
-      if (c2 == cell) st_meta[1] = pos;
-    }
-    if (lane == kWave - 1) {
-      st_meta[0] = __popcll(km);
-      st_off[__popcll(km)] = inc;
-    }
-  }
-  __syncthreads();
-  const int nst = st_meta[0];
-  const int total = st_off[nst];
-  const int home_off = st_off[st_meta[1]];
-  const int cx = cell % a.nc[0], cy = (cell / a.nc[0]) % a.nc[1], cz = cell / (a.nc[0] * a.nc[1]);
-  const bool wrap = cell_wraps(cx, cy, cz, a.nc);
-  if (tid == 0 && a.cell_start_out) {
-    a.cell_start_out[cell] = hb;
-    if (cell == a.nc[0] * a.nc[1] * a.nc[2] - 1) a.cell_start_out[cell + 1] = he;
-  }
   // home atoms staged in the chunk that holds them all, else read from x
   int hl_last = -1;
   for (int c0 = 0; c0 < total; c0 += kBuildChunk) {
@@ -892,7 +861,70 @@ __device__ inline int build_cell(const BuildArgs& a, const BuildLds& L, int cell
                                        P.pid)
                    : finish_home<false>(a, L, hl_last, hb, he, tid, P.pre, P.pi, P.v0, P.v1,
                                         P.v2, P.pid);
-  __syncthreads();   // LDS (candidates, hcnt) free for the next cell
+  __syncthreads();   // LDS (candidates, hcnt) free for the next piece
+  return mx;
+}
+
+// Home atoms per piece when a cell's home atoms are split over several
+// workgroups (dense cells: long cutoffs, few cells).
+constexpr int kHomePiece = 64;
+
+// The lists of one cell's home atoms, general path: the (up to) 27 stencil
+// entries, in stencil order and slot order inside a cell, staged in chunks of
+// kBuildChunk.  With parts > 1 the home atoms come in pieces of kHomePiece and
+// this workgroup takes pieces part, part + parts, ...; each piece stages the
+// whole stencil again.  Every thread of the workgroup calls it.  Returns this
+// thread's largest list length; part 0 copies cell_start into cell_start_out.
+__device__ inline int build_cell(const BuildArgs& a, const BuildLds& L, int cell, int part,
+                                 int parts, int* st_start, int* st_off, int* st_meta) {
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wave = tid / kWave;
+  const int hb = a.cell_start[cell], he = a.cell_start[cell + 1];
+  if (wave == 0) {
+    // Stencil entry (oz, oy, ox) = lane, all 27 looked up at once; the kept
+    // entries keep the z, y, x offset order, their offsets by a wave scan.
+    bool kept;
+    const int c2 = stencil_lane(cell, lane, a.nc, &kept);
+    const unsigned long long km = __ballot(kept);
+    int b = 0, cnt = 0;
+    if (kept) {
+      b = a.cell_start[c2];
+      cnt = a.cell_start[c2 + 1] - b;
+    }
+    int inc = cnt;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const int y = __shfl_up(inc, off, kWave);
+      if (lane >= off) inc += y;
+    }
+    if (kept) {
+      const int pos = __popcll(km & ((1ull << lane) - 1));
+      st_start[pos] = b;
+      st_off[pos] = inc - cnt;
+      if (c2 == cell) st_meta[1] = pos;
+    }
+    if (lane == kWave - 1) {
+      st_meta[0] = __popcll(km);
+      st_off[__popcll(km)] = inc;
+    }
+  }
+  __syncthreads();
+  const int nst = st_meta[0];
+  const int total = st_off[nst];
+  const int home_off = st_off[st_meta[1]];
+  const int cx = cell % a.nc[0], cy = (cell / a.nc[0]) % a.nc[1], cz = cell / (a.nc[0] * a.nc[1]);
+  const bool wrap = cell_wraps(cx, cy, cz, a.nc);
+  if (tid == 0 && part == 0 && a.cell_start_out) {
+    a.cell_start_out[cell] = hb;
+    if (cell == a.nc[0] * a.nc[1] * a.nc[2] - 1) a.cell_start_out[cell + 1] = he;
+  }
+  const int piece = parts > 1 ? kHomePiece : max(he - hb, 1);
+  int mx = 0;
+  for (int h0 = hb + part * piece; h0 < he; h0 += parts * piece) {   // uniform
+    mx = max(mx, build_piece(a, L, h0, min(he, h0 + piece), home_off + (h0 - hb), total, nst,
+                             wrap, st_start, st_off, lane, wave, tid));
+  }
+  __syncthreads();   // stencil tables free for the next cell (also when no piece ran)
   return mx;
 }
 
@@ -914,8 +946,9 @@ __device__ inline void report_max(const BuildArgs& a, int mx, int* red) {
   }
 }
 
-// One workgroup per cell (general path).
-__global__ __launch_bounds__(kBlock) void k_build(BuildArgs a) {
+// General path: `parts` workgroups per cell, consecutive in the (XCD-aware)
+// numbering so a cell's pieces share one L2.
+__global__ __launch_bounds__(kBlock) void k_build(BuildArgs a, int parts) {
   if (a.gate && *a.gate == 0) return;
   __shared__ double cxs[kBuildChunk], cys[kBuildChunk], czs[kBuildChunk];
   __shared__ int cjs[kBuildChunk];
@@ -924,9 +957,10 @@ __global__ __launch_bounds__(kBlock) void k_build(BuildArgs a) {
   __shared__ int st_start[27], st_off[28], st_meta[2];
   __shared__ int red[kBlock / kWave];
   const BuildLds L{cxs, cys, czs, cjs, hcnt, lbuf};
-  const int cell = xcd_block();
-  if (cell == 0 && threadIdx.x == 0) atomicAdd(&a.status[MD_ST_BUILDS], 1);
-  const int mx = build_cell(a, L, cell, st_start, st_off, st_meta);
+  const int blk = xcd_block();
+  const int cell = blk / parts, part = blk % parts;
+  if (blk == 0 && threadIdx.x == 0) atomicAdd(&a.status[MD_ST_BUILDS], 1);
+  const int mx = build_cell(a, L, cell, part, parts, st_start, st_off, st_meta);
   report_max(a, mx, red);
 }
 
@@ -1152,7 +1186,8 @@ __device__ inline int build_row_segment(const BuildArgs& a, const BuildLds& L, i
   int mx = 0;
   if (*big) {
     for (int k = 0; k < nh; ++k)
-      mx = max(mx, build_cell(a, L, (cz * nc1 + cy) * nc0 + cx0 + k, st_start, st_off, st_meta));
+      mx = max(mx, build_cell(a, L, (cz * nc1 + cy) * nc0 + cx0 + k, 0, 1, st_start, st_off,
+                              st_meta));
     __syncthreads();
     return mx;
   }
@@ -1328,22 +1363,23 @@ hipError_t launch_scatter(const int* atom_cell, const int* slot, const int* cell
 
 hipError_t launch_cell_sort(const int* tmp_perm, const int* cell_start, int ncell, int* perm,
                             const double* x, const double* v, const int* id, const double* f,
-                            int n, double* sx, double* sv, int* sid, double* sf,
-                            const int* gate, hipStream_t s) {
+                            const int* type, int n, double* sx, double* sv, int* sid,
+                            double* sf, int* stype, const int* gate, hipStream_t s) {
   k_cell_sort<<<blocks_for((int64_t)ncell * kWave), kBlock, 0, s>>>(
-      tmp_perm, cell_start, ncell, perm, x, v, id, f, n, sx, sv, sid, sf, gate);
+      tmp_perm, cell_start, ncell, perm, x, v, id, f, type, n, sx, sv, sid, sf,
+      type ? stype : nullptr, gate);
   return hipGetLastError();
 }
 
 hipError_t launch_gather_sort(const int* old_start, int* new_start, const int* count,
                               const int* scount, const int* atom_cell, const int nc[3], BoxK box,
-                              int* perm, const double* xq, const double* v, const int* id, int n,
-                              double* sx, double* sv, int* sid, int* status, const int* gate,
-                              hipStream_t s) {
+                              int* perm, const double* xq, const double* v, const int* id,
+                              const int* type, int n, double* sx, double* sv, int* sid,
+                              int* stype, int* status, const int* gate, hipStream_t s) {
   const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
   k_gather_sort<<<resident_grid(8, blocks_for(ncell * kWave)), kBlock, 0, s>>>(
-      old_start, new_start, count, scount, atom_cell, nc[0], nc[1], nc[2], box, perm, xq, v, id, n,
-      sx, sv, sid, status, gate);
+      old_start, new_start, count, scount, atom_cell, nc[0], nc[1], nc[2], box, perm, xq, v, id,
+      type, n, sx, sv, sid, type ? stype : nullptr, status, gate);
   return hipGetLastError();
 }
 
@@ -1370,13 +1406,21 @@ hipError_t launch_gather_int(const int* perm, int n, const int* src, int* dst, h
   return hipGetLastError();
 }
 
+// The row path needs a run's slabs (kMaxSlabs x 9 cells) in LDS; when the
+// mean occupancy says they would not fit (long cutoffs), every run would fall
+// back to one cell at a time, so the general path with home pieces is taken.
 hipError_t launch_build(const BuildArgs& a, hipStream_t s) {
-  if (a.sorted && a.nc[0] >= 3) {
+  const int64_t ncell = (int64_t)a.nc[0] * a.nc[1] * a.nc[2];
+  const double per_cell = (double)a.n / (double)ncell;
+  if (a.sorted && a.nc[0] >= 3 && kMaxSlabs * 9 * per_cell <= 0.9 * kRowCap) {
     const int64_t segs = (int64_t)((a.nc[0] + kRowCells - 1) / kRowCells) * a.nc[1] * a.nc[2];
     k_build_rows<<<resident_grid(3, segs), kBlock, 0, s>>>(a);
   } else {
-    const unsigned ncell = (unsigned)(a.nc[0] * a.nc[1] * a.nc[2]);
-    k_build<<<ncell, kBlock, 0, s>>>(a);
+    // pieces of kHomePiece home atoms at the mean occupancy; denser cells
+    // loop over further pieces
+    const int parts = (int)std::min<int64_t>(
+        64, std::max<int64_t>(1, (int64_t)std::ceil(per_cell / kHomePiece)));
+    k_build<<<(unsigned)(ncell * parts), kBlock, 0, s>>>(a, parts);
   }
   return hipGetLastError();
 }

@@ -151,6 +151,7 @@ struct Lane {
 // the minimum image; interior wavefronts skip it (see interior()).
 struct Batch {
   int j[kUnroll];
+  int t[kUnroll];   // species of j (TYPED batches only)
   bool ok[kUnroll];
   double dx[kUnroll], dy[kUnroll], dz[kUnroll], s[kUnroll];
 };
@@ -166,7 +167,7 @@ struct XView {
 // record and the second half of its partner's, and a three-word lane swap
 // completes every lane's record.  Otherwise each lane reads (x, y) and z of
 // its own record with a 16- and an 8-byte load.
-template <int K, bool WRAP, bool PAIRED>
+template <int K, bool WRAP, bool PAIRED, bool TYPED = false>
 __device__ inline void load_batch(const FK& a, const XView& xv, const Lane<K>& ln, int t,
                                   int* jn, double xi, double yi, double zi, Batch& b) {
   double xj[kUnroll], yj[kUnroll], zj[kUnroll];
@@ -191,6 +192,15 @@ __device__ inline void load_batch(const FK& a, const XView& xv, const Lane<K>& l
       xj[u] = __builtin_bit_cast(double, make_uint2(own.x, own.y));
       yj[u] = __builtin_bit_cast(double, make_uint2(own.z, r0));
       zj[u] = __builtin_bit_cast(double, make_uint2(r1, r2));
+    } else if (TYPED) {
+      // (x, y) and (z, species) of the record
+      const unsigned off = (unsigned)b.j[u] * 32u;
+      const f64x2 xy = load16(xv.r, off);
+      const f64x2 zt = load16(xv.r, off + 16u);
+      xj[u] = xy.x;
+      yj[u] = xy.y;
+      zj[u] = zt.x;
+      b.t[u] = (int)zt.y & 3;   // species 0..3 (the mask keeps table reads in bounds)
     } else {
       const unsigned off = (unsigned)b.j[u] * 32u;
       const f64x2 xy = load16(xv.r, off);
@@ -222,7 +232,7 @@ __device__ inline XView xview(const FK& a) { return XView{buffer_of(a.xq, a.n)};
 // Runs body(batch) over the wavefront's list entries (a uniform loop to the
 // largest count).  The choice between the plain and the minimum-image
 // separation is uniform over the wavefront.
-template <int K, bool PAIRED, typename F>
+template <int K, bool PAIRED, bool TYPED = false, typename F>
 __device__ inline void for_each_batch(const FK& a, const Lane<K>& ln, double xi, double yi,
                                       double zi, F&& body) {
   const XView xv = xview(a);
@@ -232,13 +242,13 @@ __device__ inline void for_each_batch(const FK& a, const Lane<K>& ln, double xi,
   if (__all(interior(xi, yi, zi, a))) {
     for (int t = 0; t < ln.tmax; t += kUnroll) {
       Batch b;
-      load_batch<K, false, PAIRED>(a, xv, ln, t, jn, xi, yi, zi, b);
+      load_batch<K, false, PAIRED, TYPED>(a, xv, ln, t, jn, xi, yi, zi, b);
       body(b);
     }
   } else {
     for (int t = 0; t < ln.tmax; t += kUnroll) {
       Batch b;
-      load_batch<K, true, PAIRED>(a, xv, ln, t, jn, xi, yi, zi, b);
+      load_batch<K, true, PAIRED, TYPED>(a, xv, ln, t, jn, xi, yi, zi, b);
       body(b);
     }
   }
@@ -396,6 +406,72 @@ __global__ __launch_bounds__(kBlock) void k_lj(FK a, LJK p) {
       acc.add_force(g, b.dx[u], b.dy[u], b.dz[u]);
       if (EV) {
         acc.e += use ? phi - p.ecut : 0.0;
+        acc.add_virial(g, b.dx[u], b.dy[u], b.dz[u]);
+      }
+    }
+  });
+  if (K > 1) acc.reduce<K>(EV);
+  finish_atom<FUSED>(a, acc, ln.i, ln.live && ln.s == 0, xi, yi, zi, EV, 0.0);
+}
+
+// ------------------------------------------- Buckingham + cut Coulomb --
+
+// g = -(dphi/dr) / r and phi at r^2 = s for one species pair, from its row
+// (A, A / rho, 1 / rho, C, 6 C, qq): phi = A e - C / r^6 + qq / r with
+// e = exp(-r / rho), -(dphi/dr) = (A / rho) e - 6 C / r^7 + qq / r^2.
+template <int PREC>
+__device__ inline void buck_pair(double s, const double* row, const float* rowf, double& g,
+                                 double& phi) {
+  if (PREC == MD_FP64) {
+    const double r = sqrt(s);
+    const double ri = rcp64(r);
+    const double r2i = ri * ri;
+    const double r6i = r2i * r2i * r2i;
+    const double ex = exp(-r * row[2]);
+    phi = row[0] * ex - row[3] * r6i + row[5] * ri;
+    g = ri * (row[1] * ex - row[4] * r6i * ri + row[5] * r2i);
+  } else {
+    const float sf = (float)s;
+    const float r = __builtin_sqrtf(sf);
+    const float ri = __builtin_amdgcn_rcpf(r);
+    const float r2i = ri * ri;
+    const float r6i = r2i * r2i * r2i;
+    const float ex = expf(-r * rowf[2]);
+    phi = (double)(rowf[0] * ex - rowf[3] * r6i + rowf[5] * ri);
+    g = (double)(ri * (rowf[1] * ex - rowf[4] * r6i * ri + rowf[5] * r2i));
+  }
+}
+
+template <int PREC, bool EV, int K, bool FUSED>
+__global__ __launch_bounds__(kBlock) void k_buck(FK a, BuckK p) {
+  // the species-pair rows, staged once per workgroup
+  __shared__ double rows[16 * 6];
+  __shared__ float rowsf[16 * 6];
+  if (threadIdx.x < 16 * 6) {
+    rows[threadIdx.x] = p.row[threadIdx.x / 6][threadIdx.x % 6];
+    rowsf[threadIdx.x] = p.rowf[threadIdx.x / 6][threadIdx.x % 6];
+  }
+  __syncthreads();
+  if (a.clear && blockIdx.x == 0 && threadIdx.x == 0) *a.clear = 0;
+  const Lane<K> ln(a);
+  const int n = a.n;
+  const int io = ln.live ? ln.i : n - 1;
+  double xi, yi, zi;
+  home_pos(a, io, xi, yi, zi);
+  const int ti = (int)a.xq[4 * (size_t)io + 3] & 3;
+  Acc acc;
+  for_each_batch<K, false, true>(a, ln, xi, yi, zi, [&](const Batch& b) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      // pairs outside the cutoff or past the lane's list contribute an exact zero
+      const bool use = b.ok[u] && b.s[u] < p.rc2;
+      const int ab = 6 * (4 * ti + b.t[u]);
+      double g, phi;
+      buck_pair<PREC>(use ? b.s[u] : 1.0, rows + ab, rowsf + ab, g, phi);
+      g = use ? g : 0.0;
+      acc.add_force(g, b.dx[u], b.dy[u], b.dz[u]);
+      if (EV) {
+        acc.e += use ? phi : 0.0;
         acc.add_virial(g, b.dx[u], b.dy[u], b.dz[u]);
       }
     }
@@ -598,9 +674,10 @@ hipError_t launch_timed(void (*kern)(KArgs...), unsigned grid, hipStream_t s, hi
 }
 
 __global__ __launch_bounds__(kBlock) void k_pack_positions(const double* __restrict__ x, int n,
-                                                            double* __restrict__ xq) {
+                                                            double* __restrict__ xq,
+                                                            const int* __restrict__ type) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) store_packed(xq, i, x[i], x[n + i], x[2 * n + i]);
+  if (i < n) store_packed(xq, i, x[i], x[n + i], x[2 * n + i], type ? type[i] : 0);
 }
 
 // Workgroups covering n atoms with K lanes each.
@@ -626,8 +703,9 @@ hipError_t with_lanes(int k, F&& f) {
 
 }  // namespace
 
-hipError_t launch_pack_positions(const double* x, int n, double* xq, hipStream_t s) {
-  k_pack_positions<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(x, n, xq);
+hipError_t launch_pack_positions(const double* x, int n, double* xq, const int* type,
+                                 hipStream_t s) {
+  k_pack_positions<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(x, n, xq, type);
   return hipGetLastError();
 }
 
@@ -650,6 +728,28 @@ hipError_t launch_lj(const ForceArgs& a, const LJK& p, int prec, int lanes, hipS
                 : launch_timed(k_lj<MD_MIXED, false, K, true>, g, s, a.t0, a.t1, k, p);
     return ev ? launch_timed(k_lj<MD_MIXED, true, K, false>, g, s, a.t0, a.t1, k, p)
               : launch_timed(k_lj<MD_MIXED, false, K, false>, g, s, a.t0, a.t1, k, p);
+  });
+}
+
+hipError_t launch_buck(const ForceArgs& a, const BuckK& p, int prec, int lanes, hipStream_t s) {
+  const FK k = make_fk(a);
+  const bool ev = a.ev.eatom || a.ev.vatom;
+  return with_lanes(lanes, [&](auto kc) -> hipError_t {
+    constexpr int K = decltype(kc)::value;
+    const unsigned g = grid_for(a.n, K);
+    const bool fused = a.in.mode != MD_INT_NONE;
+    if (prec == MD_FP64) {
+      if (fused)
+        return ev ? launch_timed(k_buck<MD_FP64, true, K, true>, g, s, a.t0, a.t1, k, p)
+                  : launch_timed(k_buck<MD_FP64, false, K, true>, g, s, a.t0, a.t1, k, p);
+      return ev ? launch_timed(k_buck<MD_FP64, true, K, false>, g, s, a.t0, a.t1, k, p)
+                : launch_timed(k_buck<MD_FP64, false, K, false>, g, s, a.t0, a.t1, k, p);
+    }
+    if (fused)
+      return ev ? launch_timed(k_buck<MD_MIXED, true, K, true>, g, s, a.t0, a.t1, k, p)
+                : launch_timed(k_buck<MD_MIXED, false, K, true>, g, s, a.t0, a.t1, k, p);
+    return ev ? launch_timed(k_buck<MD_MIXED, true, K, false>, g, s, a.t0, a.t1, k, p)
+              : launch_timed(k_buck<MD_MIXED, false, K, false>, g, s, a.t0, a.t1, k, p);
   });
 }
 

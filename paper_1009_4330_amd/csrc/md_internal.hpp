@@ -94,10 +94,13 @@ __device__ inline int cell_of(double x, double y, double z, const BoxK& box, con
 // Where the integrator records each atom's cell after the drift (the cell of
 // its wrapped image), for the gated rebuild; atom_cell == null skips it.
 // Packed position record of atom i: (x, y, z, 0) at xq[4 i], 32-byte aligned.
-__device__ inline void store_packed(double* xq, int i, double x, double y, double z) {
+// Packed record of atom i: x, y, z and the atom's species (as a double; 0
+// for single-species potentials).
+__device__ inline void store_packed(double* xq, int i, double x, double y, double z,
+                                    int type = 0) {
   double2* q = reinterpret_cast<double2*>(xq + 4 * (size_t)i);
   q[0] = make_double2(x, y);
-  q[1] = make_double2(z, 0.0);
+  q[1] = make_double2(z, (double)type);
 }
 
 // The integrator also refreshes the packed positions the force kernels read.
@@ -107,6 +110,7 @@ struct BinOut {
   int* atom_cell;
   double* xq;    // nullable: packed [n][4] copy of x
   int* flag;     // the rebuild-request word this drift sets
+  const int* type;   // nullable: species per atom (stored in the packed records)
 };
 
 // Flags of a drift: a rebuild request (to bin.flag) when |x - x_ref|^2 >
@@ -123,7 +127,7 @@ __device__ inline void drift_flags(const double* xn, const double* dd, double tr
   if (leader && far) atomicOr(bin.flag, 1);
   if (leader && bad) atomicOr(&status[MD_ST_ERRORS], 2);
   if (live && bin.atom_cell) bin.atom_cell[i] = cell_of(xn[0], xn[1], xn[2], bin.box, bin.nc);
-  if (live && bin.xq) store_packed(bin.xq, i, xn[0], xn[1], xn[2]);
+  if (live && bin.xq) store_packed(bin.xq, i, xn[0], xn[1], xn[2], bin.type ? bin.type[i] : 0);
 }
 
 // Velocity-Verlet work a force kernel does for each atom once its force is
@@ -160,6 +164,15 @@ struct SCK {
   int n, m;
 };
 
+// Buckingham + cut Coulomb: per species pair ab = a * 4 + b the row
+// A, A / rho, 1 / rho, C, 6 C, qqr2e q_a q_b (A / rho and 1 / rho are 0 where
+// A is), in FP64 and FP32.
+struct BuckK {
+  double rc2;
+  double row[16][6];
+  float rowf[16][6];
+};
+
 // Where per-atom energy / virial / kinetic terms go for the thermo sums.
 struct EVOut {
   double* eatom;   // [n] or null
@@ -175,6 +188,7 @@ struct WsLayout {
   size_t tmp_v;      // double [3][n]     sorted staging of v
   size_t tmp_f;      // double [3][n]     sorted staging of f / x_ref
   size_t tmp_id;     // int [n]           sorted staging of ids
+  size_t tmp_type;   // int [n]           sorted staging of species
   size_t eatom;      // double [n]
   size_t vatom;      // double [6][n]
   size_t keatom;     // double [n]
@@ -207,12 +221,12 @@ hipError_t launch_bin_count(double* x, int n, BoxK box, const int nc[3], int* at
 hipError_t launch_scan_cells(const int* count, int ncell, int* cell_start, hipStream_t s);
 hipError_t launch_scatter(const int* atom_cell, const int* slot, const int* cell_start, int n,
                           int* tmp_perm, const int* gate, hipStream_t s);
-// Stable order inside each cell; optionally gathers x, v, id (and f, xr) into
-// the sorted staging buffers (null sources are skipped).
+// Stable order inside each cell; optionally gathers x, v, id, species (and
+// f) into the sorted staging buffers (null destinations are skipped).
 hipError_t launch_cell_sort(const int* tmp_perm, const int* cell_start, int ncell, int* perm,
                             const double* x, const double* v, const int* id, const double* f,
-                            int n, double* sx, double* sv, int* sid, double* sf,
-                            const int* gate, hipStream_t s);
+                            const int* type, int n, double* sx, double* sv, int* sid,
+                            double* sf, int* stype, const int* gate, hipStream_t s);
 // Rebuild-time sort for atoms already in the previous build's cell order that
 // moved less than a cell edge, with atom_cell holding their new cells:
 // launch_cell_count counts each new cell's members among the old ranges of
@@ -224,9 +238,9 @@ hipError_t launch_cell_count(const int* old_start, const int* atom_cell, const i
                              int* count, int* scount, const int* gate, hipStream_t s);
 hipError_t launch_gather_sort(const int* old_start, int* new_start, const int* count,
                               const int* scount, const int* atom_cell, const int nc[3], BoxK box,
-                              int* perm, const double* xq, const double* v, const int* id, int n,
-                              double* sx, double* sv, int* sid, int* status, const int* gate,
-                              hipStream_t s);
+                              int* perm, const double* xq, const double* v, const int* id,
+                              const int* type, int n, double* sx, double* sv, int* sid,
+                              int* stype, int* status, const int* gate, hipStream_t s);
 hipError_t launch_copy_back(double* x, double* v, int* id, double* f, double* xr,
                             const double* sx, const double* sv, const int* sid,
                             const double* sf, int n, hipStream_t s);
@@ -263,6 +277,8 @@ struct BuildArgs {
   const double* v_in;
   int* id_out;
   const int* id_in;
+  int* type_out;         // nullable: species copied back like id
+  const int* type_in;    // nullable: species of the home atoms (for xq_out and type_out)
   const int* gate;
 };
 hipError_t launch_build(const BuildArgs& a, hipStream_t s);
@@ -285,7 +301,9 @@ struct ForceArgs {
   hipEvent_t t0, t1;     // non-null: timed launch
   IntArgs in;            // mode MD_INT_NONE unless md_step fuses integration
 };
-hipError_t launch_pack_positions(const double* x, int n, double* xq, hipStream_t s);
+hipError_t launch_pack_positions(const double* x, int n, double* xq, const int* type,
+                                 hipStream_t s);
+hipError_t launch_buck(const ForceArgs& a, const BuckK& p, int prec, int lanes, hipStream_t s);
 hipError_t launch_lj(const ForceArgs& a, const LJK& p, int prec, int kernel, hipStream_t s);
 hipError_t launch_sc(const ForceArgs& a, const SCK& p, int prec, int kernel, double* sc_e,
                      hipStream_t s);

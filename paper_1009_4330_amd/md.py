@@ -22,7 +22,7 @@ MD_FP64, MD_MIXED = 0, 1
 MD_KERNEL_AUTO, MD_KERNEL_TPA, MD_KERNEL_WPA = 0, 1, 64
 LANES = (1, 2, 4, 8, 16, 32, 64)
 MD_EFLAG, MD_VFLAG = 1, 2
-MD_POT_LJ, MD_POT_SC = 0, 1
+MD_POT_LJ, MD_POT_SC, MD_POT_BUCK = 0, 1, 2
 MD_LAYOUT_TPA, MD_LAYOUT_WPA = 1, 64
 MD_ST_ERRORS, MD_ST_MAXNEIGH, MD_ST_BUILDS, MD_ST_REBUILD, MD_STATUS_WORDS = 0, 1, 2, 3, 8
 EXPORTS = ("md_workspace_bytes", "md_nlist_ints", "md_thermo_rows", "md_bin_cells", "md_sort_atoms",
@@ -45,7 +45,10 @@ class md_potential(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("rc", ctypes.c_double), ("lj_eps", ctypes.c_double),
                 ("lj_sigma", ctypes.c_double), ("lj_shift", ctypes.c_int),
                 ("sc_eps", ctypes.c_double), ("sc_a", ctypes.c_double),
-                ("sc_c", ctypes.c_double), ("sc_n", ctypes.c_int), ("sc_m", ctypes.c_int)]
+                ("sc_c", ctypes.c_double), ("sc_n", ctypes.c_int), ("sc_m", ctypes.c_int),
+                ("buck_A", ctypes.c_double * 16), ("buck_rho", ctypes.c_double * 16),
+                ("buck_C", ctypes.c_double * 16), ("q", ctypes.c_double * 4),
+                ("qqr2e", ctypes.c_double), ("type", ctypes.c_void_p)]
 
 
 class md_cells(ctypes.Structure):
@@ -151,6 +154,22 @@ def lj_potential(rc: float, eps: float = 1.0, sigma: float = 1.0, shift: int = 0
 
 def sc_potential(rc, eps, a, c, n, m) -> md_potential:
     return md_potential(kind=MD_POT_SC, rc=rc, sc_eps=eps, sc_a=a, sc_c=c, sc_n=n, sc_m=m)
+
+
+def buck_potential(rc, A, rho, C, q, qqr2e, type_tensor) -> md_potential:
+    """Buckingham + cut Coulomb.  A, rho, C: 16 values each (species pair
+    a * 4 + b); q: up to 4 charges; type_tensor: device int32 species per atom,
+    which md_step permutes in place with the atoms (the descriptor keeps its
+    address, so the tensor must outlive it)."""
+    if type_tensor.dtype != torch.int32 or not type_tensor.is_contiguous():
+        raise ValueError("species must be a contiguous int32 tensor")
+    qs = list(q) + [0.0] * (4 - len(q))
+    p = md_potential(kind=MD_POT_BUCK, rc=rc, qqr2e=qqr2e, type=type_tensor.data_ptr())
+    for k in range(16):
+        p.buck_A[k], p.buck_rho[k], p.buck_C[k] = float(A[k]), float(rho[k]), float(C[k])
+    for k in range(4):
+        p.q[k] = float(qs[k])
+    return p
 
 
 class Cells:

@@ -14,24 +14,31 @@ import numpy as np
 import torch
 
 from . import md
-from .inputs import Workload
+from .inputs import Workload, pair_table
 
 PREC = {"fp64": md.MD_FP64, "mixed": md.MD_MIXED}
 KERNEL = {"auto": md.MD_KERNEL_AUTO, "tpa": md.MD_KERNEL_TPA, "wpa": md.MD_KERNEL_WPA,
           **{f"k{k}": k for k in md.LANES}}
 
 
-def potential_of(w: Workload, **over) -> md.md_potential:
+def potential_of(w: Workload, type_tensor: Optional[torch.Tensor] = None,
+                 **over) -> md.md_potential:
+    """The workload's potential; Buckingham needs the device species tensor."""
     if w.potential == "lj":
         return md.lj_potential(w.rc, over.get("eps", w.lj_eps), over.get("sigma", w.lj_sigma),
                                w.lj_shift)
+    if w.potential == "buck":
+        if type_tensor is None:
+            raise ValueError("Buckingham needs a species tensor")
+        return md.buck_potential(w.rc, pair_table(w, "buck_A"), pair_table(w, "buck_rho"),
+                                 pair_table(w, "buck_C"), w.charges, w.qqr2e, type_tensor)
     return md.sc_potential(w.rc, w.sc_eps, w.sc_a, w.sc_c, w.sc_n, w.sc_m)
 
 
 def capacity_guess(w: Workload) -> int:
     """Neighbour capacity from the mean count in the list sphere, with
     headroom for density fluctuations of a liquid."""
-    rho = 4.0 / w.a ** 3
+    rho = (8.0 if w.lattice == "rocksalt" else 4.0) / w.a ** 3
     mean = rho * 4.0 / 3.0 * math.pi * (w.rc + w.skin) ** 3
     return int(mean * 1.35 + 4.0 * math.sqrt(mean) + 16)
 
@@ -43,9 +50,12 @@ class MDSystem:
         self.prec = PREC[prec]
         self.kernel = KERNEL[kernel]
         self.box = md.make_box(w.box)
-        self.pot = potential_of(w)
-        self.rl = w.rc + w.skin
         n = x.shape[1]
+        # species, permuted by md_step along with the atoms (Buckingham only)
+        self.type = (torch.as_tensor(w.species(), dtype=torch.int32, device=device)
+                     if w.potential == "buck" else None)
+        self.pot = potential_of(w, self.type)
+        self.rl = w.rc + w.skin
         self.n = n
         u = w.units
         self.state = md.State(torch.as_tensor(x, dtype=torch.float64, device=device),
@@ -60,14 +70,16 @@ class MDSystem:
         self.device = device
 
     # -- helpers -------------------------------------------------------------
-    def _snapshot(self):
+    def _tensors(self):
         s = self.state
-        return (s.x.clone(), s.v.clone(), s.f.clone(), s.id.clone(), self.nl.x_ref.clone(),
-                self.nl.status.clone())
+        out = [s.x, s.v, s.f, s.id, self.nl.x_ref, self.nl.status]
+        return out + ([self.type] if self.type is not None else [])
+
+    def _snapshot(self):
+        return tuple(t.clone() for t in self._tensors())
 
     def _restore(self, snap):
-        s = self.state
-        for dst, src in zip((s.x, s.v, s.f, s.id, self.nl.x_ref, self.nl.status), snap):
+        for dst, src in zip(self._tensors(), snap):
             dst.copy_(src)
 
     def _grow(self, need: int):

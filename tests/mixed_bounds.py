@@ -87,3 +87,21 @@ def assert_vector(got, want, mag_per_atom, u=U32, what=""):
     err = float(np.linalg.norm((np.asarray(got) - np.asarray(want)).ravel()))
     bound = K * u * float(np.linalg.norm(mag_per_atom))
     assert err <= bound, f"{what}: error {err:.3e} > bound {bound:.3e}"
+
+
+def buck_magnitudes(x, box, onl, rc, types, A, rho, C, q, qqr2e):
+    """Magnitude sums for Buckingham + cut Coulomb.  The FP32 exponential of
+    -r / rho carries the relative error of its argument times |r / rho|, so
+    the Born-Mayer parts are weighted by (1 + r / rho)."""
+    n = x.shape[1]
+    i, j, d, s = pair_geometry(x, box, onl, rc)
+    ab = 4 * np.asarray(types)[i] + np.asarray(types)[j]
+    r = np.sqrt(s)
+    a_, c_ = np.asarray(A)[ab], np.asarray(C)[ab]
+    rh = np.where(a_ > 0, np.asarray(rho)[ab], 1.0)
+    qq = np.abs(qqr2e * np.asarray(q)[np.asarray(types)[i]] * np.asarray(q)[np.asarray(types)[j]])
+    ex = a_ * np.exp(-r / rh) * (1.0 + r / rh)
+    mag_g = (ex / rh + 6.0 * c_ / s ** 3.5 + qq / s) / r
+    return {"f": _per_atom(n, i, mag_g * r),
+            "e": 0.5 * np.sum(ex + c_ / s ** 3 + qq / r),
+            "w": np.array([0.5 * np.sum(np.abs(d[a] * d[b]) * mag_g) for a, b in VPAIRS])}

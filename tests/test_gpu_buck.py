@@ -1,0 +1,169 @@
+"""Buckingham + cut Coulomb on the GPU (the pair potential of the paper's
+silicate benchmark, Appendix A) against the oracle: forces, energy and virial
+for each precision and lanes-per-atom layout, the species carried through
+md_step's sorts and rebuilds, and a short NVE run."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import mixed_bounds as MB
+from gpu_helpers import forces_gpu, gpu_list, gpu_pairs, rel
+from paper_1009_4330_amd import inputs as I
+from paper_1009_4330_amd import md
+from paper_1009_4330_amd.system import MDSystem, potential_of
+
+pytestmark = pytest.mark.gpu
+
+LAYOUTS = [(md.MD_LAYOUT_TPA, md.MD_KERNEL_TPA), (4, 4), (16, 16),
+           (md.MD_LAYOUT_WPA, md.MD_KERNEL_WPA)]
+IDS = ["tpa", "k4", "k16", "wpa"]
+W8 = I.scaled(I.BUCK_141K, 8)                    # 4096 ions, L = 35.0 A > 2 (rc + skin)
+# In the crystal no ion drifts the workload's half skin (1 A); a 0.3 A skin
+# makes the run rebuild every ten steps or so, so the sorts move species.
+W8_RUN = dataclasses.replace(I.scaled(I.BUCK_141K, 8, steps=60), skin=0.3)
+W4_SHORT = dataclasses.replace(I.scaled(I.BUCK_141K, 4), rc=7.0, skin=1.0)  # 512 ions, L = 17.5
+
+
+def tables(w):
+    return [I.pair_table(w, k) for k in ("buck_A", "buck_rho", "buck_C")]
+
+
+def charges(w):
+    return np.array(list(w.charges) + [0.0] * (4 - len(w.charges)))
+
+
+def ionic(w, seed, amp):
+    x, _, box = I.initial_state(w)
+    return I.jitter(x, amp, seed), box
+
+
+def oracle(orc, w, x, box):
+    onl, oc = orc.build_nlist(x, box, w.rc + w.skin)
+    A, rho, C = tables(w)
+    r = orc.buck_forces(oc.x, box, onl, w.rc, w.species(), A, rho, C, charges(w), w.qqr2e)
+    return r, onl, oc
+
+
+def check(orc, w, x_np, box, layout, kernel, prec, cap):
+    x, cells, nl, ws, mbox = gpu_list(x_np, box, w.rc, w.skin, layout, cap)
+    types = torch.as_tensor(w.species(), dtype=torch.int32, device="cuda")
+    pot = potential_of(w, types)
+    f, ev = forces_gpu(pot, x, mbox, nl, prec, kernel, ws)
+    ref, onl, oc = oracle(orc, w, x_np, box)
+    if prec == md.MD_FP64:
+        assert rel(f, ref.f) < 1e-12
+        assert ev[0] == pytest.approx(ref.energy, rel=1e-12)
+        assert rel(ev[1:], ref.virial) < 1e-12
+        return
+    print(f"mixed Buckingham force rel-RMS {rel(f, ref.f):.3e}")
+    A, rho, C = tables(w)
+    mag = MB.buck_magnitudes(oc.x, box, onl, w.rc, w.species(), A, rho, C, charges(w), w.qqr2e)
+    MB.assert_vector(f, ref.f, mag["f"], what="force")
+    MB.assert_total(ev[0], ref.energy, mag["e"], what="energy")
+    for c in range(6):
+        MB.assert_total(ev[1 + c], ref.virial[c], mag["w"][c], what=f"virial {c}")
+
+
+@pytest.mark.parametrize("layout,kernel", LAYOUTS, ids=IDS)
+@pytest.mark.parametrize("prec", [md.MD_FP64, md.MD_MIXED], ids=["fp64", "mixed"])
+def test_buck_forces_short_cutoff(orc, layout, kernel, prec):
+    """512 ions, rc = 7 A: every layout, ragged last wavefront groups."""
+    x, box = ionic(W4_SHORT, 71, 0.12)
+    check(orc, W4_SHORT, x, box, layout, kernel, prec, 320)
+
+
+@pytest.mark.parametrize("layout,kernel", [LAYOUTS[0], LAYOUTS[2]], ids=["tpa", "k16"])
+@pytest.mark.parametrize("prec", [md.MD_FP64, md.MD_MIXED], ids=["fp64", "mixed"])
+def test_buck_forces_workload_cutoff(orc, layout, kernel, prec):
+    """4096 ions at the workload's rc = 15 A (about 1900 list partners each)."""
+    x, box = ionic(W8, 72, 0.08)
+    check(orc, W8, x, box, layout, kernel, prec, 2300)
+
+
+@pytest.mark.parametrize("w", [W8, I.scaled(I.BUCK_141K, 9)], ids=["8cells", "9cells"])
+def test_buck_neighbour_sets(orc, w):
+    """Dense cells (512-730 ions per list cell): each cell's home atoms are
+    split over several workgroups; the pair set is still exact."""
+    x, box = ionic(w, 74, 0.1)
+    xg, cells, nl, ws, mbox = gpu_list(x, box, w.rc, w.skin, 16, 2400)
+    onl, _ = orc.build_nlist(x, box, w.rc + w.skin)
+    got = gpu_pairs(nl)
+    want = onl.pairs()
+    want = want[np.lexsort((want[:, 1], want[:, 0]))]
+    assert np.array_equal(got, want)
+    assert np.array_equal(nl.numneigh.cpu().numpy(), onl.numneigh)
+
+
+def test_buck_perfect_crystal(orc):
+    """On the perfect lattice every ion's force cancels; both sides agree on
+    the energy and leave forces at rounding level."""
+    x, _, box = I.initial_state(W8)
+    xg, cells, nl, ws, mbox = gpu_list(x, box, W8.rc, W8.skin, md.MD_LAYOUT_TPA, 2300)
+    types = torch.as_tensor(W8.species(), dtype=torch.int32, device="cuda")
+    f, ev = forces_gpu(potential_of(W8, types), xg, mbox, nl, md.MD_FP64, md.MD_KERNEL_TPA, ws)
+    ref, _, _ = oracle(orc, W8, x, box)
+    assert ev[0] == pytest.approx(ref.energy, rel=1e-12)
+    assert np.abs(f).max() < 1e-9
+
+
+def test_buck_rejects_bad_tables():
+    x, box = ionic(W4_SHORT, 73, 0.05)
+    xg, cells, nl, ws, mbox = gpu_list(x, box, W4_SHORT.rc, W4_SHORT.skin, md.MD_LAYOUT_TPA, 320)
+    types = torch.as_tensor(W4_SHORT.species(), dtype=torch.int32, device="cuda")
+    f = torch.zeros(3, x.shape[1], dtype=torch.float64, device="cuda")
+    pot = potential_of(W4_SHORT, types)
+    pot.buck_A[1] = 2.0 * pot.buck_A[4]          # asymmetric table
+    with pytest.raises(md.MDError):
+        md.md_compute_forces(pot, xg, mbox, nl, md.MD_FP64, md.MD_KERNEL_TPA, 0, f, None, ws)
+    pot = potential_of(W4_SHORT, types)
+    pot.type = None                               # species missing
+    with pytest.raises(md.MDError):
+        md.md_compute_forces(pot, xg, mbox, nl, md.MD_FP64, md.MD_KERNEL_TPA, 0, f, None, ws)
+
+
+@pytest.mark.parametrize("kernel", ["tpa", "k16"])
+def test_buck_step_fp64(orc, kernel):
+    """NVE from the 600 K rocksalt start: same rebuild steps and thermo as the
+    oracle's run, and the same final state (species permuted with the atoms
+    by every sort, or the forces would differ)."""
+    w = W8_RUN
+    x, v, box = I.initial_state(w)
+    ref = orc.md_run(orc.params_for(w), x, v, box, w.steps, 5)
+    sysm = MDSystem(w, x, v, "fp64", kernel, capacity=2300)
+    rows = np.concatenate([sysm.setup(True), sysm.run(w.steps, 5)])
+    gx, gv, gf = sysm.host_state()
+    assert np.array_equal(rows[:, 6].astype(int), ref.thermo[:, 6].astype(int))
+    assert rows[-1, 6] > 3, "the run should rebuild several times"
+    for c in (1, 2, 3, 4, 5):
+        assert rel(rows[:, c], ref.thermo[:, c]) < 1e-10, c
+    L = np.array(box)[:, None]
+    d = gx - ref.x
+    assert np.abs(d - L * np.round(d / L)).max() < 1e-9
+    assert rel(gf, ref.f) < 1e-9
+    # the species array ends in the device's atom order: id -> species intact
+    order = torch.argsort(sysm.state.id.long())
+    assert np.array_equal(sysm.type[order].cpu().numpy(), w.species())
+
+
+def test_buck_step_mixed_tracks_fp64():
+    """MIXED NVE against the FP64 run from the same state.  The cut Coulomb
+    energy jumps by q_a q_b qqr2e / rc whenever a pair crosses rc, so total
+    energy is no conservation check here; instead temperature and potential
+    energy must follow the FP64 run (a pair crossing rc one step apart moves
+    the potential energy by about 3e-5 of its size)."""
+    w = W8_RUN
+    x, v, box = I.initial_state(w)
+    rows = {}
+    for prec in ("fp64", "mixed"):
+        s = MDSystem(w, x, v, prec, "k16", capacity=2300)
+        rows[prec] = np.concatenate([s.setup(True), s.run(w.steps, 1)])
+        if prec == "mixed":
+            vsum = s.state.v.sum(dim=1).cpu().numpy()
+    dt_ = rel(rows["mixed"][:, 4], rows["fp64"][:, 4])
+    dpe = rel(rows["mixed"][:, 1], rows["fp64"][:, 1])
+    print(f"Buckingham MIXED vs FP64 over {w.steps} steps: T rel {dt_:.2e}, pe rel {dpe:.2e}")
+    assert dt_ < 1e-3 and dpe < 1e-3
+    # pair terms are antisymmetric bit for bit: momentum stays at its start
+    assert np.abs(vsum - v.sum(axis=1)).max() < 1e-10 * w.natoms
