@@ -24,8 +24,9 @@
  *   - velocity-Verlet NVE integration ("NVE integrator", section "Design
  *     objectives") with a rebuild of the list whenever an atom moved more than
  *     skin/2 since the last build;
- *   - the vector-Jacobian product of the LJ forces with respect to positions
- *     and to (eps, sigma).
+ *   - the vector-Jacobian products of the LJ forces (with respect to
+ *     positions and (eps, sigma)) and of the Sutton-Chen forces (positions and
+ *     (eps, a, c)).
  * Status codes: 0 ok, 1 invalid argument, 2 box too small, 3 list overflow
  * (numneigh still holds the true counts; *max_count the largest).
  */
@@ -435,6 +436,106 @@ int orc_lj_vjp(int64_t n, const double* x, const double* L, const int* numneigh,
   }
   free(pe);
   free(ps);
+  return ORC_OK;
+}
+
+/* Vector-Jacobian product of the Sutton-Chen forces.  With s = r^2,
+   phi(s) = (a^2/s)^(n/2), psi(s) = (a^2/s)^(m/2), rho_i = sum_j psi(s_ij) and
+   e_i = rho_i^(-1/2) (0 for an atom without partners), the force is
+   F_i = sum_j h_ij d_ij with
+     h_ij = A(s_ij) + B(s_ij) (e_i + e_j),
+     A(s) = n eps phi / s,   B(s) = -(m/2) eps c psi / s.
+   For L = sum_i u_i . F_i = 1/2 sum_ij h_ij w_ij, w_ij = (u_i - u_j) . d_ij,
+   differentiating at fixed e and then through e_i(rho_i(x)) gives
+     g_i   = sum_j B(s_ij) w_ij                      (dL/de_i)
+     lam_i = -1/2 e_i^3 g_i                          (dL/drho_i)
+     dL/dx_i = sum_j [ h_ij (u_i - u_j) + 2 h'_ij w_ij d_ij
+                       + 2 (lam_i + lam_j) psi'(s_ij) d_ij ]
+   with h' = A'(s) + B'(s) (e_i + e_j), A' = -(n/2 + 1) A / s,
+   B' = -(m/2 + 1) B / s, psi' = -(m/2) psi / s.  The parameters enter through
+   LA = 1/2 sum_ij A_ij w_ij and LB = sum_i e_i g_i (L = LA + LB):
+   dL/deps = L / eps, dL/dc = LB / c, dL/da = (n LA + (m/2) LB) / a
+   (A ~ a^n, B ~ a^m, e ~ a^(-m/2)).  B and g are carried per unit c, so that
+   dL/dc = sum_i e_i g_i / c stays defined at c = 0.  Three passes over the
+   list. */
+int orc_sc_vjp(int64_t n, const double* x, const double* L, const int* numneigh,
+               const int* neigh, int cap, double rc, double eps, double a, double c,
+               int nexp, int mexp, const double* u, double* gx, double* gparam) {
+  if (n <= 0 || !x || !numneigh || !neigh || !u || !gx) return ORC_EINVAL;
+  const double rc2 = rc * rc, a2 = a * a;
+  double* e = (double*)calloc((size_t)n, sizeof(double));
+  double* lam = (double*)calloc((size_t)n, sizeof(double));
+  double* la = (double*)calloc((size_t)n, sizeof(double));
+  double* lb = (double*)calloc((size_t)n, sizeof(double));
+  if (!e || !lam || !la || !lb) { free(e); free(lam); free(la); free(lb); return ORC_EINVAL; }
+  /* pass 1: densities */
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double ri = 0.0;
+    int cnt = numneigh[i] < cap ? numneigh[i] : cap;
+    for (int k = 0; k < cnt; ++k) {
+      int64_t j = neigh[i * (int64_t)cap + k];
+      double d[3];
+      double s = dist2(x, n, L, i, j, d);
+      if (s < rc2) ri += pow(a2 / s, 0.5 * mexp);
+    }
+    e[i] = ri > 0.0 ? 1.0 / sqrt(ri) : 0.0;
+  }
+  /* pass 2: g_i, lam_i and the per-atom parts of LA, LB */
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double gci = 0.0, lai = 0.0;   /* gci = g_i / c */
+    int cnt = numneigh[i] < cap ? numneigh[i] : cap;
+    for (int k = 0; k < cnt; ++k) {
+      int64_t j = neigh[i * (int64_t)cap + k];
+      double d[3];
+      double s = dist2(x, n, L, i, j, d);
+      if (!(s < rc2)) continue;
+      double A = nexp * eps * pow(a2 / s, 0.5 * nexp) / s;
+      double Bc = -0.5 * mexp * eps * pow(a2 / s, 0.5 * mexp) / s;   /* B / c */
+      double w = (u[i] - u[j]) * d[0] + (u[n + i] - u[n + j]) * d[1] +
+                 (u[2 * n + i] - u[2 * n + j]) * d[2];
+      gci += Bc * w;
+      lai += 0.5 * A * w;
+    }
+    lam[i] = -0.5 * e[i] * e[i] * e[i] * (c * gci);
+    la[i] = lai;
+    lb[i] = e[i] * gci;               /* per unit c */
+  }
+  /* pass 3: dL/dx */
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double gi[3] = {0.0, 0.0, 0.0};
+    int cnt = numneigh[i] < cap ? numneigh[i] : cap;
+    for (int k = 0; k < cnt; ++k) {
+      int64_t j = neigh[i * (int64_t)cap + k];
+      double d[3];
+      double s = dist2(x, n, L, i, j, d);
+      if (!(s < rc2)) continue;
+      double phi = pow(a2 / s, 0.5 * nexp), psi = pow(a2 / s, 0.5 * mexp);
+      double A = nexp * eps * phi / s;
+      double B = -0.5 * mexp * eps * c * psi / s;
+      double h = A + B * (e[i] + e[j]);
+      double hp = -(0.5 * nexp + 1.0) * A / s - (0.5 * mexp + 1.0) * B / s * (e[i] + e[j]);
+      double psip = -0.5 * mexp * psi / s;
+      double du[3] = {u[i] - u[j], u[n + i] - u[n + j], u[2 * n + i] - u[2 * n + j]};
+      double w = du[0] * d[0] + du[1] * d[1] + du[2] * d[2];
+      for (int q = 0; q < 3; ++q)
+        gi[q] += h * du[q] + 2.0 * hp * w * d[q] + 2.0 * (lam[i] + lam[j]) * psip * d[q];
+    }
+    for (int q = 0; q < 3; ++q) gx[q * n + i] = gi[q];
+  }
+  if (gparam) {
+    double ta = 0.0, tb = 0.0;
+    for (int64_t i = 0; i < n; ++i) { ta += la[i]; tb += lb[i]; }
+    gparam[0] = (ta + c * tb) / eps;
+    gparam[1] = (nexp * ta + 0.5 * mexp * c * tb) / a;
+    gparam[2] = tb;
+  }
+  free(e);
+  free(lam);
+  free(la);
+  free(lb);
   return ORC_OK;
 }
 

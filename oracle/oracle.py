@@ -112,10 +112,14 @@ def _declare(L):
                                   _dp, _dp]
     L.orc_lj_vjp.argtypes = [_i64, _dp, _dp, _ip, _ip, ctypes.c_int, ctypes.c_double,
                              ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
+    L.orc_sc_vjp.argtypes = [_i64, _dp, _dp, _ip, _ip, ctypes.c_int, ctypes.c_double,
+                             ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                             ctypes.c_int, _dp, _dp, _dp]
     L.orc_md_run.argtypes = [ctypes.POINTER(Params), _i64, _dp, _dp, _dp, ctypes.c_int,
                              ctypes.c_int, ctypes.c_int, _dp, _ip, _dp]
     for name in ("orc_cell_dims", "orc_bin", "orc_build_nlist", "orc_lj_forces",
-                 "orc_sc_forces", "orc_buck_forces", "orc_lj_vjp", "orc_md_run"):
+                 "orc_sc_forces", "orc_buck_forces", "orc_lj_vjp", "orc_sc_vjp",
+                 "orc_md_run"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -301,6 +305,21 @@ def lj_vjp(x, box, nl: NList, rc, eps, sigma, u):
                           rc, eps, sigma, _d(u), _d(gx), _d(gp))
     if st:
         raise OracleError(st, "lj_vjp")
+    return gx, gp
+
+
+def sc_vjp(x, box, nl: NList, rc, eps, a, c, nexp, mexp, u):
+    """Returns (gx [3][N], gparam [3] = dL/deps, dL/da, dL/dc) for
+    L = sum_i u_i . F_i of the Sutton-Chen forces."""
+    x = _f64(x)
+    u = _f64(u)
+    n = x.shape[1]
+    gx = np.zeros((3, n))
+    gp = np.zeros(3)
+    st = lib().orc_sc_vjp(n, _d(x), _d(_f64(box)), _i(nl.numneigh), _i(nl.neigh), nl.cap,
+                          rc, eps, a, c, int(nexp), int(mexp), _d(u), _d(gx), _d(gp))
+    if st:
+        raise OracleError(st, "sc_vjp")
     return gx, gp
 
 

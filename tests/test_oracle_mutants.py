@@ -9,6 +9,7 @@ import pytest
 
 import test_oracle as T
 import test_oracle_buck as TB
+import test_oracle_sc_vjp as TS
 from paper_1009_4330_amd import inputs as I
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle",
@@ -46,7 +47,23 @@ MUTANTS = {
                                ["buck_fd", "buck_brute_disp"]),
     "buck_energy_half_dropped": ("eb += 0.5 * phi;", "eb += phi;",
                                  ["buck_lattice", "buck_brute_disp"]),
+    "scvjp_embedding_dropped": ("+ 2.0 * (lam[i] + lam[j]) * psip * d[q];",
+                                "+ 0.0 * (lam[i] + lam[j]) * psip * d[q];", ["fd_scvjp"]),
+    "scvjp_partner_lambda": ("(lam[i] + lam[j])", "(lam[i] + lam[i])",
+                             ["fd_scvjp", "sym_scvjp"]),
+    "scvjp_hprime_power": ("-(0.5 * nexp + 1.0) * A / s", "-(0.5 * nexp) * A / s",
+                           ["fd_scvjp", "sym_scvjp"]),
+    "scvjp_lambda_power": ("lam[i] = -0.5 * e[i] * e[i] * e[i] * (c * gci);",
+                           "lam[i] = -0.5 * e[i] * e[i] * (c * gci);", ["fd_scvjp"]),
+    "scvjp_da_factor": ("gparam[1] = (nexp * ta + 0.5 * mexp * c * tb) / a;",
+                        "gparam[1] = (nexp * ta + mexp * c * tb) / a;", ["par_scvjp_a"]),
 }
+
+
+def _scsys(o):
+    x, box = TS.sc_system(5, 0.25, 81)
+    nl, _ = o.build_nlist(x, box, TS.RC + 1.0)
+    return x, box, nl
 
 
 def _jittered():
@@ -76,6 +93,9 @@ PINS = {
     "buck_brute_coul": lambda o: TB.test_each_term_against_brute_force(o, _jittered(), "coulomb"),
     "buck_fd": lambda o: TB.test_forces_are_minus_energy_gradient(o, _jittered()),
     "buck_lattice": lambda o: TB.test_dispersion_lattice_sum(o),
+    "fd_scvjp": lambda o: TS.test_sc_vjp_matches_central_differences_in_x(o, _scsys(o)),
+    "sym_scvjp": lambda o: TS.test_sc_vjp_symmetry_translation_and_linearity(o, _scsys(o)),
+    "par_scvjp_a": lambda o: TS.test_sc_vjp_parameter_gradients(o, _scsys(o), 1, "a"),
 }
 
 
