@@ -471,15 +471,15 @@ int orc_sc_vjp(int64_t n, const double* x, const double* L, const int* numneigh,
   /* pass 1: densities */
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
-    double ri = 0.0;
+    double rho_i = 0.0;
     int cnt = numneigh[i] < cap ? numneigh[i] : cap;
     for (int k = 0; k < cnt; ++k) {
       int64_t j = neigh[i * (int64_t)cap + k];
       double d[3];
       double s = dist2(x, n, L, i, j, d);
-      if (s < rc2) ri += pow(a2 / s, 0.5 * mexp);
+      if (s < rc2) rho_i += pow(a2 / s, 0.5 * mexp);
     }
-    e[i] = ri > 0.0 ? 1.0 / sqrt(ri) : 0.0;
+    e[i] = rho_i > 0.0 ? 1.0 / sqrt(rho_i) : 0.0;
   }
   /* pass 2: g_i, lam_i and the per-atom parts of LA, LB */
 #pragma omp parallel for schedule(static)
