@@ -167,6 +167,35 @@ def bench_vjp(reps: int):
     return out
 
 
+def bench_sc_vjp(reps: int):
+    """Sutton-Chen force-VJP atoms/s (three passes, positions and (eps, a, c))
+    on the 500k-atom copper-like solid after its setup."""
+    import torch
+    from paper_1009_4330_amd import inputs as I
+    from paper_1009_4330_amd import md
+    from paper_1009_4330_amd.system import MDSystem
+
+    w = I.SC_500K
+    x, v, _ = I.initial_state(w)
+    s = MDSystem(w, x, v, "fp64", "auto")
+    s.setup(thermo=False)
+    n = w.natoms
+    u = torch.randn(3, n, dtype=torch.float64, device="cuda",
+                    generator=torch.Generator(device="cuda").manual_seed(5))
+    gx = torch.empty_like(u)
+    gp = torch.empty(3, dtype=torch.float64, device="cuda")
+    out = {"lanes_per_atom": s.nl.layout}
+    for prec_name, prec in (("mixed", md.MD_MIXED), ("fp64", md.MD_FP64)):
+        md.md_force_vjp(s.pot, s.state.x, s.box, s.nl, prec, u, gx, gp, s.ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            md.md_force_vjp(s.pot, s.state.x, s.box, s.nl, prec, u, gx, gp, s.ws)
+        torch.cuda.synchronize()
+        out[prec_name] = n * reps / (time.perf_counter() - t0)
+    return out
+
+
 def cpu_baseline(w, x, v, target_s: float = 15.0):
     """The oracle's own NVE run on the host cores, on a bounded number of
     steps of the same workload; setup (first build + forces) is subtracted."""
@@ -334,6 +363,7 @@ def suite(steps: int):
               "lanes_per_atom": r["kernel"], "atom_steps_per_s": steps * w.natoms / r["elapsed"],
               "force_us": 1e3 * r["force_ms_avg"], "rebuilds": r["rebuilds"],
               "mean_neighbors": r["mean_neigh"], "steps": steps})
+    emit({"item": "C4_sc_vjp_atoms_per_s", **bench_sc_vjp(20)})
     emit({"item": "C5_fit", **{k: v for k, v in fit_timing().items()}})
     for nc in (10, 20, 30, 40, 60, 80):
         w = I.scaled(I.LJ_256K, nc)

@@ -226,10 +226,14 @@ md_status md_step(md_state* st, const md_potential* p, const md_box* box, md_cel
                   int nsteps, int thermo_every, int setup, double* thermo, void* ws,
                   size_t ws_bytes, void* stream);
 
-/* Vector-Jacobian product of the LJ forces: gx = (dF/dx)^T u = -H u, with
-   u, gx [3][n]; gparam (may be NULL) receives dL/deps, dL/dsigma for the
-   cotangent u (2 doubles).  Pair set: listed pairs with r^2 < rc^2 (rc is not
-   scaled by sigma).  SC returns MD_ERR_UNSUPPORTED. */
+/* Vector-Jacobian product of the forces for L = sum_i u_i . F_i:
+   gx = (dF/dx)^T u = -H u, with u, gx [device, 3][n]; gparam [device, may be
+   NULL] receives the parameter gradients of L.  LJ: dL/deps, dL/dsigma
+   (2 doubles).  SC: dL/deps, dL/da, dL/dc (3 doubles); its Hessian includes
+   the many-body embedding term, through a density pass, a pass for
+   dL/drho_i and the position pass.  Pair set: listed pairs with r^2 < rc^2
+   (rc is not scaled by sigma or a).  Buckingham returns MD_ERR_UNSUPPORTED.
+   Uses the workspace's per-atom columns (not preserved). */
 md_status md_force_vjp(const md_potential* p, const double* x, int64_t n, const md_box* box,
                        const md_nlist* nl, md_precision prec, const double* u, double* gx,
                        double* gparam, void* ws, size_t ws_bytes, void* stream);

@@ -151,6 +151,10 @@ SCK make_sc(const md_potential* p) {
   k.neps = p->sc_n * p->sc_eps;
   k.mepsc_half = 0.5 * p->sc_m * p->sc_eps * p->sc_c;
   k.epsc = p->sc_eps * p->sc_c;
+  k.meps_half = 0.5 * p->sc_m * p->sc_eps;
+  k.c = p->sc_c;
+  k.meps_halff = (float)k.meps_half;
+  k.cf = (float)k.c;
   k.a2f = (float)k.a2;
   k.nepsf = (float)k.neps;
   k.mepsc_halff = (float)k.mepsc_half;
@@ -547,7 +551,7 @@ md_status md_force_vjp(const md_potential* p, const double* x, int64_t n, const 
                        double* gparam, void* ws, size_t ws_bytes, void* stream) {
   md_status st = check_pot(p);
   if (st != MD_OK) return st;
-  if (p->kind != MD_POT_LJ) return MD_ERR_UNSUPPORTED;
+  if (p->kind != MD_POT_LJ && p->kind != MD_POT_SC) return MD_ERR_UNSUPPORTED;
   if (!x || !nl || !nl->neigh || !nl->numneigh || !u || !gx || !n_ok(n) || nl->capacity < 1 ||
       (prec != MD_FP64 && prec != MD_MIXED) || !lanes_ok(nl->layout))
     return MD_ERR_INVALID_ARG;
@@ -566,6 +570,27 @@ md_status md_force_vjp(const md_potential* p, const double* x, int64_t n, const 
   fa.numneigh = nl->numneigh;
   fa.cap = nl->capacity;
   timing_events(&fa.t0, &fa.t1);
+  if (p->kind == MD_POT_SC) {
+    // e, lam, la, lb in the workspace's per-atom columns
+    double* e = at<double>(ws, L.sc_e);
+    double* lam = at<double>(ws, L.vatom);
+    double* la = at<double>(ws, L.eatom);
+    double* lb = at<double>(ws, L.keatom);
+    const SCK k = make_sc(p);
+    MD_CK(launch_sc_vjp(fa, k, prec, nl->layout, u, e, lam, la, lb, gx, s));
+    if (gparam) {
+      SumArgs sa{};
+      sa.cols = 2;
+      sa.col[0] = la;
+      sa.col[1] = lb;
+      sa.n = (int)n;
+      sa.partials = at<double>(ws, L.partials);
+      sa.out = at<double>(ws, L.scalars);
+      MD_CK(launch_sum(sa, s));
+      MD_CK(launch_sc_vjp_params(at<double>(ws, L.scalars), k, p->sc_a, gparam, s));
+    }
+    return MD_OK;
+  }
   double* pe = gparam ? at<double>(ws, L.eatom) : nullptr;
   double* ps = gparam ? at<double>(ws, L.keatom) : nullptr;
   MD_CK(launch_lj_vjp(fa, make_lj(p), prec, nl->layout, u, gx, pe, ps, s));

@@ -644,6 +644,133 @@ __global__ __launch_bounds__(kBlock) void k_lj_vjp(FK a, LJK p, const double* __
   if (ps) ps[i] = dsig;
 }
 
+// ------------------------------------------------------- Sutton-Chen VJP --
+
+// Pair factors of the Sutton-Chen forces at r^2 = s, t = a^2 / s:
+// A = n eps t^(n/2) / s and Bc = -(m/2) eps t^(m/2) / s (B = c Bc), so that
+// F_i = sum_j [A + B (e_i + e_j)] d_ij; psi = t^(m/2).
+template <int PREC>
+__device__ inline void sc_pair_factors(const SCK& p, double s, double& r2i, double& A,
+                                       double& Bc, double& psi) {
+  if (PREC == MD_FP64) {
+    r2i = rcp64(s);
+    const double tt = p.a2 * r2i;
+    psi = half_power(tt, p.m);
+    A = p.neps * half_power(tt, p.n) * r2i;
+    Bc = -p.meps_half * psi * r2i;
+  } else {
+    const float rf = __builtin_amdgcn_rcpf((float)s);
+    const float tt = p.a2f * rf;
+    const float pm = half_power(tt, p.m);
+    r2i = (double)rf;
+    psi = (double)pm;
+    A = (double)(p.nepsf * half_power(tt, p.n) * rf);
+    Bc = (double)(-p.meps_halff * pm * rf);
+  }
+}
+
+// Pass 2 of the adjoint: with w_ij = (u_i - u_j) . d_ij, g_i / c = sum_j Bc w,
+// la_i = 1/2 sum_j A w; stores lam_i = -1/2 e_i^3 c (g_i / c) (= dL/drho_i),
+// la_i and lb_i = e_i (g_i / c).
+template <int PREC, int K>
+__global__ __launch_bounds__(kBlock) void k_sc_vjp_rho(FK a, SCK p, const double* __restrict__ u,
+                                                        const double* __restrict__ e,
+                                                        double* __restrict__ lam,
+                                                        double* __restrict__ la,
+                                                        double* __restrict__ lb) {
+  const Lane<K> ln(a);
+  const int n = a.n;
+  const int io = ln.live ? ln.i : n - 1;
+  double xi, yi, zi;
+  home_pos(a, io, xi, yi, zi);
+  const double uxi = u[io], uyi = u[n + io], uzi = u[2 * n + io];
+  double gc = 0.0, lai = 0.0;
+  for_each_batch<K, PREC == MD_MIXED>(a, ln, xi, yi, zi, [&](const Batch& b) {
+    double ux[kUnroll], uy[kUnroll], uz[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      ux[q] = u[b.j[q]];
+      uy[q] = u[n + b.j[q]];
+      uz[q] = u[2 * n + b.j[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      if (!(b.ok[q] && b.s[q] < p.rc2)) continue;
+      double r2i, A, Bc, psi;
+      sc_pair_factors<PREC>(p, b.s[q], r2i, A, Bc, psi);
+      const double w = (uxi - ux[q]) * b.dx[q] + (uyi - uy[q]) * b.dy[q] +
+                       (uzi - uz[q]) * b.dz[q];
+      gc = fma(Bc, w, gc);
+      lai = fma(0.5 * A, w, lai);
+    }
+  });
+  if (K > 1) {
+    gc = group_sum<K>(gc);
+    lai = group_sum<K>(lai);
+  }
+  if (!ln.live || ln.s != 0) return;
+  const int i = ln.i;
+  const double ei = e[i];
+  lam[i] = -0.5 * ei * ei * ei * (p.c * gc);
+  la[i] = lai;
+  lb[i] = ei * gc;
+}
+
+// Pass 3: dL/dx_i = sum_j [h (u_i - u_j) + 2 h' w d + 2 (lam_i + lam_j) psi' d],
+// h = A + B (e_i + e_j), h' = -(n/2 + 1) A / s - (m/2 + 1) B (e_i + e_j) / s,
+// psi' = -(m/2) psi / s.
+template <int PREC, int K>
+__global__ __launch_bounds__(kBlock) void k_sc_vjp_x(FK a, SCK p, const double* __restrict__ u,
+                                                      const double* __restrict__ e,
+                                                      const double* __restrict__ lam,
+                                                      double* __restrict__ gx) {
+  const Lane<K> ln(a);
+  const int n = a.n;
+  const int io = ln.live ? ln.i : n - 1;
+  double xi, yi, zi;
+  home_pos(a, io, xi, yi, zi);
+  const double uxi = u[io], uyi = u[n + io], uzi = u[2 * n + io];
+  const double ei = e[io], li = lam[io];
+  const double hn = 0.5 * p.n + 1.0, hm = 0.5 * p.m + 1.0, mh = 0.5 * p.m;
+  double gxa = 0.0, gya = 0.0, gza = 0.0;
+  for_each_batch<K, PREC == MD_MIXED>(a, ln, xi, yi, zi, [&](const Batch& b) {
+    double ux[kUnroll], uy[kUnroll], uz[kUnroll], ej[kUnroll], lj[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      ux[q] = u[b.j[q]];
+      uy[q] = u[n + b.j[q]];
+      uz[q] = u[2 * n + b.j[q]];
+      ej[q] = e[b.j[q]];
+      lj[q] = lam[b.j[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      if (!(b.ok[q] && b.s[q] < p.rc2)) continue;
+      double r2i, A, Bc, psi;
+      sc_pair_factors<PREC>(p, b.s[q], r2i, A, Bc, psi);
+      const double Be = p.c * Bc * (ei + ej[q]);
+      const double h = A + Be;
+      const double hp = -(hn * A + hm * Be) * r2i;
+      const double lp = -2.0 * mh * (li + lj[q]) * psi * r2i;   // 2 (lam_i + lam_j) psi'
+      const double dux = uxi - ux[q], duy = uyi - uy[q], duz = uzi - uz[q];
+      const double c2 = 2.0 * hp * (dux * b.dx[q] + duy * b.dy[q] + duz * b.dz[q]) + lp;
+      gxa += h * dux + c2 * b.dx[q];
+      gya += h * duy + c2 * b.dy[q];
+      gza += h * duz + c2 * b.dz[q];
+    }
+  });
+  if (K > 1) {
+    gxa = group_sum<K>(gxa);
+    gya = group_sum<K>(gya);
+    gza = group_sum<K>(gza);
+  }
+  if (!ln.live || ln.s != 0) return;
+  const int i = ln.i;
+  gx[i] = gxa;
+  gx[n + i] = gya;
+  gx[2 * n + i] = gza;
+}
+
 // ------------------------------------------------------------ launching --
 
 FK make_fk(const ForceArgs& a) {
@@ -788,6 +915,25 @@ hipError_t launch_lj_vjp(const ForceArgs& a, const LJK& p, int prec, int lanes,
     if (prec == MD_FP64)
       return launch_timed(k_lj_vjp<MD_FP64, K>, g, s, a.t0, a.t1, k, p, u, gx, pe, ps);
     return launch_timed(k_lj_vjp<MD_MIXED, K>, g, s, a.t0, a.t1, k, p, u, gx, pe, ps);
+  });
+}
+
+hipError_t launch_sc_vjp(const ForceArgs& a, const SCK& p, int prec, int lanes, const double* u,
+                         double* e, double* lam, double* la, double* lb, double* gx,
+                         hipStream_t s) {
+  const FK k = make_fk(a);
+  return with_lanes(lanes, [&](auto kc) -> hipError_t {
+    constexpr int K = decltype(kc)::value;
+    const unsigned g = grid_for(a.n, K);
+    auto run = [&](auto prec_c) -> hipError_t {
+      constexpr int P = decltype(prec_c)::value;
+      k_sc_density<P, false, K><<<g, kBlock, 0, s>>>(k, p, e);
+      k_sc_vjp_rho<P, K><<<g, kBlock, 0, s>>>(k, p, u, e, lam, la, lb);
+      return launch_timed(k_sc_vjp_x<P, K>, g, s, a.t0, a.t1, k, p, u,
+                          static_cast<const double*>(e), static_cast<const double*>(lam), gx);
+    };
+    if (prec == MD_FP64) return run(std::integral_constant<int, MD_FP64>());
+    return run(std::integral_constant<int, MD_MIXED>());
   });
 }
 

@@ -97,6 +97,16 @@ __global__ void k_vjp_params(const double* sums, double eps, double* gparam) {
   gparam[1] = sums[1];
 }
 
+// Sutton-Chen: L = LA + c LB with LA ~ a^n and c LB ~ a^(m/2) (A ~ a^n,
+// B ~ a^m, e ~ a^(-m/2)); sums = (LA, LB).
+__global__ void k_sc_vjp_params(const double* sums, double eps, double a, double c, double n,
+                                double m, double* gparam) {
+  if (threadIdx.x != 0) return;
+  gparam[0] = (sums[0] + c * sums[1]) / eps;
+  gparam[1] = (n * sums[0] + 0.5 * m * c * sums[1]) / a;
+  gparam[2] = sums[1];
+}
+
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -126,6 +136,12 @@ hipError_t launch_sum(const SumArgs& a, hipStream_t s) {
 
 hipError_t launch_thermo_row(const ThermoArgs& a, hipStream_t s) {
   k_thermo_row<<<1, 64, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sc_vjp_params(const double* sums, const SCK& p, double a, double* gparam,
+                                hipStream_t s) {
+  k_sc_vjp_params<<<1, 64, 0, s>>>(sums, p.eps, a, p.c, (double)p.n, (double)p.m, gparam);
   return hipGetLastError();
 }
 

@@ -160,7 +160,8 @@ struct LJK {
 // Sutton-Chen constants.
 struct SCK {
   double rc2, a2, eps, neps, mepsc_half, epsc;
-  float a2f, nepsf, mepsc_halff;
+  double meps_half, c;          // (m/2) eps (the embedding pair factor per unit c), c
+  float a2f, nepsf, mepsc_halff, meps_halff, cf;
   int n, m;
 };
 
@@ -335,5 +336,13 @@ struct ThermoArgs {
 hipError_t launch_thermo_row(const ThermoArgs& a, hipStream_t s);
 // gparam[0] = sums[0] / eps, gparam[1] = sums[1].
 hipError_t launch_vjp_params(const double* sums, double eps, double* gparam, hipStream_t s);
+// Sutton-Chen adjoint: density pass into e, then the pass for lam (dL/drho),
+// la and lb (per-atom parameter sums), then the position pass into gx.
+hipError_t launch_sc_vjp(const ForceArgs& a, const SCK& p, int prec, int lanes, const double* u,
+                         double* e, double* lam, double* la, double* lb, double* gx,
+                         hipStream_t s);
+// gparam = (dL/deps, dL/da, dL/dc) from sums = (LA, LB per unit c).
+hipError_t launch_sc_vjp_params(const double* sums, const SCK& p, double a, double* gparam,
+                                hipStream_t s);
 
 }  // namespace md

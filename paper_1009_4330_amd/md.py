@@ -316,7 +316,8 @@ def md_force_vjp(pot: md_potential, x: torch.Tensor, box: md_box, nl: NList, pre
     _check(lib().md_force_vjp(ctypes.byref(pot), _ptr(x, torch.float64, 3 * n), n,
                               ctypes.byref(box), ctypes.byref(nl.c), prec,
                               _ptr(u, torch.float64, 3 * n), _ptr(gx, torch.float64, 3 * n),
-                              _ptr(gparam, torch.float64, 2), _ptr(ws), ws.numel(),
+                              _ptr(gparam, torch.float64, 3 if pot.kind == MD_POT_SC else 2),
+                              _ptr(ws), ws.numel(),
                               _stream(stream)), "md_force_vjp")
 
 

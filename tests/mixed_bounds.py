@@ -105,3 +105,31 @@ def buck_magnitudes(x, box, onl, rc, types, A, rho, C, q, qqr2e):
     return {"f": _per_atom(n, i, mag_g * r),
             "e": 0.5 * np.sum(ex + c_ / s ** 3 + qq / r),
             "w": np.array([0.5 * np.sum(np.abs(d[a] * d[b]) * mag_g) for a, b in VPAIRS])}
+
+
+def sc_vjp_magnitudes(x, box, onl, rc, eps, a, c, nexp, mexp, rho, u):
+    """Magnitude sums for the Sutton-Chen adjoint: 'gx' [n] per atom, and the
+    parameter gradients 'geps', 'ga', 'gc'.  The error of dL/drho_i (lam_i)
+    from its own sum enters the position pass through 2 (lam_i + lam_j) psi',
+    so the lam magnitudes are carried into 'gx'."""
+    n = x.shape[1]
+    i, j, d, s = pair_geometry(x, box, onl, rc)
+    t = a * a / s
+    phi, psi = t ** (0.5 * nexp), t ** (0.5 * mexp)
+    e = np.where(rho > 0, 1.0 / np.sqrt(np.where(rho > 0, rho, 1.0)), 0.0)
+    A = nexp * eps * phi / s
+    Bc = 0.5 * mexp * eps * psi / s                    # |B| / c
+    du = u[:, i] - u[:, j]
+    dun = np.sqrt(np.sum(du * du, axis=0))
+    r = np.sqrt(s)
+    wmag = dun * r                                     # bound on |w|
+    lam = 0.5 * e ** 3 * c * _per_atom(n, i, Bc * wmag)
+    eij = e[i] + e[j]
+    h = A + c * Bc * eij
+    hp = ((0.5 * nexp + 1.0) * A + (0.5 * mexp + 1.0) * c * Bc * eij) / s
+    psip = 0.5 * mexp * psi / s
+    gx = _per_atom(n, i, h * dun + 2.0 * hp * wmag * r + 2.0 * (lam[i] + lam[j]) * psip * r)
+    la = 0.5 * np.sum(A * wmag)
+    lb = np.sum(e[i] * Bc * wmag)
+    return {"gx": gx, "geps": (la + c * lb) / eps, "ga": (nexp * la + 0.5 * mexp * c * lb) / a,
+            "gc": lb}

@@ -99,9 +99,17 @@ def test_host_validation_precedes_any_launch(mdlib):
     bad = mdlib.lj_potential(-1.0)
     assert lib.md_compute_forces(R(bad), fake, 4000, R(box), R(nl), 0, 1, 0, fake, None, fake,
                                  1 << 30, None) == 1
-    sc = mdlib.sc_potential(7.22, 0.012, 3.61, 39.4, 9, 6)
-    assert lib.md_force_vjp(R(sc), fake, 4000, R(box), R(nl), 0, fake, fake, None, fake,
+    buck = mdlib.md_potential(kind=mdlib.MD_POT_BUCK, rc=2.5, qqr2e=14.4, type=0x1000)
+    assert lib.md_force_vjp(R(buck), fake, 4000, R(box), R(nl), 0, fake, fake, None, fake,
                             1 << 30, None) == 5
+    # Buckingham tables: species array required, tables symmetric
+    nospecies = mdlib.md_potential(kind=mdlib.MD_POT_BUCK, rc=2.5, qqr2e=14.4)
+    assert lib.md_compute_forces(R(nospecies), fake, 4000, R(box), R(nl), 0, 1, 0, fake, None,
+                                 fake, 1 << 30, None) == 1
+    asym = mdlib.md_potential(kind=mdlib.MD_POT_BUCK, rc=2.5, qqr2e=14.4, type=0x1000)
+    asym.buck_A[1], asym.buck_rho[1] = 100.0, 0.3
+    assert lib.md_compute_forces(R(asym), fake, 4000, R(box), R(nl), 0, 1, 0, fake, None,
+                                 fake, 1 << 30, None) == 1
     nl0 = mdlib.md_nlist(capacity=0, layout=1, rl=2.8, neigh=0x1000, numneigh=0x1000,
                          x_ref=0x1000, status=0x1000)
     assert lib.md_build_neighbors(fake, 4000, R(box), R(cells), 2.5, 0.3, R(nl0), None) == 1

@@ -1,0 +1,137 @@
+"""Sutton-Chen force adjoint on the GPU (md_force_vjp, three passes) against
+the oracle's adjoint on the same seeded inputs, for every lanes-per-atom
+layout and both precisions; SCForces through torch autograd; and a
+force-matching fit of (eps, a, c) to forces the oracle computed."""
+import numpy as np
+import pytest
+import torch
+
+import mixed_bounds as MB
+from gpu_helpers import SC_KW, dev, gpu_list, rel, sc_solid
+from paper_1009_4330_amd import autograd as AG
+from paper_1009_4330_amd import inputs as I
+from paper_1009_4330_amd import md
+
+pytestmark = pytest.mark.gpu
+
+LAYOUTS = [(md.MD_LAYOUT_TPA, md.MD_KERNEL_TPA), (4, 4), (16, 16),
+           (md.MD_LAYOUT_WPA, md.MD_KERNEL_WPA)]
+IDS = ["tpa", "k4", "k16", "wpa"]
+RC, SKIN = 7.22, 1.0
+EPS, A, C = SC_KW["eps"], SC_KW["a"], SC_KW["c"]
+
+
+def oracle_vjp(orc, x_np, box, u_np, eps=EPS, a=A, c=C):
+    onl, oc = orc.build_nlist(x_np, box, RC + SKIN)
+    gx, gp = orc.sc_vjp(oc.x, box, onl, RC, eps, a, c, 9, 6, u_np)
+    rho = orc.sc_forces(oc.x, box, onl, RC, eps=eps, a=a, c=c, nexp=9, mexp=6).rho
+    mag = MB.sc_vjp_magnitudes(oc.x, box, onl, RC, eps, a, c, 9, 6, rho, u_np)
+    return gx, gp, mag
+
+
+@pytest.mark.parametrize("layout,kernel", LAYOUTS, ids=IDS)
+@pytest.mark.parametrize("prec", [md.MD_FP64, md.MD_MIXED], ids=["fp64", "mixed"])
+def test_sc_vjp(orc, layout, kernel, prec):
+    x_np, box = sc_solid(6, 91)
+    n = x_np.shape[1]
+    u_np = I.random_unit_vectors(n, 92)
+    x, cells, nl, ws, mbox = gpu_list(x_np, box, RC, SKIN, layout, 260)
+    pot = md.sc_potential(RC, EPS, A, C, 9, 6)
+    gx = torch.zeros(3, n, dtype=torch.float64, device="cuda")
+    gp = torch.zeros(3, dtype=torch.float64, device="cuda")
+    md.md_force_vjp(pot, x, mbox, nl, prec, dev(u_np), gx, gp, ws)
+    rgx, rgp, mag = oracle_vjp(orc, x_np, box, u_np)
+    ggx, ggp = gx.cpu().numpy(), gp.cpu().numpy()
+    u = MB.U64 if prec == md.MD_FP64 else MB.U32
+    print(f"SC vjp ({'fp64' if prec == md.MD_FP64 else 'mixed'}): gx rel {rel(ggx, rgx):.3e}, "
+          f"gparam {ggp} vs {rgp}")
+    if prec == md.MD_FP64:
+        assert rel(ggx, rgx) < 1e-12
+    MB.assert_vector(ggx, rgx, mag["gx"], u=u, what="gx")
+    for k, name in enumerate(("geps", "ga", "gc")):
+        MB.assert_total(ggp[k], rgp[k], mag[name], u=u, what=name)
+
+
+def test_sc_vjp_without_parameter_output(orc):
+    """gparam = NULL: positions only, same values."""
+    x_np, box = sc_solid(5, 93)
+    n = x_np.shape[1]
+    u_np = I.random_unit_vectors(n, 94)
+    x, cells, nl, ws, mbox = gpu_list(x_np, box, RC, SKIN, 4, 260)
+    pot = md.sc_potential(RC, EPS, A, C, 9, 6)
+    gx = torch.zeros(3, n, dtype=torch.float64, device="cuda")
+    md.md_force_vjp(pot, x, mbox, nl, md.MD_FP64, dev(u_np), gx, None, ws)
+    rgx, _, _ = oracle_vjp(orc, x_np, box, u_np)
+    assert rel(gx.cpu().numpy(), rgx) < 1e-12
+
+
+def test_sc_autograd_matches_oracle(orc):
+    x_np, box = sc_solid(6, 95)
+    n = x_np.shape[1]
+    u_np = I.random_unit_vectors(n, 96)
+    x, cells, nl, ws, mbox = gpu_list(x_np, box, RC, SKIN, 4, 260)
+    xg = x.clone().requires_grad_(True)
+    t = lambda v: torch.tensor(v, dtype=torch.float64, device="cuda", requires_grad=True)
+    eps, a, c = t(EPS), t(A), t(C)
+    f = AG.sc_forces(xg, eps, a, c, mbox, nl, RC, 9, 6, md.MD_FP64, ws)
+    (f * dev(u_np)).sum().backward()
+    rgx, rgp, mag = oracle_vjp(orc, x_np, box, u_np)
+    assert rel(xg.grad.cpu().numpy(), rgx) < 1e-12
+    for k, (p, name) in enumerate(((eps, "geps"), (a, "ga"), (c, "gc"))):
+        MB.assert_total(p.grad.item(), rgp[k], mag[name], u=MB.U64, what=name)
+
+
+@pytest.mark.parametrize("prec", [md.MD_FP64, md.MD_MIXED], ids=["fp64", "mixed"])
+def test_sc_force_matching_fit(orc, prec):
+    """Mean squared force error against the oracle's forces at (eps, a, c).
+    The forces depend on the parameters only through eps a^n and eps c a^(m/2),
+    so a is held at its value and (eps, c) are fitted by L-BFGS from a start
+    10 % and 5 % off, in relative coordinates (parameter = start x (1 + z))."""
+    x_np, box = sc_solid(6, 97, amp=0.2)
+    x, cells, nl, ws, mbox = gpu_list(x_np, box, RC, SKIN, 4, 260)
+    onl, oc = orc.build_nlist(x_np, box, RC + SKIN)
+    target = dev(orc.sc_forces(oc.x, box, onl, RC, **SC_KW).f)
+    start = torch.tensor([EPS * 0.9, C * 0.95], dtype=torch.float64, device="cuda")
+    a = torch.tensor(A, dtype=torch.float64, device="cuda")
+    z = torch.zeros(2, dtype=torch.float64, device="cuda", requires_grad=True)
+    opt = torch.optim.LBFGS([z], lr=1.0, max_iter=80, tolerance_grad=1e-16,
+                            tolerance_change=1e-20, history_size=10,
+                            line_search_fn="strong_wolfe")
+    scale = float(target.abs().mean()) ** 2
+
+    def closure():
+        opt.zero_grad()
+        p = start * (1.0 + z)
+        f = AG.sc_forces(x, p[0], a, p[1], mbox, nl, RC, 9, 6, prec, ws)
+        loss = ((f - target) ** 2).mean() / scale
+        loss.backward()
+        return loss
+
+    for _ in range(4):
+        loss = opt.step(closure)
+    got = (start * (1.0 + z)).detach().cpu().numpy()
+    err = np.abs(got / np.array([EPS, C]) - 1.0)
+    print(f"SC fit ({'fp64' if prec == md.MD_FP64 else 'mixed'}): rel errors {err}, "
+          f"loss {loss.item():.3e}")
+    assert err.max() < (1e-8 if prec == md.MD_FP64 else 1e-4)
+
+
+def test_sc_parameter_degeneracy_is_in_the_gradient(orc):
+    """Along the direction that keeps eps a^n and eps c a^(m/2) fixed the
+    forces do not change, so dL/dtheta is orthogonal to it for any cotangent:
+    (eps, a, c) . (-n t, t, (n - m/2) t) scaled per parameter."""
+    x_np, box = sc_solid(5, 98)
+    n_at = x_np.shape[1]
+    u_np = I.random_unit_vectors(n_at, 99)
+    x, cells, nl, ws, mbox = gpu_list(x_np, box, RC, SKIN, 4, 260)
+    gp = torch.zeros(3, dtype=torch.float64, device="cuda")
+    gx = torch.zeros(3, n_at, dtype=torch.float64, device="cuda")
+    md.md_force_vjp(md.sc_potential(RC, EPS, A, C, 9, 6), x, mbox, nl, md.MD_FP64, dev(u_np),
+                    gx, gp, ws)
+    g = gp.cpu().numpy()
+    # d(log eps) = -n d(log a), d(log c) = (n - m/2) d(log a)
+    tangent = np.array([-9.0 * EPS, A, (9.0 - 3.0) * C])
+    _, _, mag = oracle_vjp(orc, x_np, box, u_np)
+    bound = MB.K * MB.U64 * (abs(tangent[0]) * mag["geps"] + abs(tangent[1]) * mag["ga"]
+                             + abs(tangent[2]) * mag["gc"])
+    assert abs(float(g @ tangent)) <= bound
