@@ -24,6 +24,10 @@
  *   - velocity-Verlet NVE integration ("NVE integrator", section "Design
  *     objectives") with a rebuild of the list whenever an atom moved more than
  *     skin/2 since the last build;
+ *   - NVT integration (the NVT integrator named in "Design objectives") by a
+ *     Nose-Hoover chain thermostat in the standard time-reversible splitting
+ *     of Martyna, Tuckerman and Klein: a thermostat half step, the
+ *     velocity-Verlet step, a thermostat half step;
  *   - the vector-Jacobian products of the LJ forces (with respect to
  *     positions and (eps, sigma)) and of the Sutton-Chen forces (positions and
  *     (eps, a, c)).
@@ -676,6 +680,162 @@ int orc_md_run(const orc_params* p, int64_t n, double* x, double* v, const doubl
     for (int64_t i = 0; i < 3 * n; ++i) v[i] = v[i] + dtfm * f[i];
     if (thermo && s % thermo_every == 0)
       thermo_row(p, n, v, L, (double)s, pe, vir, nreb, maxc, thermo + 8 * row++);
+  }
+  if (f_out) memcpy(f_out, f, sizeof(double) * 3 * (size_t)n);
+done:
+  free(w.atom_cell);
+  free(w.perm);
+  free(w.numneigh);
+  free(w.neigh);
+  free(w.xref);
+  free(w.cell_start);
+  free(f);
+  return st;
+}
+
+/* ------------------------------------------------- Nose-Hoover chain NVT -- */
+
+/* One thermostat half step (a time dt/2) of a Nose-Hoover chain of length M
+   acting on kinetic energy ke2 = sum m v^2 (energy units), in the Trotter
+   splitting of Martyna, Tuckerman and Klein: the chain velocities are updated
+   from the end of the chain down to the first thermostat, the particle
+   velocities are scaled by exp(-dt/2 veta_1), the chain positions advance,
+   and the chain velocities are updated back up.  The forces on the
+   thermostats are G_1 = (ke2 - Nf kT) / Q_1 and
+   G_j = (Q_{j-1} veta_{j-1}^2 - kT) / Q_j; each velocity update is
+   veta_j <- veta_j exp(-dt/8 veta_{j+1})^2 + dt/4 G_j exp(-dt/8 veta_{j+1}).
+   Returns the velocity scale factor; *ke2 is updated to the scaled value. */
+static double nhc_half(int M, const double* Q, double* eta, double* veta, double kT,
+                       double nf, double dt, double* ke2) {
+  const double dt2 = 0.5 * dt, dt4 = 0.25 * dt, dt8 = 0.125 * dt;
+  double G;
+  G = M > 1 ? (Q[M - 2] * veta[M - 2] * veta[M - 2] - kT) / Q[M - 1] : (*ke2 - nf * kT) / Q[0];
+  veta[M - 1] = veta[M - 1] + dt4 * G;
+  for (int j = M - 2; j >= 0; --j) {
+    double aa = exp(-dt8 * veta[j + 1]);
+    G = j == 0 ? (*ke2 - nf * kT) / Q[0] : (Q[j - 1] * veta[j - 1] * veta[j - 1] - kT) / Q[j];
+    veta[j] = veta[j] * aa * aa + dt4 * G * aa;
+  }
+  double scale = exp(-dt2 * veta[0]);
+  *ke2 = *ke2 * scale * scale;
+  for (int j = 0; j < M; ++j) eta[j] = eta[j] + dt2 * veta[j];
+  for (int j = 0; j < M - 1; ++j) {
+    double aa = exp(-dt8 * veta[j + 1]);
+    G = j == 0 ? (*ke2 - nf * kT) / Q[0] : (Q[j - 1] * veta[j - 1] * veta[j - 1] - kT) / Q[j];
+    veta[j] = veta[j] * aa * aa + dt4 * G * aa;
+  }
+  G = M > 1 ? (Q[M - 2] * veta[M - 2] * veta[M - 2] - kT) / Q[M - 1] : (*ke2 - nf * kT) / Q[0];
+  veta[M - 1] = veta[M - 1] + dt4 * G;
+  return scale;
+}
+
+/* Energy of the chain: sum_j Q_j veta_j^2 / 2 + Nf kT eta_1 + kT sum_{j>1} eta_j;
+   with it, pe + ke + this is conserved by the exact NVT flow. */
+static double nhc_energy(int M, const double* Q, const double* eta, const double* veta,
+                         double kT, double nf) {
+  double e = 0.0;
+  for (int j = 0; j < M; ++j) e += 0.5 * Q[j] * veta[j] * veta[j];
+  e += nf * kT * eta[0];
+  for (int j = 1; j < M; ++j) e += kT * eta[j];
+  return e;
+}
+
+/* NVT run: per step a thermostat half step, the velocity-Verlet step (with the
+   half-skin rebuild rule of orc_md_run), a thermostat half step.  Thermostat
+   masses Q_1 = Nf kT t_damp^2, Q_j = kT t_damp^2 (j > 1), Nf = 3n - 3,
+   kT = boltz t_target.  chain [in/out] holds eta[0..M) then veta[0..M).
+   Thermo rows have nine columns: the eight of orc_md_run and
+   pe + ke + the chain energy.  The kinetic energy entering the first half
+   step of a step is the scaled value the previous half step left (the
+   scaling multiplies it by scale^2), not a recount. */
+int orc_md_run_nvt(const orc_params* p, int64_t n, double* x, double* v, const double* L,
+                   int nsteps, int thermo_every, int cap, double t_target, double t_damp,
+                   int M, double* chain, double* thermo, int* rebuilt, double* f_out) {
+  if (n <= 1 || !p || !x || !v || !L || nsteps < 0 || thermo_every < 1 || cap < 1 || M < 1 ||
+      M > 8 || !chain || !(t_target > 0.0) || !(t_damp > 0.0))
+    return ORC_EINVAL;
+  orc_work w;
+  memset(&w, 0, sizeof(w));
+  w.cap = cap;
+  w.atom_cell = (int*)malloc(sizeof(int) * (size_t)n);
+  w.perm = (int*)malloc(sizeof(int) * (size_t)n);
+  w.numneigh = (int*)malloc(sizeof(int) * (size_t)n);
+  w.neigh = (int*)malloc(sizeof(int) * (size_t)n * (size_t)cap);
+  w.xref = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+  double* f = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+  int st = ORC_OK;
+  if (!w.atom_cell || !w.perm || !w.numneigh || !w.neigh || !w.xref || !f) {
+    st = ORC_EINVAL;
+    goto done;
+  }
+  const double dtfm = (0.5 * p->dt * p->ftm2v) / p->mass;
+  const double trig = 0.5 * p->skin;
+  const double trig2 = trig * trig;
+  const double kT = p->boltz * t_target;
+  const double nf = 3.0 * (double)n - 3.0;
+  double Q[8];
+  Q[0] = nf * kT * t_damp * t_damp;
+  for (int j = 1; j < M; ++j) Q[j] = kT * t_damp * t_damp;
+  double* eta = chain;
+  double* veta = chain + M;
+  double pe = 0.0, vir[6];
+  int nreb = 0, row = 0, maxc = 0;
+  st = rebuild(p, n, x, L, &w);
+  if (st) goto done;
+  ++nreb;
+  maxc = w.maxcount;
+  if (rebuilt) rebuilt[0] = 1;
+  st = forces(p, n, x, L, &w, f, &pe, vir);
+  if (st) goto done;
+  double ke2 = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double a = v[i], b = v[n + i], c = v[2 * n + i];
+    ke2 += (a * a + b * b) + c * c;
+  }
+  ke2 = p->mass * p->mvv2e * ke2;
+  if (thermo) {
+    thermo_row(p, n, v, L, 0.0, pe, vir, nreb, maxc, thermo + 9 * row);
+    thermo[9 * row + 8] = thermo[9 * row + 3] + nhc_energy(M, Q, eta, veta, kT, nf);
+    ++row;
+  }
+  for (int s = 1; s <= nsteps; ++s) {
+    double scale = nhc_half(M, Q, eta, veta, kT, nf, p->dt, &ke2);
+    for (int64_t i = 0; i < 3 * n; ++i) v[i] = v[i] * scale;
+    for (int d = 0; d < 3; ++d)
+      for (int64_t i = 0; i < n; ++i) {
+        v[d * n + i] = v[d * n + i] + dtfm * f[d * n + i];
+        x[d * n + i] = x[d * n + i] + p->dt * v[d * n + i];
+      }
+    double dmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      double a = x[i] - w.xref[i], b = x[n + i] - w.xref[n + i], c = x[2 * n + i] - w.xref[2 * n + i];
+      double d2 = (a * a + b * b) + c * c;
+      if (d2 > dmax) dmax = d2;
+    }
+    int reb = dmax > trig2;
+    if (rebuilt) rebuilt[s] = reb;
+    if (reb) {
+      st = rebuild(p, n, x, L, &w);
+      if (st) goto done;
+      ++nreb;
+      if (w.maxcount > maxc) maxc = w.maxcount;
+    }
+    st = forces(p, n, x, L, &w, f, &pe, vir);
+    if (st) goto done;
+    for (int64_t i = 0; i < 3 * n; ++i) v[i] = v[i] + dtfm * f[i];
+    ke2 = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      double a = v[i], b = v[n + i], c = v[2 * n + i];
+      ke2 += (a * a + b * b) + c * c;
+    }
+    ke2 = p->mass * p->mvv2e * ke2;
+    scale = nhc_half(M, Q, eta, veta, kT, nf, p->dt, &ke2);
+    for (int64_t i = 0; i < 3 * n; ++i) v[i] = v[i] * scale;
+    if (thermo && s % thermo_every == 0) {
+      thermo_row(p, n, v, L, (double)s, pe, vir, nreb, maxc, thermo + 9 * row);
+      thermo[9 * row + 8] = thermo[9 * row + 3] + nhc_energy(M, Q, eta, veta, kT, nf);
+      ++row;
+    }
   }
   if (f_out) memcpy(f_out, f, sizeof(double) * 3 * (size_t)n);
 done:

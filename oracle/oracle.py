@@ -117,9 +117,12 @@ def _declare(L):
                              ctypes.c_int, _dp, _dp, _dp]
     L.orc_md_run.argtypes = [ctypes.POINTER(Params), _i64, _dp, _dp, _dp, ctypes.c_int,
                              ctypes.c_int, ctypes.c_int, _dp, _ip, _dp]
+    L.orc_md_run_nvt.argtypes = [ctypes.POINTER(Params), _i64, _dp, _dp, _dp, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_int, _dp, _dp, _ip, _dp]
     for name in ("orc_cell_dims", "orc_bin", "orc_build_nlist", "orc_lj_forces",
                  "orc_sc_forces", "orc_buck_forces", "orc_lj_vjp", "orc_sc_vjp",
-                 "orc_md_run"):
+                 "orc_md_run", "orc_md_run_nvt"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -376,3 +379,26 @@ def md_run(params: Params, x, v, box, nsteps: int, thermo_every: int = 1,
     if st:
         raise OracleError(st, "md_run")
     return RunResult(x, v, f, thermo, rebuilt)
+
+
+def md_run_nvt(params: Params, x, v, box, nsteps: int, t_target: float, t_damp: float,
+               chain_len: int = 3, chain=None, thermo_every: int = 1, cap: int = 0):
+    """Nose-Hoover chain NVT run; x, v, chain are copied.  Returns
+    (RunResult with nine-column thermo rows, final chain [eta..., veta...])."""
+    x = _f64(x).copy()
+    v = _f64(v).copy()
+    n = x.shape[1]
+    ch = np.zeros(2 * chain_len) if chain is None else np.array(chain, dtype=np.float64)
+    if cap <= 0:
+        nl, _ = build_nlist(x, box, params.rc + params.skin)
+        cap = int(nl.max_count * 1.5) + 32
+    rows = 1 + nsteps // thermo_every
+    thermo = np.zeros((rows, 9))
+    rebuilt = np.zeros(nsteps + 1, np.int32)
+    f = np.zeros((3, n))
+    st = lib().orc_md_run_nvt(ctypes.byref(params), n, _d(x), _d(v), _d(_f64(box)), nsteps,
+                              thermo_every, cap, t_target, t_damp, chain_len, _d(ch),
+                              _d(thermo), _i(rebuilt), _d(f))
+    if st:
+        raise OracleError(st, "md_run_nvt")
+    return RunResult(x, v, f, thermo, rebuilt), ch

@@ -9,6 +9,7 @@ import pytest
 
 import test_oracle as T
 import test_oracle_buck as TB
+import test_oracle_nvt as TN
 import test_oracle_sc_vjp as TS
 from paper_1009_4330_amd import inputs as I
 
@@ -57,6 +58,13 @@ MUTANTS = {
                            "lam[i] = -0.5 * e[i] * e[i] * (c * gci);", ["fd_scvjp"]),
     "scvjp_da_factor": ("gparam[1] = (nexp * ta + 0.5 * mexp * c * tb) / a;",
                         "gparam[1] = (nexp * ta + mexp * c * tb) / a;", ["par_scvjp_a"]),
+    "nvt_scale_quarter_step": ("double scale = exp(-dt2 * veta[0]);",
+                               "double scale = exp(-dt4 * veta[0]);", ["nvt_conserved"]),
+    "nvt_energy_dof": ("e += nf * kT * eta[0];", "e += kT * eta[0];", ["nvt_conserved"]),
+    "nvt_ke_scaled_once": ("*ke2 = *ke2 * scale * scale;", "*ke2 = *ke2 * scale;",
+                           ["nvt_conserved", "nvt_reversible"]),
+    "nvt_eta_full_step": ("eta[j] = eta[j] + dt2 * veta[j];", "eta[j] = eta[j] + dt * veta[j];",
+                          ["nvt_conserved"]),
 }
 
 
@@ -96,6 +104,8 @@ PINS = {
     "fd_scvjp": lambda o: TS.test_sc_vjp_matches_central_differences_in_x(o, _scsys(o)),
     "sym_scvjp": lambda o: TS.test_sc_vjp_symmetry_translation_and_linearity(o, _scsys(o)),
     "par_scvjp_a": lambda o: TS.test_sc_vjp_parameter_gradients(o, _scsys(o), 1, "a"),
+    "nvt_conserved": lambda o: TN.test_nvt_conserved_energy_is_second_order(o, 3),
+    "nvt_reversible": lambda o: TN.test_nvt_time_reversible(o),
 }
 
 
