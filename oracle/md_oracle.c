@@ -768,7 +768,7 @@ int orc_md_run_nvt(const orc_params* p, int64_t n, double* x, double* v, const d
     st = ORC_EINVAL;
     goto done;
   }
-  const double dtfm = (0.5 * p->dt * p->ftm2v) / p->mass;
+  const double kick = (0.5 * p->dt * p->ftm2v) / p->mass;   /* dt/2 F/m factor */
   const double trig = 0.5 * p->skin;
   const double trig2 = trig * trig;
   const double kT = p->boltz * t_target;
@@ -803,7 +803,7 @@ int orc_md_run_nvt(const orc_params* p, int64_t n, double* x, double* v, const d
     for (int64_t i = 0; i < 3 * n; ++i) v[i] = v[i] * scale;
     for (int d = 0; d < 3; ++d)
       for (int64_t i = 0; i < n; ++i) {
-        v[d * n + i] = v[d * n + i] + dtfm * f[d * n + i];
+        v[d * n + i] = v[d * n + i] + kick * f[d * n + i];
         x[d * n + i] = x[d * n + i] + p->dt * v[d * n + i];
       }
     double dmax = 0.0;
@@ -812,9 +812,9 @@ int orc_md_run_nvt(const orc_params* p, int64_t n, double* x, double* v, const d
       double d2 = (a * a + b * b) + c * c;
       if (d2 > dmax) dmax = d2;
     }
-    int reb = dmax > trig2;
-    if (rebuilt) rebuilt[s] = reb;
-    if (reb) {
+    const int rebuild_now = dmax > trig2;
+    if (rebuilt) rebuilt[s] = rebuild_now;
+    if (rebuild_now) {
       st = rebuild(p, n, x, L, &w);
       if (st) goto done;
       ++nreb;
@@ -822,7 +822,7 @@ int orc_md_run_nvt(const orc_params* p, int64_t n, double* x, double* v, const d
     }
     st = forces(p, n, x, L, &w, f, &pe, vir);
     if (st) goto done;
-    for (int64_t i = 0; i < 3 * n; ++i) v[i] = v[i] + dtfm * f[i];
+    for (int64_t i = 0; i < 3 * n; ++i) v[i] = v[i] + kick * f[i];
     ke2 = 0.0;
     for (int64_t i = 0; i < n; ++i) {
       double a = v[i], b = v[n + i], c = v[2 * n + i];
