@@ -68,12 +68,12 @@ def measured_traffic(kernel_name: str, launches_bytes: float):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def run_md(w, x, v, prec, kernel, steps, warmup):
+def run_md(w, x, v, prec, kernel, steps, warmup, nvt=None):
     import torch
     from paper_1009_4330_amd import md
     from paper_1009_4330_amd.system import MDSystem
 
-    sysm = MDSystem(w, x, v, prec, kernel)
+    sysm = MDSystem(w, x, v, prec, kernel, nvt=nvt)
     sysm.setup(thermo=False)
     if warmup:
         sysm.run(warmup, THERMO_EVERY)
@@ -363,6 +363,15 @@ def suite(steps: int):
               "lanes_per_atom": r["kernel"], "atom_steps_per_s": steps * w.natoms / r["elapsed"],
               "force_us": 1e3 * r["force_ms_avg"], "rebuilds": r["rebuilds"],
               "mean_neighbors": r["mean_neigh"], "steps": steps})
+    w = I.LJ_256K
+    x, v, _ = I.initial_state(w)
+    for prec in ("mixed", "fp64"):
+        r = run_md(w, x, v, prec, "auto", steps, 10, nvt=(w.temp, 100 * w.dt, 3))
+        emit({"item": "nvt", "workload": w.name, "precision": prec, "kernel": "auto",
+              "thermostat": "Nose-Hoover chain, 3 links, period 100 dt",
+              "lanes_per_atom": r["kernel"], "atom_steps_per_s": steps * w.natoms / r["elapsed"],
+              "ms_per_step": 1e3 * r["elapsed"] / steps, "force_us": 1e3 * r["force_ms_avg"],
+              "rebuilds": r["rebuilds"], "steps": steps})
     emit({"item": "C4_sc_vjp_atoms_per_s", **bench_sc_vjp(20)})
     emit({"item": "C5_fit", **{k: v for k, v in fit_timing().items()}})
     for nc in (10, 20, 30, 40, 60, 80):

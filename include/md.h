@@ -226,6 +226,37 @@ md_status md_step(md_state* st, const md_potential* p, const md_box* box, md_cel
                   int nsteps, int thermo_every, int setup, double* thermo, void* ws,
                   size_t ws_bytes, void* stream);
 
+/* Nose-Hoover chain thermostat for md_step_nvt (the NVT integrator among the
+   integrators listed in the paper's "Design objectives"), in the
+   time-reversible splitting of Martyna, Tuckerman and Klein.  Masses
+   Q_1 = Nf kB T t_damp^2, Q_j = kB T t_damp^2 (j > 1), Nf = 3n - 3.
+   state [device, MD_NHC_STATE doubles, caller-owned, zero for a fresh
+   thermostat]: eta[0..MD_NHC_MAX), eta_dot[0..MD_NHC_MAX), then the chain
+   energy sum_j Q_j eta_dot_j^2 / 2 + Nf kB T eta_1 + kB T sum_{j>1} eta_j at the
+   last step, then two words of working storage.  md_step_nvt updates it in
+   place; pass it unchanged to the next call to continue the run. */
+enum { MD_NHC_MAX = 8, MD_NHC_STATE = 2 * MD_NHC_MAX + 4 };
+typedef struct {
+  double t_target;   /* target temperature, the run's units */
+  double t_damp;     /* thermostat period, time units */
+  int chain;         /* chain length, 1..MD_NHC_MAX */
+  double* state;     /* [device] MD_NHC_STATE doubles (see above) */
+} md_nhc;
+
+/* md_step under the Nose-Hoover chain thermostat nhc: each step is a
+   thermostat half step (velocities scaled by exp(-dt/2 eta_dot_1)), the
+   velocity-Verlet step of md_step (same kick, drift, rebuild rule and
+   forces), and a thermostat half step.  The kinetic energy entering a step's
+   first half step is the one the previous half step left (scaled by the
+   square of its factor); at the start of a call it is summed from v.  thermo
+   rows have nine doubles: the eight of md_step (pe, ke and T after the
+   step's thermostat half step) and pe + ke + chain energy, which the exact
+   NVT flow conserves.  Every other argument, status and rule as md_step. */
+md_status md_step_nvt(md_state* st, const md_potential* p, const md_box* box, md_cells* cells,
+                      md_nlist* nl, md_precision prec, md_kernel k, double skin, double dt,
+                      const md_nhc* nhc, int nsteps, int thermo_every, int setup,
+                      double* thermo, void* ws, size_t ws_bytes, void* stream);
+
 /* Vector-Jacobian product of the forces for L = sum_i u_i . F_i:
    gx = (dF/dx)^T u = -H u, with u, gx [device, 3][n]; gparam [device, may be
    NULL] receives the parameter gradients of L.  LJ: dL/deps, dL/dsigma

@@ -640,10 +640,13 @@ md_status md_autoselect(const md_potential* p, const double* x, int64_t n, const
                          static_cast<hipStream_t>(stream));
 }
 
-md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_cells* cells,
-                  md_nlist* nl, md_precision prec, md_kernel k, double skin, double dt,
-                  int nsteps, int thermo_every, int setup, double* thermo, void* ws,
-                  size_t ws_bytes, void* stream) {
+// md_step and md_step_nvt: NVE when nhc is null, else the Nose-Hoover chain
+// splitting around the same velocity-Verlet step.
+static md_status step_impl(md_state* stt, const md_potential* p, const md_box* box,
+                           md_cells* cells, md_nlist* nl, md_precision prec, md_kernel k,
+                           double skin, double dt, const md_nhc* nhc, int nsteps,
+                           int thermo_every, int setup, double* thermo, void* ws,
+                           size_t ws_bytes, void* stream) {
   md_status st = check_pot(p);
   if (st != MD_OK) return st;
   if (!stt || !stt->x || !stt->v || !stt->f || !stt->id || stt->n < 2 || !n_ok(stt->n) ||
@@ -778,7 +781,8 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
   const double dof = 3.0 * (double)n - 3.0;
   const double volume = box->L[0] * box->L[1] * box->L[2];
   int row = 0;
-  auto thermo_out = [&](double stepno) -> md_status {
+  const int row_cols = nhc ? 9 : 8;
+  auto sums_out = [&]() -> md_status {
     SumArgs sa{};
     sa.cols = 8;
     sa.col[0] = eatom;
@@ -788,9 +792,13 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
     sa.partials = at<double>(ws, L.partials);
     sa.out = sums;
     MD_CK(launch_sum(sa, s));
+    return MD_OK;
+  };
+  auto row_out = [&](double stepno) -> md_status {
     ThermoArgs ta{};
     ta.sums = sums;
-    ta.row = thermo + 8 * (size_t)row++;
+    ta.extra = nhc ? nhc->state + kNhcEnergy : nullptr;
+    ta.row = thermo + (size_t)row_cols * (size_t)row++;
     ta.step = stepno;
     ta.mass = stt->mass;
     ta.mvv2e = stt->mvv2e;
@@ -801,6 +809,31 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
     MD_CK(launch_thermo_row(ta, s));
     return MD_OK;
   };
+  auto thermo_out = [&](double stepno) -> md_status {
+    md_status r = sums_out();
+    return r != MD_OK ? r : row_out(stepno);
+  };
+  // Nose-Hoover chain constants and the kinetic-energy-only sum (into
+  // sums[8]) that steps without a thermo row use.
+  NhcArgs na{};
+  SumArgs ka{};
+  double* const nhc_scale = nhc ? nhc->state + kNhcScale : nullptr;
+  if (nhc) {
+    const double kT = stt->boltz * nhc->t_target;
+    na.state = nhc->state;
+    na.M = nhc->chain;
+    na.kT = kT;
+    na.nf = dof;
+    na.Q0 = dof * kT * nhc->t_damp * nhc->t_damp;
+    na.Qj = kT * nhc->t_damp * nhc->t_damp;
+    na.dt = dt;
+    na.mke = stt->mass * stt->mvv2e;
+    ka.cols = 1;
+    ka.col[0] = keatom;
+    ka.n = n;
+    ka.partials = at<double>(ws, L.partials);
+    ka.out = sums + 8;
+  }
 
   int kernel = nl->layout;   // lanes per atom == list layout
   if (setup) {
@@ -834,7 +867,12 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
     if ((st = forces(ev, kernel, xqs[0], nullptr)) != MD_OK) return st;
     if (ev) {
       MD_CK(launch_ke(stt->v, n, keatom, s));
-      if ((st = thermo_out(0.0)) != MD_OK) return st;
+      if ((st = sums_out()) != MD_OK) return st;
+      if (nhc) {   // the chain energy of the state as given
+        NhcArgs e = na;
+        MD_CK(launch_nhc(e, s));
+      }
+      if ((st = row_out(0.0)) != MD_OK) return st;
     }
   }
   const int layout = kernel;
@@ -845,7 +883,71 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
   // step s, then (s < nsteps) step s + 1's kick, drift into xq[(s + 1) & 1]
   // and check, or (s = nsteps) the state's x and f.  The thermo row of step s
   // is summed right after its force kernel.
-  if (nsteps > 0) {
+  if (nsteps > 0 && nhc) {
+    // Per step: thermostat half step and kick + drift + check (one kernel
+    // reading the scale the chain update left), gated rebuild, forces with
+    // the closing kick only (x, f, v and |v|^2 stored), the kinetic-energy
+    // sum, the closing half step fused with the next step's opening half
+    // step, and the thermo row.  The first opening half step takes its
+    // kinetic energy from a sum over the current velocities.
+    BinOut bin{};
+    bin.box = bk;
+    for (int d = 0; d < 3; ++d) bin.nc[d] = nc[d];
+    bin.atom_cell = cells->atom_cell;
+    bin.xq = xqs[1];
+    bin.flag = gates[1];
+    bin.type = type;
+    MD_CK(launch_fill_int(gates[0], 1, 0, s));
+    MD_CK(launch_fill_int(gates[1], 1, 0, s));
+    MD_CK(launch_ke(stt->v, n, keatom, s));
+    MD_CK(launch_sum(ka, s));
+    {
+      NhcArgs a = na;
+      a.vsum = sums + 8;
+      a.start = 1;
+      MD_CK(launch_nhc(a, s));
+    }
+    MD_CK(launch_kick_drift_check(stt->x, stt->v, stt->f, nl->x_ref, n, dtfm, dt, trig2, status,
+                                  bin, nhc_scale, s));
+    for (int step = 1; step <= nsteps; ++step) {
+      double* cur = xqs[step & 1];
+      gate = gates[step & 1];
+      if ((st = rebuild(gate, layout, cur)) != MD_OK) return st;
+      const bool th = is_thermo(step);
+      IntArgs in{};
+      in.mode = MD_INT_LAST;
+      in.v = stt->v;
+      in.xr = nl->x_ref;
+      in.x = stt->x;
+      in.keatom = keatom;
+      in.status = status;
+      in.dtfm = dtfm;
+      in.dt = dt;
+      in.trig2 = trig2;
+      in.bin = bin;
+      if ((st = forces(th, kernel, cur, &in)) != MD_OK) return st;
+      if (th) {
+        if ((st = sums_out()) != MD_OK) return st;
+      } else {
+        MD_CK(launch_sum(ka, s));
+      }
+      NhcArgs a = na;
+      a.vsum = th ? sums + 7 : sums + 8;
+      a.vsum_out = th ? sums + 7 : nullptr;
+      a.end = 1;
+      a.start = step < nsteps;
+      MD_CK(launch_nhc(a, s));
+      if (th && (st = row_out((double)step)) != MD_OK) return st;
+      if (step < nsteps) {
+        bin.xq = xqs[(step + 1) & 1];
+        bin.flag = gates[(step + 1) & 1];
+        MD_CK(launch_kick_drift_check(stt->x, stt->v, stt->f, nl->x_ref, n, dtfm, dt, trig2,
+                                      status, bin, nhc_scale, s));
+      } else {
+        MD_CK(launch_scale_v(stt->v, n, nhc_scale, s));
+      }
+    }
+  } else if (nsteps > 0) {
     BinOut bin{};
     bin.box = bk;
     for (int d = 0; d < 3; ++d) bin.nc[d] = nc[d];
@@ -856,7 +958,7 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
     MD_CK(launch_fill_int(gates[0], 1, 0, s));
     MD_CK(launch_fill_int(gates[1], 1, 0, s));
     MD_CK(launch_kick_drift_check(stt->x, stt->v, stt->f, nl->x_ref, n, dtfm, dt, trig2, status,
-                                  bin, s));
+                                  bin, nullptr, s));
     for (int step = 1; step <= nsteps; ++step) {
       double* cur = xqs[step & 1];
       gate = gates[step & 1];
@@ -883,6 +985,25 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
   MD_CK(hipMemcpyAsync(words, status, sizeof(words), hipMemcpyDeviceToHost, s));
   MD_CK(hipStreamSynchronize(s));
   return status_from_words(words);
+}
+
+md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_cells* cells,
+                  md_nlist* nl, md_precision prec, md_kernel k, double skin, double dt,
+                  int nsteps, int thermo_every, int setup, double* thermo, void* ws,
+                  size_t ws_bytes, void* stream) {
+  return step_impl(stt, p, box, cells, nl, prec, k, skin, dt, nullptr, nsteps, thermo_every,
+                   setup, thermo, ws, ws_bytes, stream);
+}
+
+md_status md_step_nvt(md_state* stt, const md_potential* p, const md_box* box, md_cells* cells,
+                      md_nlist* nl, md_precision prec, md_kernel k, double skin, double dt,
+                      const md_nhc* nhc, int nsteps, int thermo_every, int setup,
+                      double* thermo, void* ws, size_t ws_bytes, void* stream) {
+  if (!nhc || !nhc->state || nhc->chain < 1 || nhc->chain > MD_NHC_MAX ||
+      !finite_pos(nhc->t_target) || !finite_pos(nhc->t_damp))
+    return MD_ERR_INVALID_ARG;
+  return step_impl(stt, p, box, cells, nl, prec, k, skin, dt, nhc, nsteps, thermo_every, setup,
+                   thermo, ws, ws_bytes, stream);
 }
 
 md_status md_timing_enable(int every) {

@@ -6,20 +6,23 @@ namespace md {
 namespace {
 
 // v += dtfm f; x += dt v; request a rebuild when |x - x_ref|^2 > (skin/2)^2.
-// All products and sums are evaluated as written (no contraction), so the
+// With a thermostat the velocities are first multiplied by *scale.  All
+// products and sums are evaluated as written (no contraction), so the
 // trajectory arithmetic is plain IEEE double.
 __global__ __launch_bounds__(kBlock) void k_kick_drift_check(
     double* __restrict__ x, double* __restrict__ v, const double* __restrict__ f,
     const double* __restrict__ xr, int n, double dtfm, double dt, double trig2,
-    int* __restrict__ status, BinOut bin) {
+    int* __restrict__ status, BinOut bin, const double* __restrict__ scale) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const bool live = i < n;
   bool finite = true;
   double xn[3] = {0.0, 0.0, 0.0}, dd[3] = {0.0, 0.0, 0.0};
   if (live) {
+    const double sc = scale ? *scale : 1.0;
     for (int d = 0; d < 3; ++d) {
       const int q = d * n + i;
-      const double vn = v[q] + dtfm * f[q];
+      const double vs = scale ? v[q] * sc : v[q];
+      const double vn = vs + dtfm * f[q];
       xn[d] = x[q] + dt * vn;
       v[q] = vn;
       x[q] = xn[d];
@@ -28,6 +31,65 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift_check(
     }
   }
   drift_flags(xn, dd, trig2, i, finite, live, status, bin);
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale_v(double* __restrict__ v, int n,
+                                                     const double* __restrict__ scale) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= 3 * n) return;
+  v[i] = v[i] * *scale;
+}
+
+// Nose-Hoover chain half step over a time dt/2 (Martyna-Tuckerman-Klein
+// splitting): chain velocities updated from the last thermostat down to the
+// first, particle velocities scaled by exp(-dt/2 w_1), chain positions
+// advanced, chain velocities updated back up.  Thermostat forces:
+// G_1 = (ke2 - nf kT) / Q_1, G_j = (Q_{j-1} w_{j-1}^2 - kT) / Q_j.  Each
+// velocity update: w_j <- w_j c^2 + (dt/4) G_j c with c = exp(-(dt/8) w_{j+1})
+// (no factor for the last thermostat).  Returns the scale factor and
+// leaves ke2 scaled.
+__device__ double nhc_half_step(const NhcArgs& a, double* eta, double* w, double& ke2) {
+  const int M = a.M;
+  const double h4 = 0.25 * a.dt, h8 = 0.125 * a.dt;
+  auto mass = [&](int j) { return j == 0 ? a.Q0 : a.Qj; };
+  auto force = [&](int j) {
+    return j == 0 ? (ke2 - a.nf * a.kT) / a.Q0
+                  : (mass(j - 1) * w[j - 1] * w[j - 1] - a.kT) / mass(j);
+  };
+  auto update = [&](int j) {
+    if (j == M - 1) {
+      w[j] = w[j] + h4 * force(j);
+    } else {
+      const double c = exp(-h8 * w[j + 1]);
+      w[j] = w[j] * c * c + h4 * force(j) * c;
+    }
+  };
+  for (int j = M - 1; j >= 0; --j) update(j);
+  const double sc = exp(-0.5 * a.dt * w[0]);
+  ke2 = ke2 * sc * sc;
+  for (int j = 0; j < M; ++j) eta[j] = eta[j] + 0.5 * a.dt * w[j];
+  for (int j = 0; j < M; ++j) update(j);
+  return sc;
+}
+
+__global__ void k_nhc(NhcArgs a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double* eta = a.state;
+  double* w = a.state + MD_NHC_MAX;
+  double ke2 = a.vsum ? a.mke * *a.vsum : a.state[kNhcKe2];
+  double sc = 1.0;
+  if (a.end) {
+    const double f = nhc_half_step(a, eta, w, ke2);
+    if (a.vsum_out) *a.vsum_out = *a.vsum * f * f;
+    sc = f;
+  }
+  double e = a.nf * a.kT * eta[0];
+  for (int j = 0; j < a.M; ++j) e += 0.5 * (j == 0 ? a.Q0 : a.Qj) * w[j] * w[j];
+  for (int j = 1; j < a.M; ++j) e += a.kT * eta[j];
+  a.state[kNhcEnergy] = e;
+  if (a.start) sc = sc * nhc_half_step(a, eta, w, ke2);
+  a.state[kNhcScale] = sc;
+  a.state[kNhcKe2] = ke2;
 }
 
 __global__ __launch_bounds__(kBlock) void k_ke(const double* __restrict__ v, int n,
@@ -89,6 +151,7 @@ __global__ void k_thermo_row(ThermoArgs a) {
   a.row[5] = (2.0 * ke + (s[1] + s[2] + s[3])) / (3.0 * a.volume);
   a.row[6] = (double)a.status[MD_ST_BUILDS];
   a.row[7] = (double)a.status[MD_ST_MAXNEIGH];
+  if (a.extra) a.row[8] = a.row[3] + *a.extra;
 }
 
 __global__ void k_vjp_params(const double* sums, double eps, double* gparam) {
@@ -113,9 +176,19 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBl
 
 hipError_t launch_kick_drift_check(double* x, double* v, const double* f, const double* xr,
                                    int n, double dtfm, double dt, double trig2, int* status,
-                                   const BinOut& bin, hipStream_t s) {
+                                   const BinOut& bin, const double* scale, hipStream_t s) {
   k_kick_drift_check<<<blocks_for(n), kBlock, 0, s>>>(x, v, f, xr, n, dtfm, dt, trig2, status,
-                                                       bin);
+                                                       bin, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_v(double* v, int n, const double* scale, hipStream_t s) {
+  k_scale_v<<<blocks_for(3 * (int64_t)n), kBlock, 0, s>>>(v, n, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_nhc(const NhcArgs& a, hipStream_t s) {
+  k_nhc<<<1, 64, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -312,9 +312,29 @@ hipError_t launch_lj_vjp(const ForceArgs& a, const LJK& p, int prec, int kernel,
                          const double* u, double* gx, double* pe, double* ps, hipStream_t s);
 
 // Integration.
+// scale (device scalar, nullable): v is multiplied by it before the kick.
 hipError_t launch_kick_drift_check(double* x, double* v, const double* f, const double* xr,
                                    int n, double dtfm, double dt, double trig2, int* status,
-                                   const BinOut& bin, hipStream_t s);
+                                   const BinOut& bin, const double* scale, hipStream_t s);
+// v *= *scale.
+hipError_t launch_scale_v(double* v, int n, const double* scale, hipStream_t s);
+
+// Nose-Hoover chain update (one thread).  ke2 = mke * (*vsum) (sum m v^2 in
+// energy units) or, with vsum null, the value carried in the state.  end:
+// the half step closing a step (vsum_out, if set, receives vsum times the
+// square of its factor, for the thermo row); then the chain energy is stored;
+// start: the half step opening the next step.  The product of the factors
+// is stored in the state's scale word.
+struct NhcArgs {
+  double* state;
+  int M;
+  double Q0, Qj, kT, nf, dt, mke;
+  const double* vsum;
+  double* vsum_out;
+  int end, start;
+};
+hipError_t launch_nhc(const NhcArgs& a, hipStream_t s);
+constexpr int kNhcEnergy = 16, kNhcScale = 17, kNhcKe2 = 18;   // state words after the chain
 hipError_t launch_ke(const double* v, int n, double* keatom, hipStream_t s);
 
 // Deterministic sums: cols arrays of n doubles (col c at base[c] ) -> out[cols].
@@ -329,6 +349,7 @@ hipError_t launch_sum(const SumArgs& a, hipStream_t s);
 // Thermo row from out = {pe, W0..W5, sv} sums.
 struct ThermoArgs {
   const double* sums;  // pe, w0..w5, sum v^2
+  const double* extra; // nullable: an energy added to pe + ke in a ninth column
   double* row;
   double step, mass, mvv2e, boltz, dof, volume;
   const int* status;

@@ -26,7 +26,7 @@ MD_POT_LJ, MD_POT_SC, MD_POT_BUCK = 0, 1, 2
 MD_LAYOUT_TPA, MD_LAYOUT_WPA = 1, 64
 MD_ST_ERRORS, MD_ST_MAXNEIGH, MD_ST_BUILDS, MD_ST_REBUILD, MD_STATUS_WORDS = 0, 1, 2, 3, 8
 EXPORTS = ("md_workspace_bytes", "md_nlist_ints", "md_thermo_rows", "md_bin_cells", "md_sort_atoms",
-           "md_build_neighbors", "md_compute_forces", "md_step", "md_force_vjp",
+           "md_build_neighbors", "md_compute_forces", "md_step", "md_step_nvt", "md_force_vjp",
            "md_autoselect", "md_nlist_status", "md_timing_enable", "md_timing_read",
            "md_status_string")
 
@@ -61,6 +61,14 @@ class md_nlist(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int), ("layout", ctypes.c_int), ("rl", ctypes.c_double),
                 ("neigh", ctypes.c_void_p), ("numneigh", ctypes.c_void_p),
                 ("x_ref", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
+MD_NHC_MAX, MD_NHC_STATE = 8, 20
+
+
+class md_nhc(ctypes.Structure):
+    _fields_ = [("t_target", ctypes.c_double), ("t_damp", ctypes.c_double),
+                ("chain", ctypes.c_int), ("state", ctypes.c_void_p)]
 
 
 class md_state(ctypes.Structure):
@@ -98,6 +106,9 @@ def lib() -> ctypes.CDLL:
                                         V, V, V, ctypes.c_size_t, V]
         L.md_step.argtypes = [P(md_state), P(md_potential), P(md_box), P(md_cells), P(md_nlist),
                               I, I, D, D, I, I, I, V, V, ctypes.c_size_t, V]
+        L.md_step_nvt.argtypes = [P(md_state), P(md_potential), P(md_box), P(md_cells),
+                                  P(md_nlist), I, I, D, D, P(md_nhc), I, I, I, V, V,
+                                  ctypes.c_size_t, V]
         L.md_force_vjp.argtypes = [P(md_potential), V, I64, P(md_box), P(md_nlist), I, V, V, V,
                                    V, ctypes.c_size_t, V]
         L.md_autoselect.argtypes = [P(md_potential), V, I64, P(md_box), P(md_cells), D,
@@ -307,6 +318,33 @@ def md_step(state: State, pot: md_potential, box: md_box, cells: Cells, nl: NLis
                          nsteps, thermo_every, setup,
                          _ptr(thermo, torch.float64, 8 * rows) if rows else None, _ptr(ws),
                          ws.numel(), _stream(stream)), "md_step")
+
+
+class NHC:
+    """Nose-Hoover chain thermostat: parameters plus its device state (zero
+    for a fresh thermostat; md_step_nvt updates it in place)."""
+
+    def __init__(self, t_target: float, t_damp: float, chain: int = 3, device="cuda"):
+        self.state = torch.zeros(MD_NHC_STATE, dtype=torch.float64, device=device)
+        self.c = md_nhc(t_target=t_target, t_damp=t_damp, chain=chain,
+                        state=self.state.data_ptr())
+
+    @property
+    def chain_energy(self) -> float:
+        return float(self.state[2 * MD_NHC_MAX].item())
+
+
+def md_step_nvt(state: State, pot: md_potential, box: md_box, cells: Cells, nl: NList, prec: int,
+                kernel: int, skin: float, dt: float, nhc: NHC, nsteps: int, thermo_every: int,
+                setup: int, thermo: Optional[torch.Tensor], ws: torch.Tensor,
+                stream=None) -> None:
+    """thermo: rows x 9 doubles (md_step's eight and the conserved energy)."""
+    rows = md_thermo_rows(nsteps, thermo_every, setup)
+    _check(lib().md_step_nvt(ctypes.byref(state.c), ctypes.byref(pot), ctypes.byref(box),
+                             ctypes.byref(cells.c), ctypes.byref(nl.c), prec, kernel, skin, dt,
+                             ctypes.byref(nhc.c), nsteps, thermo_every, setup,
+                             _ptr(thermo, torch.float64, 9 * rows) if rows else None, _ptr(ws),
+                             ws.numel(), _stream(stream)), "md_step_nvt")
 
 
 def md_force_vjp(pot: md_potential, x: torch.Tensor, box: md_box, nl: NList, prec: int,

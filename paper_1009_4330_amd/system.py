@@ -45,8 +45,13 @@ def capacity_guess(w: Workload) -> int:
 
 class MDSystem:
     def __init__(self, w: Workload, x: np.ndarray, v: np.ndarray, prec: str = "fp64",
-                 kernel: str = "tpa", capacity: Optional[int] = None, device="cuda"):
+                 kernel: str = "tpa", capacity: Optional[int] = None, device="cuda",
+                 nvt: Optional[tuple] = None):
+        """nvt = (t_target, t_damp, chain length) runs md_step_nvt (thermo rows
+        of nine columns) instead of NVE md_step."""
         self.w = w
+        self.nhc = md.NHC(*nvt, device=device) if nvt else None
+        self.cols = 9 if nvt else 8
         self.prec = PREC[prec]
         self.kernel = KERNEL[kernel]
         self.box = md.make_box(w.box)
@@ -73,7 +78,8 @@ class MDSystem:
     def _tensors(self):
         s = self.state
         out = [s.x, s.v, s.f, s.id, self.nl.x_ref, self.nl.status]
-        return out + ([self.type] if self.type is not None else [])
+        out += [self.type] if self.type is not None else []
+        return out + ([self.nhc.state] if self.nhc is not None else [])
 
     def _snapshot(self):
         return tuple(t.clone() for t in self._tensors())
@@ -87,14 +93,23 @@ class MDSystem:
         layout = self.nl.layout
         self.nl = md.NList(self.n, cap, layout, self.device)
 
+    def _step(self, kernel, nsteps, every, setup, rows):
+        if self.nhc is None:
+            md.md_step(self.state, self.pot, self.box, self.cells, self.nl, self.prec, kernel,
+                       self.w.skin, self.w.dt, nsteps, every, setup, rows, self.ws)
+        else:
+            md.md_step_nvt(self.state, self.pot, self.box, self.cells, self.nl, self.prec,
+                           kernel, self.w.skin, self.w.dt, self.nhc, nsteps, every, setup, rows,
+                           self.ws)
+
     def setup(self, thermo: bool = True) -> Optional[np.ndarray]:
         """Wrap, bin, sort, build and evaluate forces for the current state."""
         while True:
             snap = self._snapshot()
-            rows = torch.zeros(1, 8, dtype=torch.float64, device=self.device) if thermo else None
+            rows = (torch.zeros(1, self.cols, dtype=torch.float64, device=self.device)
+                    if thermo else None)
             try:
-                md.md_step(self.state, self.pot, self.box, self.cells, self.nl, self.prec,
-                           self.kernel, self.w.skin, self.w.dt, 0, 1, 1, rows, self.ws)
+                self._step(self.kernel, 0, 1, 1, rows)
             except md.MDError as e:
                 if e.code != md.MD_ERR_NLIST_OVERFLOW:
                     raise
@@ -118,11 +133,9 @@ class MDSystem:
             k = min(chunk, nsteps - done)
             rows_n = md.md_thermo_rows(k, every, 0)
             snap = self._snapshot()
-            th = torch.zeros(max(rows_n, 1), 8, dtype=torch.float64, device=self.device)
+            th = torch.zeros(max(rows_n, 1), self.cols, dtype=torch.float64, device=self.device)
             try:
-                md.md_step(self.state, self.pot, self.box, self.cells, self.nl, self.prec,
-                           self.kernel, self.w.skin, self.w.dt, k, every, 0,
-                           th if rows_n else None, self.ws)
+                self._step(self.kernel, k, every, 0, th if rows_n else None)
             except md.MDError as e:
                 if e.code != md.MD_ERR_NLIST_OVERFLOW:
                     raise
@@ -138,7 +151,7 @@ class MDSystem:
                 out.append(r)
             done += k
             self.steps_done += k
-        return np.concatenate(out) if out else np.zeros((0, 8))
+        return np.concatenate(out) if out else np.zeros((0, self.cols))
 
     def host_state(self):
         """(x, v, f) as numpy [3][n] arrays in the caller's original atom order."""
