@@ -196,6 +196,49 @@ def bench_sc_vjp(reps: int):
     return out
 
 
+def bench_half_list(reps: int = 20):
+    """Force-kernel time (md_compute_forces, no energy) from full and half
+    lists on the 256k LJ melt after 200 steps, per lanes-per-atom layout."""
+    import math
+    import torch
+    from paper_1009_4330_amd import inputs as I
+    from paper_1009_4330_amd import md
+    from paper_1009_4330_amd.system import MDSystem
+
+    w = I.LJ_256K
+    x, v, _ = I.initial_state(w)
+    s = MDSystem(w, x, v, "mixed", "k4")
+    s.setup(thermo=False)
+    s.run(200, 200)
+    xs = s.state.x.clone()
+    n = w.natoms
+    box = md.make_box(w.box)
+    rl = w.rc + w.skin
+    ncell = int(np.prod([math.floor(L / rl) for L in w.box]))
+    cells = md.Cells(n, ncell)
+    ws = md.workspace(n, box, rl)
+    md.md_bin_cells(xs, box, rl, cells, ws)
+    pot = md.lj_potential(w.rc, 1.0, 1.0, 1)
+    f = torch.empty(3, n, dtype=torch.float64, device="cuda")
+    out = {}
+    for half in (False, True):
+        for k in (1, 4, 64):
+            nl = md.NList(n, 160, k, half=half)
+            md.md_build_neighbors(xs, box, cells, w.rc, w.skin, nl)
+            for prec_name, prec in (("mixed", md.MD_MIXED), ("fp64", md.MD_FP64)):
+                md.md_compute_forces(pot, xs, box, nl, prec, md.MD_KERNEL_AUTO, 0, f, None, ws)
+                torch.cuda.synchronize()
+                md.md_timing_enable(1)
+                for _ in range(reps):
+                    md.md_compute_forces(pot, xs, box, nl, prec, md.MD_KERNEL_AUTO, 0, f, None,
+                                         ws)
+                launches, ms = md.md_timing_read()
+                md.md_timing_enable(0)
+                key = f"{'half' if half else 'full'}_k{k}_{prec_name}_us"
+                out[key] = 1e3 * ms / max(launches, 1)
+    return out
+
+
 def cpu_baseline(w, x, v, target_s: float = 15.0):
     """The oracle's own NVE run on the host cores, on a bounded number of
     steps of the same workload; setup (first build + forces) is subtracted."""
@@ -373,6 +416,8 @@ def suite(steps: int):
               "ms_per_step": 1e3 * r["elapsed"] / steps, "force_us": 1e3 * r["force_ms_avg"],
               "rebuilds": r["rebuilds"], "steps": steps})
     emit({"item": "C4_sc_vjp_atoms_per_s", **bench_sc_vjp(20)})
+    emit({"item": "half_vs_full_list_force_kernel", "workload": "lj_melt_256k",
+          **bench_half_list()})
     emit({"item": "C5_fit", **{k: v for k, v in fit_timing().items()}})
     for nc in (10, 20, 30, 40, 60, 80):
         w = I.scaled(I.LJ_256K, nc)

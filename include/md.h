@@ -127,7 +127,13 @@ typedef struct {
 } md_cells;
 
 /* Full Verlet list: every ordered pair i != j with r_ij^2 < rl^2 appears in
-   row i, rl = rc + skin. */
+   row i, rl = rc + skin.  With half = 1 (Newton's third law, after the
+   paper's section "Cell list approach": each pair computed once), row i holds
+   only the partners j > i, in the order the full row would list them;
+   capacity must still hold the full row while it is built, and
+   status[MD_ST_MAXNEIGH] reports the full count.  Half lists serve
+   md_build_neighbors and md_compute_forces (LJ); md_step, md_step_nvt,
+   md_autoselect and md_force_vjp return MD_ERR_UNSUPPORTED for them. */
 typedef struct {
   int capacity;        /* entries per atom the neigh buffer holds */
   int layout;          /* lanes per atom K (MD_LAYOUT_TPA = 1 ... MD_LAYOUT_WPA = 64) */
@@ -136,6 +142,7 @@ typedef struct {
   int* numneigh;       /* [n] */
   double* x_ref;       /* [3][n] positions at the last build (rebuild trigger reference) */
   int* status;         /* [MD_STATUS_WORDS], zero it once before first use */
+  int half;            /* 0: full list; 1: half list (see above) */
 } md_nlist;
 
 /* Dynamic state advanced by md_step.  Units: ftm2v converts force/mass * time
@@ -195,7 +202,10 @@ md_status md_build_neighbors(const double* x, int64_t n, const md_box* box,
    forms d and r^2 in FP64, evaluates the scalar pair function in FP32, and
    accumulates forces, energy and virial in FP64.  k = AUTO uses the kernel
    matching nl->layout; TPA / WPA must match the layout (else
-   MD_ERR_INVALID_ARG). */
+   MD_ERR_INVALID_ARG).  From a half list (LJ only) each pair is evaluated
+   once and its force added to both atoms with FP64 atomic adds, so the
+   summation order (and the last bits) can change from call to call; the
+   whole pair energy and virial go to the atom with the smaller index. */
 md_status md_compute_forces(const md_potential* p, const double* x, int64_t n,
                             const md_box* box, const md_nlist* nl, md_precision prec,
                             md_kernel k, int flags, double* f, double* ev, void* ws,

@@ -253,6 +253,7 @@ md_status build_list(const double* x, int n, int sorted, const md_box* box, cons
   a.x_ref = nl->x_ref;
   a.status = nl->status;
   MD_CK(launch_build(a, s));
+  if (nl->half) MD_CK(launch_halve(nl->neigh, nl->numneigh, n, nl->capacity, layout, s));
   nl->layout = layout;
   nl->rl = rl;
   return MD_OK;
@@ -512,6 +513,7 @@ md_status md_compute_forces(const md_potential* p, const double* x, int64_t n,
     return MD_ERR_INVALID_ARG;
   const int kernel = resolve_lanes(k, nl->layout);
   if (!kernel) return MD_ERR_INVALID_ARG;
+  if (nl->half && p->kind != MD_POT_LJ) return MD_ERR_UNSUPPORTED;
   if ((st = check_box(box, nl->rl > p->rc ? nl->rl : p->rc)) != MD_OK) return st;
   const WsLayout L = ws_layout(n, 1);
   if ((st = check_ws(ws, ws_bytes, L)) != MD_OK) return st;
@@ -532,7 +534,13 @@ md_status md_compute_forces(const md_potential* p, const double* x, int64_t n,
     fa.ev.vatom = at<double>(ws, L.vatom);
   }
   timing_events(&fa.t0, &fa.t1);
-  if ((st = force_dispatch(p, fa, prec, kernel, at<double>(ws, L.sc_e), s)) != MD_OK) return st;
+  if (nl->half) {
+    // each pair once; both atoms' shares are added atomically into f
+    MD_CK(launch_fill_double(f, 3 * n, 0.0, s));
+    MD_CK(launch_lj_half(fa, make_lj(p), prec, kernel, s));
+  } else if ((st = force_dispatch(p, fa, prec, kernel, at<double>(ws, L.sc_e), s)) != MD_OK) {
+    return st;
+  }
   if (flags) {
     SumArgs sa{};
     sa.cols = 7;
@@ -551,7 +559,8 @@ md_status md_force_vjp(const md_potential* p, const double* x, int64_t n, const 
                        double* gparam, void* ws, size_t ws_bytes, void* stream) {
   md_status st = check_pot(p);
   if (st != MD_OK) return st;
-  if (p->kind != MD_POT_LJ && p->kind != MD_POT_SC) return MD_ERR_UNSUPPORTED;
+  if ((p->kind != MD_POT_LJ && p->kind != MD_POT_SC) || (nl && nl->half))
+    return MD_ERR_UNSUPPORTED;
   if (!x || !nl || !nl->neigh || !nl->numneigh || !u || !gx || !n_ok(n) || nl->capacity < 1 ||
       (prec != MD_FP64 && prec != MD_MIXED) || !lanes_ok(nl->layout))
     return MD_ERR_INVALID_ARG;
@@ -627,6 +636,7 @@ md_status md_autoselect(const md_potential* p, const double* x, int64_t n, const
       !n_ok(n) || nl->capacity < 1 || reps < 1 || (prec != MD_FP64 && prec != MD_MIXED) ||
       !(skin >= 0.0))
     return MD_ERR_INVALID_ARG;
+  if (nl->half) return MD_ERR_UNSUPPORTED;
   const double rl = p->rc + skin;
   if ((st = check_box(box, rl)) != MD_OK) return st;
   int nc[3];
@@ -657,6 +667,7 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
       !finite_pos(stt->boltz) || (prec != MD_FP64 && prec != MD_MIXED) ||
       (k != MD_KERNEL_AUTO && !lanes_ok((int)k)))
     return MD_ERR_INVALID_ARG;
+  if (nl->half) return MD_ERR_UNSUPPORTED;
   const double rl = p->rc + skin;
   if ((st = check_box(box, rl)) != MD_OK) return st;
   int nc[3];

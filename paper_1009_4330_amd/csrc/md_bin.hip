@@ -16,6 +16,29 @@ __global__ __launch_bounds__(kBlock) void k_fill_int(int* __restrict__ p, int64_
   if (i < count) p[i] = value;
 }
 
+__global__ __launch_bounds__(kBlock) void k_fill_double(double* __restrict__ p, int64_t count,
+                                                         double value) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < count) p[i] = value;
+}
+
+// Half list from a full one, in place: thread i walks its row in order and
+// keeps the partners j > i at the front (a kept entry never lands past the
+// entry being read, so the walk reads only entries not yet overwritten).
+__global__ __launch_bounds__(kBlock) void k_halve(int* __restrict__ neigh,
+                                                   int* __restrict__ numneigh, int n, int cap,
+                                                   int layout) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int cnt = min(numneigh[i], cap);
+  int kept = 0;
+  for (int m = 0; m < cnt; ++m) {
+    const int j = neigh[nl_index(i, m, cap, layout)];
+    if (j > i) neigh[nl_index(i, kept++, cap, layout)] = j;
+  }
+  numneigh[i] = kept;
+}
+
 // Exclusive scan of one int per thread over a 256-thread block; *total gets
 // the block sum.  sh holds 4 ints.
 __device__ inline int block_excl_scan(int v, int* sh, int* total) {
@@ -1332,6 +1355,17 @@ unsigned resident_grid(int per_cu, int64_t need) {
   }
   const int64_t g = ((int64_t)cus[dev] * per_cu + kXcds - 1) / kXcds * kXcds;
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, need));
+}
+
+hipError_t launch_fill_double(double* p, int64_t count, double value, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  k_fill_double<<<blocks_for(count), kBlock, 0, s>>>(p, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_halve(int* neigh, int* numneigh, int n, int cap, int layout, hipStream_t s) {
+  k_halve<<<blocks_for(n), kBlock, 0, s>>>(neigh, numneigh, n, cap, layout);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t s) {

@@ -414,6 +414,60 @@ __global__ __launch_bounds__(kBlock) void k_lj(FK a, LJK p) {
   finish_atom<FUSED>(a, acc, ln.i, ln.live && ln.s == 0, xi, yi, zi, EV, 0.0);
 }
 
+// LJ from a half list (each pair once, Newton's third law): atom i's own sum
+// as in k_lj, and -F_ij added to atom j with an FP64 atomic add per
+// component; atom i's total is added atomically too (other rows add into it
+// concurrently), so f must be zero on entry.  The whole pair energy and
+// virial go to atom i.
+template <int PREC, bool EV, int K>
+__global__ __launch_bounds__(kBlock) void k_lj_half(FK a, LJK p) {
+  const Lane<K> ln(a);
+  const int n = a.n;
+  const int io = ln.live ? ln.i : n - 1;
+  double xi, yi, zi;
+  home_pos(a, io, xi, yi, zi);
+  Acc acc;
+  double* __restrict__ f = a.f;
+  for_each_batch<K, PREC == MD_MIXED>(a, ln, xi, yi, zi, [&](const Batch& b) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const bool use = b.ok[u] && b.s[u] < p.rc2;
+      double g, phi;
+      lj_pair<PREC>(use ? b.s[u] : 1.0, p, g, phi);
+      g = use ? g : 0.0;
+      acc.add_force(g, b.dx[u], b.dy[u], b.dz[u]);
+      if (use) {
+        const int j = b.j[u];
+        unsafeAtomicAdd(f + j, -(g * b.dx[u]));
+        unsafeAtomicAdd(f + n + j, -(g * b.dy[u]));
+        unsafeAtomicAdd(f + 2 * n + j, -(g * b.dz[u]));
+      }
+      if (EV) {
+        acc.e += use ? phi - p.ecut : 0.0;
+        acc.add_virial(g, b.dx[u], b.dy[u], b.dz[u]);
+      }
+    }
+  });
+  if (K > 1) acc.reduce<K>(EV);
+  if (!ln.live || ln.s != 0) return;
+  const int i = ln.i;
+  unsafeAtomicAdd(f + i, acc.fx);
+  unsafeAtomicAdd(f + n + i, acc.fy);
+  unsafeAtomicAdd(f + 2 * n + i, acc.fz);
+  if (EV) {
+    // store_ev halves its sums (full-list convention); the half list's are whole
+    Acc whole = acc;
+    whole.e *= 2.0;
+    whole.w0 *= 2.0;
+    whole.w1 *= 2.0;
+    whole.w2 *= 2.0;
+    whole.w3 *= 2.0;
+    whole.w4 *= 2.0;
+    whole.w5 *= 2.0;
+    whole.store_ev(a, i, true, 0.0);
+  }
+}
+
 // ------------------------------------------- Buckingham + cut Coulomb --
 
 // g = -(dphi/dr) / r and phi at r^2 = s for one species pair, from its row
@@ -855,6 +909,20 @@ hipError_t launch_lj(const ForceArgs& a, const LJK& p, int prec, int lanes, hipS
                 : launch_timed(k_lj<MD_MIXED, false, K, true>, g, s, a.t0, a.t1, k, p);
     return ev ? launch_timed(k_lj<MD_MIXED, true, K, false>, g, s, a.t0, a.t1, k, p)
               : launch_timed(k_lj<MD_MIXED, false, K, false>, g, s, a.t0, a.t1, k, p);
+  });
+}
+
+hipError_t launch_lj_half(const ForceArgs& a, const LJK& p, int prec, int lanes, hipStream_t s) {
+  const FK k = make_fk(a);
+  const bool ev = a.ev.eatom || a.ev.vatom;
+  return with_lanes(lanes, [&](auto kc) -> hipError_t {
+    constexpr int K = decltype(kc)::value;
+    const unsigned g = grid_for(a.n, K);
+    if (prec == MD_FP64)
+      return ev ? launch_timed(k_lj_half<MD_FP64, true, K>, g, s, a.t0, a.t1, k, p)
+                : launch_timed(k_lj_half<MD_FP64, false, K>, g, s, a.t0, a.t1, k, p);
+    return ev ? launch_timed(k_lj_half<MD_MIXED, true, K>, g, s, a.t0, a.t1, k, p)
+              : launch_timed(k_lj_half<MD_MIXED, false, K>, g, s, a.t0, a.t1, k, p);
   });
 }
 

@@ -305,6 +305,11 @@ struct ForceArgs {
 hipError_t launch_pack_positions(const double* x, int n, double* xq, const int* type,
                                  hipStream_t s);
 hipError_t launch_buck(const ForceArgs& a, const BuckK& p, int prec, int lanes, hipStream_t s);
+// LJ from a half list: f must be zero on entry (forces are added atomically).
+hipError_t launch_lj_half(const ForceArgs& a, const LJK& p, int prec, int lanes, hipStream_t s);
+// Keep only the partners j > i of each row, in order (in place).
+hipError_t launch_halve(int* neigh, int* numneigh, int n, int cap, int layout, hipStream_t s);
+hipError_t launch_fill_double(double* p, int64_t count, double value, hipStream_t s);
 hipError_t launch_lj(const ForceArgs& a, const LJK& p, int prec, int kernel, hipStream_t s);
 hipError_t launch_sc(const ForceArgs& a, const SCK& p, int prec, int kernel, double* sc_e,
                      hipStream_t s);

@@ -60,7 +60,7 @@ class md_cells(ctypes.Structure):
 class md_nlist(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int), ("layout", ctypes.c_int), ("rl", ctypes.c_double),
                 ("neigh", ctypes.c_void_p), ("numneigh", ctypes.c_void_p),
-                ("x_ref", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+                ("x_ref", ctypes.c_void_p), ("status", ctypes.c_void_p), ("half", ctypes.c_int)]
 
 
 MD_NHC_MAX, MD_NHC_STATE = 8, 20
@@ -202,14 +202,16 @@ class NList:
     """Device neighbour-list arrays + their md_nlist descriptor.  The neigh
     buffer is sized for every layout K (md_nlist_ints)."""
 
-    def __init__(self, n: int, capacity: int, layout: int = MD_LAYOUT_TPA, device="cuda"):
+    def __init__(self, n: int, capacity: int, layout: int = MD_LAYOUT_TPA, device="cuda",
+                 half: bool = False):
         self.neigh = torch.zeros(md_nlist_ints(n, capacity), dtype=torch.int32, device=device)
         self.numneigh = torch.zeros(n, dtype=torch.int32, device=device)
         self.x_ref = torch.zeros(3, n, dtype=torch.float64, device=device)
         self.status = torch.zeros(MD_STATUS_WORDS, dtype=torch.int32, device=device)
         self.c = md_nlist(capacity=capacity, layout=layout, rl=0.0,
                           neigh=self.neigh.data_ptr(), numneigh=self.numneigh.data_ptr(),
-                          x_ref=self.x_ref.data_ptr(), status=self.status.data_ptr())
+                          x_ref=self.x_ref.data_ptr(), status=self.status.data_ptr(),
+                          half=1 if half else 0)
 
     @property
     def capacity(self) -> int:
