@@ -993,10 +993,10 @@ __global__ __launch_bounds__(kBlock) void k_build(BuildArgs a, int parts) {
 // sit back to back in LDS, so the 27-cell stencil of home cell k is the one
 // contiguous candidate range slabs k .. k + 2.  Candidate order: slab x - 1,
 // x, x + 1, cells in increasing order inside a slab, slot order inside a cell.
-constexpr int kRowCells = 4;
+constexpr int kRowCells = 2;
 constexpr int kMaxSlabs = kRowCells + 2;
 constexpr int kRowCells9 = kMaxSlabs * 9;   // (slab, cell) entries of a run
-constexpr int kRowCap = 1408;               // candidates of a run held in LDS
+constexpr int kRowCap = 960;                // candidates of a run held in LDS
 // The last iteration of a pair's loop prefetches one row of 64 slots past its
 // range: the arrays extend two rows past kRowCap.
 constexpr int kRowSlots = kRowCap + 2 * kWave;
@@ -1317,7 +1317,7 @@ __device__ inline int build_row_segment(const BuildArgs& a, const BuildLds& L, i
 
 // Sorted atoms, at least 3 cells along x: a resident grid working through
 // the row segments (build_row_segment).
-__global__ __launch_bounds__(kBlock) void k_build_rows(BuildArgs a) {
+__global__ __launch_bounds__(kBlock, 4) void k_build_rows(BuildArgs a) {
   if (a.gate && *a.gate == 0) return;
   __shared__ double cxs[kRowSlots], cys[kRowSlots], czs[kRowSlots];
   __shared__ int cjs[kRowSlots];
@@ -1448,7 +1448,7 @@ hipError_t launch_build(const BuildArgs& a, hipStream_t s) {
   const double per_cell = (double)a.n / (double)ncell;
   if (a.sorted && a.nc[0] >= 3 && kMaxSlabs * 9 * per_cell <= 0.9 * kRowCap) {
     const int64_t segs = (int64_t)((a.nc[0] + kRowCells - 1) / kRowCells) * a.nc[1] * a.nc[2];
-    k_build_rows<<<resident_grid(3, segs), kBlock, 0, s>>>(a);
+    k_build_rows<<<resident_grid(4, segs), kBlock, 0, s>>>(a);
   } else {
     // pieces of kHomePiece home atoms at the mean occupancy; denser cells
     // loop over further pieces
