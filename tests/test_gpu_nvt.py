@@ -97,3 +97,27 @@ def test_nvt_rejects_bad_thermostat():
         s = MDSystem(w, x, v, "fp64", "tpa", nvt=bad)
         with pytest.raises(md.MDError):
             s.setup(False)
+
+
+@pytest.mark.parametrize("which", ["sc", "buck"])
+def test_nvt_other_potentials_fp64(orc, which):
+    """The thermostat is independent of the potential: Sutton-Chen (metal
+    units) and Buckingham + Coulomb (two species permuted by the sorts) NVT
+    runs against the oracle's."""
+    if which == "sc":
+        w = I.scaled(I.SC_500K, 6, steps=40)
+        t_target, cap = 300.0, None
+    else:
+        w = dataclasses.replace(I.scaled(I.BUCK_141K, 8, steps=40), skin=0.3)
+        t_target, cap = 300.0, 2300
+    x, v, box = I.initial_state(w)
+    ref, ch = orc.md_run_nvt(orc.params_for(w), x, v, box, w.steps, t_target, 0.1, 3,
+                             thermo_every=5)
+    sysm = MDSystem(w, x, v, "fp64", "k4", capacity=cap, nvt=(t_target, 0.1, 3))
+    rows = np.concatenate([sysm.setup(True), sysm.run(w.steps, 5)])
+    assert np.array_equal(rows[:, 6].astype(int), ref.thermo[:, 6].astype(int))
+    for c in (1, 2, 3, 4, 5, 8):
+        assert rel(rows[:, c], ref.thermo[:, c]) < 1e-10, c
+    gx, gv, gf = sysm.host_state()
+    assert np.abs(min_image_diff(gx, ref.x, box)).max() < 1e-9
+    assert rel(gf, ref.f) < 1e-9
