@@ -1,0 +1,140 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times (AUTO lanes per atom, fused md_step): the 256,000-atom LJ melt against
+the oracle's own run of the same size, the 141k-ion Buckingham crystal and the
+500k-atom Sutton-Chen solid against the oracle's forces over all atoms."""
+import numpy as np
+import pytest
+import torch
+
+import mixed_bounds as MB
+from gpu_helpers import rel
+from paper_1009_4330_amd import inputs as I
+from paper_1009_4330_amd import md
+from paper_1009_4330_amd.system import MDSystem
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 40
+
+
+def min_image_diff(a, b, box):
+    L = np.array(box)[:, None]
+    d = a - b
+    return d - L * np.round(d / L)
+
+
+def to_input_order(sysm, t):
+    """A [3][n] (or [n]) device array in md_step's atom order, as numpy in
+    the caller's original order."""
+    order = torch.argsort(sysm.state.id.long())
+    return t[..., order].cpu().numpy()
+
+
+def test_fullsize_lj_fp64_trajectory(orc):
+    """FP64: 40 steps of the 256k melt; rebuild steps, thermo rows and the
+    final state equal the oracle's run of the same size."""
+    w = I.LJ_256K
+    x, v, box = I.initial_state(w)
+    print(f"[fullsize] lj_melt_256k fp64 {STEPS} steps", flush=True)
+    sysm = MDSystem(w, x, v, "fp64", "auto")
+    rows = np.concatenate([sysm.setup(True), sysm.run(STEPS, 5)])
+    ref = orc.md_run(orc.params_for(w), x, v, box, STEPS, 5)
+    assert np.array_equal(rows[:, 6].astype(int), ref.thermo[:, 6].astype(int))
+    assert rows[-1, 6] > 3
+    for c in (1, 2, 3, 4, 5):
+        assert rel(rows[:, c], ref.thermo[:, c]) < 1e-10, c
+    gx, gv, gf = sysm.host_state()
+    assert np.abs(min_image_diff(gx, ref.x, box)).max() < 1e-9
+    assert np.abs(gv - ref.v).max() < 1e-9
+    assert rel(gf, ref.f) < 1e-9
+
+
+def test_fullsize_lj_mixed_list_and_forces(orc):
+    """MIXED (the headline configuration): after 40 steps the neighbour list
+    equals the oracle's list built from the same reference positions, pair
+    for pair, and the forces at the final positions match the oracle's to
+    the 1e-6 rel-RMS bar and the derived rounding bound."""
+    w = I.LJ_256K
+    x, v, box = I.initial_state(w)
+    print(f"[fullsize] lj_melt_256k mixed {STEPS} steps", flush=True)
+    sysm = MDSystem(w, x, v, "mixed", "auto")
+    sysm.setup(False)
+    sysm.run(STEPS, STEPS)
+    n = w.natoms
+    ids = sysm.state.id.long().cpu().numpy()
+    # list: device rows -> pairs of original ids, against the oracle at x_ref
+    xref = to_input_order(sysm, sysm.nl.x_ref)
+    onl, _ = orc.build_nlist(xref, box, w.rc + w.skin)
+    rows = sysm.nl.rows().cpu().numpy()
+    cnt = np.minimum(sysm.nl.numneigh.cpu().numpy(), sysm.nl.capacity)
+    i = np.repeat(np.arange(n), cnt)
+    mask = np.arange(sysm.nl.capacity)[None, :] < cnt[:, None]
+    j = rows[mask].astype(np.int64)
+    got = np.stack([ids[i], ids[j]], axis=1)
+    got = got[np.lexsort((got[:, 1], got[:, 0]))]
+    assert np.array_equal(got, onl.pairs())
+    # forces at the final positions
+    gx, _, gf = sysm.host_state()
+    onl2, oc = orc.build_nlist(gx, box, w.rc + w.skin)
+    ref = orc.lj_forces(oc.x, box, onl2, w.rc, shift=1)
+    err = rel(gf, ref.f)
+    print(f"[fullsize] mixed force rel-RMS {err:.3e}")
+    assert err < 1e-6
+    mag = MB.lj_magnitudes(oc.x, box, onl2, w.rc, 1.0, 1.0)
+    MB.assert_vector(gf, ref.f, mag["f"], what="force")
+
+
+def test_fullsize_buckingham_forces(orc):
+    """141k-ion rocksalt crystal (jittered), FP64 and MIXED forces, energy
+    and virial against the oracle over all ions."""
+    w = I.BUCK_141K
+    x, _, box = I.initial_state(w)
+    x = I.jitter(x, 0.08, 101)
+    print("[fullsize] buck_coul_141k forces", flush=True)
+    n = x.shape[1]
+    xd = torch.as_tensor(x, dtype=torch.float64, device="cuda")
+    mbox = md.make_box(box)
+    rl = w.rc + w.skin
+    import math
+    cells = md.Cells(n, int(np.prod([math.floor(L / rl) for L in box])))
+    ws = md.workspace(n, mbox, rl)
+    md.md_bin_cells(xd, mbox, rl, cells, ws)
+    types = torch.as_tensor(w.species(), dtype=torch.int32, device="cuda")
+    from paper_1009_4330_amd.system import potential_of
+    pot = potential_of(w, types)
+    nl = md.NList(n, 2100, 16)
+    md.md_build_neighbors(xd, mbox, cells, w.rc, w.skin, nl)
+    onl, oc = orc.build_nlist(x, box, rl)
+    A, rho, C = (I.pair_table(w, k) for k in ("buck_A", "buck_rho", "buck_C"))
+    q = np.array(list(w.charges) + [0.0, 0.0])
+    ref = orc.buck_forces(oc.x, box, onl, w.rc, w.species(), A, rho, C, q, w.qqr2e)
+    for prec in (md.MD_FP64, md.MD_MIXED):
+        f = torch.zeros(3, n, dtype=torch.float64, device="cuda")
+        ev = torch.zeros(7, dtype=torch.float64, device="cuda")
+        md.md_compute_forces(pot, xd, mbox, nl, prec, md.MD_KERNEL_AUTO,
+                             md.MD_EFLAG | md.MD_VFLAG, f, ev, ws)
+        f, ev = f.cpu().numpy(), ev.cpu().numpy()
+        if prec == md.MD_FP64:
+            assert rel(f, ref.f) < 1e-12
+            assert ev[0] == pytest.approx(ref.energy, rel=1e-12)
+            assert rel(ev[1:], ref.virial) < 1e-12
+        else:
+            print(f"[fullsize] buck mixed force rel-RMS {rel(f, ref.f):.3e}")
+            mag = MB.buck_magnitudes(oc.x, box, onl, w.rc, w.species(), A, rho, C, q, w.qqr2e)
+            MB.assert_vector(f, ref.f, mag["f"], what="force")
+            MB.assert_total(ev[0], ref.energy, mag["e"], what="energy")
+
+
+def test_fullsize_sutton_chen_step(orc):
+    """500k-atom Sutton-Chen solid, FP64, 10 fused steps against the oracle."""
+    w = I.SC_500K
+    x, v, box = I.initial_state(w)
+    print("[fullsize] sc_cu_500k fp64 10 steps", flush=True)
+    sysm = MDSystem(w, x, v, "fp64", "auto")
+    rows = np.concatenate([sysm.setup(True), sysm.run(10, 5)])
+    ref = orc.md_run(orc.params_for(w), x, v, box, 10, 5)
+    for c in (1, 2, 3, 4, 5):
+        assert rel(rows[:, c], ref.thermo[:, c]) < 1e-10, c
+    gx, gv, gf = sysm.host_state()
+    assert np.abs(min_image_diff(gx, ref.x, box)).max() < 1e-9
+    assert rel(gf, ref.f) < 1e-9
