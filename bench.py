@@ -431,8 +431,10 @@ def suite(steps: int):
     emit({"item": "oracle_one_thread", **oracle_one_thread(w, x, v)})
 
 
-def one_workload(name: str, kernel: str, steps: int, warmup: int):
-    """Time one named workload in FP64 and FP32-mixed; one JSON line each."""
+def one_workload(name: str, kernel: str, steps: int, warmup: int, nvt: bool = False):
+    """Time one named workload in FP64 and FP32-mixed; one JSON line each.
+    With nvt, under a Nose-Hoover chain of 3 at the workload's temperature
+    with a period of 100 time steps."""
     from paper_1009_4330_amd import inputs as I
 
     if name not in I.WORKLOADS:
@@ -442,8 +444,10 @@ def one_workload(name: str, kernel: str, steps: int, warmup: int):
     x, v, _ = I.initial_state(w)
     for prec in ("fp64", "mixed"):
         log(f"[bench] {w.name}: {w.natoms} atoms, {prec}, kernel {kernel}")
-        r = run_md(w, x, v, prec, kernel, steps, warmup)
+        r = run_md(w, x, v, prec, kernel, steps, warmup,
+                   nvt=(w.temp, 100 * w.dt, 3) if nvt else None)
         print(json.dumps({"item": "workload", "workload": w.name, "precision": prec,
+                          "ensemble": "nvt" if nvt else "nve",
                           "kernel": kernel, "lanes_per_atom": r["kernel"],
                           "atom_steps_per_s": steps * w.natoms / r["elapsed"],
                           "ms_per_step": 1e3 * r["elapsed"] / steps,
@@ -466,6 +470,8 @@ def main():
     ap.add_argument("--workload", default="",
                     help="time one other workload by name (e.g. buck_coul_141k, sc_cu_500k) in "
                          "both precisions with --kernel; one JSON line per precision")
+    ap.add_argument("--nvt", action="store_true",
+                    help="with --workload: run under the Nose-Hoover chain thermostat")
     ap.add_argument("--suite", action="store_true",
                     help="the other configurations (rc 5.0 LJ, Sutton-Chen, Buckingham + Coulomb, "
                          "the force-matching fit, a size sweep, copy peak, one-thread oracle); "
@@ -479,7 +485,7 @@ def main():
         return
     if args.workload:
         one_workload(args.workload, args.kernel, args.steps if args.steps != 1000 else 200,
-                     args.warmup)
+                     args.warmup, args.nvt)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
