@@ -793,7 +793,7 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
   const double volume = box->L[0] * box->L[1] * box->L[2];
   int row = 0;
   const int row_cols = nhc ? 9 : 8;
-  auto sums_out = [&]() -> md_status {
+  auto sums_out = [&](const NhcArgs* h) -> md_status {
     SumArgs sa{};
     sa.cols = 8;
     sa.col[0] = eatom;
@@ -802,7 +802,7 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
     sa.n = n;
     sa.partials = at<double>(ws, L.partials);
     sa.out = sums;
-    MD_CK(launch_sum(sa, s));
+    MD_CK(launch_sum(sa, s, h));
     return MD_OK;
   };
   auto row_out = [&](double stepno) -> md_status {
@@ -821,7 +821,7 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
     return MD_OK;
   };
   auto thermo_out = [&](double stepno) -> md_status {
-    md_status r = sums_out();
+    md_status r = sums_out(nullptr);
     return r != MD_OK ? r : row_out(stepno);
   };
   // Nose-Hoover chain constants and the kinetic-energy-only sum (into
@@ -878,11 +878,8 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
     if ((st = forces(ev, kernel, xqs[0], nullptr)) != MD_OK) return st;
     if (ev) {
       MD_CK(launch_ke(stt->v, n, keatom, s));
-      if ((st = sums_out()) != MD_OK) return st;
-      if (nhc) {   // the chain energy of the state as given
-        NhcArgs e = na;
-        MD_CK(launch_nhc(e, s));
-      }
+      // with a thermostat, also the chain energy of the state as given
+      if ((st = sums_out(nhc ? &na : nullptr)) != MD_OK) return st;
       if ((st = row_out(0.0)) != MD_OK) return st;
     }
   }
@@ -911,12 +908,11 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
     MD_CK(launch_fill_int(gates[0], 1, 0, s));
     MD_CK(launch_fill_int(gates[1], 1, 0, s));
     MD_CK(launch_ke(stt->v, n, keatom, s));
-    MD_CK(launch_sum(ka, s));
     {
       NhcArgs a = na;
       a.vsum = sums + 8;
       a.start = 1;
-      MD_CK(launch_nhc(a, s));
+      MD_CK(launch_sum(ka, s, &a));
     }
     MD_CK(launch_kick_drift_check(stt->x, stt->v, stt->f, nl->x_ref, n, dtfm, dt, trig2, status,
                                   bin, nhc_scale, s));
@@ -937,17 +933,18 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
       in.trig2 = trig2;
       in.bin = bin;
       if ((st = forces(th, kernel, cur, &in)) != MD_OK) return st;
-      if (th) {
-        if ((st = sums_out()) != MD_OK) return st;
-      } else {
-        MD_CK(launch_sum(ka, s));
-      }
+      // kinetic-energy sum (all thermo columns on thermo steps), then the
+      // chain update in the sum's last kernel
       NhcArgs a = na;
       a.vsum = th ? sums + 7 : sums + 8;
       a.vsum_out = th ? sums + 7 : nullptr;
       a.end = 1;
       a.start = step < nsteps;
-      MD_CK(launch_nhc(a, s));
+      if (th) {
+        if ((st = sums_out(&a)) != MD_OK) return st;
+      } else {
+        MD_CK(launch_sum(ka, s, &a));
+      }
       if (th && (st = row_out((double)step)) != MD_OK) return st;
       if (step < nsteps) {
         bin.xq = xqs[(step + 1) & 1];

@@ -46,36 +46,45 @@ __global__ __launch_bounds__(kBlock) void k_scale_v(double* __restrict__ v, int 
 // advanced, chain velocities updated back up.  Thermostat forces:
 // G_1 = (ke2 - nf kT) / Q_1, G_j = (Q_{j-1} w_{j-1}^2 - kT) / Q_j.  Each
 // velocity update: w_j <- w_j c^2 + (dt/4) G_j c with c = exp(-(dt/8) w_{j+1})
-// (no factor for the last thermostat).  Returns the scale factor and
+// (no factor for the last thermostat).  The chain lives in registers (loops
+// over the fixed maximum length, guarded by M).  Returns the scale factor and
 // leaves ke2 scaled.
-__device__ double nhc_half_step(const NhcArgs& a, double* eta, double* w, double& ke2) {
+__device__ double nhc_half_step(const NhcArgs& a, double (&eta)[MD_NHC_MAX],
+                                double (&w)[MD_NHC_MAX], double& ke2) {
   const int M = a.M;
   const double h4 = 0.25 * a.dt, h8 = 0.125 * a.dt;
-  auto mass = [&](int j) { return j == 0 ? a.Q0 : a.Qj; };
-  auto force = [&](int j) {
-    return j == 0 ? (ke2 - a.nf * a.kT) / a.Q0
-                  : (mass(j - 1) * w[j - 1] * w[j - 1] - a.kT) / mass(j);
-  };
   auto update = [&](int j) {
+    const double G = j == 0 ? (ke2 - a.nf * a.kT) / a.Q0
+                            : ((j == 1 ? a.Q0 : a.Qj) * w[j - 1] * w[j - 1] - a.kT) / a.Qj;
     if (j == M - 1) {
-      w[j] = w[j] + h4 * force(j);
+      w[j] = w[j] + h4 * G;
     } else {
-      const double c = exp(-h8 * w[j + 1]);
-      w[j] = w[j] * c * c + h4 * force(j) * c;
+      const double c = exp(-h8 * w[j + 1 < MD_NHC_MAX ? j + 1 : j]);
+      w[j] = w[j] * c * c + h4 * G * c;
     }
   };
-  for (int j = M - 1; j >= 0; --j) update(j);
+#pragma unroll
+  for (int j = MD_NHC_MAX - 1; j >= 0; --j)
+    if (j < M) update(j);
   const double sc = exp(-0.5 * a.dt * w[0]);
   ke2 = ke2 * sc * sc;
-  for (int j = 0; j < M; ++j) eta[j] = eta[j] + 0.5 * a.dt * w[j];
-  for (int j = 0; j < M; ++j) update(j);
+#pragma unroll
+  for (int j = 0; j < MD_NHC_MAX; ++j)
+    if (j < M) eta[j] = eta[j] + 0.5 * a.dt * w[j];
+#pragma unroll
+  for (int j = 0; j < MD_NHC_MAX; ++j)
+    if (j < M) update(j);
   return sc;
 }
 
-__global__ void k_nhc(NhcArgs a) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double* eta = a.state;
-  double* w = a.state + MD_NHC_MAX;
+// The chain update of one step (see NhcArgs), by one thread.
+__device__ void nhc_update(const NhcArgs& a) {
+  double eta[MD_NHC_MAX], w[MD_NHC_MAX];
+#pragma unroll
+  for (int j = 0; j < MD_NHC_MAX; ++j) {
+    eta[j] = a.state[j];
+    w[j] = a.state[MD_NHC_MAX + j];
+  }
   double ke2 = a.vsum ? a.mke * *a.vsum : a.state[kNhcKe2];
   double sc = 1.0;
   if (a.end) {
@@ -84,12 +93,25 @@ __global__ void k_nhc(NhcArgs a) {
     sc = f;
   }
   double e = a.nf * a.kT * eta[0];
-  for (int j = 0; j < a.M; ++j) e += 0.5 * (j == 0 ? a.Q0 : a.Qj) * w[j] * w[j];
-  for (int j = 1; j < a.M; ++j) e += a.kT * eta[j];
-  a.state[kNhcEnergy] = e;
+#pragma unroll
+  for (int j = 0; j < MD_NHC_MAX; ++j)
+    if (j < a.M) e += 0.5 * (j == 0 ? a.Q0 : a.Qj) * w[j] * w[j];
+#pragma unroll
+  for (int j = 1; j < MD_NHC_MAX; ++j)
+    if (j < a.M) e += a.kT * eta[j];
   if (a.start) sc = sc * nhc_half_step(a, eta, w, ke2);
+#pragma unroll
+  for (int j = 0; j < MD_NHC_MAX; ++j) {
+    a.state[j] = eta[j];
+    a.state[MD_NHC_MAX + j] = w[j];
+  }
+  a.state[kNhcEnergy] = e;
   a.state[kNhcScale] = sc;
   a.state[kNhcKe2] = ke2;
+}
+
+__global__ void k_nhc(NhcArgs a) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) nhc_update(a);
 }
 
 __global__ __launch_bounds__(kBlock) void k_ke(const double* __restrict__ v, int n,
@@ -129,13 +151,16 @@ __global__ __launch_bounds__(kBlock) void k_sum_stage1(SumArgs a) {
   }
 }
 
-// Stage 2: one block sums the kReduceBlocks partials of each column.
-__global__ __launch_bounds__(kReduceBlocks) void k_sum_stage2(SumArgs a) {
+// Stage 2: one block sums the kReduceBlocks partials of each column; with
+// NHC, thread 0 then runs the thermostat chain update on the sums it wrote.
+template <bool NHC>
+__global__ __launch_bounds__(kReduceBlocks) void k_sum_stage2(SumArgs a, NhcArgs h) {
   __shared__ double sh[kReduceBlocks];
   for (int c = 0; c < a.cols; ++c) {
     const double s = block_sum(a.partials[threadIdx.x * kReduceCols + c], sh);
     if (threadIdx.x == 0) a.out[c] = s;
   }
+  if (NHC && threadIdx.x == 0) nhc_update(h);
 }
 
 __global__ void k_thermo_row(ThermoArgs a) {
@@ -199,11 +224,14 @@ hipError_t launch_ke(const double* v, int n, double* keatom, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_sum(const SumArgs& a, hipStream_t s) {
+hipError_t launch_sum(const SumArgs& a, hipStream_t s, const NhcArgs* nhc) {
   k_sum_stage1<<<kReduceBlocks, kBlock, 0, s>>>(a);
   hipError_t st = hipGetLastError();
   if (st != hipSuccess) return st;
-  k_sum_stage2<<<1, kReduceBlocks, 0, s>>>(a);
+  if (nhc)
+    k_sum_stage2<true><<<1, kReduceBlocks, 0, s>>>(a, *nhc);
+  else
+    k_sum_stage2<false><<<1, kReduceBlocks, 0, s>>>(a, NhcArgs{});
   return hipGetLastError();
 }
 

@@ -350,7 +350,10 @@ struct SumArgs {
   double* partials;
   double* out;
 };
-hipError_t launch_sum(const SumArgs& a, hipStream_t s);
+struct NhcArgs;
+// With nhc, the thermostat chain update (launch_nhc) runs at the end of the
+// sum's last stage, on the sums it wrote.
+hipError_t launch_sum(const SumArgs& a, hipStream_t s, const NhcArgs* nhc = nullptr);
 // Thermo row from out = {pe, W0..W5, sv} sums.
 struct ThermoArgs {
   const double* sums;  // pe, w0..w5, sum v^2
