@@ -11,16 +11,20 @@
  * objectives, features and usage"); precision modes follow the same section
  * (double, and mixed: pair forces in single precision, integration in double).
  * Kernel choice follows the TpA / BpA discussion and the built-in
- * mini-benchmark of section "Neighbor list approach".
+ * mini-benchmark of section "Neighbor list approach".  Beyond that path the
+ * library has the Buckingham + cut Coulomb potential of the silicate system
+ * (Appendix A), the force adjoints (LJ and Sutton-Chen) for force matching,
+ * NVT integration with a Nose-Hoover chain, and half lists with Newton's
+ * third law for forces.
  *
  * Conventions
  *  - Every pointer is a DEVICE pointer unless marked [host].  The caller owns
  *    every buffer; no call allocates or frees device memory, and no call
- *    synchronises except md_step (once, at its end), md_nlist_status and
- *    md_autoselect.  Work is enqueued on `stream` (a hipStream_t; NULL is the
+ *    synchronises except md_step and md_step_nvt (once, at their end),
+ *    md_nlist_status and md_autoselect.  Work is enqueued on `stream` (a hipStream_t; NULL is the
  *    default stream).
  *  - Per-atom vectors are SoA FP64 [3][n]: n x values, then n y, then n z.
-  - n (atoms) is at most MD_MAX_ATOMS; larger n returns MD_ERR_INVALID_ARG.
+ *  - n (atoms) is at most MD_MAX_ATOMS; larger n returns MD_ERR_INVALID_ARG.
  *  - The box is orthorhombic, periodic, with origin 0 and edges L[0..2].
  *  - Errors are returned; nothing is thrown across the ABI.  Host-detectable
  *    errors return before anything is enqueued.  Device-detected errors
