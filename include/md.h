@@ -184,7 +184,8 @@ md_status md_bin_cells(double* x, int64_t n, const md_box* box, double rl,
 /* Reorder atoms into cell order (slot k takes atom cells->perm[k]): x, v, id
    and, when not NULL, f and x_ref are gathered through perm.  Makes neighbour
    gathers spatially local (the paper assumes spatially ordered atoms for its
-   cached neighbour reads). */
+   cached neighbour reads).  Per-atom data outside md_state (Buckingham
+   species) is the caller's to gather through cells->perm. */
 md_status md_sort_atoms(md_state* st, const md_cells* cells, double* x_ref, void* ws,
                         size_t ws_bytes, void* stream);
 
