@@ -152,6 +152,7 @@ struct Lane {
 struct Batch {
   int j[kUnroll];
   int t[kUnroll];   // species of j (TYPED batches only)
+  double w3[kUnroll];   // fourth word of j's record (FOURTH batches only)
   bool ok[kUnroll];
   double dx[kUnroll], dy[kUnroll], dz[kUnroll], s[kUnroll];
 };
@@ -167,7 +168,7 @@ struct XView {
 // record and the second half of its partner's, and a three-word lane swap
 // completes every lane's record.  Otherwise each lane reads (x, y) and z of
 // its own record with a 16- and an 8-byte load.
-template <int K, bool WRAP, bool PAIRED, bool TYPED = false>
+template <int K, bool WRAP, bool PAIRED, bool TYPED = false, bool FOURTH = false>
 __device__ inline void load_batch(const FK& a, const XView& xv, const Lane<K>& ln, int t,
                                   int* jn, double xi, double yi, double zi, Batch& b) {
   double xj[kUnroll], yj[kUnroll], zj[kUnroll];
@@ -192,15 +193,16 @@ __device__ inline void load_batch(const FK& a, const XView& xv, const Lane<K>& l
       xj[u] = __builtin_bit_cast(double, make_uint2(own.x, own.y));
       yj[u] = __builtin_bit_cast(double, make_uint2(own.z, r0));
       zj[u] = __builtin_bit_cast(double, make_uint2(r1, r2));
-    } else if (TYPED) {
-      // (x, y) and (z, species) of the record
+    } else if (TYPED || FOURTH) {
+      // (x, y) and (z, fourth word) of the record
       const unsigned off = (unsigned)b.j[u] * 32u;
       const f64x2 xy = load16(xv.r, off);
       const f64x2 zt = load16(xv.r, off + 16u);
       xj[u] = xy.x;
       yj[u] = xy.y;
       zj[u] = zt.x;
-      b.t[u] = (int)zt.y & 3;   // species 0..3 (the mask keeps table reads in bounds)
+      if (TYPED) b.t[u] = (int)zt.y & 3;   // species 0..3 (the mask keeps table reads in bounds)
+      if (FOURTH) b.w3[u] = zt.y;
     } else {
       const unsigned off = (unsigned)b.j[u] * 32u;
       const f64x2 xy = load16(xv.r, off);
@@ -232,7 +234,7 @@ __device__ inline XView xview(const FK& a) { return XView{buffer_of(a.xq, a.n)};
 // Runs body(batch) over the wavefront's list entries (a uniform loop to the
 // largest count).  The choice between the plain and the minimum-image
 // separation is uniform over the wavefront.
-template <int K, bool PAIRED, bool TYPED = false, typename F>
+template <int K, bool PAIRED, bool TYPED = false, bool FOURTH = false, typename F>
 __device__ inline void for_each_batch(const FK& a, const Lane<K>& ln, double xi, double yi,
                                       double zi, F&& body) {
   const XView xv = xview(a);
@@ -242,13 +244,13 @@ __device__ inline void for_each_batch(const FK& a, const Lane<K>& ln, double xi,
   if (__all(interior(xi, yi, zi, a))) {
     for (int t = 0; t < ln.tmax; t += kUnroll) {
       Batch b;
-      load_batch<K, false, PAIRED, TYPED>(a, xv, ln, t, jn, xi, yi, zi, b);
+      load_batch<K, false, PAIRED, TYPED, FOURTH>(a, xv, ln, t, jn, xi, yi, zi, b);
       body(b);
     }
   } else {
     for (int t = 0; t < ln.tmax; t += kUnroll) {
       Batch b;
-      load_batch<K, true, PAIRED, TYPED>(a, xv, ln, t, jn, xi, yi, zi, b);
+      load_batch<K, true, PAIRED, TYPED, FOURTH>(a, xv, ln, t, jn, xi, yi, zi, b);
       body(b);
     }
   }
@@ -546,9 +548,13 @@ __device__ inline T half_power(T t, int k) {
 }
 
 // Pass 1: rho_i = sum_j (a^2/s)^(m/2); stores e_i = rho_i^(-1/2) (0 if rho_i = 0)
-// and, with EV, the embedding energy -eps c sqrt(rho_i).
+// in e_out and in the fourth word of atom i's packed record (xq_w: the same
+// buffer as a.xq, of which this pass reads only the first three words), where
+// pass 2 finds it with the neighbour's position; with EV, also the embedding
+// energy -eps c sqrt(rho_i).
 template <int PREC, bool EV, int K>
-__global__ __launch_bounds__(kBlock) void k_sc_density(FK a, SCK p, double* __restrict__ e_out) {
+__global__ __launch_bounds__(kBlock) void k_sc_density(FK a, SCK p, double* __restrict__ e_out,
+                                                        double* xq_w) {
   const Lane<K> ln(a);
   const int n = a.n;
   const int io = ln.live ? ln.i : n - 1;
@@ -568,7 +574,9 @@ __global__ __launch_bounds__(kBlock) void k_sc_density(FK a, SCK p, double* __re
   });
   if (K > 1) rho = group_sum<K>(rho);
   if (!ln.live || ln.s != 0) return;
-  e_out[ln.i] = rho > 0.0 ? 1.0 / sqrt(rho) : 0.0;
+  const double ei = rho > 0.0 ? 1.0 / sqrt(rho) : 0.0;
+  e_out[ln.i] = ei;
+  xq_w[4 * (size_t)ln.i + 3] = ei;
   if (EV && a.eatom) a.eatom[ln.i] = -p.epsc * sqrt(rho);
 }
 
@@ -584,10 +592,9 @@ __global__ __launch_bounds__(kBlock) void k_sc_force(FK a, SCK p,
   home_pos(a, io, xi, yi, zi);
   const double ei = e_in[io];
   Acc acc;
-  for_each_batch<K, PREC == MD_MIXED>(a, ln, xi, yi, zi, [&](const Batch& b) {
-    double ej[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) ej[u] = e_in[b.j[u]];
+  // e_j comes with j's position: the fourth word of its record (pass 1)
+  for_each_batch<K, false, false, true>(a, ln, xi, yi, zi, [&](const Batch& b) {
+    const double* ej = b.w3;
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       if (b.ok[u] && b.s[u] < p.rc2) {
@@ -961,7 +968,7 @@ hipError_t launch_sc(const ForceArgs& a, const SCK& p, int prec, int lanes, doub
     auto force = [&](auto prec_c, auto ev_c) -> hipError_t {
       constexpr int P = decltype(prec_c)::value;
       constexpr bool E = decltype(ev_c)::value;
-      k_sc_density<P, E, K><<<g, kBlock, 0, s>>>(k, p, sc_e);
+      k_sc_density<P, E, K><<<g, kBlock, 0, s>>>(k, p, sc_e, const_cast<double*>(a.xq));
       return fused ? launch_timed(k_sc_force<P, E, K, true>, g, s, a.t0, a.t1, k, p, e)
                    : launch_timed(k_sc_force<P, E, K, false>, g, s, a.t0, a.t1, k, p, e);
     };
@@ -995,7 +1002,7 @@ hipError_t launch_sc_vjp(const ForceArgs& a, const SCK& p, int prec, int lanes, 
     const unsigned g = grid_for(a.n, K);
     auto run = [&](auto prec_c) -> hipError_t {
       constexpr int P = decltype(prec_c)::value;
-      k_sc_density<P, false, K><<<g, kBlock, 0, s>>>(k, p, e);
+      k_sc_density<P, false, K><<<g, kBlock, 0, s>>>(k, p, e, const_cast<double*>(a.xq));
       k_sc_vjp_rho<P, K><<<g, kBlock, 0, s>>>(k, p, u, e, lam, la, lb);
       return launch_timed(k_sc_vjp_x<P, K>, g, s, a.t0, a.t1, k, p, u,
                           static_cast<const double*>(e), static_cast<const double*>(lam), gx);
