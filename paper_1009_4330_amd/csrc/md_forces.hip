@@ -794,14 +794,15 @@ __global__ __launch_bounds__(kBlock) void k_sc_vjp_x(FK a, SCK p, const double* 
   const double ei = e[io], li = lam[io];
   const double hn = 0.5 * p.n + 1.0, hm = 0.5 * p.m + 1.0, mh = 0.5 * p.m;
   double gxa = 0.0, gya = 0.0, gza = 0.0;
-  for_each_batch<K, PREC == MD_MIXED>(a, ln, xi, yi, zi, [&](const Batch& b) {
-    double ux[kUnroll], uy[kUnroll], uz[kUnroll], ej[kUnroll], lj[kUnroll];
+  // e_j comes with j's position (the density pass stored it in the record)
+  for_each_batch<K, false, false, true>(a, ln, xi, yi, zi, [&](const Batch& b) {
+    double ux[kUnroll], uy[kUnroll], uz[kUnroll], lj[kUnroll];
+    const double* ej = b.w3;
 #pragma unroll
     for (int q = 0; q < kUnroll; ++q) {
       ux[q] = u[b.j[q]];
       uy[q] = u[n + b.j[q]];
       uz[q] = u[2 * n + b.j[q]];
-      ej[q] = e[b.j[q]];
       lj[q] = lam[b.j[q]];
     }
 #pragma unroll
