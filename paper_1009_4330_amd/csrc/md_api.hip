@@ -586,7 +586,8 @@ md_status md_force_vjp(const md_potential* p, const double* x, int64_t n, const 
     double* la = at<double>(ws, L.eatom);
     double* lb = at<double>(ws, L.keatom);
     const SCK k = make_sc(p);
-    MD_CK(launch_sc_vjp(fa, k, prec, nl->layout, u, e, lam, la, lb, gx, s));
+    MD_CK(launch_sc_vjp(fa, k, prec, nl->layout, u, e, lam, la, lb, at<double>(ws, L.xq2), gx,
+                        s));
     if (gparam) {
       SumArgs sa{};
       sa.cols = 2;

@@ -231,6 +231,19 @@ __device__ inline void load_batch(const FK& a, const XView& xv, const Lane<K>& l
 
 __device__ inline XView xview(const FK& a) { return XView{buffer_of(a.xq, a.n)}; }
 
+// A packed [n][4] record of per-atom cotangent data (u_j and one more word),
+// gathered like the position records: two 16-byte loads.
+__device__ inline void load_rec(__amdgpu_buffer_rsrc_t r, int j, double& w0, double& w1,
+                                double& w2, double& w3) {
+  const unsigned off = (unsigned)j * 32u;
+  const f64x2 a = load16(r, off);
+  const f64x2 b = load16(r, off + 16u);
+  w0 = a.x;
+  w1 = a.y;
+  w2 = b.x;
+  w3 = b.y;
+}
+
 // Runs body(batch) over the wavefront's list entries (a uniform loop to the
 // largest count).  The choice between the plain and the minimum-image
 // separation is uniform over the wavefront.
@@ -738,7 +751,8 @@ __global__ __launch_bounds__(kBlock) void k_sc_vjp_rho(FK a, SCK p, const double
                                                         const double* __restrict__ e,
                                                         double* __restrict__ lam,
                                                         double* __restrict__ la,
-                                                        double* __restrict__ lb) {
+                                                        double* __restrict__ lb,
+                                                        double* __restrict__ uq) {
   const Lane<K> ln(a);
   const int n = a.n;
   const int io = ln.live ? ln.i : n - 1;
@@ -772,9 +786,14 @@ __global__ __launch_bounds__(kBlock) void k_sc_vjp_rho(FK a, SCK p, const double
   if (!ln.live || ln.s != 0) return;
   const int i = ln.i;
   const double ei = e[i];
-  lam[i] = -0.5 * ei * ei * ei * (p.c * gc);
+  const double li = -0.5 * ei * ei * ei * (p.c * gc);
+  lam[i] = li;
   la[i] = lai;
   lb[i] = ei * gc;
+  // (u_i, lam_i) packed for the position pass's neighbour gathers
+  double2* rec = reinterpret_cast<double2*>(uq + 4 * (size_t)i);
+  rec[0] = make_double2(uxi, uyi);
+  rec[1] = make_double2(uzi, li);
 }
 
 // Pass 3: dL/dx_i = sum_j [h (u_i - u_j) + 2 h' w d + 2 (lam_i + lam_j) psi' d],
@@ -784,6 +803,7 @@ template <int PREC, int K>
 __global__ __launch_bounds__(kBlock) void k_sc_vjp_x(FK a, SCK p, const double* __restrict__ u,
                                                       const double* __restrict__ e,
                                                       const double* __restrict__ lam,
+                                                      const double* __restrict__ uq,
                                                       double* __restrict__ gx) {
   const Lane<K> ln(a);
   const int n = a.n;
@@ -794,17 +814,14 @@ __global__ __launch_bounds__(kBlock) void k_sc_vjp_x(FK a, SCK p, const double* 
   const double ei = e[io], li = lam[io];
   const double hn = 0.5 * p.n + 1.0, hm = 0.5 * p.m + 1.0, mh = 0.5 * p.m;
   double gxa = 0.0, gya = 0.0, gza = 0.0;
-  // e_j comes with j's position (the density pass stored it in the record)
+  const __amdgpu_buffer_rsrc_t ur = buffer_of(uq, n);
+  // e_j comes with j's position (the density pass stored it in the record),
+  // u_j and lam_j with the record the previous pass packed
   for_each_batch<K, false, false, true>(a, ln, xi, yi, zi, [&](const Batch& b) {
     double ux[kUnroll], uy[kUnroll], uz[kUnroll], lj[kUnroll];
     const double* ej = b.w3;
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) {
-      ux[q] = u[b.j[q]];
-      uy[q] = u[n + b.j[q]];
-      uz[q] = u[2 * n + b.j[q]];
-      lj[q] = lam[b.j[q]];
-    }
+    for (int q = 0; q < kUnroll; ++q) load_rec(ur, b.j[q], ux[q], uy[q], uz[q], lj[q]);
 #pragma unroll
     for (int q = 0; q < kUnroll; ++q) {
       if (!(b.ok[q] && b.s[q] < p.rc2)) continue;
@@ -891,6 +908,10 @@ hipError_t with_lanes(int k, F&& f) {
 }
 
 }  // namespace
+
+hipError_t launch_pack_positions(const double* x, int n, double* xq, const int* type,
+                                 hipStream_t s);
+
 
 hipError_t launch_pack_positions(const double* x, int n, double* xq, const int* type,
                                  hipStream_t s) {
@@ -995,7 +1016,7 @@ hipError_t launch_lj_vjp(const ForceArgs& a, const LJK& p, int prec, int lanes,
 }
 
 hipError_t launch_sc_vjp(const ForceArgs& a, const SCK& p, int prec, int lanes, const double* u,
-                         double* e, double* lam, double* la, double* lb, double* gx,
+                         double* e, double* lam, double* la, double* lb, double* uq, double* gx,
                          hipStream_t s) {
   const FK k = make_fk(a);
   return with_lanes(lanes, [&](auto kc) -> hipError_t {
@@ -1004,9 +1025,10 @@ hipError_t launch_sc_vjp(const ForceArgs& a, const SCK& p, int prec, int lanes, 
     auto run = [&](auto prec_c) -> hipError_t {
       constexpr int P = decltype(prec_c)::value;
       k_sc_density<P, false, K><<<g, kBlock, 0, s>>>(k, p, e, const_cast<double*>(a.xq));
-      k_sc_vjp_rho<P, K><<<g, kBlock, 0, s>>>(k, p, u, e, lam, la, lb);
+      k_sc_vjp_rho<P, K><<<g, kBlock, 0, s>>>(k, p, u, e, lam, la, lb, uq);
       return launch_timed(k_sc_vjp_x<P, K>, g, s, a.t0, a.t1, k, p, u,
-                          static_cast<const double*>(e), static_cast<const double*>(lam), gx);
+                          static_cast<const double*>(e), static_cast<const double*>(lam),
+                          static_cast<const double*>(uq), gx);
     };
     if (prec == MD_FP64) return run(std::integral_constant<int, MD_FP64>());
     return run(std::integral_constant<int, MD_MIXED>());

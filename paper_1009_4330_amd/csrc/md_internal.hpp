@@ -313,7 +313,7 @@ hipError_t launch_fill_double(double* p, int64_t count, double value, hipStream_
 hipError_t launch_lj(const ForceArgs& a, const LJK& p, int prec, int kernel, hipStream_t s);
 hipError_t launch_sc(const ForceArgs& a, const SCK& p, int prec, int kernel, double* sc_e,
                      hipStream_t s);
-hipError_t launch_lj_vjp(const ForceArgs& a, const LJK& p, int prec, int kernel,
+hipError_t launch_lj_vjp(const ForceArgs& a, const LJK& p, int prec, int lanes,
                          const double* u, double* gx, double* pe, double* ps, hipStream_t s);
 
 // Integration.
@@ -366,9 +366,10 @@ hipError_t launch_thermo_row(const ThermoArgs& a, hipStream_t s);
 // gparam[0] = sums[0] / eps, gparam[1] = sums[1].
 hipError_t launch_vjp_params(const double* sums, double eps, double* gparam, hipStream_t s);
 // Sutton-Chen adjoint: density pass into e, then the pass for lam (dL/drho),
-// la and lb (per-atom parameter sums), then the position pass into gx.
+// la and lb (per-atom parameter sums) and the packed (u_i, lam_i) records uq
+// ([n][4] scratch), then the position pass into gx.
 hipError_t launch_sc_vjp(const ForceArgs& a, const SCK& p, int prec, int lanes, const double* u,
-                         double* e, double* lam, double* la, double* lb, double* gx,
+                         double* e, double* lam, double* la, double* lb, double* uq, double* gx,
                          hipStream_t s);
 // gparam = (dL/deps, dL/da, dL/dc) from sums = (LA, LB per unit c).
 hipError_t launch_sc_vjp_params(const double* sums, const SCK& p, double a, double* gparam,
