@@ -156,3 +156,40 @@ def test_velocities_seeded_zero_momentum_exact_temperature():
     vm = I.gaussian_velocities(500, 600.0, 63.55, I.METAL_UNITS, 5)
     tm = 63.55 * I.METAL_MVV2E * np.sum(vm * vm) / ((3 * 500 - 3) * I.METAL_BOLTZ)
     assert tm == pytest.approx(600.0, rel=1e-14)
+
+
+def test_binding_structs_match_the_header(mdlib, tmp_path):
+    """Every ctypes structure of the Python binding has the size and field
+    offsets the C compiler gives the header's struct (compiled here with gcc),
+    and the binding's constants equal the header's."""
+    structs = {"md_box": mdlib.md_box, "md_potential": mdlib.md_potential,
+               "md_cells": mdlib.md_cells, "md_nlist": mdlib.md_nlist,
+               "md_state": mdlib.md_state, "md_nhc": mdlib.md_nhc}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "md.h"', 'int main(void) {']
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    for const in ("MD_NHC_MAX", "MD_NHC_STATE", "MD_MAX_ATOMS", "MD_STATUS_WORDS",
+                  "MD_POT_BUCK", "MD_LAYOUT_WPA"):
+        lines.append(f'  printf("const {const} %lld\\n", (long long){const});')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o",
+                           str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    got = {}
+    for line in out:
+        if line:
+            a, b, c = line.split()
+            got[(a, b)] = int(c)
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)
+    for const in ("MD_NHC_MAX", "MD_NHC_STATE", "MD_MAX_ATOMS", "MD_STATUS_WORDS",
+                  "MD_POT_BUCK", "MD_LAYOUT_WPA"):
+        assert got[("const", const)] == getattr(mdlib, const), const
