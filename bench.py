@@ -1,18 +1,24 @@
 """Throughput of the MD hot path on one MI355X.
 
 Headline: atom-timesteps/s of the 256,000-atom LJ melt (fcc 40^3 at reduced
-density 0.8442, rc 2.5, skin 0.3, T* 3.0, dt 0.005) in FP32-mixed precision
-with the force kernel the setup mini-benchmark picks (K lanes per atom); the
-plain FP64 path and the thread-per-atom kernel (K = 1) on the same workload,
-and the LJ adjoint (force VJP) throughput in atoms/s on eight 32,000-atom
-snapshots thermalised for 500 NVE steps, are reported beside it.
+density 0.8442, rc 2.5, skin 0.3, T* 3.0, dt 0.005), 1,000 NVE steps (more if
+--steps asks for more, never fewer: the workload is defined as a 1,000-step
+run), in FP32-mixed precision with the force kernel the setup mini-benchmark
+picks (K lanes per atom).  The plain FP64 path and the thread-per-atom kernel
+(K = 1) on the same workload, and the LJ adjoint (force VJP) throughput in
+atoms/s on eight 32,000-atom snapshots thermalised for 500 NVE steps, are
+reported beside it; each of those extras is guarded so that its failure
+cannot suppress the headline line.
 
 Each "step" is one full velocity-Verlet step of md_step: the rebuild chain
 when the half-skin check fired (count, gather-sort, list), then the force
 kernel, which also does the closing kick, the next kick, drift and check;
-thermo output every 100 steps.  Inputs are resident in HBM before the timed
-region starts.  The roofline object describes that force kernel.  Prints one
-JSON line on stdout.
+thermo output every min(100, steps) steps.  Inputs are resident in HBM before
+the timed region starts.  The roofline object describes that force kernel
+(its duration from events recorded inside its own dispatches) and, as
+step_frac, the whole step.  The cpu_baseline leg times the oracle on the host
+cores and checks the final state's forces against it.  Prints one JSON line on
+stdout.
 """
 from __future__ import annotations
 
@@ -32,6 +38,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
 THERMO_EVERY = 100
+HEADLINE_STEPS = 1000          # the 256k melt is defined as a 1,000-step NVE run
 
 
 def log(*a):
@@ -40,11 +47,26 @@ def log(*a):
 
 def force_bytes_per_atom(mean_neigh: float) -> float:
     """Algorithmic HBM bytes per atom of md_step's force kernel, which also
-    integrates: numneigh (4) and the neighbour indices (4 per entry), the
-    atom's packed position record (32), velocity read and written (24 + 24),
-    x_ref (24), the drifted packed record (32) and the new cell (4).  The
-    neighbour positions are cache-served gathers (atoms are cell-sorted)."""
-    return 4.0 + 4.0 * mean_neigh + 32.0 + 48.0 + 24.0 + 32.0 + 4.0
+    integrates.  Force part: numneigh (4), the neighbour indices (4 per
+    entry), x_i (24) and f_i (24); the neighbour positions are cache-served
+    gathers (atoms are cell-sorted).  Fused integration (the closing kick of
+    one step with the kick, drift and check of the next): x, v, f and x_ref
+    read, x and v written, 144."""
+    return 4.0 + 4.0 * mean_neigh + 24.0 + 24.0 + 144.0
+
+
+def rebuild_bytes_per_atom(mean_neigh: float) -> float:
+    """Algorithmic bytes per atom of one rebuild: binning and the permutation
+    of the state (about 132), then the list build (x 24, the count 4, the
+    entries 4 per neighbour, x_ref 24)."""
+    return 132.0 + 24.0 + 4.0 + 4.0 * mean_neigh + 24.0
+
+
+def step_bytes_per_atom(mean_neigh: float, rebuilds: int, steps: int) -> float:
+    """Algorithmic bytes per atom-step of the whole fused step: the force
+    kernel with its integration plus the rebuilds amortised over the run."""
+    return force_bytes_per_atom(mean_neigh) + rebuild_bytes_per_atom(mean_neigh) * rebuilds / max(
+        steps, 1)
 
 
 def source_hash() -> str:
@@ -68,21 +90,22 @@ def measured_traffic(kernel_name: str, launches_bytes: float):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def run_md(w, x, v, prec, kernel, steps, warmup, nvt=None):
+def run_md(w, x, v, prec, kernel, steps, warmup, nvt=None, thermo_every=THERMO_EVERY):
     import torch
     from paper_1009_4330_amd import md
     from paper_1009_4330_amd.system import MDSystem
 
     sysm = MDSystem(w, x, v, prec, kernel, nvt=nvt)
     sysm.setup(thermo=False)
+    every = max(1, min(thermo_every, steps))
     if warmup:
-        sysm.run(warmup, THERMO_EVERY)
+        sysm.run(warmup, every)
     torch.cuda.synchronize()
     md.md_timing_enable(10)
     builds0 = md.md_nlist_status(sysm.nl)[md.MD_ST_BUILDS]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rows = sysm.run(steps, THERMO_EVERY)
+    rows = sysm.run(steps, every)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     launches, ms = md.md_timing_read()
@@ -92,32 +115,33 @@ def run_md(w, x, v, prec, kernel, steps, warmup, nvt=None):
     return dict(elapsed=elapsed, rows=rows, force_launches=launches,
                 force_ms_avg=ms / max(launches, 1), rebuilds=words[md.MD_ST_BUILDS] - builds0,
                 mean_neigh=nn, max_neigh=words[md.MD_ST_MAXNEIGH], n=w.natoms,
-                kernel=sysm.kernel, system=sysm)
+                kernel=sysm.kernel, system=sysm, thermo_every=every)
 
 
 def nve_drift(rows, n: int, dt: float):
     """Total-energy drift over the thermo rows of a timed run: largest
-    |E - E0| / |E0| and the least-squares slope of E/N per time unit."""
+    |E - E0| / |E0| and the least-squares slope of E/N per time unit.  None
+    below two rows (no drift is defined)."""
+    rows = np.asarray(rows, dtype=np.float64)
+    if rows.ndim != 2 or rows.shape[0] < 2:
+        return None
     e = rows[:, 3]
     t = rows[:, 0] * dt
-    slope = float(np.polyfit(t, e / n, 1)[0]) if len(e) > 1 else 0.0
+    slope = float(np.polyfit(t, e / n, 1)[0])
     return {"max_rel": float(np.max(np.abs(e - e[0])) / abs(e[0])), "slope_per_tau": slope,
-            "rows": int(len(e))}
+            "rows": int(len(e)), "first_step": int(rows[0, 0]), "last_step": int(rows[-1, 0])}
 
 
-def mixed_force_error(sysm) -> float:
-    """rel-RMS of the MIXED forces against the library's FP64 forces on the
-    final state of a run (same list)."""
+def gpu_forces(sysm, prec):
+    """Forces of the run's potential at the state's positions, through
+    md_compute_forces on the run's own list (no integration)."""
     import torch
     from paper_1009_4330_amd import md
-    out = {}
-    for prec in (md.MD_FP64, md.MD_MIXED):
-        f = torch.empty_like(sysm.state.f)
-        md.md_compute_forces(sysm.pot, sysm.state.x, sysm.box, sysm.nl, prec, sysm.nl.layout, 0, f,
-                             None, sysm.ws)
-        out[prec] = f
-    d = out[md.MD_MIXED] - out[md.MD_FP64]
-    return float(torch.sqrt((d * d).sum() / (out[md.MD_FP64] ** 2).sum()))
+    f = torch.empty_like(sysm.state.f)
+    md.md_compute_forces(sysm.pot, sysm.state.x, sysm.box, sysm.nl, prec, sysm.nl.layout, 0, f,
+                         None, sysm.ws)
+    torch.cuda.synchronize()
+    return f
 
 
 def host_info():
@@ -259,6 +283,28 @@ def cpu_baseline(w, x, v, target_s: float = 15.0):
                 kind="oracle",
                 sample=f"{steps} NVE steps of the {w.natoms}-atom LJ melt from the same seeded "
                        f"state (FP64, setup excluded, {t:.1f} s)")
+
+
+def oracle_force_check(sysm, w):
+    """Forces at the final state of the timed MIXED run: the GPU's MIXED and
+    FP64 forces (md_compute_forces on the run's list) against the oracle's
+    FP64 forces at the same positions (its own list; the pairs inside rc are
+    the same).  rel-RMS over all 3N components and the largest per-atom
+    error relative to the largest force."""
+    import oracle
+    from paper_1009_4330_amd import md
+    x = sysm.state.x.cpu().numpy()
+    onl, oc = oracle.build_nlist(x, w.box, w.rc + w.skin)
+    ref = oracle.lj_forces(oc.x, w.box, onl, w.rc, w.lj_eps, w.lj_sigma, w.lj_shift).f
+    out = {}
+    for name, prec in (("mixed", md.MD_MIXED), ("fp64", md.MD_FP64)):
+        f = gpu_forces(sysm, prec).cpu().numpy()
+        d = f - ref
+        out[f"{name}_force_rel_rms_vs_oracle"] = float(np.linalg.norm(d) / np.linalg.norm(ref))
+        out[f"{name}_force_max_atom_err_rel"] = float(
+            np.sqrt((d * d).sum(0)).max() / np.sqrt((ref * ref).sum(0)).max())
+    out["atoms"] = int(x.shape[1])
+    return out
 
 
 def profile_force(steps: int, kernel: str):
@@ -477,6 +523,10 @@ def main():
                          "the force-matching fit, a size sweep, copy peak, one-thread oracle); "
                          "JSON lines")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
     if args.profile_force:
         profile_force(args.profile_force, args.kernel)
         return
@@ -487,11 +537,23 @@ def main():
         one_workload(args.workload, args.kernel, args.steps if args.steps != 1000 else 200,
                      args.warmup, args.nvt)
         return
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
-              "multi-GPU path", file=sys.stderr)
-        sys.exit(2)
+    headline(args)
 
+
+def guarded(name: str, fn, *a, **kw):
+    """Run one extra measurement; a failure there is logged and reported as
+    an error string, never allowed to suppress the headline line."""
+    try:
+        return fn(*a, **kw)
+    except Exception as e:  # noqa: BLE001 -- any failure of an extra is reported, not raised
+        log(f"[bench] {name} failed: {type(e).__name__}: {e}")
+        return {"error": f"{type(e).__name__}: {e}"}
+
+
+def headline(args):
+    """The 256k LJ melt, 1,000 NVE steps (or more when --steps asks for more),
+    FP32-mixed; FP64 and thread-per-atom runs, the adjoint, the step-level
+    roofline and the oracle (timing and force check) beside it."""
     import torch
     from paper_1009_4330_amd import inputs as I
 
@@ -499,50 +561,37 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     w = I.LJ_256K
+    steps = max(args.steps, HEADLINE_STEPS)
     x, v, _ = I.initial_state(w)
-    log(f"[bench] {w.name}: {w.natoms} atoms, mixed precision, kernel {args.kernel}")
-    mixed = run_md(w, x, v, "mixed", args.kernel, args.steps, args.warmup)
-    value = args.steps * w.natoms / mixed["elapsed"]
+    log(f"[bench] {w.name}: {w.natoms} atoms, mixed precision, kernel {args.kernel}, "
+        f"{steps} timed steps after {args.warmup} warm-up steps")
+    mixed = run_md(w, x, v, "mixed", args.kernel, steps, args.warmup)
+    value = steps * w.natoms / mixed["elapsed"]
     lanes = mixed["kernel"]
     log(f"[bench] mixed K={lanes}: {value:.4g} atom-steps/s, "
-        f"{1e3 * mixed['elapsed'] / args.steps:.4f} ms/step, "
+        f"{1e3 * mixed['elapsed'] / steps:.4f} ms/step, "
         f"force avg {1e3 * mixed['force_ms_avg']:.2f} us, rebuilds {mixed['rebuilds']}")
-    extras = {}
-    if not args.no_extras:
-        fp64 = run_md(w, x, v, "fp64", args.kernel, args.steps, args.warmup)
-        v64 = args.steps * w.natoms / fp64["elapsed"]
-        log(f"[bench] fp64 K={fp64['kernel']}: {v64:.4g} atom-steps/s, "
-            f"force avg {1e3 * fp64['force_ms_avg']:.2f} us")
-        tpa = run_md(w, x, v, "mixed", "tpa", args.steps, args.warmup)
-        vt = args.steps * w.natoms / tpa["elapsed"]
-        log(f"[bench] mixed K=1 (thread per atom): {vt:.4g} atom-steps/s, "
-            f"force avg {1e3 * tpa['force_ms_avg']:.2f} us")
-        vjp = bench_vjp(reps=20)
-        log(f"[bench] vjp atoms/s: {vjp}")
-        extras = {"fp64_atom_timesteps_per_s": v64, "mixed_over_fp64": value / v64,
-                  "nve_drift_fp64": nve_drift(fp64["rows"], w.natoms, w.dt),
-                  "fp64_force_kernel_us": 1e3 * fp64["force_ms_avg"],
-                  "fp64_lanes_per_atom": fp64["kernel"],
-                  "mixed_tpa_atom_timesteps_per_s": vt,
-                  "mixed_tpa_force_kernel_us": 1e3 * tpa["force_ms_avg"],
-                  "adjoint_hvp_atoms_per_s": vjp["mixed"],
-                  "adjoint_hvp_atoms_per_s_fp64": vjp["fp64"]}
 
-    bpa = force_bytes_per_atom(mixed["mean_neigh"])
+    nn = mixed["mean_neigh"]
+    bpa = force_bytes_per_atom(nn)
     alg_bytes = bpa * w.natoms
     avg_s = mixed["force_ms_avg"] * 1e-3
     achieved = alg_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
     kname = f"k_lj<MIXED, no energy/virial, K={lanes}, fused step>"
     traffic = measured_traffic(kname, alg_bytes)
-    copy_gbs = copy_peak()   # the measured stream peak, the second reference
+    b_step = step_bytes_per_atom(nn, mixed["rebuilds"], steps)
+    step_gbs = b_step * value / 1e9
+    copy_gbs = guarded("copy_peak", copy_peak)
+    copy_gbs = copy_gbs if isinstance(copy_gbs, float) else None
     line = {
         "metric": "atom-timesteps/s, LJ 256k atoms FP32-mixed vs FP64; adjoint HVP atoms/s",
         "value": value,
         "unit": "atom-timesteps/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
+        "steps_requested": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * mixed["elapsed"] / args.steps,
+        "ms_per_step": 1e3 * mixed["elapsed"] / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -550,24 +599,62 @@ def main():
         "data": "synthetic",
         "config": {"workload": "lj_melt_256k", "atoms": w.natoms, "lattice": "fcc 40^3",
                    "density": 0.8442, "rc": w.rc, "skin": w.skin, "dt": w.dt, "temp": w.temp,
-                   "precision": "mixed", "kernel_selection": args.kernel,
-                   "lanes_per_atom": lanes, "thermo_every": THERMO_EVERY},
+                   "ensemble": "nve", "precision": "mixed", "kernel_selection": args.kernel,
+                   "lanes_per_atom": lanes, "thermo_every": mixed["thermo_every"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kname, "bytes_per_atom": bpa,
-                     "measured_copy_GBps": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs,
                      "launch_us": 1e3 * mixed["force_ms_avg"],
-                     "timed_launches": mixed["force_launches"]},
+                     "timed_launches": mixed["force_launches"],
+                     "measured_copy_GBps": copy_gbs,
+                     "frac_of_measured_copy": achieved / copy_gbs if copy_gbs else None,
+                     "step_bytes_per_atom": b_step, "step_achieved": step_gbs,
+                     "step_frac": step_gbs / HBM_PEAK_GBS},
         "rebuilds": mixed["rebuilds"],
-        "mean_neighbors": mixed["mean_neigh"],
+        "mean_neighbors": nn,
         "nve_drift_mixed": nve_drift(mixed["rows"], w.natoms, w.dt),
-        "mixed_force_rel_rms_vs_fp64": mixed_force_error(mixed["system"]),
-        **extras,
     }
+    if not args.no_extras:
+        fp64 = guarded("fp64 run", run_md, w, x, v, "fp64", args.kernel, steps, args.warmup)
+        if "error" not in fp64:
+            v64 = steps * w.natoms / fp64["elapsed"]
+            log(f"[bench] fp64 K={fp64['kernel']}: {v64:.4g} atom-steps/s, "
+                f"force avg {1e3 * fp64['force_ms_avg']:.2f} us")
+            line.update({"fp64_atom_timesteps_per_s": v64, "mixed_over_fp64": value / v64,
+                         "nve_drift_fp64": nve_drift(fp64["rows"], w.natoms, w.dt),
+                         "fp64_force_kernel_us": 1e3 * fp64["force_ms_avg"],
+                         "fp64_lanes_per_atom": fp64["kernel"]})
+            del fp64
+        else:
+            line["fp64_run"] = fp64
+        tpa = guarded("thread-per-atom run", run_md, w, x, v, "mixed", "tpa", steps, args.warmup)
+        if "error" not in tpa:
+            vt = steps * w.natoms / tpa["elapsed"]
+            log(f"[bench] mixed K=1 (thread per atom): {vt:.4g} atom-steps/s, "
+                f"force avg {1e3 * tpa['force_ms_avg']:.2f} us")
+            line.update({"mixed_tpa_atom_timesteps_per_s": vt,
+                         "mixed_tpa_force_kernel_us": 1e3 * tpa["force_ms_avg"]})
+            del tpa
+        else:
+            line["mixed_tpa_run"] = tpa
+        vjp = guarded("adjoint", bench_vjp, reps=20)
+        log(f"[bench] vjp atoms/s: {vjp}")
+        if "error" not in vjp:
+            line.update({"adjoint_hvp_atoms_per_s": vjp["mixed"],
+                         "adjoint_hvp_atoms_per_s_fp64": vjp["fp64"]})
+        else:
+            line["adjoint"] = vjp
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(w, x, v)
-        line["cpu_baseline"]["host"] = host_info()
+        cb = guarded("cpu baseline", cpu_baseline, w, x, v)
+        if "error" not in cb:
+            cb["host"] = host_info()
+        line["cpu_baseline"] = cb
+        fc = guarded("oracle force check", oracle_force_check, mixed["system"], w)
+        line["force_check_final_state"] = fc
+        if "error" not in fc:
+            line["mixed_force_rel_rms_vs_oracle"] = fc["mixed_force_rel_rms_vs_oracle"]
+        log(f"[bench] force check at the final state: {fc}")
     print(json.dumps(line), flush=True)
 
 

@@ -147,6 +147,19 @@ def _ptr(t: Optional[torch.Tensor], dtype=None, numel: Optional[int] = None):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _check_list(nl: "NList", n: int, call: str) -> None:
+    """The list's buffers must cover n atoms: a list sized for fewer atoms
+    would be read past its end by the kernels (the C descriptor carries no
+    atom count to check against)."""
+    if nl.numneigh.numel() < n:
+        raise ValueError(f"{call}: list holds {nl.numneigh.numel()} atoms, positions have {n}")
+    need = md_nlist_ints(n, nl.capacity)
+    if nl.neigh.numel() < need:
+        raise ValueError(f"{call}: neigh holds {nl.neigh.numel()} ints, {need} needed")
+    if nl.x_ref.numel() < 3 * n:
+        raise ValueError(f"{call}: x_ref holds {nl.x_ref.numel()} values, {3 * n} needed")
+
+
 def _stream(stream=None):
     s = torch.cuda.current_stream() if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
@@ -296,6 +309,7 @@ def md_sort_atoms(state: State, cells: Cells, x_ref: Optional[torch.Tensor], ws:
 def md_build_neighbors(x: torch.Tensor, box: md_box, cells: Cells, rc: float, skin: float,
                        nl: NList, stream=None) -> None:
     n = x.shape[1]
+    _check_list(nl, n, "md_build_neighbors")
     _check(lib().md_build_neighbors(_ptr(x, torch.float64, 3 * n), n, ctypes.byref(box),
                                     ctypes.byref(cells.c), rc, skin, ctypes.byref(nl.c),
                                     _stream(stream)), "md_build_neighbors")
@@ -305,6 +319,7 @@ def md_compute_forces(pot: md_potential, x: torch.Tensor, box: md_box, nl: NList
                       kernel: int, flags: int, f: torch.Tensor, ev: Optional[torch.Tensor],
                       ws: torch.Tensor, stream=None) -> None:
     n = x.shape[1]
+    _check_list(nl, n, "md_compute_forces")
     _check(lib().md_compute_forces(ctypes.byref(pot), _ptr(x, torch.float64, 3 * n), n,
                                    ctypes.byref(box), ctypes.byref(nl.c), prec, kernel, flags,
                                    _ptr(f, torch.float64, 3 * n), _ptr(ev, torch.float64, 7),
@@ -353,6 +368,7 @@ def md_force_vjp(pot: md_potential, x: torch.Tensor, box: md_box, nl: NList, pre
                  u: torch.Tensor, gx: torch.Tensor, gparam: Optional[torch.Tensor],
                  ws: torch.Tensor, stream=None) -> None:
     n = x.shape[1]
+    _check_list(nl, n, "md_force_vjp")
     _check(lib().md_force_vjp(ctypes.byref(pot), _ptr(x, torch.float64, 3 * n), n,
                               ctypes.byref(box), ctypes.byref(nl.c), prec,
                               _ptr(u, torch.float64, 3 * n), _ptr(gx, torch.float64, 3 * n),
@@ -364,6 +380,7 @@ def md_force_vjp(pot: md_potential, x: torch.Tensor, box: md_box, nl: NList, pre
 def md_autoselect(pot: md_potential, x: torch.Tensor, box: md_box, cells: Cells, skin: float,
                   nl: NList, prec: int, reps: int, ws: torch.Tensor, stream=None) -> int:
     n = x.shape[1]
+    _check_list(nl, n, "md_autoselect")
     choice = ctypes.c_int(0)
     _check(lib().md_autoselect(ctypes.byref(pot), _ptr(x, torch.float64, 3 * n), n,
                                ctypes.byref(box), ctypes.byref(cells.c), skin, ctypes.byref(nl.c),

@@ -193,3 +193,26 @@ def test_binding_structs_match_the_header(mdlib, tmp_path):
     for const in ("MD_NHC_MAX", "MD_NHC_STATE", "MD_MAX_ATOMS", "MD_STATUS_WORDS",
                   "MD_POT_BUCK", "MD_LAYOUT_WPA"):
         assert got[("const", const)] == getattr(mdlib, const), const
+
+
+def test_binding_rejects_a_list_sized_for_fewer_atoms(mdlib):
+    """A list built for fewer atoms than the positions hold is refused on the
+    host, before any pointer reaches a kernel (host tensors suffice: the
+    check runs first)."""
+    import torch
+    nl = mdlib.NList(50, 8, mdlib.MD_LAYOUT_TPA, device="cpu")
+    x = torch.zeros(3, 100, dtype=torch.float64)
+    f = torch.zeros_like(x)
+    ws = torch.zeros(16, dtype=torch.uint8)
+    box = mdlib.make_box((20.0, 20.0, 20.0))
+    pot = mdlib.lj_potential(2.5)
+    for call in (lambda: mdlib.md_compute_forces(pot, x, box, nl, mdlib.MD_FP64, 0, 0, f, None, ws),
+                 lambda: mdlib.md_force_vjp(pot, x, box, nl, mdlib.MD_FP64, x, f, None, ws),
+                 lambda: mdlib.md_build_neighbors(x, box, None, 2.5, 0.3, nl)):
+        with pytest.raises(ValueError, match="list holds 50 atoms"):
+            call()
+    # a list whose neigh buffer is too short for its capacity
+    nl2 = mdlib.NList(100, 8, mdlib.MD_LAYOUT_TPA, device="cpu")
+    nl2.neigh = nl2.neigh[:10]
+    with pytest.raises(ValueError, match="neigh holds 10 ints"):
+        mdlib.md_compute_forces(pot, x, box, nl2, mdlib.MD_FP64, 0, 0, f, None, ws)

@@ -10,6 +10,7 @@ import pytest
 import test_oracle as T
 import test_oracle_buck as TB
 import test_oracle_nvt as TN
+import test_oracle_pressure as TP
 import test_oracle_sc_vjp as TS
 from paper_1009_4330_amd import inputs as I
 
@@ -65,6 +66,13 @@ MUTANTS = {
                            ["nvt_conserved", "nvt_reversible"]),
     "nvt_eta_full_step": ("eta[j] = eta[j] + dt2 * veta[j];", "eta[j] = eta[j] + dt * veta[j];",
                           ["nvt_conserved"]),
+    "pressure_volume_factor": ("/ (3.0 * vol);", "/ (2.0 * vol);",
+                               ["ideal_gas", "pressure_dEdV"]),
+    "pressure_kinetic_factor": ("row[5] = (2.0 * ke + ", "row[5] = (ke + ", ["ideal_gas"]),
+    "pressure_virial_sign": ("(2.0 * ke + (vir[0] + vir[1] + vir[2]))",
+                             "(2.0 * ke - (vir[0] + vir[1] + vir[2]))", ["pressure_dEdV"]),
+    "pressure_virial_diagonal": ("(vir[0] + vir[1] + vir[2])", "(vir[0] + vir[1] + vir[3])",
+                                 ["pressure_dEdV"]),
 }
 
 
@@ -106,6 +114,9 @@ PINS = {
     "par_scvjp_a": lambda o: TS.test_sc_vjp_parameter_gradients(o, _scsys(o), 1, "a"),
     "nvt_conserved": lambda o: TN.test_nvt_conserved_energy_is_second_order(o, 3),
     "nvt_reversible": lambda o: TN.test_nvt_time_reversible(o),
+    "ideal_gas": lambda o: TP.test_ideal_gas_law(o, TP.LJ, dict(lj_eps=0.0)),
+    "pressure_dEdV": lambda o: TP.test_pressure_is_minus_energy_volume_derivative(o,
+                                                                                  "lj_jittered"),
 }
 
 
