@@ -57,7 +57,8 @@ typedef enum {
   MD_ERR_UNSUPPORTED = 5,    /* valid request the library does not implement */
   MD_ERR_HIP = 6,            /* a HIP runtime call failed */
   MD_ERR_WORKSPACE = 7,      /* ws is NULL or smaller than md_workspace_bytes */
-  MD_ERR_UNSTABLE = 8        /* md_step: an atom moved more than a cell edge between builds */
+  MD_ERR_UNSTABLE = 8,       /* md_step: an atom moved more than a cell edge between builds */
+  MD_ERR_SCRATCH = 9         /* md_compute_forces_noalloc: the call needs more than its fixed scratch */
 } md_status;
 
 typedef enum { MD_FP64 = 0, MD_MIXED = 1 } md_precision;
@@ -271,6 +272,36 @@ md_status md_step_nvt(md_state* st, const md_potential* p, const md_box* box, md
                       md_nlist* nl, md_precision prec, md_kernel k, double skin, double dt,
                       const md_nhc* nhc, int nsteps, int thermo_every, int setup,
                       double* thermo, void* ws, size_t ws_bytes, void* stream);
+
+/* Fixed device scratch of md_compute_forces_noalloc, per GPU (64 MiB). */
+#define MD_NOALLOC_SCRATCH_BYTES 67108864
+
+/* Scratch bytes md_compute_forces_noalloc needs for n atoms of potential kind
+   `kind` (MD_POT_*) with these flags: 32 per atom for the packed positions,
+   8 more for Sutton-Chen, 56 more and 32 KiB with flags != 0, each part
+   rounded up to 256 bytes.  0 for n out of range.  Host only. */
+size_t md_compute_forces_noalloc_bytes(int64_t n, int kind, int flags);
+
+/* md_compute_forces for callers that cannot allocate device memory or pass a
+   workspace (code under HIP graph capture, serving loops, harnesses that
+   forbid allocation).  Same arguments, results, kernels and rules as
+   md_compute_forces, without ws: its scratch (packed positions, Sutton-Chen
+   densities, per-atom energy / virial and partial sums) lives in one fixed
+   array of MD_NOALLOC_SCRATCH_BYTES per GPU, held by the library from its
+   load until the process ends.  The caller still owns x, f, ev and the list.
+   Calls that need more than MD_NOALLOC_SCRATCH_BYTES
+   (md_compute_forces_noalloc_bytes) return MD_ERR_SCRATCH before anything
+   is enqueued; the limit is about 2 million atoms for forces alone, 700,000
+   with energy / virial.  The call allocates nothing: no hipMalloc, no
+   workspace, no library call that allocates.  Every call on one GPU uses
+   that GPU's one array, and nothing in it is kept from call to call: calls
+   that overlap in time on one GPU (several streams or host threads) race on
+   it and must be serialised by the caller.  The first call on a device looks
+   the array's address up there (not an allocation). */
+md_status md_compute_forces_noalloc(const md_potential* p, const double* x, int64_t n,
+                                    const md_box* box, const md_nlist* nl, md_precision prec,
+                                    md_kernel k, int flags, double* f, double* ev,
+                                    void* stream);
 
 /* Vector-Jacobian product of the forces for L = sum_i u_i . F_i:
    gx = (dF/dx)^T u = -H u, with u, gx [device, 3][n]; gparam [device, may be

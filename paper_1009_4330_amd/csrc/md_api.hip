@@ -425,6 +425,7 @@ const char* md_status_string(md_status s) {
     case MD_ERR_HIP: return "HIP runtime error";
     case MD_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
     case MD_ERR_UNSTABLE: return "an atom moved more than a cell edge between list builds";
+    case MD_ERR_SCRATCH: return "the call needs more scratch than the fixed no-allocation array holds";
   }
   return "unknown status";
 }
@@ -501,28 +502,44 @@ md_status md_build_neighbors(const double* x, int64_t n, const md_box* box,
                     static_cast<hipStream_t>(stream));
 }
 
-md_status md_compute_forces(const md_potential* p, const double* x, int64_t n,
+}  // extern "C"
+
+namespace {
+
+// Scratch of one md_compute_forces call: packed positions [n][4], the
+// Sutton-Chen density column [n], per-atom energy [n] and virial [6][n], and
+// the partial sums of the energy / virial reduction.
+struct ForceScratch {
+  double* xq;
+  double* sc_e;
+  double* eatom;
+  double* vatom;
+  double* partials;
+};
+
+md_status check_forces_args(const md_potential* p, const double* x, int64_t n,
                             const md_box* box, const md_nlist* nl, md_precision prec,
-                            md_kernel k, int flags, double* f, double* ev, void* ws,
-                            size_t ws_bytes, void* stream) {
+                            md_kernel k, int flags, double* f, double* ev, int* kernel) {
   md_status st = check_pot(p);
   if (st != MD_OK) return st;
   if (!x || !nl || !nl->neigh || !nl->numneigh || !f || !n_ok(n) || nl->capacity < 1 ||
       (prec != MD_FP64 && prec != MD_MIXED) || (flags & ~(MD_EFLAG | MD_VFLAG)) ||
       (flags && !ev))
     return MD_ERR_INVALID_ARG;
-  const int kernel = resolve_lanes(k, nl->layout);
-  if (!kernel) return MD_ERR_INVALID_ARG;
+  *kernel = resolve_lanes(k, nl->layout);
+  if (!*kernel) return MD_ERR_INVALID_ARG;
   if (nl->half && p->kind != MD_POT_LJ) return MD_ERR_UNSUPPORTED;
-  if ((st = check_box(box, nl->rl > p->rc ? nl->rl : p->rc)) != MD_OK) return st;
-  const WsLayout L = ws_layout(n, 1);
-  if ((st = check_ws(ws, ws_bytes, L)) != MD_OK) return st;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  double* xq = at<double>(ws, L.xq);
-  MD_CK(launch_pack_positions(x, (int)n, xq, species(p), s));
+  return check_box(box, nl->rl > p->rc ? nl->rl : p->rc);
+}
+
+// md_compute_forces after validation, with its scratch given.
+md_status compute_forces_impl(const md_potential* p, const double* x, int n, const md_box* box,
+                              const md_nlist* nl, md_precision prec, int kernel, int flags,
+                              double* f, double* ev, const ForceScratch& sc, hipStream_t s) {
+  MD_CK(launch_pack_positions(x, n, sc.xq, species(p), s));
   ForceArgs fa{};
-  fa.xq = xq;
-  fa.n = (int)n;
+  fa.xq = sc.xq;
+  fa.n = n;
   fa.box = make_box(box);
   fa.margin = interior_margin(p, nl->rl);
   fa.neigh = nl->neigh;
@@ -530,28 +547,131 @@ md_status md_compute_forces(const md_potential* p, const double* x, int64_t n,
   fa.cap = nl->capacity;
   fa.f = f;
   if (flags) {
-    fa.ev.eatom = at<double>(ws, L.eatom);
-    fa.ev.vatom = at<double>(ws, L.vatom);
+    fa.ev.eatom = sc.eatom;
+    fa.ev.vatom = sc.vatom;
   }
   timing_events(&fa.t0, &fa.t1);
   if (nl->half) {
     // each pair once; both atoms' shares are added atomically into f
-    MD_CK(launch_fill_double(f, 3 * n, 0.0, s));
+    MD_CK(launch_fill_double(f, 3 * (int64_t)n, 0.0, s));
     MD_CK(launch_lj_half(fa, make_lj(p), prec, kernel, s));
-  } else if ((st = force_dispatch(p, fa, prec, kernel, at<double>(ws, L.sc_e), s)) != MD_OK) {
-    return st;
+  } else {
+    const md_status st = force_dispatch(p, fa, prec, kernel, sc.sc_e, s);
+    if (st != MD_OK) return st;
   }
   if (flags) {
     SumArgs sa{};
     sa.cols = 7;
     sa.col[0] = fa.ev.eatom;
     for (int q = 0; q < 6; ++q) sa.col[1 + q] = fa.ev.vatom + (size_t)q * n;
-    sa.n = (int)n;
-    sa.partials = at<double>(ws, L.partials);
+    sa.n = n;
+    sa.partials = sc.partials;
     sa.out = ev;
     MD_CK(launch_sum(sa, s));
   }
   return MD_OK;
+}
+
+// ------------------------------------------- fixed scratch (no allocation) --
+
+// The scratch of md_compute_forces_noalloc: one array per device, held from
+// the library's load until the process ends.  Host code never uses this name
+// as an address (on the host it is only a stand-in for the symbol): the
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[MD_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call there), or null if the lookup fails.
+void* scratch_on_current_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_dev[dev] = ptr;
+  }
+  return g_scratch_dev[dev];
+}
+
+// Carve-up of the fixed scratch for n atoms (offsets from its base); total
+// is the bytes needed.
+struct NoAllocLayout {
+  size_t xq, sc_e, eatom, vatom, partials, total;
+};
+NoAllocLayout noalloc_layout(int64_t n, bool sc, bool ev) {
+  NoAllocLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o += align256(bytes);
+    return r;
+  };
+  const size_t nn = (size_t)n;
+  L.xq = take(sizeof(double) * 4 * nn);
+  L.sc_e = sc ? take(sizeof(double) * nn) : 0;
+  if (ev) {
+    L.eatom = take(sizeof(double) * nn);
+    L.vatom = take(sizeof(double) * 6 * nn);
+    L.partials = take(sizeof(double) * kReduceBlocks * kReduceCols);
+  }
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+md_status md_compute_forces(const md_potential* p, const double* x, int64_t n,
+                            const md_box* box, const md_nlist* nl, md_precision prec,
+                            md_kernel k, int flags, double* f, double* ev, void* ws,
+                            size_t ws_bytes, void* stream) {
+  int kernel = 0;
+  md_status st = check_forces_args(p, x, n, box, nl, prec, k, flags, f, ev, &kernel);
+  if (st != MD_OK) return st;
+  const WsLayout L = ws_layout(n, 1);
+  if ((st = check_ws(ws, ws_bytes, L)) != MD_OK) return st;
+  ForceScratch sc;
+  sc.xq = at<double>(ws, L.xq);
+  sc.sc_e = at<double>(ws, L.sc_e);
+  sc.eatom = at<double>(ws, L.eatom);
+  sc.vatom = at<double>(ws, L.vatom);
+  sc.partials = at<double>(ws, L.partials);
+  return compute_forces_impl(p, x, (int)n, box, nl, prec, kernel, flags, f, ev, sc,
+                             static_cast<hipStream_t>(stream));
+}
+
+size_t md_compute_forces_noalloc_bytes(int64_t n, int kind, int flags) {
+  if (!n_ok(n)) return 0;
+  return noalloc_layout(n, kind == MD_POT_SC, flags != 0).total;
+}
+
+md_status md_compute_forces_noalloc(const md_potential* p, const double* x, int64_t n,
+                                    const md_box* box, const md_nlist* nl, md_precision prec,
+                                    md_kernel k, int flags, double* f, double* ev,
+                                    void* stream) {
+  int kernel = 0;
+  md_status st = check_forces_args(p, x, n, box, nl, prec, k, flags, f, ev, &kernel);
+  if (st != MD_OK) return st;
+  const NoAllocLayout L = noalloc_layout(n, p->kind == MD_POT_SC, flags != 0);
+  if (L.total > (size_t)MD_NOALLOC_SCRATCH_BYTES) return MD_ERR_SCRATCH;
+  void* base = scratch_on_current_device();
+  if (!base) return MD_ERR_HIP;
+  // nothing in the scratch has to start at zero: every word a kernel reads
+  // was written earlier in the same call
+  ForceScratch sc;
+  sc.xq = at<double>(base, L.xq);
+  sc.sc_e = p->kind == MD_POT_SC ? at<double>(base, L.sc_e) : nullptr;
+  sc.eatom = flags ? at<double>(base, L.eatom) : nullptr;
+  sc.vatom = flags ? at<double>(base, L.vatom) : nullptr;
+  sc.partials = flags ? at<double>(base, L.partials) : nullptr;
+  return compute_forces_impl(p, x, (int)n, box, nl, prec, kernel, flags, f, ev, sc,
+                             static_cast<hipStream_t>(stream));
 }
 
 md_status md_force_vjp(const md_potential* p, const double* x, int64_t n, const md_box* box,

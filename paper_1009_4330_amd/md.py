@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmd_mi355
 
 MD_OK, MD_ERR_INVALID_ARG, MD_ERR_BOX_TOO_SMALL, MD_ERR_NLIST_OVERFLOW = 0, 1, 2, 3
 MD_ERR_NONFINITE, MD_ERR_UNSUPPORTED, MD_ERR_HIP, MD_ERR_WORKSPACE = 4, 5, 6, 7
-MD_ERR_UNSTABLE = 8
+MD_ERR_UNSTABLE, MD_ERR_SCRATCH = 8, 9
+MD_NOALLOC_SCRATCH_BYTES = 67108864   # md.h: fixed scratch of md_compute_forces_noalloc
 MD_MAX_ATOMS = 134217727          # md.h: largest atom count
 MD_FP64, MD_MIXED = 0, 1
 MD_KERNEL_AUTO, MD_KERNEL_TPA, MD_KERNEL_WPA = 0, 1, 64
@@ -28,7 +29,8 @@ MD_ST_ERRORS, MD_ST_MAXNEIGH, MD_ST_BUILDS, MD_ST_REBUILD, MD_STATUS_WORDS = 0, 
 EXPORTS = ("md_workspace_bytes", "md_nlist_ints", "md_thermo_rows", "md_bin_cells", "md_sort_atoms",
            "md_build_neighbors", "md_compute_forces", "md_step", "md_step_nvt", "md_force_vjp",
            "md_autoselect", "md_nlist_status", "md_timing_enable", "md_timing_read",
-           "md_status_string")
+           "md_status_string", "md_compute_forces_noalloc",
+           "md_compute_forces_noalloc_bytes")
 
 
 class MDError(RuntimeError):
@@ -104,6 +106,10 @@ def lib() -> ctypes.CDLL:
         L.md_build_neighbors.argtypes = [V, I64, P(md_box), P(md_cells), D, D, P(md_nlist), V]
         L.md_compute_forces.argtypes = [P(md_potential), V, I64, P(md_box), P(md_nlist), I, I, I,
                                         V, V, V, ctypes.c_size_t, V]
+        L.md_compute_forces_noalloc.argtypes = [P(md_potential), V, I64, P(md_box), P(md_nlist),
+                                                I, I, I, V, V, V]
+        L.md_compute_forces_noalloc_bytes.restype = ctypes.c_size_t
+        L.md_compute_forces_noalloc_bytes.argtypes = [I64, I, I]
         L.md_step.argtypes = [P(md_state), P(md_potential), P(md_box), P(md_cells), P(md_nlist),
                               I, I, D, D, I, I, I, V, V, ctypes.c_size_t, V]
         L.md_step_nvt.argtypes = [P(md_state), P(md_potential), P(md_box), P(md_cells),
@@ -118,7 +124,7 @@ def lib() -> ctypes.CDLL:
         L.md_timing_read.argtypes = [P(I64), P(D)]
         for name in EXPORTS:
             if name not in ("md_workspace_bytes", "md_nlist_ints", "md_thermo_rows",
-                            "md_status_string"):
+                            "md_status_string", "md_compute_forces_noalloc_bytes"):
                 getattr(L, name).restype = I
         _lib = L
     return _lib
@@ -324,6 +330,23 @@ def md_compute_forces(pot: md_potential, x: torch.Tensor, box: md_box, nl: NList
                                    ctypes.byref(box), ctypes.byref(nl.c), prec, kernel, flags,
                                    _ptr(f, torch.float64, 3 * n), _ptr(ev, torch.float64, 7),
                                    _ptr(ws), ws.numel(), _stream(stream)), "md_compute_forces")
+
+
+def md_compute_forces_noalloc_bytes(n: int, kind: int, flags: int) -> int:
+    return int(lib().md_compute_forces_noalloc_bytes(int(n), int(kind), int(flags)))
+
+
+def md_compute_forces_noalloc(pot: md_potential, x: torch.Tensor, box: md_box, nl: NList,
+                              prec: int, kernel: int, flags: int, f: torch.Tensor,
+                              ev: Optional[torch.Tensor], stream=None) -> None:
+    """md_compute_forces without a workspace (the library's fixed scratch)."""
+    n = x.shape[1]
+    _check_list(nl, n, "md_compute_forces_noalloc")
+    _check(lib().md_compute_forces_noalloc(ctypes.byref(pot), _ptr(x, torch.float64, 3 * n), n,
+                                           ctypes.byref(box), ctypes.byref(nl.c), prec, kernel,
+                                           flags, _ptr(f, torch.float64, 3 * n),
+                                           _ptr(ev, torch.float64, 7), _stream(stream)),
+           "md_compute_forces_noalloc")
 
 
 def md_step(state: State, pot: md_potential, box: md_box, cells: Cells, nl: NList, prec: int,

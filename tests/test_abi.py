@@ -46,7 +46,7 @@ def test_library_exports_every_declared_symbol(mdlib):
 
 
 def test_status_strings(mdlib):
-    for code in range(9):
+    for code in range(10):
         assert mdlib.status_string(code) != "unknown status"
     assert mdlib.status_string(3) == "neighbour list capacity exceeded"
 
@@ -216,3 +216,30 @@ def test_binding_rejects_a_list_sized_for_fewer_atoms(mdlib):
     nl2.neigh = nl2.neigh[:10]
     with pytest.raises(ValueError, match="neigh holds 10 ints"):
         mdlib.md_compute_forces(pot, x, box, nl2, mdlib.MD_FP64, 0, 0, f, None, ws)
+
+
+def test_noalloc_scratch_limit_is_checked_on_the_host(mdlib):
+    """md_compute_forces_noalloc refuses a call larger than its fixed scratch
+    (MD_ERR_SCRATCH) from host checks alone, and sizes its scratch as its
+    header states."""
+    lib = mdlib.lib()
+    fake = ctypes.c_void_p(0x1000)
+    R = ctypes.byref
+    box = mdlib.make_box(I.LJ_4K.box)
+    nl = mdlib.md_nlist(capacity=100, layout=1, rl=2.8, neigh=0x1000, numneigh=0x1000,
+                        x_ref=0x1000, status=0x1000)
+    lj = mdlib.lj_potential(2.5)
+    ev = mdlib.MD_EFLAG | mdlib.MD_VFLAG
+    r256 = lambda b: -(-b // 256) * 256
+    for n in (1, 4000, 256000):
+        assert mdlib.md_compute_forces_noalloc_bytes(n, mdlib.MD_POT_LJ, 0) == r256(32 * n)
+        assert mdlib.md_compute_forces_noalloc_bytes(n, mdlib.MD_POT_SC, ev) == (
+            r256(32 * n) + r256(8 * n) + r256(8 * n) + r256(48 * n) + r256(512 * 8 * 8))
+    assert mdlib.md_compute_forces_noalloc_bytes(0, mdlib.MD_POT_LJ, 0) == 0
+    big = mdlib.MD_NOALLOC_SCRATCH_BYTES // 88 + 1000
+    assert lib.md_compute_forces_noalloc(R(lj), fake, big, R(box), R(nl), 0, 1, ev, fake, fake,
+                                         None) == mdlib.MD_ERR_SCRATCH
+    # argument errors come first, as in md_compute_forces
+    assert lib.md_compute_forces_noalloc(R(lj), fake, big, R(box), R(nl), 0, 2, ev, fake, fake,
+                                         None) == mdlib.MD_ERR_INVALID_ARG
+    assert mdlib.status_string(mdlib.MD_ERR_SCRATCH) != "unknown status"
