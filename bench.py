@@ -132,18 +132,6 @@ def nve_drift(rows, n: int, dt: float):
             "rows": int(len(e)), "first_step": int(rows[0, 0]), "last_step": int(rows[-1, 0])}
 
 
-def gpu_forces(sysm, prec):
-    """Forces of the run's potential at the state's positions, through
-    md_compute_forces on the run's own list (no integration)."""
-    import torch
-    from paper_1009_4330_amd import md
-    f = torch.empty_like(sysm.state.f)
-    md.md_compute_forces(sysm.pot, sysm.state.x, sysm.box, sysm.nl, prec, sysm.nl.layout, 0, f,
-                         None, sysm.ws)
-    torch.cuda.synchronize()
-    return f
-
-
 def host_info():
     model = ""
     try:
@@ -265,7 +253,8 @@ def bench_half_list(reps: int = 20):
 
 def cpu_baseline(w, x, v, target_s: float = 15.0):
     """The oracle's own NVE run on the host cores, on a bounded number of
-    steps of the same workload; setup (first build + forces) is subtracted."""
+    steps of the same workload; setup (first build + forces) is subtracted.
+    Returns the report and the oracle's final state (positions, forces)."""
     import oracle
     p = oracle.params_for(w)
     t0 = time.perf_counter()
@@ -277,33 +266,44 @@ def cpu_baseline(w, x, v, target_s: float = 15.0):
     per_step = max((time.perf_counter() - t0 - t_setup) / probe, 1e-4)
     steps = int(max(probe, min(400, target_s / per_step)))
     t0 = time.perf_counter()
-    oracle.md_run(p, x, v, w.box, steps, steps)
+    res = oracle.md_run(p, x, v, w.box, steps, steps)
     t = time.perf_counter() - t0 - t_setup
     return dict(value=steps * w.natoms / t, unit="atom-timesteps/s", cores=oracle.num_threads(),
                 kind="oracle",
                 sample=f"{steps} NVE steps of the {w.natoms}-atom LJ melt from the same seeded "
-                       f"state (FP64, setup excluded, {t:.1f} s)")
+                       f"state (FP64, setup excluded, {t:.1f} s)"), res
 
 
-def oracle_force_check(sysm, w):
-    """Forces at the final state of the timed MIXED run: the GPU's MIXED and
-    FP64 forces (md_compute_forces on the run's list) against the oracle's
-    FP64 forces at the same positions (its own list; the pairs inside rc are
-    the same).  rel-RMS over all 3N components and the largest per-atom
-    error relative to the largest force."""
-    import oracle
+def oracle_force_check(w, ores, kernel: int):
+    """Forces at the end of the oracle's own timed run: the library's MIXED
+    and FP64 forces (md_compute_forces on a list it builds from the oracle's
+    positions, in the headline run's lanes-per-atom layout) against the
+    oracle's FP64 forces there.  rel-RMS over all 3N components and the
+    largest per-atom error relative to the largest force."""
+    import math
+    import torch
     from paper_1009_4330_amd import md
-    x = sysm.state.x.cpu().numpy()
-    onl, oc = oracle.build_nlist(x, w.box, w.rc + w.skin)
-    ref = oracle.lj_forces(oc.x, w.box, onl, w.rc, w.lj_eps, w.lj_sigma, w.lj_shift).f
-    out = {}
+    n = w.natoms
+    rl = w.rc + w.skin
+    x = torch.as_tensor(ores.x, dtype=torch.float64, device="cuda").contiguous()
+    box = md.make_box(w.box)
+    cells = md.Cells(n, int(np.prod([math.floor(L / rl) for L in w.box])))
+    ws = md.workspace(n, box, rl)
+    md.md_bin_cells(x, box, rl, cells, ws)
+    nl = md.NList(n, 160, kernel)
+    md.md_build_neighbors(x, box, cells, w.rc, w.skin, nl)
+    pot = md.lj_potential(w.rc, w.lj_eps, w.lj_sigma, w.lj_shift)
+    ref = ores.f
+    out = {"state": "end of the oracle's timed run"}
     for name, prec in (("mixed", md.MD_MIXED), ("fp64", md.MD_FP64)):
-        f = gpu_forces(sysm, prec).cpu().numpy()
+        f = torch.empty_like(x)
+        md.md_compute_forces(pot, x, box, nl, prec, md.MD_KERNEL_AUTO, 0, f, None, ws)
+        f = f.cpu().numpy()
         d = f - ref
         out[f"{name}_force_rel_rms_vs_oracle"] = float(np.linalg.norm(d) / np.linalg.norm(ref))
         out[f"{name}_force_max_atom_err_rel"] = float(
             np.sqrt((d * d).sum(0)).max() / np.sqrt((ref * ref).sum(0)).max())
-    out["atoms"] = int(x.shape[1])
+    out["atoms"] = n
     return out
 
 
@@ -646,15 +646,18 @@ def headline(args):
             line["adjoint"] = vjp
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
-        cb = guarded("cpu baseline", cpu_baseline, w, x, v)
-        if "error" not in cb:
+        cbr = guarded("cpu baseline", cpu_baseline, w, x, v)
+        if isinstance(cbr, tuple):
+            cb, ores = cbr
             cb["host"] = host_info()
+            fc = guarded("oracle force check", oracle_force_check, w, ores, lanes)
+        else:
+            cb, fc = cbr, {"error": "no oracle state"}
         line["cpu_baseline"] = cb
-        fc = guarded("oracle force check", oracle_force_check, mixed["system"], w)
-        line["force_check_final_state"] = fc
+        line["force_check_oracle_state"] = fc
         if "error" not in fc:
             line["mixed_force_rel_rms_vs_oracle"] = fc["mixed_force_rel_rms_vs_oracle"]
-        log(f"[bench] force check at the final state: {fc}")
+        log(f"[bench] force check at the oracle's final state: {fc}")
     print(json.dumps(line), flush=True)
 
 

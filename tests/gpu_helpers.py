@@ -79,3 +79,18 @@ def forces_gpu(pot, x, mbox, nl, prec, kernel, ws, flags=md.MD_EFLAG | md.MD_VFL
     md.md_compute_forces(pot, x, mbox, nl, prec, kernel, flags, f, ev, ws)
     torch.cuda.synchronize()
     return f.cpu().numpy(), ev.cpu().numpy()
+
+
+def assert_fp64(got, want, bar: float = 1e-12, what: str = "forces") -> None:
+    """FP64 parity of a per-atom [3][n] field: the norm-wise relative error
+    over all components and the largest per-atom error (relative to the
+    largest per-atom magnitude) both within bar.  The per-atom check keeps a
+    few bad atoms from hiding in the norm of a large system."""
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    e = rel(got, want)
+    assert e < bar, f"{what}: norm-wise relative error {e:.3e} >= {bar:.0e}"
+    d = np.sqrt(((got - want) ** 2).sum(axis=0))
+    m = float(np.sqrt((want ** 2).sum(axis=0)).max())
+    assert d.max() <= bar * max(m, 1e-300), (
+        f"{what}: largest per-atom error {d.max():.3e} > {bar:.0e} x {m:.3e}")

@@ -7,8 +7,18 @@ rounding of a few units of u32 = 2^-24.  The error of any sum of such terms is
 therefore bounded by K u32 times the sum of the *magnitudes* of the parts, not
 by the size of the (often heavily cancelled) total.  These helpers form those
 magnitude sums per pair from the oracle's neighbour list, so a test can assert
-|GPU - oracle| <= K u32 M.  K = 32 allows for the handful of FP32 operations
-(reciprocal, powers, products) per pair term.
+|GPU - oracle| <= K u32 M.
+
+Worst case per pair (K_WORST = 32): the FP32 separation s carries one
+rounding and the hardware reciprocal up to one ulp (2 u), and the powers
+amplify that relative error by their exponent: the LJ repulsion
+sigma^12 / s^7 by 7, so about 21 u, plus the roundings of the products and
+of the difference of the two parts -- about 25 u in all.  Sums of many pair
+terms have independent-signed rounding errors, so each tested quantity is
+held to a tighter factor (K_BY_QUANTITY), about ten times the largest ratio
+error / (u M) measured over the GPU parity suite (forces at rc = 5 sigma 4.2,
+virial components 1.1, position adjoint 1.2, energy 0.4, parameter
+gradients 0.07), and never above the worst case.
 """
 from __future__ import annotations
 
@@ -16,7 +26,15 @@ import numpy as np
 
 U32 = 2.0 ** -24
 U64 = 2.0 ** -53
-K = 32.0
+K_WORST = 32.0
+K = K_WORST
+K_BY_QUANTITY = {"force": 32.0, "energy": 4.0, "virial": 12.0, "gx": 12.0,
+                 "dL/deps": 1.0, "dL/dsigma": 1.0, "geps": 1.0, "ga": 1.0, "gc": 1.0}
+
+
+def k_for(what: str) -> float:
+    """The bar factor of a quantity ('virial 3' uses the virial's)."""
+    return K_BY_QUANTITY.get(what.rstrip("0123456789 "), K_WORST)
 VPAIRS = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
 
 
@@ -77,15 +95,19 @@ def sc_magnitudes(x, box, onl, rc, eps, a, c, nexp, mexp, rho):
 
 
 def assert_total(got, want, mag, u=U32, what=""):
+    k = k_for(what)
     err = abs(got - want)
-    bound = K * u * mag
+    bound = k * u * mag
+    print(f"[bound] {what}: error {err:.3e} = {err / bound:.3g} of the bound (K = {k:g})")
     assert err <= bound, f"{what}: |{got} - {want}| = {err:.3e} > {bound:.3e}"
 
 
 def assert_vector(got, want, mag_per_atom, u=U32, what=""):
     """Norm-wise: ||got - want|| <= K u ||per-atom magnitude||."""
+    k = k_for(what)
     err = float(np.linalg.norm((np.asarray(got) - np.asarray(want)).ravel()))
-    bound = K * u * float(np.linalg.norm(mag_per_atom))
+    bound = k * u * float(np.linalg.norm(mag_per_atom))
+    print(f"[bound] {what}: error {err:.3e} = {err / bound:.3g} of the bound (K = {k:g})")
     assert err <= bound, f"{what}: error {err:.3e} > bound {bound:.3e}"
 
 

@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import mixed_bounds as MB
-from gpu_helpers import forces_gpu, gpu_list, gpu_pairs, rel
+from gpu_helpers import assert_fp64, forces_gpu, gpu_list, gpu_pairs, rel
 from paper_1009_4330_amd import inputs as I
 from paper_1009_4330_amd import md
 from paper_1009_4330_amd.system import MDSystem, potential_of
@@ -53,11 +53,15 @@ def check(orc, w, x_np, box, layout, kernel, prec, cap):
     f, ev = forces_gpu(pot, x, mbox, nl, prec, kernel, ws)
     ref, onl, oc = oracle(orc, w, x_np, box)
     if prec == md.MD_FP64:
-        assert rel(f, ref.f) < 1e-12
+        assert_fp64(f, ref.f)
         assert ev[0] == pytest.approx(ref.energy, rel=1e-12)
         assert rel(ev[1:], ref.virial) < 1e-12
         return
-    print(f"mixed Buckingham force rel-RMS {rel(f, ref.f):.3e}")
+    err = rel(f, ref.f)
+    print(f"mixed Buckingham force rel-RMS {err:.3e}")
+    # measured 7.9e-7 at rc 7 A and 2.8e-6 at rc 15 A: sums of ~2000 large,
+    # cancelling Coulomb terms
+    assert err < 5e-6
     A, rho, C = tables(w)
     mag = MB.buck_magnitudes(oc.x, box, onl, w.rc, w.species(), A, rho, C, charges(w), w.qqr2e)
     MB.assert_vector(f, ref.f, mag["f"], what="force")
@@ -141,7 +145,7 @@ def test_buck_step_fp64(orc, kernel):
     L = np.array(box)[:, None]
     d = gx - ref.x
     assert np.abs(d - L * np.round(d / L)).max() < 1e-9
-    assert rel(gf, ref.f) < 1e-9
+    assert_fp64(gf, ref.f, 1e-9)
     # the species array ends in the device's atom order: id -> species intact
     order = torch.argsort(sysm.state.id.long())
     assert np.array_equal(sysm.type[order].cpu().numpy(), w.species())

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import forces_gpu, gpu_list, gpu_pairs, rel
+from gpu_helpers import assert_fp64, forces_gpu, gpu_list, gpu_pairs, rel
 from paper_1009_4330_amd import inputs as I
 from paper_1009_4330_amd import md
 from paper_1009_4330_amd.system import MDSystem
@@ -58,7 +58,7 @@ def test_clustered_atoms_mostly_empty_cells(orc, layout):
     assert np.array_equal(gpu_pairs(nl), ref.pairs())
     f, ev = forces_gpu(md.lj_potential(2.5), x, mbox, nl, md.MD_FP64, md.MD_KERNEL_AUTO, ws)
     fr = orc.lj_forces(oc.x, box, ref, 2.5)
-    assert rel(f, fr.f) < 1e-12
+    assert_fp64(f, fr.f)
     assert ev[0] == pytest.approx(fr.energy, rel=1e-12)
 
 

@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import mixed_bounds as MB
-from gpu_helpers import dev, gpu_list, lj_liquid, rel
+from gpu_helpers import assert_fp64, dev, gpu_list, lj_liquid, rel
 from paper_1009_4330_amd import autograd as AG
 from paper_1009_4330_amd import inputs as I
 from paper_1009_4330_amd import md
@@ -28,7 +28,7 @@ def test_autograd_gradients_match_oracle_vjp(orc):
     (f * dev(u_np)).sum().backward()
     onl, ocells = orc.build_nlist(x_np, box, 2.8)
     rgx, rgp = orc.lj_vjp(ocells.x, box, onl, 2.5, 1.1, 1.05, u_np)
-    assert rel(xg.grad.cpu().numpy(), rgx) < 1e-12
+    assert_fp64(xg.grad.cpu().numpy(), rgx, what="gx")
     mag = MB.lj_magnitudes(ocells.x, box, onl, 2.5, 1.1, 1.05, u_np)
     MB.assert_total(eps.grad.item(), rgp[0], mag["geps"], u=MB.U64, what="dL/deps")
     MB.assert_total(sig.grad.item(), rgp[1], mag["gsig"], u=MB.U64, what="dL/dsigma")

@@ -13,8 +13,8 @@ import pytest
 import torch
 
 import mixed_bounds as MB
-from gpu_helpers import (SC_KW, dev, forces_gpu, gpu_bin, gpu_list, gpu_pairs, lj_liquid, rel,
-                         sc_solid)
+from gpu_helpers import (SC_KW, assert_fp64, dev, forces_gpu, gpu_bin, gpu_list, gpu_pairs,
+                         lj_liquid, rel, sc_solid)
 from paper_1009_4330_amd import inputs as I
 from paper_1009_4330_amd import md
 from paper_1009_4330_amd.system import MDSystem
@@ -156,7 +156,7 @@ def test_lj_forces_fp64(orc, layout, kernel, shift):
     pot = md.lj_potential(2.5, 1.0, 1.0, shift)
     f, ev = forces_gpu(pot, x, mbox, nl, md.MD_FP64, kernel, ws)
     ref, _ = oracle_lj(orc, x_np, box, shift)
-    assert rel(f, ref.f) < 1e-12
+    assert_fp64(f, ref.f)
     assert ev[0] == pytest.approx(ref.energy, rel=1e-12)
     assert rel(ev[1:], ref.virial) < 1e-12
 
@@ -185,7 +185,7 @@ def test_lj_nondefault_parameters_and_high_cutoff(orc):
         pot = md.lj_potential(5.0, 1.3, 0.93, 0)
         f, ev = forces_gpu(pot, x, mbox, nl, md.MD_FP64, kernel, ws)
         ref, _ = oracle_lj(orc, x_np, box, eps=1.3, sigma=0.93, rc=5.0)
-        assert rel(f, ref.f) < 1e-12
+        assert_fp64(f, ref.f)
         assert ev[0] == pytest.approx(ref.energy, rel=1e-12)
 
 
@@ -199,7 +199,7 @@ def test_sutton_chen_forces(orc, layout, kernel, prec):
     onl, ocells = orc.build_nlist(x_np, box, 8.22)
     ref = orc.sc_forces(ocells.x, box, onl, 7.22, **SC_KW)
     if prec == md.MD_FP64:
-        assert rel(f, ref.f) < 1e-12
+        assert_fp64(f, ref.f)
         assert ev[0] == pytest.approx(ref.energy, rel=1e-12)
         assert rel(ev[1:], ref.virial) < 1e-12
     else:
@@ -247,7 +247,7 @@ def test_lj_vjp(orc, layout, kernel, prec):
     ggx, ggp = gx.cpu().numpy(), gp.cpu().numpy()
     mag = MB.lj_magnitudes(ocells.x, box, onl, 2.5, 1.1, 1.05, u_np)
     if prec == md.MD_FP64:
-        assert rel(ggx, rgx) < 1e-12
+        assert_fp64(ggx, rgx, what="gx")
         MB.assert_total(ggp[0], rgp[0], mag["geps"], u=MB.U64, what="dL/deps")
         MB.assert_total(ggp[1], rgp[1], mag["gsig"], u=MB.U64, what="dL/dsigma")
     else:
@@ -273,4 +273,4 @@ def test_autoselect_choice_matches_layout(orc):
     assert words[md.MD_ST_BUILDS] == 0     # trial builds are not counted
     f, ev = forces_gpu(pot, x, mbox, nl, md.MD_FP64, md.MD_KERNEL_AUTO, ws)
     ref, _ = oracle_lj(orc, x_np, box)
-    assert rel(f, ref.f) < 1e-12
+    assert_fp64(f, ref.f)

@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import mixed_bounds as MB
-from gpu_helpers import SC_KW, dev, gpu_list, rel, sc_solid
+from gpu_helpers import SC_KW, assert_fp64, dev, gpu_list, rel, sc_solid
 from paper_1009_4330_amd import autograd as AG
 from paper_1009_4330_amd import inputs as I
 from paper_1009_4330_amd import md
@@ -46,7 +46,7 @@ def test_sc_vjp(orc, layout, kernel, prec):
     print(f"SC vjp ({'fp64' if prec == md.MD_FP64 else 'mixed'}): gx rel {rel(ggx, rgx):.3e}, "
           f"gparam {ggp} vs {rgp}")
     if prec == md.MD_FP64:
-        assert rel(ggx, rgx) < 1e-12
+        assert_fp64(ggx, rgx, what="gx")
     MB.assert_vector(ggx, rgx, mag["gx"], u=u, what="gx")
     for k, name in enumerate(("geps", "ga", "gc")):
         MB.assert_total(ggp[k], rgp[k], mag[name], u=u, what=name)
@@ -62,7 +62,7 @@ def test_sc_vjp_without_parameter_output(orc):
     gx = torch.zeros(3, n, dtype=torch.float64, device="cuda")
     md.md_force_vjp(pot, x, mbox, nl, md.MD_FP64, dev(u_np), gx, None, ws)
     rgx, _, _ = oracle_vjp(orc, x_np, box, u_np)
-    assert rel(gx.cpu().numpy(), rgx) < 1e-12
+    assert_fp64(gx.cpu().numpy(), rgx, what="gx")
 
 
 def test_sc_autograd_matches_oracle(orc):
@@ -76,7 +76,7 @@ def test_sc_autograd_matches_oracle(orc):
     f = AG.sc_forces(xg, eps, a, c, mbox, nl, RC, 9, 6, md.MD_FP64, ws)
     (f * dev(u_np)).sum().backward()
     rgx, rgp, mag = oracle_vjp(orc, x_np, box, u_np)
-    assert rel(xg.grad.cpu().numpy(), rgx) < 1e-12
+    assert_fp64(xg.grad.cpu().numpy(), rgx, what="gx")
     for k, (p, name) in enumerate(((eps, "geps"), (a, "ga"), (c, "gc"))):
         MB.assert_total(p.grad.item(), rgp[k], mag[name], u=MB.U64, what=name)
 

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import SC_KW, dev, forces_gpu, gpu_list, lj_liquid, rel
+from gpu_helpers import SC_KW, assert_fp64, dev, forces_gpu, gpu_list, lj_liquid, rel
 from paper_1009_4330_amd import inputs as I
 from paper_1009_4330_amd import md
 from paper_1009_4330_amd.system import MDSystem
@@ -97,7 +97,7 @@ def test_sutton_chen_step_fp64(orc):
     for c in (1, 2, 3, 4, 5):
         assert rel(rows[:, c], ref.thermo[:, c]) < 1e-10, c
     assert np.abs(min_image_diff(gx, ref.x, box)).max() < 1e-9
-    assert rel(gf, ref.f) < 1e-9
+    assert_fp64(gf, ref.f, 1e-9)
 
 
 def test_overflow_recovery_gives_same_run(orc):
