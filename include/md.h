@@ -83,6 +83,19 @@ enum { MD_POT_LJ = 0, MD_POT_SC = 1, MD_POT_BUCK = 2 };
    own K.  md_nlist_ints() gives the buffer size that fits every K. */
 enum { MD_LAYOUT_TPA = 1, MD_LAYOUT_WPA = 64 };
 
+/* LDS-tiled layouts (md_step / md_step_nvt only).  Layout MD_LAYOUT_TILE | K,
+   K in {1, 2, 4, 8}, is the layout-K list above in neigh plus, in nl->tile, a
+   copy whose entries are 16-bit indices into a window of atoms that the force
+   kernel stages in LDS (the paper's shared-memory staging of neighbour
+   positions, section "Cell list approach", applied to the neighbour-list
+   kernels): atoms in cell order are grouped into runs of up to R consecutive
+   cells along x, and a run's window is the 3 x 3 rows of cells around it, from
+   one cell before the run to one after.  The same value as an md_kernel asks
+   md_step for that kernel; MD_KERNEL_AUTO also tries them.  Every other call
+   reads the neigh part of such a list with the K-lane kernel.  Needs at least
+   4 cells along x and 3 along y and z. */
+enum { MD_LAYOUT_TILE = 256 };
+
 /* nl->status words (device int[MD_STATUS_WORDS]). */
 enum {
   MD_ST_ERRORS = 0,    /* bit 0: list overflow, bit 1: non-finite value */
@@ -148,6 +161,8 @@ typedef struct {
   double* x_ref;       /* [3][n] positions at the last build (rebuild trigger reference) */
   int* status;         /* [MD_STATUS_WORDS], zero it once before first use */
   int half;            /* 0: full list; 1: half list (see above) */
+  unsigned short* tile;  /* nullable: md_nlist_tile_entries() 16-bit entries for the tiled
+                            layouts (MD_LAYOUT_TILE | K); written by md_step's builds */
 } md_nlist;
 
 /* Dynamic state advanced by md_step.  Units: ftm2v converts force/mass * time
@@ -170,6 +185,12 @@ size_t md_workspace_bytes(int64_t n, const md_box* box, double rl);
 /* Ints the neigh buffer must hold for n atoms and this capacity, in any
    layout K (md_step and md_autoselect may switch layouts).  0 on bad input. */
 size_t md_nlist_ints(int64_t n, int capacity);
+
+/* 16-bit entries nl->tile must hold for the tiled layouts of n atoms with
+   this capacity in this box at list radius rl (every K they take).  0 when
+   the tiled kernels do not apply to this system (too few cells, or windows
+   too large for LDS) or on bad input. */
+size_t md_nlist_tile_entries(int64_t n, int capacity, const md_box* box, double rl);
 
 /* Number of thermo rows md_step writes. */
 int md_thermo_rows(int nsteps, int thermo_every, int setup);

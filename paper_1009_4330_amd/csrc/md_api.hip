@@ -66,6 +66,16 @@ BoxK make_box(const md_box* b) {
 
 bool n_ok(int64_t n) { return n >= 1 && n <= (int64_t)MD_MAX_ATOMS; }
 
+// Lanes per atom of a list layout (the tiled flag off) and whether a layout
+// value is valid: K a power of two in [1, 64], or MD_LAYOUT_TILE | K with
+// K <= kTileMaxK.
+int lanes_of(int layout) { return layout & ~MD_LAYOUT_TILE; }
+bool is_tile(int layout) { return (layout & MD_LAYOUT_TILE) != 0; }
+bool layout_ok(int layout) {
+  const int k = lanes_of(layout);
+  return lanes_ok(k) && (!is_tile(layout) || k <= kTileMaxK);
+}
+
 md_status check_pot(const md_potential* p) {
   if (!p || !finite_pos(p->rc)) return MD_ERR_INVALID_ARG;
   if (p->kind == MD_POT_LJ) {
@@ -204,7 +214,7 @@ void timing_events(hipEvent_t* t0, hipEvent_t* t1) {
 // Key: device, potential kind, precision, log2 buckets of the largest
 // neighbour count and of the atom count (the winner moves with both: a small
 // system needs more lanes per atom to fill the chip).
-using AutoKey = std::tuple<int, int, int, int, int>;
+using AutoKey = std::tuple<int, int, int, int, int, int>;
 std::mutex g_auto_mu;
 std::map<AutoKey, md_kernel> g_auto_cache;
 
@@ -214,10 +224,12 @@ int count_bucket(int maxcount) {
   return b;
 }
 
-AutoKey auto_key(const md_potential* p, md_precision prec, int maxcount, int n) {
+// `tiled`: whether the tiled kernels were among the candidates.
+AutoKey auto_key(const md_potential* p, md_precision prec, int maxcount, int n, bool tiled) {
   int dev = 0;
   (void)hipGetDevice(&dev);
-  return std::make_tuple(dev, p->kind, (int)prec, count_bucket(maxcount), count_bucket(n));
+  return std::make_tuple(dev, p->kind, (int)prec, count_bucket(maxcount), count_bucket(n),
+                         tiled ? 1 : 0);
 }
 
 md_status force_dispatch(const md_potential* p, const ForceArgs& fa, md_precision prec,
@@ -232,10 +244,14 @@ md_status force_dispatch(const md_potential* p, const ForceArgs& fa, md_precisio
   return e == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 
-// Build a list in `layout` from positions x (sorted or input order).
+// Build a list in `layout` from positions x (sorted or input order).  A tiled
+// layout (sorted atoms only) also writes the tile list.
 md_status build_list(const double* x, int n, int sorted, const md_box* box, const int nc[3],
                      const md_cells* cells, double rl, md_nlist* nl, int layout,
                      hipStream_t s) {
+  TileGeom tg{};
+  if (is_tile(layout) && (!sorted || !nl->tile || nl->half || !tile_geom(n, nc, &tg)))
+    return MD_ERR_UNSUPPORTED;
   BuildArgs a{};
   a.x = x;
   a.n = n;
@@ -247,17 +263,25 @@ md_status build_list(const double* x, int n, int sorted, const md_box* box, cons
   a.perm = cells->perm;
   a.rl2 = rl * rl;
   a.cap = nl->capacity;
-  a.layout = layout;
+  a.layout = lanes_of(layout);
   a.neigh = nl->neigh;
   a.numneigh = nl->numneigh;
   a.x_ref = nl->x_ref;
   a.status = nl->status;
   MD_CK(launch_build(a, s));
   if (nl->half) MD_CK(launch_halve(nl->neigh, nl->numneigh, n, nl->capacity, layout, s));
+  if (is_tile(layout))
+    MD_CK(launch_tile_convert(nl->neigh, nl->numneigh, n, nl->capacity, lanes_of(layout),
+                              cells->cell_start, tg, nl->tile, nl->status, nullptr, s));
   nl->layout = layout;
   nl->rl = rl;
   return MD_OK;
 }
+
+// Steps per list build assumed when the mini-benchmark weighs a tiled
+// kernel's conversion against its force time (the LJ melt rebuilds about
+// every five steps).
+constexpr int kTileBuildEvery = 5;
 
 // Time `reps` force launches for every lanes-per-atom count K = 1, 2, ..., 64
 // (each with its own list layout) and keep the fastest.  Leaves the list in
@@ -278,7 +302,13 @@ md_status autoselect_impl(const md_potential* p, const double* x, int n, int sor
   int maxcount = 0;
   double* xq = at<double>(ws, L.xq);
   MD_CK(launch_pack_positions(x, n, xq, species(p), s));
-  for (int k = 1; k <= kWave; k *= 2) {
+  // candidates: K = 1 .. 64, then the tiled K = 1 .. 8 where they apply
+  std::vector<int> trials;
+  for (int k = 1; k <= kWave; k *= 2) trials.push_back(k);
+  TileGeom tg{};
+  if (sorted && p->kind == MD_POT_LJ && nl->tile && !nl->half && tile_geom(n, nc, &tg))
+    for (int k = 1; k <= kTileMaxK; k *= 2) trials.push_back(MD_LAYOUT_TILE | k);
+  for (int k : trials) {
     md_status st = build_list(x, n, sorted, box, nc, cells, rl, nl, k, s);
     if (st != MD_OK) return st;
     ForceArgs fa{};
@@ -289,6 +319,9 @@ md_status autoselect_impl(const md_potential* p, const double* x, int n, int sor
     fa.neigh = nl->neigh;
     fa.numneigh = nl->numneigh;
     fa.cap = nl->capacity;
+    fa.tile = nl->tile;
+    fa.cell_start = cells->cell_start;
+    fa.tg = tg;
     fa.f = at<double>(ws, L.tmp_f);   // scratch forces: the caller's f is untouched
     st = force_dispatch(p, fa, prec, k, at<double>(ws, L.sc_e), s);
     if (st != MD_OK) return st;
@@ -296,6 +329,11 @@ md_status autoselect_impl(const md_potential* p, const double* x, int n, int sor
     for (int r = 0; r < reps; ++r) {
       st = force_dispatch(p, fa, prec, k, at<double>(ws, L.sc_e), s);
       if (st != MD_OK) return st;
+      // a tiled list is also converted at every build: charge one
+      // conversion per kTileBuildEvery force evaluations
+      if (is_tile(k) && r % kTileBuildEvery == 0)
+        MD_CK(launch_tile_convert(nl->neigh, nl->numneigh, n, nl->capacity, lanes_of(k),
+                                  cells->cell_start, tg, nl->tile, nl->status, nullptr, s));
     }
     MD_CK(hipEventRecord(e1, s));
     MD_CK(hipEventSynchronize(e1));
@@ -312,7 +350,7 @@ md_status autoselect_impl(const md_potential* p, const double* x, int n, int sor
   maxcount = words[MD_ST_MAXNEIGH];
   MD_CK(hipEventDestroy(e0));
   MD_CK(hipEventDestroy(e1));
-  if (win != kWave) {
+  if (win != trials.back()) {
     md_status st = build_list(x, n, sorted, box, nc, cells, rl, nl, win, s);
     if (st != MD_OK) return st;
   }
@@ -321,16 +359,17 @@ md_status autoselect_impl(const md_potential* p, const double* x, int n, int sor
   MD_CK(hipStreamSynchronize(s));
   {
     std::lock_guard<std::mutex> lk(g_auto_mu);
-    g_auto_cache[auto_key(p, prec, maxcount, n)] = (md_kernel)win;
+    g_auto_cache[auto_key(p, prec, maxcount, n, trials.back() != kWave)] = (md_kernel)win;
   }
   *choice = (md_kernel)win;
   return MD_OK;
 }
 
 // Cached AUTO winner for this device, potential, precision and size buckets.
-bool cached_choice(const md_potential* p, md_precision prec, int maxcount, int n, int* lanes) {
+bool cached_choice(const md_potential* p, md_precision prec, int maxcount, int n, bool tiled,
+                   int* lanes) {
   std::lock_guard<std::mutex> lk(g_auto_mu);
-  auto it = g_auto_cache.find(auto_key(p, prec, maxcount, n));
+  auto it = g_auto_cache.find(auto_key(p, prec, maxcount, n, tiled));
   if (it == g_auto_cache.end()) return false;
   *lanes = (int)it->second;
   return true;
@@ -339,9 +378,10 @@ bool cached_choice(const md_potential* p, md_precision prec, int maxcount, int n
 // The lanes-per-atom count a kernel request resolves to for a list layout,
 // or 0 when the request does not match the layout.
 int resolve_lanes(md_kernel k, int layout) {
-  if (!lanes_ok(layout)) return 0;
-  if (k == MD_KERNEL_AUTO) return layout;
-  return (int)k == layout ? layout : 0;
+  if (!layout_ok(layout)) return 0;
+  const int lanes = lanes_of(layout);
+  if (k == MD_KERNEL_AUTO) return lanes;
+  return ((int)k == layout || (int)k == lanes) ? lanes : 0;
 }
 
 md_status status_from_words(const int* w) {
@@ -407,6 +447,15 @@ size_t md_nlist_ints(int64_t n, int capacity) {
     most = ints > most ? ints : most;
   }
   return most;
+}
+
+size_t md_nlist_tile_entries(int64_t n, int capacity, const md_box* box, double rl) {
+  if (!n_ok(n) || capacity < 1 || check_box(box, rl) != MD_OK) return 0;
+  int nc[3];
+  int64_t ncell;
+  TileGeom tg{};
+  if (!cell_dims(box, rl, nc, &ncell) || !tile_geom(n, nc, &tg)) return 0;
+  return tile_list_entries(n, capacity, tg);
 }
 
 int md_thermo_rows(int nsteps, int thermo_every, int setup) {
@@ -487,7 +536,7 @@ md_status md_build_neighbors(const double* x, int64_t n, const md_box* box,
                              const md_cells* cells, double rc, double skin, md_nlist* nl,
                              void* stream) {
   if (!x || !cells || !nl || !nl->neigh || !nl->numneigh || !nl->status || !n_ok(n) ||
-      nl->capacity < 1 || !(skin >= 0.0) || !std::isfinite(skin) || !lanes_ok(nl->layout) ||
+      nl->capacity < 1 || !(skin >= 0.0) || !std::isfinite(skin) || !layout_ok(nl->layout) ||
       !cells->cell_start || !cells->atom_cell || !cells->perm)
     return MD_ERR_INVALID_ARG;
   const double rl = rc + skin;
@@ -682,7 +731,7 @@ md_status md_force_vjp(const md_potential* p, const double* x, int64_t n, const 
   if ((p->kind != MD_POT_LJ && p->kind != MD_POT_SC) || (nl && nl->half))
     return MD_ERR_UNSUPPORTED;
   if (!x || !nl || !nl->neigh || !nl->numneigh || !u || !gx || !n_ok(n) || nl->capacity < 1 ||
-      (prec != MD_FP64 && prec != MD_MIXED) || !lanes_ok(nl->layout))
+      (prec != MD_FP64 && prec != MD_MIXED) || !layout_ok(nl->layout))
     return MD_ERR_INVALID_ARG;
   if ((st = check_box(box, nl->rl > p->rc ? nl->rl : p->rc)) != MD_OK) return st;
   const WsLayout L = ws_layout(n, 1);
@@ -706,7 +755,7 @@ md_status md_force_vjp(const md_potential* p, const double* x, int64_t n, const 
     double* la = at<double>(ws, L.eatom);
     double* lb = at<double>(ws, L.keatom);
     const SCK k = make_sc(p);
-    MD_CK(launch_sc_vjp(fa, k, prec, nl->layout, u, e, lam, la, lb, at<double>(ws, L.xq2), gx,
+    MD_CK(launch_sc_vjp(fa, k, prec, lanes_of(nl->layout), u, e, lam, la, lb, at<double>(ws, L.xq2), gx,
                         s));
     if (gparam) {
       SumArgs sa{};
@@ -723,7 +772,7 @@ md_status md_force_vjp(const md_potential* p, const double* x, int64_t n, const 
   }
   double* pe = gparam ? at<double>(ws, L.eatom) : nullptr;
   double* ps = gparam ? at<double>(ws, L.keatom) : nullptr;
-  MD_CK(launch_lj_vjp(fa, make_lj(p), prec, nl->layout, u, gx, pe, ps, s));
+  MD_CK(launch_lj_vjp(fa, make_lj(p), prec, lanes_of(nl->layout), u, gx, pe, ps, s));
   if (gparam) {
     SumArgs sa{};
     sa.cols = 2;
@@ -786,7 +835,7 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
       thermo_every < 1 || !(skin > 0.0) || !std::isfinite(skin) || !finite_pos(dt) ||
       !finite_pos(stt->mass) || !finite_pos(stt->ftm2v) || !finite_pos(stt->mvv2e) ||
       !finite_pos(stt->boltz) || (prec != MD_FP64 && prec != MD_MIXED) ||
-      (k != MD_KERNEL_AUTO && !lanes_ok((int)k)))
+      (k != MD_KERNEL_AUTO && !layout_ok((int)k)))
     return MD_ERR_INVALID_ARG;
   if (nl->half) return MD_ERR_UNSUPPORTED;
   const double rl = p->rc + skin;
@@ -794,10 +843,17 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
   int nc[3];
   int64_t ncell;
   if (!cell_dims(box, rl, nc, &ncell) || ncell > cells->ncell_cap) return MD_ERR_INVALID_ARG;
+  // tiled kernels: LJ, a tile buffer, and a grid they apply to
+  TileGeom tg{};
+  const bool tile_ok = p->kind == MD_POT_LJ && nl->tile && tile_geom(stt->n, nc, &tg);
+  if (k != MD_KERNEL_AUTO && is_tile((int)k) && !tile_ok) return MD_ERR_UNSUPPORTED;
   if (!setup) {
     for (int d = 0; d < 3; ++d)
       if (cells->nc[d] != nc[d]) return MD_ERR_INVALID_ARG;
-    if (!resolve_lanes(k, nl->layout)) return MD_ERR_INVALID_ARG;
+    // a run continues in the layout of its setup (tiled or not)
+    if (!layout_ok(nl->layout) || (k != MD_KERNEL_AUTO && (int)k != nl->layout))
+      return MD_ERR_INVALID_ARG;
+    if (is_tile(nl->layout) && !tile_ok) return MD_ERR_UNSUPPORTED;
   }
   const WsLayout L = ws_layout(stt->n, ncell);
   if ((st = check_ws(ws, ws_bytes, L)) != MD_OK) return st;
@@ -871,7 +927,7 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
     a.perm = cells->perm;
     a.rl2 = rl * rl;
     a.cap = nl->capacity;
-    a.layout = layout;
+    a.layout = lanes_of(layout);
     a.neigh = nl->neigh;
     a.numneigh = nl->numneigh;
     a.x_ref = nl->x_ref;
@@ -886,6 +942,10 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
     a.type_in = type ? stype : nullptr;
     a.gate = g;
     MD_CK(launch_build(a, s));
+    // the tile list from the new list, on the new cell starts
+    if (is_tile(layout))
+      MD_CK(launch_tile_convert(nl->neigh, nl->numneigh, n, nl->capacity, lanes_of(layout),
+                                cells->cell_start, tg, nl->tile, status, g, s));
     return MD_OK;
   };
 
@@ -900,6 +960,9 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
     fa.neigh = nl->neigh;
     fa.numneigh = nl->numneigh;
     fa.cap = nl->capacity;
+    fa.tile = nl->tile;
+    fa.cell_start = cells->cell_start;
+    fa.tg = tg;
     fa.f = stt->f;
     if (ev) {
       fa.ev.eatom = eatom;
@@ -979,7 +1042,7 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
       MD_CK(hipMemcpyAsync(words, status, sizeof(words), hipMemcpyDeviceToHost, s));
       MD_CK(hipStreamSynchronize(s));
       int lanes = 0;
-      if (cached_choice(p, prec, words[MD_ST_MAXNEIGH], n, &lanes)) {
+      if (cached_choice(p, prec, words[MD_ST_MAXNEIGH], n, tile_ok, &lanes)) {
         if (lanes != kernel) {
           st = build_list(stt->x, n, 1, box, nc, cells, rl, nl, lanes, s);
           if (st != MD_OK) return st;

@@ -3,6 +3,8 @@
 // used here only to find neighbours; the list itself is what the kernels of
 // its "Neighbor list approach" read).
 #include <algorithm>
+#include <climits>
+#include <cmath>
 
 #include "md_internal.hpp"
 
@@ -201,14 +203,6 @@ __device__ inline int stencil_lane(int cell, int lane, const int* nc, bool* kept
   return w[0] + nc[0] * (w[1] + nc[1] * w[2]);
 }
 
-// k-th smallest of the distinct cells {c - 1, c, c + 1} of a periodic
-// dimension with nc cells (min(nc, 3) of them).
-__device__ inline int nbr_sorted(int c, int nc, int k) {
-  if (nc < 3) return k;
-  if (c == 0) return k == 2 ? nc - 1 : k;
-  if (c == nc - 1) return k == 0 ? 0 : nc - 3 + k;
-  return c - 1 + k;
-}
 
 // The same cells along x as runs of consecutive cells: [*a, *b) for run k of
 // the returned count (1, or 2 when the stencil wraps around the box).
@@ -1151,12 +1145,6 @@ __device__ inline void build_cell_groups(const BuildArgs& a, const BuildLds& L, 
                     min(kGroup, nhome - kGroup * p), hidx + kGroup * p, lane, wave);
 }
 
-// Rank of c among the distinct cells {c - 1, c, c + 1} in increasing order
-// (see nbr_sorted).
-__device__ inline int self_rank(int c, int nc) {
-  if (nc < 3) return c;
-  return c == 0 ? 0 : (c == nc - 1 ? 2 : 1);
-}
 
 // Row segment wg (a run of up to kRowCells consecutive cells of an x row) of
 // the row path; every thread of the workgroup calls it.  The run's slabs are
@@ -1337,9 +1325,146 @@ __global__ __launch_bounds__(kBlock, 4) void k_build_rows(BuildArgs a) {
   report_max(a, mx, red);
 }
 
+// Tile list from a full list in layout K: one workgroup per run (a resident
+// grid looping over them).  Wave 0 lays out the run's window segments and
+// sorts them by first atom; each wavefront then takes run-relative groups of
+// G = 64 / K home atoms and, row by row of the tile layout, maps every listed
+// partner j to its window index: the last segment (by first atom) starting at
+// or below j, plus j's offset in it.  A partner outside the window cannot
+// occur for a list built on the same cell starts; if it did (or a window had
+// more atoms than 16 bits index), status bit 2 marks the state unusable.
+__global__ __launch_bounds__(kBlock) void k_tile_convert(const int* __restrict__ neigh,
+                                                         const int* __restrict__ numneigh, int n,
+                                                         int cap, int k,
+                                                         const int* __restrict__ cs, TileGeom g,
+                                                         unsigned short* __restrict__ tile,
+                                                         int* status, const int* gate) {
+  if (gate && *gate == 0) return;
+  __shared__ int s_lo[kTileSegs], s_len[kTileSegs], s_base[kTileSegs];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int lk = __ffs(k) - 1;
+  const int G = kWave >> lk;
+  const int rows = (int)nl_rows(cap, k);
+  const int nruns = tile_nruns(g);
+  const BlockRange br = xcd_range(nruns);
+  for (int r = br.first; r < br.end; r += br.step) {
+    const TileRun t = tile_run(g, r, cs);
+    if (wave == 0) {
+      int lo = 0, len = 0;
+      if (lane < kTileSegs) tile_segment(g, t, lane, cs, &lo, &len);
+      int inc = len;
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const int y = __shfl_up(inc, off, kWave);
+        if (lane >= off) inc += y;
+      }
+      // rank by first atom (empty segments last), ties by window order
+      const int key = len > 0 ? lo : INT_MAX;
+      int rank = 0;
+      for (int u = 0; u < kTileSegs; ++u) {
+        const int ku = __shfl(key, u, kWave);
+        rank += (ku < key || (ku == key && u < lane)) ? 1 : 0;
+      }
+      if (lane < kTileSegs) {
+        s_lo[rank] = key;
+        s_len[rank] = len;
+        s_base[rank] = inc - len;
+      }
+      if (lane == kTileSegs - 1 && inc > 65536) atomicOr(&status[MD_ST_ERRORS], 4);
+    }
+    __syncthreads();
+    const int nh = t.he - t.hb;
+    const int ngroups = (nh + G - 1) / G;
+    for (int gi = wave; gi < ngroups; gi += kBlock / kWave) {
+      const int q = gi * G + (lane >> lk);
+      const int m0 = lane & (k - 1);
+      const int i = t.hb + q;
+      const bool live = q < nh;
+      const int nn = live ? min(numneigh[i], cap) : 0;
+      const int cnt = nn > m0 ? ((nn - m0 + k - 1) >> lk) : 0;
+      int tmax = cnt;
+#pragma unroll
+      for (int off = kWave / 2; off > 0; off >>= 1) tmax = max(tmax, __shfl_xor(tmax, off, kWave));
+      // 16-bit elements of this lane's words: word tt / 2, half tt % 2
+      unsigned short* row0 =
+          tile + (((size_t)(t.hb / G + r + gi) * ((rows + 1) / 2)) * kWave + lane) * 2;
+      // consecutive entries mostly fall in the segment of the previous one
+      // (lists follow the stencil's cell order): try that first, search else
+      int c_lo = 0, c_len = 0, c_base = 0;
+      constexpr int kConv = 4;   // entries per lane whose loads go out together
+      for (int t0 = 0; t0 < tmax; t0 += kConv) {
+        int jv[kConv];
+#pragma unroll
+        for (int u = 0; u < kConv; ++u)
+          jv[u] = t0 + u < cnt ? neigh[nl_index(i, (t0 + u) * k + m0, cap, k)] : -1;
+#pragma unroll
+        for (int u = 0; u < kConv; ++u) {
+          const int tt = t0 + u;
+          if (tt >= cnt) continue;
+          const int j = jv[u];
+          if ((unsigned)(j - c_lo) >= (unsigned)c_len) {
+            int lo = 0, hi = kTileSegs;   // last segment whose first atom is <= j
+            while (hi - lo > 1) {
+              const int mid = (lo + hi) >> 1;
+              if (s_lo[mid] <= j) lo = mid; else hi = mid;
+            }
+            c_lo = s_lo[lo];
+            c_len = s_len[lo];
+            c_base = s_base[lo];
+          }
+          const int off = j - c_lo;
+          const bool in = off >= 0 && off < c_len;
+          if (!in) atomicOr(&status[MD_ST_ERRORS], 4);
+          row0[(size_t)(tt >> 1) * (2 * kWave) + (tt & 1)] =
+              (unsigned short)(in ? c_base + off : 0);
+        }
+      }
+    }
+    __syncthreads();   // segment tables are reused by the next run
+  }
+}
+
 inline unsigned blocks_for(int64_t n, int per = kBlock) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
+
+bool tile_geom(int64_t n, const int nc[3], TileGeom* g) {
+  if (nc[0] < 4 || nc[1] < 3 || nc[2] < 3 || n < 1) return false;
+  const double per_cell = (double)n / ((double)nc[0] * nc[1] * nc[2]);
+  const int rmax = std::min(kTileMaxR, (nc[0] - 2) & ~1);
+  const int cap_atoms = kTileLdsBytes / (3 * (int)sizeof(double));
+  for (int R = rmax; R >= 2; R -= 2) {
+    const double mean = 9.0 * (R + 2) * per_cell;
+    // room for density fluctuations: the mean plus eight standard deviations
+    const int need = (int)std::ceil(mean + 8.0 * std::sqrt(mean) + 64.0);
+    const int wcap = (need + 63) & ~63;
+    if (wcap <= cap_atoms) {
+      g->nc[0] = nc[0];
+      g->nc[1] = nc[1];
+      g->nc[2] = nc[2];
+      g->R = R;
+      g->runs_x = (nc[0] + R - 1) / R;
+      g->wcap = wcap;
+      return true;
+    }
+  }
+  return false;
+}
+
+size_t tile_list_entries(int64_t n, int cap, const TileGeom& g) {
+  size_t most = 0;
+  for (int k = 1; k <= kTileMaxK; k *= 2)
+    most = std::max(most, tile_groups((int)n, k, tile_nruns(g)) * tile_words(cap, k) * kWave * 2);
+  return most;
+}
+
+hipError_t launch_tile_convert(const int* neigh, const int* numneigh, int n, int cap, int k,
+                               const int* cell_start, const TileGeom& g, unsigned short* tile,
+                               int* status, const int* gate, hipStream_t s) {
+  k_tile_convert<<<resident_grid(8, tile_nruns(g)), kBlock, 0, s>>>(
+      neigh, numneigh, n, cap, k, cell_start, g, tile, status, gate);
+  return hipGetLastError();
+}
 
 unsigned resident_grid(int per_cu, int64_t need) {
   // compute-unit count per device, looked up once

@@ -333,8 +333,9 @@ struct Acc {
 // x' = x + dt v' and the half-skin check, or, on the last step, v = vh and
 // the state's x and f stored.
 template <bool FUSED>
-__device__ inline void finish_atom(const FK& a, const Acc& acc, int i, bool own, double xi,
-                                   double yi, double zi, bool ev, double e_extra) {
+__device__ inline void finish_atom_with(const FK& a, const Acc& acc, int i, bool own, double xi,
+                                        double yi, double zi, bool ev, double e_extra,
+                                        const double* vi, const double* xri) {
   const IntArgs& in = a.in;
   if (!FUSED) {
     if (own) acc.store(a, i, ev, e_extra);
@@ -351,7 +352,7 @@ __device__ inline void finish_atom(const FK& a, const Acc& acc, int i, bool own,
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       finite = finite && isfinite(fq[d]);
-      vh[d] = in.v[d * n + i] + in.dtfm * fq[d];
+      vh[d] = vi[d] + in.dtfm * fq[d];
     }
     if (in.keatom) in.keatom[i] = vh[0] * vh[0] + vh[1] * vh[1] + vh[2] * vh[2];
     if (in.mode == MD_INT_LAST) {
@@ -367,7 +368,7 @@ __device__ inline void finish_atom(const FK& a, const Acc& acc, int i, bool own,
         const double vn = vh[d] + in.dtfm * fq[d];
         xn[d] = xo[d] + in.dt * vn;
         in.v[d * n + i] = vn;
-        dd[d] = xn[d] - in.xr[d * n + i];
+        dd[d] = xn[d] - xri[d];
         finite = finite && isfinite(xn[d]);
       }
     }
@@ -378,6 +379,25 @@ __device__ inline void finish_atom(const FK& a, const Acc& acc, int i, bool own,
     const unsigned long long bad = __ballot(own && !finite);
     if ((threadIdx.x & (kWave - 1)) == 0 && bad) atomicOr(&in.status[MD_ST_ERRORS], 2);
   }
+}
+
+// The state an atom's integration reads (velocity and list reference
+// position), loaded ahead by kernels that want the loads in flight early.
+__device__ inline void load_int_state(const FK& a, int i, bool own, double* vi, double* xri) {
+  const int n = a.n;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    vi[d] = own ? a.in.v[d * n + i] : 0.0;
+    xri[d] = own && a.in.mode == MD_INT_STEP ? a.in.xr[d * n + i] : 0.0;
+  }
+}
+
+template <bool FUSED>
+__device__ inline void finish_atom(const FK& a, const Acc& acc, int i, bool own, double xi,
+                                   double yi, double zi, bool ev, double e_extra) {
+  double vi[3] = {0.0, 0.0, 0.0}, xri[3] = {0.0, 0.0, 0.0};
+  if (FUSED) load_int_state(a, i, own, vi, xri);
+  finish_atom_with<FUSED>(a, acc, i, own, xi, yi, zi, ev, e_extra, vi, xri);
 }
 
 // ------------------------------------------------------------------ LJ --
@@ -427,6 +447,202 @@ __global__ __launch_bounds__(kBlock) void k_lj(FK a, LJK p) {
   });
   if (K > 1) acc.reduce<K>(EV);
   finish_atom<FUSED>(a, acc, ln.i, ln.live && ln.s == 0, xi, yi, zi, EV, 0.0);
+}
+
+// ---------------------------------------------------- LJ, LDS-tiled --
+
+// Window positions a tiled workgroup holds in LDS (x, y and z arrays of
+// kTileCap atoms each; the fixed stride lets one address serve all three).
+constexpr int kTileCap = kTileLdsBytes / (3 * (int)sizeof(double));
+
+struct TileArgs {
+  const unsigned short* __restrict__ tile;
+  const int* __restrict__ cs;
+  TileGeom g;
+};
+
+// Tiled LJ (lists in layout MD_LAYOUT_TILE | K): one workgroup per run.  The
+// run's window -- every atom any of its atoms can list -- is staged into LDS
+// with coalesced loads of the packed records, one segment of consecutive
+// atoms after another; each wavefront then takes groups of G = 64 / K of the
+// run's atoms, K lanes each as in k_lj, and gathers its partners' positions
+// from LDS through the 16-bit window indices of the tile list.  Everything a
+// wavefront's first group reads from memory (list lengths, the words of up to
+// 16 entries per lane, and with fused integration the velocity and reference
+// position) is requested together with the staging loads, so one memory
+// latency covers them all; longer lists load further words 16 entries at a
+// time.  The arithmetic per pair (FP64 separation, minimum image off the
+// interior, the cutoff test, the pair function, accumulation, the fused
+// integration) is k_lj's.  A window with more atoms than the LDS holds (a
+// rare density fluctuation) reads the same records from memory instead.
+constexpr int kTileWords = 8;    // 32-bit tile words (two entries each) a lane holds at once
+
+template <int PREC, bool EV, int K, bool FUSED>
+__global__ __launch_bounds__(kTileBlock, 2) void k_lj_tile(FK a, LJK p, TileArgs ta) {
+  __shared__ double wpos[3 * kTileCap];
+  __shared__ int s_lo[kTileSegs], s_base[kTileSegs + 1];
+  if (a.clear && blockIdx.x == 0 && threadIdx.x == 0) *a.clear = 0;
+  const TileGeom& g = ta.g;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int r = xcd_block();
+  const TileRun t = tile_run(g, r, ta.cs);
+  if (wave == 0) {
+    int lo = 0, len = 0;
+    if (lane < kTileSegs) tile_segment(g, t, lane, ta.cs, &lo, &len);
+    int inc = len;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const int y = __shfl_up(inc, off, kWave);
+      if (lane >= off) inc += y;
+    }
+    if (lane < kTileSegs) {
+      s_lo[lane] = lo;
+      s_base[lane] = inc - len;
+    }
+    if (lane == kTileSegs - 1) s_base[kTileSegs] = inc;
+  }
+  constexpr int G = kWave / K;
+  const int nh = t.he - t.hb;
+  const int ngroups = (nh + G - 1) / G;
+  const int T = (int)tile_words(a.cap, K);
+  const unsigned* __restrict__ tw = reinterpret_cast<const unsigned*>(ta.tile);
+  // per-group lane data: atom, list length and the first words of its entries
+  int q = 0, i = 0, count = 0;
+  bool live = false;
+  unsigned wd[kTileWords];
+  double vi[3] = {0.0, 0.0, 0.0}, xri[3] = {0.0, 0.0, 0.0};
+  const int sl = lane % K;
+  auto words = [&](int gi, int c) {
+    const size_t base = ((size_t)(t.hb / G + r + gi) * T + kTileWords * c) * kWave + lane;
+#pragma unroll
+    for (int u = 0; u < kTileWords; ++u)
+      wd[u] = kTileWords * c + u < T ? tw[base + (size_t)u * kWave] : 0u;
+  };
+  auto open_group = [&](int gi) {
+    q = gi * G + lane / K;
+    live = q < nh;
+    i = t.hb + (live ? q : nh - 1);
+    words(gi, 0);
+    const int nn = live ? min(a.numneigh[i], a.cap) : 0;
+    count = nn > sl ? (nn - sl + K - 1) / K : 0;
+    if (FUSED) load_int_state(a, i, live && sl == 0, vi, xri);
+  };
+  if (wave < ngroups) open_group(wave);
+  __syncthreads();
+  const int W = s_base[kTileSegs];
+  const bool fits = W <= kTileCap;
+  // window index -> atom: the last segment whose window base is <= w
+  auto atom_of = [&](int w) {
+    int lo = 0, hi = kTileSegs;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_base[mid] <= w) lo = mid; else hi = mid;
+    }
+    return s_lo[lo] + (w - s_base[lo]);
+  };
+  const __amdgpu_buffer_rsrc_t xr = buffer_of(a.xq, a.n);
+  if (fits) {
+    constexpr int kStage = 4;   // window atoms per thread whose loads go out together
+    for (int q0 = 0; q0 < W; q0 += kStage * kTileBlock) {
+      f64x2 xy[kStage];
+      double zz[kStage];
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) {
+        const int qq = q0 + u * kTileBlock + (int)threadIdx.x;
+        const unsigned off = qq < W ? (unsigned)atom_of(qq) * 32u : 0u;
+        xy[u] = load16(xr, off);
+        zz[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(xr, (int)off, 16, 0));
+      }
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) {
+        const int qq = q0 + u * kTileBlock + (int)threadIdx.x;
+        if (qq < W) {
+          wpos[qq] = xy[u].x;
+          wpos[kTileCap + qq] = xy[u].y;
+          wpos[2 * kTileCap + qq] = zz[u];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int hs = tile_home_segment(g, t);
+  const int wh0 = s_base[hs] + (t.hb - s_lo[hs]);   // window index of the run's first atom
+  // the pair loop, compiled once for positions in LDS and once for the
+  // fallback that reads them from memory (kept apart so that LDS reads never
+  // wait on the fallback's loads)
+  auto groups = [&](auto fits_c) {
+    constexpr bool FITS = decltype(fits_c)::value;
+    auto pos = [&](int w, double& x, double& y, double& z) {
+      if constexpr (FITS) {
+        x = wpos[w];
+        y = wpos[kTileCap + w];
+        z = wpos[2 * kTileCap + w];
+      } else {
+        const unsigned off = (unsigned)atom_of(w) * 32u;
+        const f64x2 v2 = load16(xr, off);
+        x = v2.x;
+        y = v2.y;
+        z = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(xr, (int)off, 16, 0));
+      }
+    };
+  for (int gi = wave; gi < ngroups; gi += kTileBlock / kWave) {
+    if (gi != wave) open_group(gi);
+    int tm = count;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) tm = max(tm, __shfl_xor(tm, off, kWave));
+    const int tmax = __builtin_amdgcn_readfirstlane(tm);
+    double xi, yi, zi;
+    pos(wh0 + (live ? q : nh - 1), xi, yi, zi);
+    const bool wrap = !__all(interior(xi, yi, zi, a));
+    Acc acc;
+    for (int c = 0; 2 * kTileWords * c < tmax; ++c) {
+      if (c > 0) words(gi, c);
+#pragma unroll
+      for (int b = 0; b < 2 * kTileWords; b += kUnroll) {
+        const int tt = 2 * kTileWords * c + b;
+        if (tt >= tmax) break;
+        double dx[kUnroll], dy[kUnroll], dz[kUnroll];
+        bool ok[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int e = b + u;
+          ok[u] = tt + u < count;
+          const int w = ok[u] ? (int)((wd[e >> 1] >> (16 * (e & 1))) & 0xFFFFu) : 0;
+          double xj, yj, zj;
+          pos(w, xj, yj, zj);
+          dx[u] = xi - xj;
+          dy[u] = yi - yj;
+          dz[u] = zi - zj;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          if (wrap) {
+            dx[u] = min_image(dx[u], a.box.L[0], a.box.inv[0]);
+            dy[u] = min_image(dy[u], a.box.L[1], a.box.inv[1]);
+            dz[u] = min_image(dz[u], a.box.L[2], a.box.inv[2]);
+          }
+          const double sv = dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u];
+          const bool use = ok[u] && sv < p.rc2;
+          double gg, phi;
+          lj_pair<PREC>(use ? sv : 1.0, p, gg, phi);
+          gg = use ? gg : 0.0;
+          acc.add_force(gg, dx[u], dy[u], dz[u]);
+          if (EV) {
+            acc.e += use ? phi - p.ecut : 0.0;
+            acc.add_virial(gg, dx[u], dy[u], dz[u]);
+          }
+        }
+      }
+    }
+    if (K > 1) acc.reduce<K>(EV);
+    finish_atom_with<FUSED>(a, acc, i, live && sl == 0, xi, yi, zi, EV, 0.0, vi, xri);
+  }
+  };
+  if (fits)
+    groups(std::true_type());
+  else
+    groups(std::false_type());
 }
 
 // LJ from a half list (each pair once, Newton's third law): atom i's own sum
@@ -919,7 +1135,41 @@ hipError_t launch_pack_positions(const double* x, int n, double* xq, const int* 
   return hipGetLastError();
 }
 
+// Tiled LJ: one workgroup of kTileBlock threads per run.
+static hipError_t launch_lj_tile(const ForceArgs& a, const LJK& p, int prec, int lanes,
+                                 hipStream_t s) {
+  const FK k = make_fk(a);
+  const bool ev = a.ev.eatom || a.ev.vatom;
+  const TileArgs ta{a.tile, a.cell_start, a.tg};
+  const unsigned grid = (unsigned)tile_nruns(a.tg);
+  const bool fused = a.in.mode != MD_INT_NONE;
+  auto go = [&](auto kern) -> hipError_t {
+    if (a.t0 && a.t1)
+      hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kTileBlock), 0, s, a.t0, a.t1, 0, k, p, ta);
+    else
+      kern<<<grid, kTileBlock, 0, s>>>(k, p, ta);
+    return hipGetLastError();
+  };
+  auto pick = [&](auto kc) -> hipError_t {
+    constexpr int K = decltype(kc)::value;
+    if (prec == MD_FP64) {
+      if (fused) return ev ? go(k_lj_tile<MD_FP64, true, K, true>) : go(k_lj_tile<MD_FP64, false, K, true>);
+      return ev ? go(k_lj_tile<MD_FP64, true, K, false>) : go(k_lj_tile<MD_FP64, false, K, false>);
+    }
+    if (fused) return ev ? go(k_lj_tile<MD_MIXED, true, K, true>) : go(k_lj_tile<MD_MIXED, false, K, true>);
+    return ev ? go(k_lj_tile<MD_MIXED, true, K, false>) : go(k_lj_tile<MD_MIXED, false, K, false>);
+  };
+  switch (lanes) {
+    case 1: return pick(std::integral_constant<int, 1>());
+    case 2: return pick(std::integral_constant<int, 2>());
+    case 4: return pick(std::integral_constant<int, 4>());
+    case 8: return pick(std::integral_constant<int, 8>());
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_lj(const ForceArgs& a, const LJK& p, int prec, int lanes, hipStream_t s) {
+  if (lanes & MD_LAYOUT_TILE) return launch_lj_tile(a, p, prec, lanes & ~MD_LAYOUT_TILE, s);
   const FK k = make_fk(a);
   const bool ev = a.ev.eatom || a.ev.vatom;
   return with_lanes(lanes, [&](auto kc) -> hipError_t {

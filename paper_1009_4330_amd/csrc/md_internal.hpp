@@ -284,6 +284,127 @@ struct BuildArgs {
 };
 hipError_t launch_build(const BuildArgs& a, hipStream_t s);
 
+// k-th smallest of the distinct cells {c - 1, c, c + 1} of a periodic
+// dimension with nc cells (min(nc, 3) of them).
+__device__ inline int nbr_sorted(int c, int nc, int k) {
+  if (nc < 3) return k;
+  if (c == 0) return k == 2 ? nc - 1 : k;
+  if (c == nc - 1) return k == 0 ? 0 : nc - 3 + k;
+  return c - 1 + k;
+}
+
+// Rank of c among the distinct cells {c - 1, c, c + 1} in increasing order
+// (see nbr_sorted).
+__device__ inline int self_rank(int c, int nc) {
+  if (nc < 3) return c;
+  return c == 0 ? 0 : (c == nc - 1 ? 2 : 1);
+}
+
+// ------------------------------------------------ LDS-tiled force kernels --
+// Atoms in cell order are grouped into runs of up to R consecutive cells of
+// one x row of cells.  The workgroup that owns a run stages its window -- the
+// 3 x 3 rows of cells around the run's row (in the sorted order of their
+// distinct row indices), each from cell x0 - 1 to x0 + Rr, where every list
+// partner of the run's atoms lies -- into LDS, and gathers neighbours there.
+// The window of a row is one contiguous range of atoms, or two where it wraps
+// around the box in x.  A tile list holds, per entry, the partner's index in
+// its run's window (16 bits), in the K-lane row layout with groups of
+// G = 64 / K atoms counted from each run's first atom, two consecutive
+// entries of a lane in one 32-bit word (entry t = m / K of the lane in half
+// t % 2 of word t / 2, so one coalesced load brings each lane two entries):
+// with T = ceil(ceil(cap / K) / 2) words per lane, entry m of atom i (run r,
+// first atom hb) is 16-bit element
+//   (((hb / G + r + (i - hb) / G) * T + m / K / 2) * 64 + ((i - hb) % G) * K + m % K) * 2
+//     + (m / K) % 2.
+constexpr int kTileMaxR = 16;                    // home cells per run, at most
+constexpr int kTileSegs = 18;                    // window segments: 9 rows x (1 or 2)
+constexpr int kTileMaxK = 8;                     // lanes per atom of the tiled kernels
+constexpr int kTileBlock = 512;                  // threads per workgroup of the tiled kernels
+constexpr int kTileLdsBytes = 48 * 1024;         // LDS budget of a window's positions
+struct TileGeom {
+  int nc[3];
+  int R;        // home cells per run: even, 2 <= R <= nc[0] - 2
+  int runs_x;   // runs per x row: ceil(nc[0] / R)
+  int wcap;     // window atoms that fit in LDS (larger windows read positions from memory)
+};
+__host__ __device__ inline int tile_nruns(const TileGeom& g) {
+  return g.runs_x * g.nc[1] * g.nc[2];
+}
+__host__ __device__ inline size_t tile_groups(int n, int k, int nruns) {
+  return (size_t)((n + kWaveConst / k - 1) / (kWaveConst / k)) + (size_t)nruns;
+}
+// 32-bit words per lane of a tile list row group.
+__host__ __device__ inline size_t tile_words(int cap, int k) { return (nl_rows(cap, k) + 1) / 2; }
+// 16-bit element of entry m of atom i (run r with first atom hb) in a tile list.
+__host__ __device__ inline size_t tile_index(int i, int m, int hb, int r, int cap, int k) {
+  const int g = kWaveConst / k;
+  const int t = m / k;
+  return (((size_t)(hb / g + r + (i - hb) / g) * tile_words(cap, k) + (size_t)(t / 2)) *
+              kWaveConst +
+          (size_t)(((i - hb) % g) * k + m % k)) * 2 + (size_t)(t % 2);
+}
+// Tile geometry for n atoms in a grid nc (false: the tiled kernels do not
+// apply -- fewer than 4 cells along x or 3 along y / z, or no run's mean
+// window fits the LDS budget).
+bool tile_geom(int64_t n, const int nc[3], TileGeom* g);
+// 16-bit entries a tile list needs for every K the tiled kernels take.
+size_t tile_list_entries(int64_t n, int cap, const TileGeom& g);
+// Tile list from a full list in layout K (atoms in cell order, cell_start of
+// the same build): each partner index becomes its index in the window of the
+// atom's run.  Gated like the build.
+hipError_t launch_tile_convert(const int* neigh, const int* numneigh, int n, int cap, int k,
+                               const int* cell_start, const TileGeom& g, unsigned short* tile,
+                               int* status, const int* gate, hipStream_t s);
+
+// Run r of a tile geometry: its row (y, z), first cell x0, cells Rr, and the
+// range [hb, he) of its atoms (cell order).
+struct TileRun {
+  int x0, Rr, y, z, hb, he;
+};
+__device__ inline TileRun tile_run(const TileGeom& g, int r, const int* __restrict__ cs) {
+  TileRun t;
+  const int rx = r % g.runs_x, row = r / g.runs_x;
+  t.y = row % g.nc[1];
+  t.z = row / g.nc[1];
+  t.x0 = rx * g.R;
+  t.Rr = min(g.R, g.nc[0] - t.x0);
+  const int base = (t.z * g.nc[1] + t.y) * g.nc[0];
+  t.hb = cs[base + t.x0];
+  t.he = cs[base + t.x0 + t.Rr];
+  return t;
+}
+// Segment l (0 <= l < kTileSegs) of run t's window: row e = l / 2 of the 3 x 3
+// rows, piece l % 2; [*lo, *lo + *len) in cell order.  A row's cells x0 - 1
+// .. x0 + Rr are one range, or two when they wrap in x: (cell nc0 - 1 | cells
+// 0 .. Rr) for the first run of a row, (cells x0 - 1 .. nc0 - 1 | cell 0) for
+// one ending at the last cell.  Segments in increasing l are the window order.
+__device__ inline void tile_segment(const TileGeom& g, const TileRun& t, int l,
+                                    const int* __restrict__ cs, int* lo, int* len) {
+  const int e = l >> 1, piece = l & 1;
+  const int nc0 = g.nc[0];
+  const int zr = nbr_sorted(t.z, g.nc[2], e / 3), yr = nbr_sorted(t.y, g.nc[1], e % 3);
+  const int base = (zr * g.nc[1] + yr) * nc0;
+  int a = 0, b = 0;   // cell range [a, b) of the row
+  if (t.x0 == 0) {
+    a = piece == 0 ? nc0 - 1 : 0;
+    b = piece == 0 ? nc0 : t.Rr + 1;
+  } else if (t.x0 + t.Rr == nc0) {
+    a = piece == 0 ? t.x0 - 1 : 0;
+    b = piece == 0 ? nc0 : 1;
+  } else if (piece == 0) {
+    a = t.x0 - 1;
+    b = t.x0 + t.Rr + 1;
+  }
+  *lo = cs[base + a];
+  *len = cs[base + b] - *lo;
+}
+// The window segment holding the run's own atoms (the run's row, the piece
+// that starts at x0 - 1, or at x0 = 0 for the first run of a row).
+__device__ inline int tile_home_segment(const TileGeom& g, const TileRun& t) {
+  const int e = self_rank(t.z, g.nc[2]) * 3 + self_rank(t.y, g.nc[1]);
+  return 2 * e + (t.x0 == 0 ? 1 : 0);
+}
+
 // Forces.  kernel: MD_KERNEL_TPA / MD_KERNEL_WPA.  clear (nullable) is zeroed
 // by the first thread, after every rebuild kernel of the step has finished.
 // Positions come packed: atom i at xq[4 i .. 4 i + 2], xq[4 i + 3] = 0, so one
@@ -301,6 +422,11 @@ struct ForceArgs {
   int* clear;
   hipEvent_t t0, t1;     // non-null: timed launch
   IntArgs in;            // mode MD_INT_NONE unless md_step fuses integration
+  // tiled kernels (kernel K | MD_LAYOUT_TILE): the tile list, the cell starts
+  // of its build and the geometry
+  const unsigned short* tile;
+  const int* cell_start;
+  TileGeom tg;
 };
 hipError_t launch_pack_positions(const double* x, int n, double* xq, const int* type,
                                  hipStream_t s);

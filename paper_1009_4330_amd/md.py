@@ -24,13 +24,14 @@ MD_KERNEL_AUTO, MD_KERNEL_TPA, MD_KERNEL_WPA = 0, 1, 64
 LANES = (1, 2, 4, 8, 16, 32, 64)
 MD_EFLAG, MD_VFLAG = 1, 2
 MD_POT_LJ, MD_POT_SC, MD_POT_BUCK = 0, 1, 2
-MD_LAYOUT_TPA, MD_LAYOUT_WPA = 1, 64
+MD_LAYOUT_TPA, MD_LAYOUT_WPA, MD_LAYOUT_TILE = 1, 64, 256
+TILE_LANES = (1, 2, 4, 8)         # lanes per atom of the tiled layouts
 MD_ST_ERRORS, MD_ST_MAXNEIGH, MD_ST_BUILDS, MD_ST_REBUILD, MD_STATUS_WORDS = 0, 1, 2, 3, 8
 EXPORTS = ("md_workspace_bytes", "md_nlist_ints", "md_thermo_rows", "md_bin_cells", "md_sort_atoms",
            "md_build_neighbors", "md_compute_forces", "md_step", "md_step_nvt", "md_force_vjp",
            "md_autoselect", "md_nlist_status", "md_timing_enable", "md_timing_read",
            "md_status_string", "md_compute_forces_noalloc",
-           "md_compute_forces_noalloc_bytes")
+           "md_compute_forces_noalloc_bytes", "md_nlist_tile_entries")
 
 
 class MDError(RuntimeError):
@@ -62,7 +63,8 @@ class md_cells(ctypes.Structure):
 class md_nlist(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int), ("layout", ctypes.c_int), ("rl", ctypes.c_double),
                 ("neigh", ctypes.c_void_p), ("numneigh", ctypes.c_void_p),
-                ("x_ref", ctypes.c_void_p), ("status", ctypes.c_void_p), ("half", ctypes.c_int)]
+                ("x_ref", ctypes.c_void_p), ("status", ctypes.c_void_p), ("half", ctypes.c_int),
+                ("tile", ctypes.c_void_p)]
 
 
 MD_NHC_MAX, MD_NHC_STATE = 8, 20
@@ -97,6 +99,8 @@ def lib() -> ctypes.CDLL:
         L.md_workspace_bytes.argtypes = [I64, P(md_box), D]
         L.md_nlist_ints.restype = ctypes.c_size_t
         L.md_nlist_ints.argtypes = [I64, I]
+        L.md_nlist_tile_entries.restype = ctypes.c_size_t
+        L.md_nlist_tile_entries.argtypes = [I64, I, P(md_box), D]
         L.md_thermo_rows.restype = I
         L.md_thermo_rows.argtypes = [I, I, I]
         L.md_status_string.restype = ctypes.c_char_p
@@ -124,7 +128,8 @@ def lib() -> ctypes.CDLL:
         L.md_timing_read.argtypes = [P(I64), P(D)]
         for name in EXPORTS:
             if name not in ("md_workspace_bytes", "md_nlist_ints", "md_thermo_rows",
-                            "md_status_string", "md_compute_forces_noalloc_bytes"):
+                            "md_status_string", "md_compute_forces_noalloc_bytes",
+                            "md_nlist_tile_entries"):
                 getattr(L, name).restype = I
         _lib = L
     return _lib
@@ -219,18 +224,23 @@ class Cells:
 
 class NList:
     """Device neighbour-list arrays + their md_nlist descriptor.  The neigh
-    buffer is sized for every layout K (md_nlist_ints)."""
+    buffer is sized for every layout K (md_nlist_ints); tile_entries > 0 adds
+    the 16-bit buffer of the tiled layouts (md_nlist_tile_entries)."""
 
     def __init__(self, n: int, capacity: int, layout: int = MD_LAYOUT_TPA, device="cuda",
-                 half: bool = False):
+                 half: bool = False, tile_entries: int = 0):
         self.neigh = torch.zeros(md_nlist_ints(n, capacity), dtype=torch.int32, device=device)
         self.numneigh = torch.zeros(n, dtype=torch.int32, device=device)
         self.x_ref = torch.zeros(3, n, dtype=torch.float64, device=device)
         self.status = torch.zeros(MD_STATUS_WORDS, dtype=torch.int32, device=device)
+        # torch has no uint16 arithmetic on every build: int16 storage, same bytes
+        self.tile = (torch.zeros(tile_entries, dtype=torch.int16, device=device)
+                     if tile_entries > 0 else None)
         self.c = md_nlist(capacity=capacity, layout=layout, rl=0.0,
                           neigh=self.neigh.data_ptr(), numneigh=self.numneigh.data_ptr(),
                           x_ref=self.x_ref.data_ptr(), status=self.status.data_ptr(),
-                          half=1 if half else 0)
+                          half=1 if half else 0,
+                          tile=self.tile.data_ptr() if self.tile is not None else None)
 
     @property
     def capacity(self) -> int:
@@ -243,7 +253,7 @@ class NList:
     def rows(self) -> torch.Tensor:
         """The list as an [n][capacity] tensor (row i = neighbours of atom i),
         gathered through the layout-K index of include/md.h."""
-        n, cap, k = self.numneigh.numel(), self.c.capacity, self.c.layout
+        n, cap, k = self.numneigh.numel(), self.c.capacity, self.c.layout & ~MD_LAYOUT_TILE
         dev = self.neigh.device
         i = torch.arange(n, device=dev, dtype=torch.int64)[:, None]
         m = torch.arange(cap, device=dev, dtype=torch.int64)[None, :]
@@ -291,6 +301,11 @@ def md_nlist_ints(n: int, capacity: int) -> int:
     if k == 0:
         raise MDError(MD_ERR_INVALID_ARG, "md_nlist_ints")
     return k
+
+
+def md_nlist_tile_entries(n: int, capacity: int, box: md_box, rl: float) -> int:
+    """Entries of the tiled layouts' 16-bit buffer (0: they do not apply)."""
+    return int(lib().md_nlist_tile_entries(int(n), int(capacity), ctypes.byref(box), float(rl)))
 
 
 def md_thermo_rows(nsteps: int, thermo_every: int, setup: int) -> int:

@@ -18,7 +18,8 @@ from .inputs import Workload, pair_table
 
 PREC = {"fp64": md.MD_FP64, "mixed": md.MD_MIXED}
 KERNEL = {"auto": md.MD_KERNEL_AUTO, "tpa": md.MD_KERNEL_TPA, "wpa": md.MD_KERNEL_WPA,
-          **{f"k{k}": k for k in md.LANES}}
+          **{f"k{k}": k for k in md.LANES},
+          **{f"t{k}": md.MD_LAYOUT_TILE | k for k in md.TILE_LANES}}
 
 
 def potential_of(w: Workload, type_tensor: Optional[torch.Tensor] = None,
@@ -50,6 +51,7 @@ class MDSystem:
         """nvt = (t_target, t_damp, chain length) runs md_step_nvt (thermo rows
         of nine columns) instead of NVE md_step."""
         self.w = w
+        self.device = device
         self.nhc = md.NHC(*nvt, device=device) if nvt else None
         self.cols = 9 if nvt else 8
         self.prec = PREC[prec]
@@ -68,13 +70,19 @@ class MDSystem:
                               w.mass, u.ftm2v, u.mvv2e, u.boltz)
         ncell = int(np.prod([math.floor(L / self.rl) for L in w.box]))
         self.cells = md.Cells(n, ncell, device)
-        self.nl = md.NList(n, capacity or capacity_guess(w), md.MD_LAYOUT_TPA, device)
+        self.nl = self._nlist(capacity or capacity_guess(w), md.MD_LAYOUT_TPA)
         self.ws = md.workspace(n, self.box, self.rl, device)
         self.ready = False
         self.steps_done = 0
-        self.device = device
 
     # -- helpers -------------------------------------------------------------
+    def _nlist(self, cap: int, layout: int) -> md.NList:
+        """A list of this capacity, with the tiled layouts' buffer where they
+        apply (LJ; enough cells)."""
+        tiles = (md.md_nlist_tile_entries(self.n, cap, self.box, self.rl)
+                 if self.w.potential == "lj" else 0)
+        return md.NList(self.n, cap, layout, self.device, tile_entries=tiles)
+
     def _tensors(self):
         s = self.state
         out = [s.x, s.v, s.f, s.id, self.nl.x_ref, self.nl.status]
@@ -90,8 +98,7 @@ class MDSystem:
 
     def _grow(self, need: int):
         cap = int(need * 1.2) + 16
-        layout = self.nl.layout
-        self.nl = md.NList(self.n, cap, layout, self.device)
+        self.nl = self._nlist(cap, self.nl.layout)
 
     def _step(self, kernel, nsteps, every, setup, rows):
         if self.nhc is None:

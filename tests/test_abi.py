@@ -243,3 +243,29 @@ def test_noalloc_scratch_limit_is_checked_on_the_host(mdlib):
     assert lib.md_compute_forces_noalloc(R(lj), fake, big, R(box), R(nl), 0, 2, ev, fake, fake,
                                          None) == mdlib.MD_ERR_INVALID_ARG
     assert mdlib.status_string(mdlib.MD_ERR_SCRATCH) != "unknown status"
+
+
+def test_tile_entries_host_logic(mdlib):
+    """The tiled layouts apply with at least 4 cells along x and 3 along y, z
+    and a window that fits the LDS; their buffer covers every K they take."""
+    lib = mdlib.lib()
+    box = mdlib.make_box(I.LJ_256K.box)
+    e = mdlib.md_nlist_tile_entries(256000, 160, box, 2.8)
+    assert e > 0 and e % 128 == 0
+    # at least one 32-bit word pair per row group and lane for each entry
+    assert e >= 2 * 256000 * 160 // 2
+    assert mdlib.md_nlist_tile_entries(4000, 160, mdlib.make_box(I.LJ_4K.box), 2.8) > 0
+    # 3 cells along x (16.8 / 5.3): no tiled layout
+    assert mdlib.md_nlist_tile_entries(4000, 160, mdlib.make_box((16.8, 16.8, 16.8)), 5.3) == 0
+    # rc 5 sigma at density 0.8442: windows far larger than the LDS
+    assert mdlib.md_nlist_tile_entries(108000, 700, mdlib.make_box(I.LJ_HI_108K.box), 5.3) == 0
+    assert lib.md_nlist_tile_entries(0, 160, ctypes.byref(box), 2.8) == 0
+    # a tiled layout is refused where the K-lane layout is the only option
+    fake = ctypes.c_void_p(0x1000)
+    R = ctypes.byref
+    nl = mdlib.md_nlist(capacity=100, layout=mdlib.MD_LAYOUT_TILE | 16, rl=2.8, neigh=0x1000,
+                        numneigh=0x1000, x_ref=0x1000, status=0x1000)
+    lj = mdlib.lj_potential(2.5)
+    bx = mdlib.make_box(I.LJ_4K.box)
+    assert lib.md_compute_forces(R(lj), fake, 4000, R(bx), R(nl), 0, 0, 0, fake, None, fake,
+                                 1 << 30, None) == mdlib.MD_ERR_INVALID_ARG
