@@ -848,3 +848,186 @@ done:
   free(f);
   return st;
 }
+
+/* ------------------------------------------- isotropic NPT (MTK + chains) -- */
+
+/* sinh(x) / x, by its Taylor series where x is small (the series to x^8 is
+   exact to rounding for |x| < 1e-3). */
+static double sinhc(double x) {
+  if (fabs(x) < 1e-3) {
+    const double x2 = x * x;
+    return 1.0 + x2 / 6.0 * (1.0 + x2 / 20.0 * (1.0 + x2 / 42.0 * (1.0 + x2 / 72.0)));
+  }
+  return sinh(x) / x;
+}
+
+/* Force on the barostat momentum: G_eps = alpha ke2 + tr W - 3 V P_ext, i.e.
+   3V (P_int - P_ext) plus the kinetic term's share (3 / Nf) ke2 that the
+   equations of motion of Martyna, Tobias and Klein add. */
+static double npt_geps(double alpha, double ke2, const double* vir, double vol,
+                       double p_target) {
+  return alpha * ke2 + (vir[0] + vir[1] + vir[2]) - 3.0 * vol * p_target;
+}
+
+/* NPT run: isotropic barostat in the equations of Martyna, Tobias and Klein
+   (box edges L_d = L0_d exp(eps), eps with momentum p_eps and mass W) with a
+   Nose-Hoover chain on the particles and another on the barostat, integrated
+   in the time-reversible splitting of Tuckerman et al.  Per step:
+     barostat chain half step (acts on p_eps; G_1 = (p_eps^2 / W - kT) / Q'_1),
+     particle chain half step (scales v, as orc_md_run_nvt),
+     p_eps += dt/2 G_eps,  G_eps = alpha ke2 + tr W - 3 V P_ext,  alpha = 1 + 3 / Nf,
+     v <- v a + dtfm f b, a = exp(-alpha v_e dt/2), b = exp(-alpha v_e dt/4) sinhc(alpha v_e dt/4),
+     x <- x c + e v,      c = exp(v_e dt),         e = dt exp(v_e dt/2) sinhc(v_e dt/2),
+     L <- L c,   (v_e = p_eps / W)
+     rebuild if max_i |x_i - s x_ref_i|^2 > (skin/2 - (1 - s) rl/2)^2, s = L / L_ref (or if
+       that bound is negative), wrapping and re-gridding in the current box,
+     forces and virial at the new positions and box,
+     v <- v a + dtfm f b,  ke2 = sum m v^2 (recount),
+     p_eps += dt/2 G_eps,
+     particle chain half step, barostat chain half step.
+   The rebuild bound keeps every pair that may come within rc in the list: a
+   pair outside r_l at the build is at least s r_l - 2 max |x - s x_ref| apart.
+   Masses: W = (Nf + 3) kT p_damp^2, Q'_j = kT p_damp^2, particle chain as in
+   orc_md_run_nvt.  Conserved: pe + ke + particle chain energy + p_eps^2 / (2W)
+   + P_ext V + barostat chain energy (sum_j Q'_j w_j^2 / 2 + kT sum_j xi_j).
+   L [in/out] is the box; chain [in/out] holds eta[M], veta[M] (particles),
+   xi[M], w[M] (barostat), p_eps.  Thermo rows have ten columns: the eight of
+   orc_md_run (P with the current volume), the conserved energy, the volume.
+   With p_damp huge (W beyond any G_eps) v_e rounds to a factor of exactly 1
+   everywhere and the run is orc_md_run_nvt's, operation for operation. */
+int orc_md_run_npt(const orc_params* p, int64_t n, double* x, double* v, double* L,
+                   int nsteps, int thermo_every, int cap, double t_target, double t_damp,
+                   int M, double p_target, double p_damp, double* chain, double* thermo,
+                   int* rebuilt, double* f_out) {
+  if (n <= 1 || !p || !x || !v || !L || nsteps < 0 || thermo_every < 1 || cap < 1 || M < 1 ||
+      M > 8 || !chain || !(t_target > 0.0) || !(t_damp > 0.0) || !(p_damp > 0.0) ||
+      !isfinite(p_target))
+    return ORC_EINVAL;
+  orc_work w;
+  memset(&w, 0, sizeof(w));
+  w.cap = cap;
+  w.atom_cell = (int*)malloc(sizeof(int) * (size_t)n);
+  w.perm = (int*)malloc(sizeof(int) * (size_t)n);
+  w.numneigh = (int*)malloc(sizeof(int) * (size_t)n);
+  w.neigh = (int*)malloc(sizeof(int) * (size_t)n * (size_t)cap);
+  w.xref = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+  double* f = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+  int st = ORC_OK;
+  if (!w.atom_cell || !w.perm || !w.numneigh || !w.neigh || !w.xref || !f) {
+    st = ORC_EINVAL;
+    goto done;
+  }
+  {
+    const double kick = (0.5 * p->dt * p->ftm2v) / p->mass;
+    const double rl = p->rc + p->skin;
+    const double kT = p->boltz * t_target;
+    const double nf = 3.0 * (double)n - 3.0;
+    const double alpha = 1.0 + 3.0 / nf;
+    double Q[8], Qb[8];
+    Q[0] = nf * kT * t_damp * t_damp;
+    for (int j = 1; j < M; ++j) Q[j] = kT * t_damp * t_damp;
+    for (int j = 0; j < M; ++j) Qb[j] = kT * p_damp * p_damp;
+    const double W = (nf + 3.0) * kT * p_damp * p_damp;
+    double* eta = chain;
+    double* veta = chain + M;
+    double* xi = chain + 2 * M;
+    double* vxi = chain + 3 * M;
+    double* peps = chain + 4 * M;
+    double Lref[3] = {L[0], L[1], L[2]};
+    double pe = 0.0, vir[6];
+    int nreb = 0, row = 0, maxc = 0;
+    st = rebuild(p, n, x, L, &w);
+    if (st) goto done;
+    ++nreb;
+    maxc = w.maxcount;
+    if (rebuilt) rebuilt[0] = 1;
+    st = forces(p, n, x, L, &w, f, &pe, vir);
+    if (st) goto done;
+    double ke2 = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      double a = v[i], b = v[n + i], c = v[2 * n + i];
+      ke2 += (a * a + b * b) + c * c;
+    }
+    ke2 = p->mass * p->mvv2e * ke2;
+    /* conserved energy of the extended system (beyond pe + ke) */
+#define NPT_EXTRA()                                                                    \
+  (nhc_energy(M, Q, eta, veta, kT, nf) + nhc_energy(M, Qb, xi, vxi, kT, 1.0) +        \
+   0.5 * *peps * *peps / W + p_target * (L[0] * L[1] * L[2]))
+    if (thermo) {
+      thermo_row(p, n, v, L, 0.0, pe, vir, nreb, maxc, thermo + 10 * row);
+      thermo[10 * row + 8] = thermo[10 * row + 3] + NPT_EXTRA();
+      thermo[10 * row + 9] = L[0] * L[1] * L[2];
+      ++row;
+    }
+    for (int s = 1; s <= nsteps; ++s) {
+      /* barostat chain and particle chain half steps */
+      double kb2 = *peps * *peps / W;
+      *peps = *peps * nhc_half(M, Qb, xi, vxi, kT, 1.0, p->dt, &kb2);
+      double scale = nhc_half(M, Q, eta, veta, kT, nf, p->dt, &ke2);
+      for (int64_t i = 0; i < 3 * n; ++i) v[i] = v[i] * scale;
+      double vol = L[0] * L[1] * L[2];
+      *peps = *peps + 0.5 * p->dt * npt_geps(alpha, ke2, vir, vol, p_target);
+      const double ve = *peps / W;
+      const double ka = exp(-alpha * ve * 0.5 * p->dt);
+      const double kb = exp(-alpha * ve * 0.25 * p->dt) * sinhc(alpha * ve * 0.25 * p->dt);
+      const double dc = exp(ve * p->dt);
+      const double de = p->dt * exp(ve * 0.5 * p->dt) * sinhc(ve * 0.5 * p->dt);
+      for (int d = 0; d < 3; ++d)
+        for (int64_t i = 0; i < n; ++i) {
+          v[d * n + i] = v[d * n + i] * ka + kick * f[d * n + i] * kb;
+          x[d * n + i] = x[d * n + i] * dc + de * v[d * n + i];
+        }
+      for (int d = 0; d < 3; ++d) L[d] = L[d] * dc;
+      const double sb = L[0] / Lref[0];
+      const double thr = 0.5 * p->skin - 0.5 * (1.0 - sb) * rl;
+      double dmax = 0.0;
+      for (int64_t i = 0; i < n; ++i) {
+        double a = x[i] - sb * w.xref[i], b = x[n + i] - sb * w.xref[n + i],
+               c = x[2 * n + i] - sb * w.xref[2 * n + i];
+        double d2 = (a * a + b * b) + c * c;
+        if (d2 > dmax) dmax = d2;
+      }
+      const int rebuild_now = thr < 0.0 || dmax > thr * thr;
+      if (rebuilt) rebuilt[s] = rebuild_now;
+      if (rebuild_now) {
+        st = rebuild(p, n, x, L, &w);
+        if (st) goto done;
+        for (int d = 0; d < 3; ++d) Lref[d] = L[d];
+        ++nreb;
+        if (w.maxcount > maxc) maxc = w.maxcount;
+      }
+      st = forces(p, n, x, L, &w, f, &pe, vir);
+      if (st) goto done;
+      for (int64_t i = 0; i < 3 * n; ++i) v[i] = v[i] * ka + kick * f[i] * kb;
+      ke2 = 0.0;
+      for (int64_t i = 0; i < n; ++i) {
+        double a = v[i], b = v[n + i], c = v[2 * n + i];
+        ke2 += (a * a + b * b) + c * c;
+      }
+      ke2 = p->mass * p->mvv2e * ke2;
+      vol = L[0] * L[1] * L[2];
+      *peps = *peps + 0.5 * p->dt * npt_geps(alpha, ke2, vir, vol, p_target);
+      scale = nhc_half(M, Q, eta, veta, kT, nf, p->dt, &ke2);
+      for (int64_t i = 0; i < 3 * n; ++i) v[i] = v[i] * scale;
+      kb2 = *peps * *peps / W;
+      *peps = *peps * nhc_half(M, Qb, xi, vxi, kT, 1.0, p->dt, &kb2);
+      if (thermo && s % thermo_every == 0) {
+        thermo_row(p, n, v, L, (double)s, pe, vir, nreb, maxc, thermo + 10 * row);
+        thermo[10 * row + 8] = thermo[10 * row + 3] + NPT_EXTRA();
+        thermo[10 * row + 9] = L[0] * L[1] * L[2];
+        ++row;
+      }
+    }
+#undef NPT_EXTRA
+  }
+  if (f_out) memcpy(f_out, f, sizeof(double) * 3 * (size_t)n);
+done:
+  free(w.atom_cell);
+  free(w.perm);
+  free(w.numneigh);
+  free(w.neigh);
+  free(w.xref);
+  free(w.cell_start);
+  free(f);
+  return st;
+}

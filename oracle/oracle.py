@@ -120,9 +120,13 @@ def _declare(L):
     L.orc_md_run_nvt.argtypes = [ctypes.POINTER(Params), _i64, _dp, _dp, _dp, ctypes.c_int,
                                  ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_int, _dp, _dp, _ip, _dp]
+    L.orc_md_run_npt.argtypes = [ctypes.POINTER(Params), _i64, _dp, _dp, _dp, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp, _ip,
+                                 _dp]
     for name in ("orc_cell_dims", "orc_bin", "orc_build_nlist", "orc_lj_forces",
                  "orc_sc_forces", "orc_buck_forces", "orc_lj_vjp", "orc_sc_vjp",
-                 "orc_md_run", "orc_md_run_nvt"):
+                 "orc_md_run", "orc_md_run_nvt", "orc_md_run_npt"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -402,3 +406,31 @@ def md_run_nvt(params: Params, x, v, box, nsteps: int, t_target: float, t_damp: 
     if st:
         raise OracleError(st, "md_run_nvt")
     return RunResult(x, v, f, thermo, rebuilt), ch
+
+
+def md_run_npt(params: Params, x, v, box, nsteps: int, t_target: float, t_damp: float,
+               p_target: float, p_damp: float, chain_len: int = 3, chain=None,
+               thermo_every: int = 1, cap: int = 0):
+    """Isotropic NPT run (MTK barostat, Nose-Hoover chains on the particles and
+    on the barostat); x, v, box, chain are copied.  chain holds eta[M],
+    veta[M], xi[M], w[M], p_eps.  Returns (RunResult with ten-column thermo
+    rows, final chain, final box)."""
+    x = _f64(x).copy()
+    v = _f64(v).copy()
+    L = np.array(box, dtype=np.float64)
+    n = x.shape[1]
+    ch = (np.zeros(4 * chain_len + 1) if chain is None
+          else np.array(chain, dtype=np.float64))
+    if cap <= 0:
+        nl, _ = build_nlist(x, box, params.rc + params.skin)
+        cap = int(nl.max_count * 1.6) + 48
+    rows = 1 + nsteps // thermo_every
+    thermo = np.zeros((rows, 10))
+    rebuilt = np.zeros(nsteps + 1, np.int32)
+    f = np.zeros((3, n))
+    st = lib().orc_md_run_npt(ctypes.byref(params), n, _d(x), _d(v), _d(L), nsteps,
+                              thermo_every, cap, t_target, t_damp, chain_len, p_target, p_damp,
+                              _d(ch), _d(thermo), _i(rebuilt), _d(f))
+    if st:
+        raise OracleError(st, "md_run_npt")
+    return RunResult(x, v, f, thermo, rebuilt), ch, L

@@ -9,6 +9,7 @@ import pytest
 
 import test_oracle as T
 import test_oracle_buck as TB
+import test_oracle_npt as TNP
 import test_oracle_nvt as TN
 import test_oracle_pressure as TP
 import test_oracle_sc_vjp as TS
@@ -73,6 +74,19 @@ MUTANTS = {
                              "(2.0 * ke - (vir[0] + vir[1] + vir[2]))", ["pressure_dEdV"]),
     "pressure_virial_diagonal": ("(vir[0] + vir[1] + vir[2])", "(vir[0] + vir[1] + vir[3])",
                                  ["pressure_dEdV"]),
+    "npt_barostat_force_kinetic": ("return alpha * ke2 + (vir[0] + vir[1] + vir[2])",
+                                   "return ke2 + (vir[0] + vir[1] + vir[2])",
+                                   ["npt_conserved"]),
+    "npt_external_pressure_sign": ("- 3.0 * vol * p_target;", "+ 3.0 * vol * p_target;",
+                                   ["npt_relax", "npt_conserved"]),
+    "npt_drift_not_scaled": ("x[d * n + i] = x[d * n + i] * dc + de * v[d * n + i];",
+                             "x[d * n + i] = x[d * n + i] + de * v[d * n + i];",
+                             ["npt_conserved"]),
+    "npt_kick_force_factor": ("const double kb = exp(-alpha * ve * 0.25 * p->dt) * sinhc",
+                              "const double kb = exp(-alpha * ve * 0.5 * p->dt) * sinhc",
+                              ["npt_conserved", "npt_reversible"]),
+    "npt_energy_without_pv": ("0.5 * *peps * *peps / W + p_target * (L[0] * L[1] * L[2]))",
+                              "0.5 * *peps * *peps / W)", ["npt_conserved"]),
 }
 
 
@@ -114,6 +128,9 @@ PINS = {
     "par_scvjp_a": lambda o: TS.test_sc_vjp_parameter_gradients(o, _scsys(o), 1, "a"),
     "nvt_conserved": lambda o: TN.test_nvt_conserved_energy_is_second_order(o, 3),
     "nvt_reversible": lambda o: TN.test_nvt_time_reversible(o),
+    "npt_conserved": lambda o: TNP.test_npt_conserved_energy_is_second_order(o),
+    "npt_relax": lambda o: TNP.test_npt_relaxes_to_target_pressure(o),
+    "npt_reversible": lambda o: TNP.test_npt_time_reversible(o),
     "ideal_gas": lambda o: TP.test_ideal_gas_law(o, TP.LJ, dict(lj_eps=0.0)),
     "pressure_dEdV": lambda o: TP.test_pressure_is_minus_energy_volume_derivative(o,
                                                                                   "lj_jittered"),
