@@ -90,12 +90,12 @@ def measured_traffic(kernel_name: str, launches_bytes: float):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def run_md(w, x, v, prec, kernel, steps, warmup, nvt=None, thermo_every=THERMO_EVERY):
+def run_md(w, x, v, prec, kernel, steps, warmup, nvt=None, thermo_every=THERMO_EVERY, npt=None):
     import torch
     from paper_1009_4330_amd import md
     from paper_1009_4330_amd.system import MDSystem
 
-    sysm = MDSystem(w, x, v, prec, kernel, nvt=nvt)
+    sysm = MDSystem(w, x, v, prec, kernel, nvt=nvt, npt=npt)
     sysm.setup(thermo=False)
     every = max(1, min(thermo_every, steps))
     if warmup:
@@ -461,6 +461,14 @@ def suite(steps: int):
               "lanes_per_atom": r["kernel"], "atom_steps_per_s": steps * w.natoms / r["elapsed"],
               "ms_per_step": 1e3 * r["elapsed"] / steps, "force_us": 1e3 * r["force_ms_avg"],
               "rebuilds": r["rebuilds"], "steps": steps})
+    for prec in ("mixed", "fp64"):
+        r = run_md(w, x, v, prec, "auto", steps, 10, npt=(w.temp, 100 * w.dt, 3, 2.0, 1000 * w.dt))
+        emit({"item": "npt", "workload": w.name, "precision": prec, "kernel": "auto",
+              "barostat": "isotropic MTK, Nose-Hoover chains of 3 on particles and barostat, "
+                          "P 2.0, periods 100 dt (thermostat) and 1000 dt (barostat)",
+              "lanes_per_atom": r["kernel"], "atom_steps_per_s": steps * w.natoms / r["elapsed"],
+              "ms_per_step": 1e3 * r["elapsed"] / steps, "force_us": 1e3 * r["force_ms_avg"],
+              "rebuilds": r["rebuilds"], "steps": steps})
     emit({"item": "C4_sc_vjp_atoms_per_s", **bench_sc_vjp(20)})
     emit({"item": "half_vs_full_list_force_kernel", "workload": "lj_melt_256k",
           **bench_half_list()})
@@ -477,7 +485,8 @@ def suite(steps: int):
     emit({"item": "oracle_one_thread", **oracle_one_thread(w, x, v)})
 
 
-def one_workload(name: str, kernel: str, steps: int, warmup: int, nvt: bool = False):
+def one_workload(name: str, kernel: str, steps: int, warmup: int, nvt: bool = False,
+                 npt: bool = False):
     """Time one named workload in FP64 and FP32-mixed; one JSON line each.
     With nvt, under a Nose-Hoover chain of 3 at the workload's temperature
     with a period of 100 time steps."""
@@ -491,9 +500,10 @@ def one_workload(name: str, kernel: str, steps: int, warmup: int, nvt: bool = Fa
     for prec in ("fp64", "mixed"):
         log(f"[bench] {w.name}: {w.natoms} atoms, {prec}, kernel {kernel}")
         r = run_md(w, x, v, prec, kernel, steps, warmup,
-                   nvt=(w.temp, 100 * w.dt, 3) if nvt else None)
+                   nvt=(w.temp, 100 * w.dt, 3) if nvt and not npt else None,
+                   npt=(w.temp, 100 * w.dt, 3, 2.0, 1000 * w.dt) if npt else None)
         print(json.dumps({"item": "workload", "workload": w.name, "precision": prec,
-                          "ensemble": "nvt" if nvt else "nve",
+                          "ensemble": "npt" if npt else ("nvt" if nvt else "nve"),
                           "kernel": kernel, "lanes_per_atom": r["kernel"],
                           "atom_steps_per_s": steps * w.natoms / r["elapsed"],
                           "ms_per_step": 1e3 * r["elapsed"] / steps,
@@ -518,6 +528,8 @@ def main():
                          "both precisions with --kernel; one JSON line per precision")
     ap.add_argument("--nvt", action="store_true",
                     help="with --workload: run under the Nose-Hoover chain thermostat")
+    ap.add_argument("--npt", action="store_true",
+                    help="with --workload: run under the barostat (P 2.0, LJ units)")
     ap.add_argument("--suite", action="store_true",
                     help="the other configurations (rc 5.0 LJ, Sutton-Chen, Buckingham + Coulomb, "
                          "the force-matching fit, a size sweep, copy peak, one-thread oracle); "
@@ -535,7 +547,7 @@ def main():
         return
     if args.workload:
         one_workload(args.workload, args.kernel, args.steps if args.steps != 1000 else 200,
-                     args.warmup, args.nvt)
+                     args.warmup, args.nvt, args.npt)
         return
     headline(args)
 

@@ -14,13 +14,13 @@
  * mini-benchmark of section "Neighbor list approach".  Beyond that path the
  * library has the Buckingham + cut Coulomb potential of the silicate system
  * (Appendix A), the force adjoints (LJ and Sutton-Chen) for force matching,
- * NVT integration with a Nose-Hoover chain, and half lists with Newton's
- * third law for forces.
+ * NVT integration with a Nose-Hoover chain, isotropic NPT integration, half
+ * lists with Newton's third law for forces, and LDS-staged neighbour tiles.
  *
  * Conventions
  *  - Every pointer is a DEVICE pointer unless marked [host].  The caller owns
  *    every buffer; no call allocates or frees device memory, and no call
- *    synchronises except md_step and md_step_nvt (once, at their end),
+ *    synchronises except md_step, md_step_nvt and md_step_npt (once, at their end),
  *    md_nlist_status and md_autoselect.  Work is enqueued on `stream` (a hipStream_t; NULL is the
  *    default stream).
  *  - Per-atom vectors are SoA FP64 [3][n]: n x values, then n y, then n z.
@@ -323,6 +323,49 @@ md_status md_compute_forces_noalloc(const md_potential* p, const double* x, int6
                                     const md_box* box, const md_nlist* nl, md_precision prec,
                                     md_kernel k, int flags, double* f, double* ev,
                                     void* stream);
+
+/* Isotropic barostat for md_step_npt (the NPT integrator among the
+   integrators listed in the paper's "Design objectives"): the equations of
+   Martyna, Tobias and Klein, box edges L_d scaled together, with a
+   Nose-Hoover chain on the particles (as md_nhc) and one on the barostat, in
+   the time-reversible splitting of Tuckerman et al.  Barostat mass
+   W = (Nf + 3) kB T p_damp^2, barostat chain masses kB T p_damp^2, Nf = 3n - 3.
+   state [device, MD_NPT_STATE doubles, caller-owned, zero for a fresh
+   barostat and thermostat]: particle chain eta[8], eta_dot[8], barostat chain
+   xi[8], xi_dot[8], the barostat momentum, the box edges, then working
+   storage; md_step_npt updates it in place (pass it unchanged to continue a
+   run). */
+enum { MD_NPT_STATE = 64 };
+typedef struct {
+  double t_target;   /* target temperature, the run's units */
+  double t_damp;     /* thermostat period */
+  int chain;         /* chain length of both thermostats, 1..MD_NHC_MAX */
+  double p_target;   /* target pressure, energy / volume units */
+  double p_damp;     /* barostat period */
+  double* state;     /* [device] MD_NPT_STATE doubles (see above) */
+} md_npt;
+
+/* md_step under the barostat npt: each step is a barostat-chain and
+   particle-chain half step, a half step of the barostat momentum
+   (G = (1 + 3/Nf) sum m v^2 + tr W - 3 V P_target), the kick
+   v <- v exp(-(1 + 3/Nf) v_e dt/2) + (dt/2) F/m exp(-(1 + 3/Nf) v_e dt/4) sinhc,
+   the drift x <- x exp(v_e dt) + dt v exp(v_e dt/2) sinhc with the box scaled
+   by exp(v_e dt) (v_e = p_eps / W, sinhc(y) = sinh(y)/y at the half
+   arguments), the rebuild check, forces, the closing kick, the closing half
+   steps in reverse order.  Lists stay valid under the box scale s since the
+   last build: a rebuild happens when max |x - s x_ref| exceeds
+   skin/2 - (1 - s) rl/2.  The box lives in npt->state during the call; box
+   [host] gives it at setup and receives the final box.  The cell grid is
+   fixed at setup from the box shrunk by 5 %; if an edge later falls below
+   nc rl the run returns MD_ERR_BOX_TOO_SMALL (the state is then unusable: run
+   setup again from a saved state).  thermo rows have ten doubles: the eight
+   of md_step (P with the current volume), pe + ke plus the extended energy
+   (both chains, p_eps^2 / 2W, P_target V), which the exact flow conserves,
+   and the volume.  Every other argument, status and rule as md_step. */
+md_status md_step_npt(md_state* st, const md_potential* p, md_box* box, md_cells* cells,
+                      md_nlist* nl, md_precision prec, md_kernel k, double skin, double dt,
+                      const md_npt* npt, int nsteps, int thermo_every, int setup,
+                      double* thermo, void* ws, size_t ws_bytes, void* stream);
 
 /* Vector-Jacobian product of the forces for L = sum_i u_i . F_i:
    gx = (dF/dx)^T u = -H u, with u, gx [device, 3][n]; gparam [device, may be

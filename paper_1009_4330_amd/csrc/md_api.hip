@@ -386,6 +386,7 @@ int resolve_lanes(md_kernel k, int layout) {
 
 md_status status_from_words(const int* w) {
   if (w[MD_ST_ERRORS] & 4) return MD_ERR_UNSTABLE;
+  if (w[MD_ST_ERRORS] & 8) return MD_ERR_BOX_TOO_SMALL;
   if (w[MD_ST_ERRORS] & 2) return MD_ERR_NONFINITE;
   if (w[MD_ST_ERRORS] & 1) return MD_ERR_NLIST_OVERFLOW;
   return MD_OK;
@@ -822,10 +823,14 @@ md_status md_autoselect(const md_potential* p, const double* x, int64_t n, const
 
 // md_step and md_step_nvt: NVE when nhc is null, else the Nose-Hoover chain
 // splitting around the same velocity-Verlet step.
-static md_status step_impl(md_state* stt, const md_potential* p, const md_box* box,
+// The cell grid of an NPT run: edges of at least rl also after the box has
+// shrunk by kNptGridMargin.
+constexpr double kNptGridMargin = 0.05;
+
+static md_status step_impl(md_state* stt, const md_potential* p, md_box* box,
                            md_cells* cells, md_nlist* nl, md_precision prec, md_kernel k,
-                           double skin, double dt, const md_nhc* nhc, int nsteps,
-                           int thermo_every, int setup, double* thermo, void* ws,
+                           double skin, double dt, const md_nhc* nhc, const md_npt* npt,
+                           int nsteps, int thermo_every, int setup, double* thermo, void* ws,
                            size_t ws_bytes, void* stream) {
   md_status st = check_pot(p);
   if (st != MD_OK) return st;
@@ -842,7 +847,29 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
   if ((st = check_box(box, rl)) != MD_OK) return st;
   int nc[3];
   int64_t ncell;
-  if (!cell_dims(box, rl, nc, &ncell) || ncell > cells->ncell_cap) return MD_ERR_INVALID_ARG;
+  if (npt) {
+    // NPT: the grid is chosen at setup with room for the box to shrink, and
+    // kept while every edge stays at least nc rl
+    if (!npt->state || !(npt->p_damp > 0.0) || !std::isfinite(npt->p_target) ||
+        !(npt->t_target > 0.0) || !(npt->t_damp > 0.0) || npt->chain < 1 ||
+        npt->chain > MD_NHC_MAX)
+      return MD_ERR_INVALID_ARG;
+    if (setup) {
+      md_box shrunk = *box;
+      for (int d = 0; d < 3; ++d) shrunk.L[d] = box->L[d] * (1.0 - kNptGridMargin);
+      if (!cell_dims(&shrunk, rl, nc, &ncell)) return MD_ERR_BOX_TOO_SMALL;
+    } else {
+      ncell = 1;
+      for (int d = 0; d < 3; ++d) {
+        nc[d] = cells->nc[d];
+        ncell *= nc[d];
+        if (nc[d] < 1 || box->L[d] < nc[d] * rl) return MD_ERR_BOX_TOO_SMALL;
+      }
+    }
+    if (ncell > cells->ncell_cap) return MD_ERR_INVALID_ARG;
+  } else if (!cell_dims(box, rl, nc, &ncell) || ncell > cells->ncell_cap) {
+    return MD_ERR_INVALID_ARG;
+  }
   // tiled kernels: LJ, a tile buffer, and a grid they apply to
   TileGeom tg{};
   const bool tile_ok = p->kind == MD_POT_LJ && nl->tile && tile_geom(stt->n, nc, &tg);
@@ -861,6 +888,15 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int n = (int)stt->n;
   const BoxK bk = make_box(box);
+  // NPT keeps the box in device memory (the barostat state); every kernel
+  // after the setup binning reads it there
+  double* const nstate = npt ? npt->state : nullptr;
+  const double* const boxd = npt ? nstate + kNptL : nullptr;
+  if (npt && setup) {
+    double init[6] = {box->L[0], box->L[1], box->L[2], box->L[0], box->L[1], box->L[2]};
+    MD_CK(hipMemcpyAsync(nstate + kNptL, init, sizeof(init), hipMemcpyHostToDevice, s));
+    MD_CK(hipStreamSynchronize(s));   // init is a host stack buffer
+  }
   const double dtfm = (0.5 * dt * stt->ftm2v) / stt->mass;
   const double trig = 0.5 * skin;
   const double trig2 = trig * trig;
@@ -905,8 +941,8 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
     if (g) {
       MD_CK(launch_cell_count(cells->cell_start, cells->atom_cell, nc, count, scount, g, s));
       MD_CK(launch_gather_sort(cells->cell_start, new_start, count, scount, cells->atom_cell, nc,
-                               bk, cells->perm, xq, stt->v, stt->id, type, n, sx, sv, sid, stype,
-                               status, g, s));
+                               bk, boxd, cells->perm, xq, stt->v, stt->id, type, n, sx, sv, sid,
+                               stype, status, g, s));
     } else {
       MD_CK(launch_fill_int(count, ncell, 0, s));
       MD_CK(launch_bin_count(stt->x, n, bk, nc, cells->atom_cell, count, slot, s));
@@ -941,6 +977,8 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
     a.type_out = type;
     a.type_in = type ? stype : nullptr;
     a.gate = g;
+    a.boxd = boxd;
+    a.lref = npt ? nstate + kNptLref : nullptr;
     MD_CK(launch_build(a, s));
     // the tile list from the new list, on the new cell starts
     if (is_tile(layout))
@@ -956,7 +994,9 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
     if (in) fa.in = *in;
     fa.n = n;
     fa.box = bk;
-    fa.margin = interior_margin(p, rl);
+    // a changing box voids the interior argument: the minimum image always
+    fa.margin = npt ? HUGE_VAL : interior_margin(p, rl);
+    fa.boxd = boxd;
     fa.neigh = nl->neigh;
     fa.numneigh = nl->numneigh;
     fa.cap = nl->capacity;
@@ -976,7 +1016,7 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
   const double dof = 3.0 * (double)n - 3.0;
   const double volume = box->L[0] * box->L[1] * box->L[2];
   int row = 0;
-  const int row_cols = nhc ? 9 : 8;
+  const int row_cols = npt ? 10 : (nhc ? 9 : 8);
   auto sums_out = [&](const NhcArgs* h) -> md_status {
     SumArgs sa{};
     sa.cols = 8;
@@ -1001,6 +1041,10 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
     ta.dof = dof;
     ta.volume = volume;
     ta.status = status;
+    if (npt) {
+      ta.extra = nstate + kNptEnergy;
+      ta.vol = nstate + kNptVol;
+    }
     MD_CK(launch_thermo_row(ta, s));
     return MD_OK;
   };
@@ -1058,8 +1102,8 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
         kernel = (int)choice;
       }
     }
-    const bool ev = thermo != nullptr;
-    if ((st = forces(ev, kernel, xqs[0], nullptr)) != MD_OK) return st;
+    const bool ev = thermo != nullptr && !npt;   // NPT evaluates its setup forces below
+    if (!npt && (st = forces(ev, kernel, xqs[0], nullptr)) != MD_OK) return st;
     if (ev) {
       MD_CK(launch_ke(stt->v, n, keatom, s));
       // with a thermostat, also the chain energy of the state as given
@@ -1075,7 +1119,102 @@ static md_status step_impl(md_state* stt, const md_potential* p, const md_box* b
   // step s, then (s < nsteps) step s + 1's kick, drift into xq[(s + 1) & 1]
   // and check, or (s = nsteps) the state's x and f.  The thermo row of step s
   // is summed right after its force kernel.
-  if (nsteps > 0 && nhc) {
+  if (npt) {
+    // Per call: forces with energy and virial at the current positions (the
+    // virial enters the barostat force), the kinetic sum, and the update
+    // that opens step 1.  Per step: the scaled kick + drift + check (factors
+    // from the update), gated rebuild in the current box, forces with the
+    // closing kick (factors a, b) storing x, f, v and |v|^2, the sums
+    // (energy, virial, |v|^2), whose last kernel runs the update closing
+    // this step and opening the next, and the thermo row.
+    const double kT = stt->boltz * npt->t_target;
+    NptArgs pa{};
+    pa.state = nstate;
+    pa.M = npt->chain;
+    pa.nf = dof;
+    pa.kT = kT;
+    pa.Q0 = dof * kT * npt->t_damp * npt->t_damp;
+    pa.Qj = kT * npt->t_damp * npt->t_damp;
+    pa.Qb = kT * npt->p_damp * npt->p_damp;
+    pa.W = (dof + 3.0) * kT * npt->p_damp * npt->p_damp;
+    pa.alpha = 1.0 + 3.0 / dof;
+    pa.dt = dt;
+    pa.mke = stt->mass * stt->mvv2e;
+    pa.ptarget = npt->p_target;
+    pa.skin = skin;
+    pa.rl = rl;
+    for (int d = 0; d < 3; ++d) pa.nc[d] = nc[d];
+    pa.status = status;
+    SumArgs sa{};
+    sa.cols = 8;
+    sa.col[0] = eatom;
+    for (int q = 0; q < 6; ++q) sa.col[1 + q] = vatom + (size_t)q * n;
+    sa.col[7] = keatom;
+    sa.n = n;
+    sa.partials = at<double>(ws, L.partials);
+    sa.out = sums;
+    MD_CK(launch_pack_positions(stt->x, n, xqs[0], type, s));
+    if ((st = forces(true, kernel, xqs[0], nullptr)) != MD_OK) return st;
+    MD_CK(launch_ke(stt->v, n, keatom, s));
+    {
+      NptArgs a = pa;
+      a.vsum = sums + 7;
+      a.sums = sums;
+      a.start = nsteps > 0;
+      MD_CK(launch_sum_npt(sa, a, s));
+    }
+    if (setup && thermo && (st = row_out(0.0)) != MD_OK) return st;
+    BinOut bin{};
+    bin.box = bk;
+    bin.boxd = boxd;
+    for (int d = 0; d < 3; ++d) bin.nc[d] = nc[d];
+    bin.atom_cell = cells->atom_cell;
+    bin.xq = xqs[1];
+    bin.flag = gates[1];
+    bin.type = type;
+    if (nsteps > 0) {
+      MD_CK(launch_fill_int(gates[0], 1, 0, s));
+      MD_CK(launch_fill_int(gates[1], 1, 0, s));
+      MD_CK(launch_kick_drift_npt(stt->x, stt->v, stt->f, nl->x_ref, n, dtfm, status, bin,
+                                  nstate, s));
+    }
+    for (int step = 1; step <= nsteps; ++step) {
+      double* cur = xqs[step & 1];
+      gate = gates[step & 1];
+      if ((st = rebuild(gate, layout, cur)) != MD_OK) return st;
+      const bool th = is_thermo(step);
+      IntArgs in{};
+      in.mode = MD_INT_LAST;
+      in.v = stt->v;
+      in.xr = nl->x_ref;
+      in.x = stt->x;
+      in.keatom = keatom;
+      in.status = status;
+      in.dtfm = dtfm;
+      in.dt = dt;
+      in.trig2 = trig2;
+      in.bin = bin;
+      in.kick = nstate + kNptKa;
+      if ((st = forces(true, kernel, cur, &in)) != MD_OK) return st;
+      NptArgs a = pa;
+      a.vsum = sums + 7;
+      a.sums = sums;
+      a.vsum_out = th ? sums + 7 : nullptr;
+      a.end = 1;
+      a.start = step < nsteps;
+      MD_CK(launch_sum_npt(sa, a, s));
+      if (th && (st = row_out((double)step)) != MD_OK) return st;
+      if (step < nsteps) {
+        bin.xq = xqs[(step + 1) & 1];
+        bin.flag = gates[(step + 1) & 1];
+        MD_CK(launch_kick_drift_npt(stt->x, stt->v, stt->f, nl->x_ref, n, dtfm, status, bin,
+                                    nstate, s));
+      } else {
+        MD_CK(launch_scale_v(stt->v, n, nstate + kNptScale, s));
+      }
+    }
+    MD_CK(hipMemcpyAsync(box->L, nstate + kNptL, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  } else if (nsteps > 0 && nhc) {
     // Per step: thermostat half step and kick + drift + check (one kernel
     // reading the scale the chain update left), gated rebuild, forces with
     // the closing kick only (x, f, v and |v|^2 stored), the kinetic-energy
@@ -1183,8 +1322,9 @@ md_status md_step(md_state* stt, const md_potential* p, const md_box* box, md_ce
                   md_nlist* nl, md_precision prec, md_kernel k, double skin, double dt,
                   int nsteps, int thermo_every, int setup, double* thermo, void* ws,
                   size_t ws_bytes, void* stream) {
-  return step_impl(stt, p, box, cells, nl, prec, k, skin, dt, nullptr, nsteps, thermo_every,
-                   setup, thermo, ws, ws_bytes, stream);
+  // the box is written only by NPT runs
+  return step_impl(stt, p, const_cast<md_box*>(box), cells, nl, prec, k, skin, dt, nullptr,
+                   nullptr, nsteps, thermo_every, setup, thermo, ws, ws_bytes, stream);
 }
 
 md_status md_step_nvt(md_state* stt, const md_potential* p, const md_box* box, md_cells* cells,
@@ -1194,8 +1334,17 @@ md_status md_step_nvt(md_state* stt, const md_potential* p, const md_box* box, m
   if (!nhc || !nhc->state || nhc->chain < 1 || nhc->chain > MD_NHC_MAX ||
       !finite_pos(nhc->t_target) || !finite_pos(nhc->t_damp))
     return MD_ERR_INVALID_ARG;
-  return step_impl(stt, p, box, cells, nl, prec, k, skin, dt, nhc, nsteps, thermo_every, setup,
-                   thermo, ws, ws_bytes, stream);
+  return step_impl(stt, p, const_cast<md_box*>(box), cells, nl, prec, k, skin, dt, nhc, nullptr,
+                   nsteps, thermo_every, setup, thermo, ws, ws_bytes, stream);
+}
+
+md_status md_step_npt(md_state* stt, const md_potential* p, md_box* box, md_cells* cells,
+                      md_nlist* nl, md_precision prec, md_kernel k, double skin, double dt,
+                      const md_npt* npt, int nsteps, int thermo_every, int setup,
+                      double* thermo, void* ws, size_t ws_bytes, void* stream) {
+  if (!npt) return MD_ERR_INVALID_ARG;
+  return step_impl(stt, p, box, cells, nl, prec, k, skin, dt, nullptr, npt, nsteps, thermo_every,
+                   setup, thermo, ws, ws_bytes, stream);
 }
 
 md_status md_timing_enable(int every) {

@@ -426,12 +426,13 @@ __device__ inline void gather_cell(
 __global__ __launch_bounds__(kBlock) void k_gather_sort(
     const int* __restrict__ old_start, int* __restrict__ new_start,
     const int* __restrict__ count, const int* __restrict__ scount,
-    const int* __restrict__ atom_cell, int nc0, int nc1, int nc2, BoxK box,
-    int* __restrict__ perm, const double* __restrict__ xq, const double* __restrict__ v,
-    const int* __restrict__ id, const int* __restrict__ type, int n, double* __restrict__ sx,
-    double* __restrict__ sv, int* __restrict__ sid, int* __restrict__ stype,
-    int* __restrict__ status, const int* __restrict__ gate) {
+    const int* __restrict__ atom_cell, int nc0, int nc1, int nc2, BoxK box0,
+    const double* __restrict__ boxd, int* __restrict__ perm, const double* __restrict__ xq,
+    const double* __restrict__ v, const int* __restrict__ id, const int* __restrict__ type, int n,
+    double* __restrict__ sx, double* __restrict__ sv, int* __restrict__ sid,
+    int* __restrict__ stype, int* __restrict__ status, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
+  const BoxK box = boxd ? box_load(boxd) : box0;
   __shared__ int members[kBlock];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -945,6 +946,19 @@ __device__ inline int build_cell(const BuildArgs& a, const BuildLds& L, int cell
   return mx;
 }
 
+// A build's view of its arguments: the box from device memory when the run
+// keeps it there (NPT), whose edges the first thread records as the box of
+// this build.
+__device__ inline BuildArgs build_view(const BuildArgs& a0) {
+  BuildArgs a = a0;
+  if (a0.boxd) {
+    a.box = box_load(a0.boxd);
+    if (a0.lref && blockIdx.x == 0 && threadIdx.x == 0)
+      for (int d = 0; d < 3; ++d) a0.lref[d] = a.box.L[d];
+  }
+  return a;
+}
+
 // Running maximum and overflow flag: one device-scope atomic per workgroup at
 // most, skipped when the word already holds at least m (a stale read only
 // costs an extra atomic).
@@ -965,8 +979,9 @@ __device__ inline void report_max(const BuildArgs& a, int mx, int* red) {
 
 // General path: `parts` workgroups per cell, consecutive in the (XCD-aware)
 // numbering so a cell's pieces share one L2.
-__global__ __launch_bounds__(kBlock) void k_build(BuildArgs a, int parts) {
-  if (a.gate && *a.gate == 0) return;
+__global__ __launch_bounds__(kBlock) void k_build(BuildArgs a0, int parts) {
+  if (a0.gate && *a0.gate == 0) return;
+  const BuildArgs a = build_view(a0);
   __shared__ double cxs[kBuildChunk], cys[kBuildChunk], czs[kBuildChunk];
   __shared__ int cjs[kBuildChunk];
   __shared__ int hcnt[kBlock];
@@ -1305,8 +1320,9 @@ __device__ inline int build_row_segment(const BuildArgs& a, const BuildLds& L, i
 
 // Sorted atoms, at least 3 cells along x: a resident grid working through
 // the row segments (build_row_segment).
-__global__ __launch_bounds__(kBlock, 4) void k_build_rows(BuildArgs a) {
-  if (a.gate && *a.gate == 0) return;
+__global__ __launch_bounds__(kBlock, 4) void k_build_rows(BuildArgs a0) {
+  if (a0.gate && *a0.gate == 0) return;
+  const BuildArgs a = build_view(a0);
   __shared__ double cxs[kRowSlots], cys[kRowSlots], czs[kRowSlots];
   __shared__ int cjs[kRowSlots];
   __shared__ int hcnt[kBlock];
@@ -1532,13 +1548,13 @@ hipError_t launch_cell_sort(const int* tmp_perm, const int* cell_start, int ncel
 
 hipError_t launch_gather_sort(const int* old_start, int* new_start, const int* count,
                               const int* scount, const int* atom_cell, const int nc[3], BoxK box,
-                              int* perm, const double* xq, const double* v, const int* id,
-                              const int* type, int n, double* sx, double* sv, int* sid,
-                              int* stype, int* status, const int* gate, hipStream_t s) {
+                              const double* boxd, int* perm, const double* xq, const double* v,
+                              const int* id, const int* type, int n, double* sx, double* sv,
+                              int* sid, int* stype, int* status, const int* gate, hipStream_t s) {
   const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
   k_gather_sort<<<resident_grid(8, blocks_for(ncell * kWave)), kBlock, 0, s>>>(
-      old_start, new_start, count, scount, atom_cell, nc[0], nc[1], nc[2], box, perm, xq, v, id,
-      type, n, sx, sv, sid, type ? stype : nullptr, status, gate);
+      old_start, new_start, count, scount, atom_cell, nc[0], nc[1], nc[2], box, boxd, perm, xq, v,
+      id, type, n, sx, sv, sid, type ? stype : nullptr, status, gate);
   return hipGetLastError();
 }
 

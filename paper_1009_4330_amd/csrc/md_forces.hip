@@ -25,6 +25,7 @@ struct FK {
   const double* __restrict__ xq;   // packed positions, atom i at xq[4 i]
   int n;
   BoxK box;
+  const double* boxd;     // nullable: the box in device memory (replaces box at kernel entry)
   double margin;          // interior test: every coordinate in [margin, L - margin)
   const int* __restrict__ neigh;
   const int* __restrict__ numneigh;
@@ -349,10 +350,19 @@ __device__ inline void finish_atom_with(const FK& a, const Acc& acc, int i, bool
     const double fq[3] = {acc.fx, acc.fy, acc.fz};
     const double xo[3] = {xi, yi, zi};
     double vh[3];
+    if (in.kick) {
+      const double ka = in.kick[0], kb = in.kick[1];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      finite = finite && isfinite(fq[d]);
-      vh[d] = vi[d] + in.dtfm * fq[d];
+      for (int d = 0; d < 3; ++d) {
+        finite = finite && isfinite(fq[d]);
+        vh[d] = vi[d] * ka + (in.dtfm * fq[d]) * kb;
+      }
+    } else {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        finite = finite && isfinite(fq[d]);
+        vh[d] = vi[d] + in.dtfm * fq[d];
+      }
     }
     if (in.keatom) in.keatom[i] = vh[0] * vh[0] + vh[1] * vh[1] + vh[2] * vh[2];
     if (in.mode == MD_INT_LAST) {
@@ -400,6 +410,14 @@ __device__ inline void finish_atom(const FK& a, const Acc& acc, int i, bool own,
   finish_atom_with<FUSED>(a, acc, i, own, xi, yi, zi, ev, e_extra, vi, xri);
 }
 
+// The kernel's view of its arguments with the box taken from device memory
+// when the run keeps it there (NPT).
+__device__ inline FK with_box(const FK& a0) {
+  FK a = a0;
+  if (a0.boxd) a.box = box_load(a0.boxd);
+  return a;
+}
+
 // ------------------------------------------------------------------ LJ --
 
 // g(s) with F_ij = g d, and phi(s) (unshifted).
@@ -421,7 +439,8 @@ __device__ inline void lj_pair(double s, const LJK& p, double& g, double& phi) {
 }
 
 template <int PREC, bool EV, int K, bool FUSED>
-__global__ __launch_bounds__(kBlock) void k_lj(FK a, LJK p) {
+__global__ __launch_bounds__(kBlock) void k_lj(FK a0, LJK p) {
+  const FK a = with_box(a0);
   if (a.clear && blockIdx.x == 0 && threadIdx.x == 0) *a.clear = 0;
   const Lane<K> ln(a);
   const int n = a.n;
@@ -478,7 +497,8 @@ struct TileArgs {
 constexpr int kTileWords = 8;    // 32-bit tile words (two entries each) a lane holds at once
 
 template <int PREC, bool EV, int K, bool FUSED>
-__global__ __launch_bounds__(kTileBlock, 2) void k_lj_tile(FK a, LJK p, TileArgs ta) {
+__global__ __launch_bounds__(kTileBlock, 2) void k_lj_tile(FK a0, LJK p, TileArgs ta) {
+  const FK a = with_box(a0);
   __shared__ double wpos[3 * kTileCap];
   __shared__ int s_lo[kTileSegs], s_base[kTileSegs + 1];
   if (a.clear && blockIdx.x == 0 && threadIdx.x == 0) *a.clear = 0;
@@ -728,7 +748,8 @@ __device__ inline void buck_pair(double s, const double* row, const float* rowf,
 }
 
 template <int PREC, bool EV, int K, bool FUSED>
-__global__ __launch_bounds__(kBlock) void k_buck(FK a, BuckK p) {
+__global__ __launch_bounds__(kBlock) void k_buck(FK a0, BuckK p) {
+  const FK a = with_box(a0);
   // the species-pair rows, staged once per workgroup
   __shared__ double rows[16 * 6];
   __shared__ float rowsf[16 * 6];
@@ -782,8 +803,9 @@ __device__ inline T half_power(T t, int k) {
 // pass 2 finds it with the neighbour's position; with EV, also the embedding
 // energy -eps c sqrt(rho_i).
 template <int PREC, bool EV, int K>
-__global__ __launch_bounds__(kBlock) void k_sc_density(FK a, SCK p, double* __restrict__ e_out,
+__global__ __launch_bounds__(kBlock) void k_sc_density(FK a0, SCK p, double* __restrict__ e_out,
                                                         double* xq_w) {
+  const FK a = with_box(a0);
   const Lane<K> ln(a);
   const int n = a.n;
   const int io = ln.live ? ln.i : n - 1;
@@ -811,8 +833,9 @@ __global__ __launch_bounds__(kBlock) void k_sc_density(FK a, SCK p, double* __re
 
 // Pass 2: F_ij = [n eps t^(n/2) - (m eps c / 2)(e_i + e_j) t^(m/2)] d / s, t = a^2/s.
 template <int PREC, bool EV, int K, bool FUSED>
-__global__ __launch_bounds__(kBlock) void k_sc_force(FK a, SCK p,
+__global__ __launch_bounds__(kBlock) void k_sc_force(FK a0, SCK p,
                                                       const double* __restrict__ e_in) {
+  const FK a = with_box(a0);
   if (a.clear && blockIdx.x == 0 && threadIdx.x == 0) *a.clear = 0;
   const Lane<K> ln(a);
   const int n = a.n;
@@ -1073,6 +1096,7 @@ FK make_fk(const ForceArgs& a) {
   k.xq = a.xq;
   k.n = a.n;
   k.box = a.box;
+  k.boxd = a.boxd;
   k.margin = a.margin;
   k.neigh = a.neigh;
   k.numneigh = a.numneigh;

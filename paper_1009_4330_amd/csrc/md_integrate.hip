@@ -168,15 +168,162 @@ __global__ void k_thermo_row(ThermoArgs a) {
   const double* s = a.sums;
   const double pe = s[0];
   const double ke = 0.5 * a.mvv2e * a.mass * s[7];
+  const double volume = a.vol ? *a.vol : a.volume;
   a.row[0] = a.step;
   a.row[1] = pe;
   a.row[2] = ke;
   a.row[3] = pe + ke;
   a.row[4] = 2.0 * ke / (a.dof * a.boltz);
-  a.row[5] = (2.0 * ke + (s[1] + s[2] + s[3])) / (3.0 * a.volume);
+  a.row[5] = (2.0 * ke + (s[1] + s[2] + s[3])) / (3.0 * volume);
   a.row[6] = (double)a.status[MD_ST_BUILDS];
   a.row[7] = (double)a.status[MD_ST_MAXNEIGH];
   if (a.extra) a.row[8] = a.row[3] + *a.extra;
+  if (a.vol) a.row[9] = volume;
+}
+
+// ------------------------------------------------------------------ NPT --
+
+// sinh(x) / x; near 0 its Taylor series (to x^8, exact to rounding there).
+__device__ inline double sinh_over_x(double x) {
+  if (fabs(x) < 1e-3) {
+    const double q = x * x;
+    return 1.0 + q / 6.0 * (1.0 + q / 20.0 * (1.0 + q / 42.0 * (1.0 + q / 72.0)));
+  }
+  return sinh(x) / x;
+}
+
+// The barostat / thermostat update of md_step_npt (one thread).  Isotropic
+// barostat of Martyna, Tobias and Klein: momentum p_eps of mass W, force
+// G_eps = alpha ke2 + tr W - 3 V P_ext (alpha = 1 + 3 / Nf), a Nose-Hoover
+// chain on the particles (nhc_half_step as for NVT) and one on the barostat
+// (the same step with G_1 = (p_eps^2 / W - kT) / Q'_1, scaling p_eps).
+// Closing half (end): p_eps half step, particle chain, barostat chain; then
+// the extended energy (both chain energies, p_eps^2 / 2W, P_ext V).  Opening
+// half (start): barostat chain, particle chain, p_eps half step, then with
+// v_e = p_eps / W the step's factors: kick a = exp(-alpha v_e dt/2),
+// b = exp(-alpha v_e dt/4) sinh(x)/x at x = alpha v_e dt/4; drift c = exp(v_e dt),
+// e = dt exp(v_e dt/2) sinh(y)/y at y = v_e dt/2; the box grows by c, and the
+// rebuild bound is skin/2 - (1 - s) rl/2 with s the box scale since the last
+// build (negative: rebuild now).  A box edge below nc rl (the run's cell grid
+// no longer covers rl) sets status bit 3.
+__device__ void npt_update(const NptArgs& a) {
+  double* st = a.state;
+  double eta[MD_NHC_MAX], w[MD_NHC_MAX], xi[MD_NHC_MAX], wx[MD_NHC_MAX];
+#pragma unroll
+  for (int j = 0; j < MD_NHC_MAX; ++j) {
+    eta[j] = st[kNptEta + j];
+    w[j] = st[kNptVeta + j];
+    xi[j] = st[kNptXi + j];
+    wx[j] = st[kNptVxi + j];
+  }
+  double peps = st[kNptPeps];
+  double L[3] = {st[kNptL], st[kNptL + 1], st[kNptL + 2]};
+  double vol = L[0] * L[1] * L[2];
+  const double trw = a.sums[1] + a.sums[2] + a.sums[3];
+  double ke2 = a.vsum ? a.mke * *a.vsum : st[kNptKe2];
+  NhcArgs pc{};
+  pc.M = a.M;
+  pc.Q0 = a.Q0;
+  pc.Qj = a.Qj;
+  pc.kT = a.kT;
+  pc.nf = a.nf;
+  pc.dt = a.dt;
+  NhcArgs bc = pc;
+  bc.Q0 = a.Qb;
+  bc.Qj = a.Qb;
+  bc.nf = 1.0;
+  double sc = 1.0;
+  if (a.end) {
+    peps = peps + 0.5 * a.dt * (a.alpha * ke2 + trw - 3.0 * vol * a.ptarget);
+    const double f = nhc_half_step(pc, eta, w, ke2);
+    if (a.vsum_out) *a.vsum_out = *a.vsum * f * f;
+    sc = f;
+    double kb2 = peps * peps / a.W;
+    peps = peps * nhc_half_step(bc, xi, wx, kb2);
+  }
+  double e = a.nf * a.kT * eta[0] + a.kT * xi[0] + 0.5 * a.Qb * wx[0] * wx[0];
+#pragma unroll
+  for (int j = 0; j < MD_NHC_MAX; ++j)
+    if (j < a.M) e += 0.5 * (j == 0 ? a.Q0 : a.Qj) * w[j] * w[j];
+#pragma unroll
+  for (int j = 1; j < MD_NHC_MAX; ++j)
+    if (j < a.M) e += a.kT * eta[j] + a.kT * xi[j] + 0.5 * a.Qb * wx[j] * wx[j];
+  e += 0.5 * peps * peps / a.W + a.ptarget * vol;
+  st[kNptVol] = vol;   // the volume of this state (thermo), before the next step's box
+  if (a.start) {
+    double kb2 = peps * peps / a.W;
+    peps = peps * nhc_half_step(bc, xi, wx, kb2);
+    sc = sc * nhc_half_step(pc, eta, w, ke2);
+    peps = peps + 0.5 * a.dt * (a.alpha * ke2 + trw - 3.0 * vol * a.ptarget);
+    const double ve = peps / a.W;
+    const double xa = a.alpha * ve * 0.25 * a.dt;
+    st[kNptKa] = exp(-a.alpha * ve * 0.5 * a.dt);
+    st[kNptKb] = exp(-xa) * sinh_over_x(xa);
+    const double dc = exp(ve * a.dt);
+    st[kNptDc] = dc;
+    st[kNptDe] = a.dt * exp(ve * 0.5 * a.dt) * sinh_over_x(ve * 0.5 * a.dt);
+    bool small = false;
+    for (int d = 0; d < 3; ++d) {
+      L[d] = L[d] * dc;
+      st[kNptL + d] = L[d];
+      small = small || L[d] < (double)a.nc[d] * a.rl;
+    }
+    if (small) atomicOr(&a.status[MD_ST_ERRORS], 8);
+    const double sb = L[0] / st[kNptLref];
+    const double thr = 0.5 * a.skin - 0.5 * (1.0 - sb) * a.rl;
+    st[kNptSb] = sb;
+    st[kNptThr2] = thr < 0.0 ? -1.0 : thr * thr;
+  }
+#pragma unroll
+  for (int j = 0; j < MD_NHC_MAX; ++j) {
+    st[kNptEta + j] = eta[j];
+    st[kNptVeta + j] = w[j];
+    st[kNptXi + j] = xi[j];
+    st[kNptVxi + j] = wx[j];
+  }
+  st[kNptPeps] = peps;
+  st[kNptScale] = sc;
+  st[kNptKe2] = ke2;
+  st[kNptEnergy] = e;
+}
+
+__global__ __launch_bounds__(kReduceBlocks) void k_sum_stage2_npt(SumArgs a, NptArgs h) {
+  __shared__ double sh[kReduceBlocks];
+  for (int c = 0; c < a.cols; ++c) {
+    const double s = block_sum(a.partials[threadIdx.x * kReduceCols + c], sh);
+    if (threadIdx.x == 0) a.out[c] = s;
+  }
+  if (threadIdx.x == 0) {
+    __threadfence_block();
+    npt_update(h);
+  }
+}
+
+// v <- v scale; v <- v a + (dtfm f) b; x <- x c + e v (factors from the
+// update kernel); rebuild request when |x - s x_ref|^2 exceeds the bound.
+__global__ __launch_bounds__(kBlock) void k_kick_drift_npt(
+    double* __restrict__ x, double* __restrict__ v, const double* __restrict__ f,
+    const double* __restrict__ xr, int n, double dtfm, int* __restrict__ status, BinOut bin,
+    const double* __restrict__ st) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const bool live = i < n;
+  const double sc = st[kNptScale], ka = st[kNptKa], kb = st[kNptKb], dc = st[kNptDc],
+               de = st[kNptDe], sb = st[kNptSb], thr2 = st[kNptThr2];
+  bool finite = true;
+  double xn[3] = {0.0, 0.0, 0.0}, dd[3] = {0.0, 0.0, 0.0};
+  if (live) {
+    for (int d = 0; d < 3; ++d) {
+      const int q = d * n + i;
+      const double vs = v[q] * sc;
+      const double vn = vs * ka + (dtfm * f[q]) * kb;
+      xn[d] = x[q] * dc + de * vn;
+      v[q] = vn;
+      x[q] = xn[d];
+      dd[d] = xn[d] - sb * xr[q];
+      finite = finite && isfinite(xn[d]);
+    }
+  }
+  drift_flags(xn, dd, thr2, i, finite, live, status, bin);
 }
 
 __global__ void k_vjp_params(const double* sums, double eps, double* gparam) {
@@ -232,6 +379,21 @@ hipError_t launch_sum(const SumArgs& a, hipStream_t s, const NhcArgs* nhc) {
     k_sum_stage2<true><<<1, kReduceBlocks, 0, s>>>(a, *nhc);
   else
     k_sum_stage2<false><<<1, kReduceBlocks, 0, s>>>(a, NhcArgs{});
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_npt(const SumArgs& a, const NptArgs& npt, hipStream_t s) {
+  k_sum_stage1<<<kReduceBlocks, kBlock, 0, s>>>(a);
+  hipError_t st = hipGetLastError();
+  if (st != hipSuccess) return st;
+  k_sum_stage2_npt<<<1, kReduceBlocks, 0, s>>>(a, npt);
+  return hipGetLastError();
+}
+
+hipError_t launch_kick_drift_npt(double* x, double* v, const double* f, const double* xr, int n,
+                                 double dtfm, int* status, const BinOut& bin,
+                                 const double* state, hipStream_t s) {
+  k_kick_drift_npt<<<blocks_for(n), kBlock, 0, s>>>(x, v, f, xr, n, dtfm, status, bin, state);
   return hipGetLastError();
 }
 

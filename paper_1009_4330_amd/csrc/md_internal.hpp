@@ -70,6 +70,17 @@ struct BoxK {
   double inv[3];
 };
 
+// The box of a run whose box lives in device memory (NPT): edges at Ld[0..2],
+// reciprocals formed here exactly as the host forms them.
+__device__ inline BoxK box_load(const double* Ld) {
+  BoxK b;
+  for (int d = 0; d < 3; ++d) {
+    b.L[d] = Ld[d];
+    b.inv[d] = 1.0 / Ld[d];
+  }
+  return b;
+}
+
 // Wrap one coordinate into [0, L): x - L floor(x / L), an exact L mapped to 0.
 __device__ inline double wrap_coord(double x, double L) {
   double r = x - L * floor(x / L);
@@ -106,6 +117,7 @@ __device__ inline void store_packed(double* xq, int i, double x, double y, doubl
 // The integrator also refreshes the packed positions the force kernels read.
 struct BinOut {
   BoxK box;
+  const double* boxd;   // nullable: the box in device memory (overrides box)
   int nc[3];
   int* atom_cell;
   double* xq;    // nullable: packed [n][4] copy of x
@@ -126,7 +138,9 @@ __device__ inline void drift_flags(const double* xn, const double* dd, double tr
   const bool leader = (threadIdx.x & (kWave - 1)) == 0;
   if (leader && far) atomicOr(bin.flag, 1);
   if (leader && bad) atomicOr(&status[MD_ST_ERRORS], 2);
-  if (live && bin.atom_cell) bin.atom_cell[i] = cell_of(xn[0], xn[1], xn[2], bin.box, bin.nc);
+  if (live && bin.atom_cell)
+    bin.atom_cell[i] = cell_of(xn[0], xn[1], xn[2], bin.boxd ? box_load(bin.boxd) : bin.box,
+                               bin.nc);
   if (live && bin.xq) store_packed(bin.xq, i, xn[0], xn[1], xn[2], bin.type ? bin.type[i] : 0);
 }
 
@@ -148,6 +162,7 @@ struct IntArgs {
   int* status;
   double dtfm, dt, trig2;
   BinOut bin;            // drift outputs (MD_INT_STEP)
+  const double* kick;    // nullable (NPT): the closing kick is v a + (dtfm f) b, (a, b) = kick[0..1]
 };
 
 // Lennard-Jones constants in both precisions.
@@ -239,9 +254,9 @@ hipError_t launch_cell_count(const int* old_start, const int* atom_cell, const i
                              int* count, int* scount, const int* gate, hipStream_t s);
 hipError_t launch_gather_sort(const int* old_start, int* new_start, const int* count,
                               const int* scount, const int* atom_cell, const int nc[3], BoxK box,
-                              int* perm, const double* xq, const double* v, const int* id,
-                              const int* type, int n, double* sx, double* sv, int* sid,
-                              int* stype, int* status, const int* gate, hipStream_t s);
+                              const double* boxd, int* perm, const double* xq, const double* v,
+                              const int* id, const int* type, int n, double* sx, double* sv,
+                              int* sid, int* stype, int* status, const int* gate, hipStream_t s);
 hipError_t launch_copy_back(double* x, double* v, int* id, double* f, double* xr,
                             const double* sx, const double* sv, const int* sid,
                             const double* sf, int n, hipStream_t s);
@@ -281,6 +296,8 @@ struct BuildArgs {
   int* type_out;         // nullable: species copied back like id
   const int* type_in;    // nullable: species of the home atoms (for xq_out and type_out)
   const int* gate;
+  const double* boxd;    // nullable: the box in device memory (overrides box)
+  double* lref;          // nullable: receives the box edges of this build (NPT)
 };
 hipError_t launch_build(const BuildArgs& a, hipStream_t s);
 
@@ -427,6 +444,7 @@ struct ForceArgs {
   const unsigned short* tile;
   const int* cell_start;
   TileGeom tg;
+  const double* boxd;    // nullable: the box in device memory (overrides box)
 };
 hipError_t launch_pack_positions(const double* x, int n, double* xq, const int* type,
                                  hipStream_t s);
@@ -487,6 +505,7 @@ struct ThermoArgs {
   double* row;
   double step, mass, mvv2e, boltz, dof, volume;
   const int* status;
+  const double* vol;   // nullable (NPT): the volume in device memory, also a tenth column
 };
 hipError_t launch_thermo_row(const ThermoArgs& a, hipStream_t s);
 // gparam[0] = sums[0] / eps, gparam[1] = sums[1].
@@ -500,5 +519,52 @@ hipError_t launch_sc_vjp(const ForceArgs& a, const SCK& p, int prec, int lanes, 
 // gparam = (dL/deps, dL/da, dL/dc) from sums = (LA, LB per unit c).
 hipError_t launch_sc_vjp_params(const double* sums, const SCK& p, double a, double* gparam,
                                 hipStream_t s);
+
+// ------------------------------------------------------------------ NPT --
+// Barostat state (md_step_npt), doubles of md_npt.state: both chains, the
+// barostat momentum, the box, the box of the last build, and the factors the
+// update kernel leaves for the step's kick / drift kernels.
+enum {
+  kNptEta = 0,          // particle chain positions [MD_NHC_MAX]
+  kNptVeta = 8,         // particle chain velocities
+  kNptXi = 16,          // barostat chain positions
+  kNptVxi = 24,         // barostat chain velocities
+  kNptPeps = 32,        // barostat momentum
+  kNptL = 33,           // box edges [3]
+  kNptLref = 36,        // box edges at the last build [3]
+  kNptScale = 39,       // velocity scale (particle thermostat) before the next kick
+  kNptKa = 40,          // kick factors a, b: v <- v a + (dtfm f) b
+  kNptKb = 41,
+  kNptDc = 42,          // drift factors c, e: x <- x c + e v
+  kNptDe = 43,
+  kNptSb = 44,          // box scale since the last build
+  kNptThr2 = 45,        // rebuild bound squared (negative: rebuild)
+  kNptKe2 = 46,         // scaled kinetic term carried to the next half step
+  kNptEnergy = 47,      // extended energy beyond pe + ke (thermo)
+  kNptVol = 48,         // volume
+  kNptWords = 49
+};
+struct NptArgs {
+  double* state;
+  int M;
+  double Q0, Qj, Qb, W, kT, nf, alpha, dt, mke, ptarget, skin, rl;
+  int nc[3];            // cell grid of the run: the box must keep L_d >= nc_d rl
+  int* status;
+  const double* vsum;   // sum v^2 (from the sums), or null: the carried kinetic term
+  const double* sums;   // pe, w0..w5 (the virial trace enters G_eps)
+  double* vsum_out;     // nullable: sum v^2 after the closing half step (thermo)
+  int end, start;
+};
+// Barostat / thermostat update (one thread) at the end of the sum's last
+// stage: with end, the closing half of a step (G_eps half step, particle
+// chain, barostat chain; the extended energy stored); with start, the
+// opening half of the next (barostat chain, particle chain, G_eps half step,
+// the new box and the factors of its kick and drift).
+hipError_t launch_sum_npt(const SumArgs& a, const NptArgs& npt, hipStream_t s);
+// v <- v scale; v <- v a + (dtfm f) b; x <- x c + e v; rebuild request when
+// |x - sb x_ref|^2 > thr2 (or thr2 < 0); cell of each atom in the new box.
+hipError_t launch_kick_drift_npt(double* x, double* v, const double* f, const double* xr, int n,
+                                 double dtfm, int* status, const BinOut& bin,
+                                 const double* state, hipStream_t s);
 
 }  // namespace md

@@ -31,7 +31,7 @@ EXPORTS = ("md_workspace_bytes", "md_nlist_ints", "md_thermo_rows", "md_bin_cell
            "md_build_neighbors", "md_compute_forces", "md_step", "md_step_nvt", "md_force_vjp",
            "md_autoselect", "md_nlist_status", "md_timing_enable", "md_timing_read",
            "md_status_string", "md_compute_forces_noalloc",
-           "md_compute_forces_noalloc_bytes", "md_nlist_tile_entries")
+           "md_compute_forces_noalloc_bytes", "md_nlist_tile_entries", "md_step_npt")
 
 
 class MDError(RuntimeError):
@@ -73,6 +73,16 @@ MD_NHC_MAX, MD_NHC_STATE = 8, 20
 class md_nhc(ctypes.Structure):
     _fields_ = [("t_target", ctypes.c_double), ("t_damp", ctypes.c_double),
                 ("chain", ctypes.c_int), ("state", ctypes.c_void_p)]
+
+
+MD_NPT_STATE = 64
+NPT_L = 33            # md_npt.state: box edges at [33, 36)
+
+
+class md_npt(ctypes.Structure):
+    _fields_ = [("t_target", ctypes.c_double), ("t_damp", ctypes.c_double),
+                ("chain", ctypes.c_int), ("p_target", ctypes.c_double),
+                ("p_damp", ctypes.c_double), ("state", ctypes.c_void_p)]
 
 
 class md_state(ctypes.Structure):
@@ -118,6 +128,9 @@ def lib() -> ctypes.CDLL:
                               I, I, D, D, I, I, I, V, V, ctypes.c_size_t, V]
         L.md_step_nvt.argtypes = [P(md_state), P(md_potential), P(md_box), P(md_cells),
                                   P(md_nlist), I, I, D, D, P(md_nhc), I, I, I, V, V,
+                                  ctypes.c_size_t, V]
+        L.md_step_npt.argtypes = [P(md_state), P(md_potential), P(md_box), P(md_cells),
+                                  P(md_nlist), I, I, D, D, P(md_npt), I, I, I, V, V,
                                   ctypes.c_size_t, V]
         L.md_force_vjp.argtypes = [P(md_potential), V, I64, P(md_box), P(md_nlist), I, V, V, V,
                                    V, ctypes.c_size_t, V]
@@ -400,6 +413,31 @@ def md_step_nvt(state: State, pot: md_potential, box: md_box, cells: Cells, nl: 
                              ctypes.byref(nhc.c), nsteps, thermo_every, setup,
                              _ptr(thermo, torch.float64, 9 * rows) if rows else None, _ptr(ws),
                              ws.numel(), _stream(stream)), "md_step_nvt")
+
+
+class NPT:
+    """Isotropic barostat with Nose-Hoover chains: parameters plus its device
+    state (zero for a fresh barostat; md_step_npt updates it in place)."""
+
+    def __init__(self, t_target: float, t_damp: float, chain: int, p_target: float,
+                 p_damp: float, device="cuda"):
+        self.state = torch.zeros(MD_NPT_STATE, dtype=torch.float64, device=device)
+        self.c = md_npt(t_target=t_target, t_damp=t_damp, chain=chain, p_target=p_target,
+                        p_damp=p_damp, state=self.state.data_ptr())
+
+
+def md_step_npt(state: State, pot: md_potential, box: md_box, cells: Cells, nl: NList,
+                prec: int, kernel: int, skin: float, dt: float, npt: NPT, nsteps: int,
+                thermo_every: int, setup: int, thermo: Optional[torch.Tensor], ws: torch.Tensor,
+                stream=None) -> None:
+    """thermo: rows x 10 doubles (md_step's eight, the conserved extended
+    energy, the volume).  box is updated in place to the final box."""
+    rows = md_thermo_rows(nsteps, thermo_every, setup)
+    _check(lib().md_step_npt(ctypes.byref(state.c), ctypes.byref(pot), ctypes.byref(box),
+                             ctypes.byref(cells.c), ctypes.byref(nl.c), prec, kernel, skin, dt,
+                             ctypes.byref(npt.c), nsteps, thermo_every, setup,
+                             _ptr(thermo, torch.float64, 10 * rows) if rows else None, _ptr(ws),
+                             ws.numel(), _stream(stream)), "md_step_npt")
 
 
 def md_force_vjp(pot: md_potential, x: torch.Tensor, box: md_box, nl: NList, prec: int,

@@ -47,13 +47,16 @@ def capacity_guess(w: Workload) -> int:
 class MDSystem:
     def __init__(self, w: Workload, x: np.ndarray, v: np.ndarray, prec: str = "fp64",
                  kernel: str = "tpa", capacity: Optional[int] = None, device="cuda",
-                 nvt: Optional[tuple] = None):
+                 nvt: Optional[tuple] = None, npt: Optional[tuple] = None):
         """nvt = (t_target, t_damp, chain length) runs md_step_nvt (thermo rows
-        of nine columns) instead of NVE md_step."""
+        of nine columns); npt = (t_target, t_damp, chain length, p_target,
+        p_damp) runs md_step_npt (ten columns, the box in self.box follows the
+        run) instead of NVE md_step."""
         self.w = w
         self.device = device
         self.nhc = md.NHC(*nvt, device=device) if nvt else None
-        self.cols = 9 if nvt else 8
+        self.npt = md.NPT(*npt, device=device) if npt else None
+        self.cols = 10 if npt else (9 if nvt else 8)
         self.prec = PREC[prec]
         self.kernel = KERNEL[kernel]
         self.box = md.make_box(w.box)
@@ -87,21 +90,28 @@ class MDSystem:
         s = self.state
         out = [s.x, s.v, s.f, s.id, self.nl.x_ref, self.nl.status]
         out += [self.type] if self.type is not None else []
+        out += [self.npt.state] if self.npt is not None else []
         return out + ([self.nhc.state] if self.nhc is not None else [])
 
     def _snapshot(self):
-        return tuple(t.clone() for t in self._tensors())
+        return tuple(t.clone() for t in self._tensors()), tuple(self.box.L)
 
     def _restore(self, snap):
-        for dst, src in zip(self._tensors(), snap):
+        tensors, box = snap
+        for dst, src in zip(self._tensors(), tensors):
             dst.copy_(src)
+        for d in range(3):
+            self.box.L[d] = box[d]
 
     def _grow(self, need: int):
         cap = int(need * 1.2) + 16
         self.nl = self._nlist(cap, self.nl.layout)
 
     def _step(self, kernel, nsteps, every, setup, rows):
-        if self.nhc is None:
+        if self.npt is not None:
+            md.md_step_npt(self.state, self.pot, self.box, self.cells, self.nl, self.prec, kernel,
+                           self.w.skin, self.w.dt, self.npt, nsteps, every, setup, rows, self.ws)
+        elif self.nhc is None:
             md.md_step(self.state, self.pot, self.box, self.cells, self.nl, self.prec, kernel,
                        self.w.skin, self.w.dt, nsteps, every, setup, rows, self.ws)
         else:

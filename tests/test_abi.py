@@ -164,14 +164,15 @@ def test_binding_structs_match_the_header(mdlib, tmp_path):
     and the binding's constants equal the header's."""
     structs = {"md_box": mdlib.md_box, "md_potential": mdlib.md_potential,
                "md_cells": mdlib.md_cells, "md_nlist": mdlib.md_nlist,
-               "md_state": mdlib.md_state, "md_nhc": mdlib.md_nhc}
+               "md_state": mdlib.md_state, "md_nhc": mdlib.md_nhc, "md_npt": mdlib.md_npt}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "md.h"', 'int main(void) {']
     for name, cls in structs.items():
         lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
         for field, _ in cls._fields_:
             lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
     for const in ("MD_NHC_MAX", "MD_NHC_STATE", "MD_MAX_ATOMS", "MD_STATUS_WORDS",
-                  "MD_POT_BUCK", "MD_LAYOUT_WPA"):
+                  "MD_POT_BUCK", "MD_LAYOUT_WPA", "MD_LAYOUT_TILE", "MD_NPT_STATE",
+                  "MD_NOALLOC_SCRATCH_BYTES"):
         lines.append(f'  printf("const {const} %lld\\n", (long long){const});')
     lines.append("  return 0;\n}")
     src = tmp_path / "layout.c"
@@ -191,7 +192,8 @@ def test_binding_structs_match_the_header(mdlib, tmp_path):
         for field, _ in cls._fields_:
             assert got[(name, field)] == getattr(cls, field).offset, (name, field)
     for const in ("MD_NHC_MAX", "MD_NHC_STATE", "MD_MAX_ATOMS", "MD_STATUS_WORDS",
-                  "MD_POT_BUCK", "MD_LAYOUT_WPA"):
+                  "MD_POT_BUCK", "MD_LAYOUT_WPA", "MD_LAYOUT_TILE", "MD_NPT_STATE",
+                  "MD_NOALLOC_SCRATCH_BYTES"):
         assert got[("const", const)] == getattr(mdlib, const), const
 
 
@@ -269,3 +271,31 @@ def test_tile_entries_host_logic(mdlib):
     bx = mdlib.make_box(I.LJ_4K.box)
     assert lib.md_compute_forces(R(lj), fake, 4000, R(bx), R(nl), 0, 0, 0, fake, None, fake,
                                  1 << 30, None) == mdlib.MD_ERR_INVALID_ARG
+
+
+def test_npt_host_checks(mdlib):
+    """md_step_npt refuses, before any launch, a continuing run whose box has
+    shrunk below its cell grid (edges under nc rl) and invalid barostat
+    parameters."""
+    lib = mdlib.lib()
+    fake = ctypes.c_void_p(0x1000)
+    R = ctypes.byref
+    cells = mdlib.md_cells(nc=(5, 5, 5), ncell_cap=125, cell_start=0x1000, atom_cell=0x1000,
+                           perm=0x1000)
+    nl = mdlib.md_nlist(capacity=100, layout=4, rl=2.8, neigh=0x1000, numneigh=0x1000,
+                        x_ref=0x1000, status=0x1000)
+    st = mdlib.md_state(n=4000, x=0x1000, v=0x1000, f=0x1000, id=0x1000, mass=1.0, ftm2v=1.0,
+                        mvv2e=1.0, boltz=1.0)
+    lj = mdlib.lj_potential(2.5)
+    npt = mdlib.md_npt(t_target=1.5, t_damp=0.5, chain=3, p_target=1.0, p_damp=0.5,
+                       state=0x1000)
+    small = mdlib.make_box((5 * 2.8 * 0.99,) * 3)      # below 5 cells of 2.8
+    assert lib.md_step_npt(R(st), R(lj), R(small), R(cells), R(nl), 0, 4, 0.3, 0.005, R(npt), 10,
+                           10, 0, None, fake, 1 << 30, None) == mdlib.MD_ERR_BOX_TOO_SMALL
+    bad = mdlib.md_npt(t_target=1.5, t_damp=0.5, chain=3, p_target=1.0, p_damp=0.0,
+                       state=0x1000)
+    box = mdlib.make_box(I.LJ_4K.box)
+    assert lib.md_step_npt(R(st), R(lj), R(box), R(cells), R(nl), 0, 4, 0.3, 0.005, R(bad), 10,
+                           10, 1, None, fake, 1 << 30, None) == mdlib.MD_ERR_INVALID_ARG
+    assert lib.md_step_npt(R(st), R(lj), R(box), R(cells), R(nl), 0, 4, 0.3, 0.005, None, 10,
+                           10, 1, None, fake, 1 << 30, None) == mdlib.MD_ERR_INVALID_ARG

@@ -72,8 +72,8 @@ MUTANTS = {
     "pressure_kinetic_factor": ("row[5] = (2.0 * ke + ", "row[5] = (ke + ", ["ideal_gas"]),
     "pressure_virial_sign": ("(2.0 * ke + (vir[0] + vir[1] + vir[2]))",
                              "(2.0 * ke - (vir[0] + vir[1] + vir[2]))", ["pressure_dEdV"]),
-    "pressure_virial_diagonal": ("(vir[0] + vir[1] + vir[2])", "(vir[0] + vir[1] + vir[3])",
-                                 ["pressure_dEdV"]),
+    "pressure_virial_diagonal": ("(2.0 * ke + (vir[0] + vir[1] + vir[2]))",
+                                 "(2.0 * ke + (vir[0] + vir[1] + vir[3]))", ["pressure_dEdV"]),
     "npt_barostat_force_kinetic": ("return alpha * ke2 + (vir[0] + vir[1] + vir[2])",
                                    "return ke2 + (vir[0] + vir[1] + vir[2])",
                                    ["npt_conserved"]),
