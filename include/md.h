@@ -93,7 +93,9 @@ enum { MD_LAYOUT_TPA = 1, MD_LAYOUT_WPA = 64 };
    one cell before the run to one after.  The same value as an md_kernel asks
    md_step for that kernel; MD_KERNEL_AUTO also tries them.  Every other call
    reads the neigh part of such a list with the K-lane kernel.  Needs at least
-   4 cells along x and 3 along y and z. */
+   4 cells along x and 3 along y and z, and a tile buffer of
+   md_nlist_tile_entries() entries (nl->tile_entries); not used in NPT runs,
+   whose cell grid differs from the box's. */
 enum { MD_LAYOUT_TILE = 256 };
 
 /* nl->status words (device int[MD_STATUS_WORDS]). */
@@ -161,8 +163,10 @@ typedef struct {
   double* x_ref;       /* [3][n] positions at the last build (rebuild trigger reference) */
   int* status;         /* [MD_STATUS_WORDS], zero it once before first use */
   int half;            /* 0: full list; 1: half list (see above) */
-  unsigned short* tile;  /* nullable: md_nlist_tile_entries() 16-bit entries for the tiled
-                            layouts (MD_LAYOUT_TILE | K); written by md_step's builds */
+  unsigned short* tile;  /* nullable: 16-bit entries for the tiled layouts
+                            (MD_LAYOUT_TILE | K); written by md_step's builds */
+  size_t tile_entries;   /* entries tile holds; the tiled layouts are used only when this
+                            covers md_nlist_tile_entries() of the run's box and grid */
 } md_nlist;
 
 /* Dynamic state advanced by md_step.  Units: ftm2v converts force/mass * time
@@ -195,7 +199,9 @@ size_t md_nlist_tile_entries(int64_t n, int capacity, const md_box* box, double 
 /* Number of thermo rows md_step writes. */
 int md_thermo_rows(int nsteps, int thermo_every, int setup);
 
-/* Cell binning (wrap + bin + stable counting sort).  Wraps x in place into
+/* Paper: section "Cell list approach" (the box cut into cells at least a
+   cutoff wide, each atom binned to one; here the cells serve the list build).
+   Cell binning (wrap + bin + stable counting sort).  Wraps x in place into
    [0, L) (x - L floor(x / L), an L result mapped to 0), bins each atom to
    clamp((int)(x_d nc_d / L_d), 0, nc_d - 1), and writes atom_cell,
    cell_start and perm.  Cells per dimension follow from box and rl; the call
@@ -211,7 +217,10 @@ md_status md_bin_cells(double* x, int64_t n, const md_box* box, double rl,
 md_status md_sort_atoms(md_state* st, const md_cells* cells, double* x_ref, void* ws,
                         size_t ws_bytes, void* stream);
 
-/* Full neighbour list at rl = rc + skin from binned positions (x as wrapped by
+/* Paper: section "Neighbor list approach" (the numneigh[i] / neighbors[i][jj]
+   arrays its TpA and BpA listings read, built from the cells of "Cell list
+   approach" with a skin added to the cutoff).
+   Full neighbour list at rl = rc + skin from binned positions (x as wrapped by
    md_bin_cells, in any atom order: cell members are taken through perm).
    Distances use the minimum image d - L rint(d / L) and
    r^2 = (dx dx + dy dy) + dz dz without fused multiply-add, so the pair set is
@@ -222,7 +231,11 @@ md_status md_build_neighbors(const double* x, int64_t n, const md_box* box,
                              const md_cells* cells, double rc, double skin, md_nlist* nl,
                              void* stream);
 
-/* Forces (and, on flags, energy / virial) from a list.  f [3][n] is
+/* Paper: section "Neighbor list approach" (the TpA and BpA listings: per atom,
+   sum the pair force over its listed neighbours inside the cutoff, store f[i]);
+   lj/cut and the EAM and silicate systems of Appendix A; precision modes of
+   "Design objectives, features and usage".
+   Forces (and, on flags, energy / virial) from a list.  f [3][n] is
    overwritten.  ev, when flags != 0, receives 7 doubles: energy, then virial
    xx yy zz xy xz yz, W = 1/2 sum_i sum_j d_ij (x) F_ij.  Only pairs with
    r^2 < rc^2 (FP64, as above) contribute, in either precision.  MD_MIXED
@@ -238,7 +251,11 @@ md_status md_compute_forces(const md_potential* p, const double* x, int64_t n,
                             md_kernel k, int flags, double* f, double* ev, void* ws,
                             size_t ws_bytes, void* stream);
 
-/* nsteps of velocity-Verlet NVE (dtfm = (0.5 dt ftm2v) / mass):
+/* Paper: "Design objectives, features and usage" (the NVE integrator, with
+   integration in double precision in the mixed mode) around the force
+   evaluation of "Neighbor list approach"; the whole step stays on the GPU
+   (the GPU-resident workflow of the same section).
+   nsteps of velocity-Verlet NVE (dtfm = (0.5 dt ftm2v) / mass):
      v += dtfm f; x += dt v;
      rebuild (wrap, bin, sort, list) if max_i |x_i - x_ref_i|^2 > (skin/2)^2;
      f = forces(x); v += dtfm f.
@@ -367,7 +384,10 @@ md_status md_step_npt(md_state* st, const md_potential* p, md_box* box, md_cells
                       const md_npt* npt, int nsteps, int thermo_every, int setup,
                       double* thermo, void* ws, size_t ws_bytes, void* stream);
 
-/* Vector-Jacobian product of the forces for L = sum_i u_i . F_i:
+/* Not a passage of the paper: an extension of this library beyond the
+   paper's method (differentiating the paper's force evaluation for force
+   matching), with the same pair set and list.
+   Vector-Jacobian product of the forces for L = sum_i u_i . F_i:
    gx = (dF/dx)^T u = -H u, with u, gx [device, 3][n]; gparam [device, may be
    NULL] receives the parameter gradients of L.  LJ: dL/deps, dL/dsigma
    (2 doubles).  SC: dL/deps, dL/da, dL/dc (3 doubles); its Hessian includes

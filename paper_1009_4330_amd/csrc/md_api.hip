@@ -76,6 +76,13 @@ bool layout_ok(int layout) {
   return lanes_ok(k) && (!is_tile(layout) || k <= kTileMaxK);
 }
 
+// Whether the list's tile buffer covers the tiled layouts of n atoms in the
+// grid nc (and the grid takes them); fills the geometry.
+bool tile_fits(const md_nlist* nl, int64_t n, const int nc[3], TileGeom* tg) {
+  return nl->tile && !nl->half && tile_geom(n, nc, tg) &&
+         nl->tile_entries >= tile_list_entries(n, nl->capacity, *tg);
+}
+
 md_status check_pot(const md_potential* p) {
   if (!p || !finite_pos(p->rc)) return MD_ERR_INVALID_ARG;
   if (p->kind == MD_POT_LJ) {
@@ -250,8 +257,7 @@ md_status build_list(const double* x, int n, int sorted, const md_box* box, cons
                      const md_cells* cells, double rl, md_nlist* nl, int layout,
                      hipStream_t s) {
   TileGeom tg{};
-  if (is_tile(layout) && (!sorted || !nl->tile || nl->half || !tile_geom(n, nc, &tg)))
-    return MD_ERR_UNSUPPORTED;
+  if (is_tile(layout) && (!sorted || !tile_fits(nl, n, nc, &tg))) return MD_ERR_UNSUPPORTED;
   BuildArgs a{};
   a.x = x;
   a.n = n;
@@ -289,7 +295,7 @@ constexpr int kTileBuildEvery = 5;
 md_status autoselect_impl(const md_potential* p, const double* x, int n, int sorted,
                           const md_box* box, const md_cells* cells, double rl, md_nlist* nl,
                           md_precision prec, int reps, md_kernel* choice, void* ws,
-                          const WsLayout& L, hipStream_t s) {
+                          const WsLayout& L, hipStream_t s, bool tiled_ok = true) {
   int nc[3] = {cells->nc[0], cells->nc[1], cells->nc[2]};
   int before[MD_STATUS_WORDS];
   MD_CK(hipMemcpyAsync(before, nl->status, sizeof(before), hipMemcpyDeviceToHost, s));
@@ -306,7 +312,7 @@ md_status autoselect_impl(const md_potential* p, const double* x, int n, int sor
   std::vector<int> trials;
   for (int k = 1; k <= kWave; k *= 2) trials.push_back(k);
   TileGeom tg{};
-  if (sorted && p->kind == MD_POT_LJ && nl->tile && !nl->half && tile_geom(n, nc, &tg))
+  if (sorted && tiled_ok && p->kind == MD_POT_LJ && tile_fits(nl, n, nc, &tg))
     for (int k = 1; k <= kTileMaxK; k *= 2) trials.push_back(MD_LAYOUT_TILE | k);
   for (int k : trials) {
     md_status st = build_list(x, n, sorted, box, nc, cells, rl, nl, k, s);
@@ -872,7 +878,7 @@ static md_status step_impl(md_state* stt, const md_potential* p, md_box* box,
   }
   // tiled kernels: LJ, a tile buffer, and a grid they apply to
   TileGeom tg{};
-  const bool tile_ok = p->kind == MD_POT_LJ && nl->tile && tile_geom(stt->n, nc, &tg);
+  const bool tile_ok = !npt && p->kind == MD_POT_LJ && tile_fits(nl, stt->n, nc, &tg);
   if (k != MD_KERNEL_AUTO && is_tile((int)k) && !tile_ok) return MD_ERR_UNSUPPORTED;
   if (!setup) {
     for (int d = 0; d < 3; ++d)
@@ -1097,7 +1103,8 @@ static md_status step_impl(md_state* stt, const md_potential* p, md_box* box,
         kernel = lanes;
       } else {
         md_kernel choice = MD_KERNEL_TPA;
-        st = autoselect_impl(p, stt->x, n, 1, box, cells, rl, nl, prec, 5, &choice, ws, L, s);
+        st = autoselect_impl(p, stt->x, n, 1, box, cells, rl, nl, prec, 5, &choice, ws, L, s,
+                             tile_ok);
         if (st != MD_OK) return st;
         kernel = (int)choice;
       }

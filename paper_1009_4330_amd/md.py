@@ -64,7 +64,7 @@ class md_nlist(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int), ("layout", ctypes.c_int), ("rl", ctypes.c_double),
                 ("neigh", ctypes.c_void_p), ("numneigh", ctypes.c_void_p),
                 ("x_ref", ctypes.c_void_p), ("status", ctypes.c_void_p), ("half", ctypes.c_int),
-                ("tile", ctypes.c_void_p)]
+                ("tile", ctypes.c_void_p), ("tile_entries", ctypes.c_size_t)]
 
 
 MD_NHC_MAX, MD_NHC_STATE = 8, 20
@@ -253,7 +253,8 @@ class NList:
                           neigh=self.neigh.data_ptr(), numneigh=self.numneigh.data_ptr(),
                           x_ref=self.x_ref.data_ptr(), status=self.status.data_ptr(),
                           half=1 if half else 0,
-                          tile=self.tile.data_ptr() if self.tile is not None else None)
+                          tile=self.tile.data_ptr() if self.tile is not None else None,
+                          tile_entries=self.tile.numel() if self.tile is not None else 0)
 
     @property
     def capacity(self) -> int:

@@ -170,6 +170,79 @@ class MDSystem:
             self.steps_done += k
         return np.concatenate(out) if out else np.zeros((0, self.cols))
 
+    # -- checkpoint / resume ----------------------------------------------------
+    def checkpoint(self, path: str) -> None:
+        """Write everything a continuing md_step reads to an .npz file: the
+        state (x, v, f, ids, species), the list (entries, lengths, reference
+        positions, tile entries), the cell starts and cells of its build, the
+        status words, thermostat / barostat state, box, layout and steps done.
+        A run restored from it continues bit for bit as if never stopped."""
+        if not self.ready:
+            raise RuntimeError("checkpoint before setup: nothing to save")
+        torch.cuda.synchronize()
+        host = lambda t: t.detach().cpu().numpy()
+        d = dict(x=host(self.state.x), v=host(self.state.v), f=host(self.state.f),
+                 id=host(self.state.id), x_ref=host(self.nl.x_ref), neigh=host(self.nl.neigh),
+                 numneigh=host(self.nl.numneigh), status=host(self.nl.status),
+                 cell_start=host(self.cells.cell_start), atom_cell=host(self.cells.atom_cell),
+                 perm=host(self.cells.perm), nc=np.array(list(self.cells.c.nc)),
+                 box=np.array(list(self.box.L)), layout=np.array(self.nl.layout),
+                 capacity=np.array(self.nl.capacity), rl=np.array(self.nl.c.rl),
+                 steps_done=np.array(self.steps_done), prec=np.array(self.prec))
+        if self.type is not None:
+            d["type"] = host(self.type)
+        if self.nl.tile is not None:
+            d["tile"] = host(self.nl.tile)
+        if self.nhc is not None:
+            d["nhc"] = host(self.nhc.state)
+        if self.npt is not None:
+            d["npt"] = host(self.npt.state)
+        np.savez(path, **d)
+
+    def restore(self, path: str) -> None:
+        """Load a checkpoint written by checkpoint() for a system of the same
+        workload, atom count and ensemble; the next run() continues it."""
+        with np.load(path, allow_pickle=False) as z:
+            if int(z["prec"]) != self.prec:
+                raise ValueError("checkpoint was taken in another precision")
+            if ("nhc" in z) != (self.nhc is not None) or ("npt" in z) != (self.npt is not None):
+                raise ValueError("checkpoint was taken in another ensemble")
+            if z["x"].shape[1] != self.n:
+                raise ValueError("checkpoint holds another atom count")
+            layout = int(z["layout"])
+            self.nl = self._nlist(int(z["capacity"]), layout)
+            if ("tile" in z) and self.nl.tile is None:
+                raise ValueError("checkpoint has a tiled list this system cannot hold")
+            dev = lambda a, t: t.copy_(torch.as_tensor(a))
+            dev(z["x"], self.state.x)
+            dev(z["v"], self.state.v)
+            dev(z["f"], self.state.f)
+            dev(z["id"], self.state.id)
+            dev(z["x_ref"], self.nl.x_ref)
+            dev(z["neigh"], self.nl.neigh)
+            dev(z["numneigh"], self.nl.numneigh)
+            dev(z["status"], self.nl.status)
+            dev(z["cell_start"], self.cells.cell_start)
+            dev(z["atom_cell"], self.cells.atom_cell)
+            dev(z["perm"], self.cells.perm)
+            if "tile" in z:
+                dev(z["tile"], self.nl.tile)
+            if self.type is not None:
+                dev(z["type"], self.type)
+            if self.nhc is not None:
+                dev(z["nhc"], self.nhc.state)
+            if self.npt is not None:
+                dev(z["npt"], self.npt.state)
+            for q in range(3):
+                self.cells.c.nc[q] = int(z["nc"][q])
+                self.box.L[q] = float(z["box"][q])
+            self.nl.c.layout = layout
+            self.nl.c.rl = float(z["rl"])
+            self.kernel = layout
+            self.steps_done = int(z["steps_done"])
+        torch.cuda.synchronize()
+        self.ready = True
+
     def host_state(self):
         """(x, v, f) as numpy [3][n] arrays in the caller's original atom order."""
         order = torch.argsort(self.state.id.long())

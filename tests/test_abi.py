@@ -299,3 +299,30 @@ def test_npt_host_checks(mdlib):
                            10, 1, None, fake, 1 << 30, None) == mdlib.MD_ERR_INVALID_ARG
     assert lib.md_step_npt(R(st), R(lj), R(box), R(cells), R(nl), 0, 4, 0.3, 0.005, None, 10,
                            10, 1, None, fake, 1 << 30, None) == mdlib.MD_ERR_INVALID_ARG
+
+
+def test_tiled_layout_needs_a_large_enough_tile_buffer(mdlib):
+    """A tiled kernel is refused (MD_ERR_UNSUPPORTED) before any launch when
+    the list's tile buffer is smaller than the run's grid needs, and in NPT
+    runs, whose cell grid is not the box's."""
+    lib = mdlib.lib()
+    fake = ctypes.c_void_p(0x1000)
+    R = ctypes.byref
+    w = I.LJ_4K
+    box = mdlib.make_box(w.box)
+    need = mdlib.md_nlist_tile_entries(w.natoms, 160, box, 2.8)
+    cells = mdlib.md_cells(ncell_cap=125, cell_start=0x1000, atom_cell=0x1000, perm=0x1000)
+    st = mdlib.md_state(n=w.natoms, x=0x1000, v=0x1000, f=0x1000, id=0x1000, mass=1.0,
+                        ftm2v=1.0, mvv2e=1.0, boltz=1.0)
+    lj = mdlib.lj_potential(2.5)
+    tiled = mdlib.MD_LAYOUT_TILE | 4
+    short = mdlib.md_nlist(capacity=160, layout=1, rl=2.8, neigh=0x1000, numneigh=0x1000,
+                           x_ref=0x1000, status=0x1000, tile=0x1000, tile_entries=need - 1)
+    assert lib.md_step(R(st), R(lj), R(box), R(cells), R(short), 0, tiled, 0.3, 0.005, 10, 10, 1,
+                       None, fake, 1 << 30, None) == mdlib.MD_ERR_UNSUPPORTED
+    full = mdlib.md_nlist(capacity=160, layout=1, rl=2.8, neigh=0x1000, numneigh=0x1000,
+                          x_ref=0x1000, status=0x1000, tile=0x1000, tile_entries=need)
+    npt = mdlib.md_npt(t_target=1.5, t_damp=0.5, chain=3, p_target=1.0, p_damp=0.5,
+                       state=0x1000)
+    assert lib.md_step_npt(R(st), R(lj), R(box), R(cells), R(full), 0, tiled, 0.3, 0.005, R(npt),
+                           10, 10, 1, None, fake, 1 << 30, None) == mdlib.MD_ERR_UNSUPPORTED
