@@ -58,10 +58,21 @@ typedef enum {
   MD_ERR_HIP = 6,            /* a HIP runtime call failed */
   MD_ERR_WORKSPACE = 7,      /* ws is NULL or smaller than md_workspace_bytes */
   MD_ERR_UNSTABLE = 8,       /* md_step: an atom moved more than a cell edge between builds */
-  MD_ERR_SCRATCH = 9         /* md_compute_forces_noalloc: the call needs more than its fixed scratch */
+  MD_ERR_SCRATCH = 9,        /* md_compute_forces_noalloc: the call needs more than its fixed scratch */
+  MD_STATUS_INT_MIN_ = -2147483647 - 1,   /* range markers: see md_precision */
+  MD_STATUS_INT_MAX_ = 2147483647
 } md_status;
 
-typedef enum { MD_FP64 = 0, MD_MIXED = 1 } md_precision;
+/* The enums taken as arguments span the whole int range (the two _INT_
+   markers), so every value a caller passes, valid or not, is a value of the
+   type that the argument checks can see and reject with MD_ERR_INVALID_ARG
+   (in C++ an enum holds only the values its enumerators' bit width covers). */
+typedef enum {
+  MD_FP64 = 0,
+  MD_MIXED = 1,
+  MD_PRECISION_INT_MIN_ = -2147483647 - 1,
+  MD_PRECISION_INT_MAX_ = 2147483647
+} md_precision;
 
 /* Force kernels.  The paper's thread-per-atom (TpA) and block-per-atom (BpA)
    designs are the two ends of one family: K lanes of a 64-wide wavefront share
@@ -70,7 +81,13 @@ typedef enum { MD_FP64 = 0, MD_MIXED = 1 } md_precision;
    wavefront per atom, reduced with cross-lane operations); any power of two in
    between may be passed as an md_kernel value.  MD_KERNEL_AUTO picks K with a
    mini-benchmark (md_autoselect). */
-typedef enum { MD_KERNEL_AUTO = 0, MD_KERNEL_TPA = 1, MD_KERNEL_WPA = 64 } md_kernel;
+typedef enum {
+  MD_KERNEL_AUTO = 0,
+  MD_KERNEL_TPA = 1,
+  MD_KERNEL_WPA = 64,
+  MD_KERNEL_INT_MIN_ = -2147483647 - 1,   /* range markers: see md_precision */
+  MD_KERNEL_INT_MAX_ = 2147483647
+} md_kernel;
 enum { MD_EFLAG = 1, MD_VFLAG = 2 };
 enum { MD_POT_LJ = 0, MD_POT_SC = 1, MD_POT_BUCK = 2 };
 

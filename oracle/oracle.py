@@ -21,6 +21,12 @@ SRC = os.path.join(HERE, "md_oracle.c")
 LIB = os.path.join(HERE, "libmd_oracle.so")
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
           "-std=c11", "-Wall", "-Wno-unused-function"]
+# AddressSanitizer + UndefinedBehaviorSanitizer build of the same source (a
+# process loading it needs gcc's libasan preloaded); MD_ORACLE_LIB selects the
+# library lib() loads.
+SAN_LIB = os.path.join(HERE, "libmd_oracle_san.so")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+             "-fno-omit-frame-pointer", "-g"]
 
 
 class OracleError(RuntimeError):
@@ -37,6 +43,15 @@ def build(force: bool = True) -> str:
         subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
+
+
+def build_sanitized() -> str:
+    """Compile md_oracle.c with the oracle's flags plus ASan and UBSan into
+    libmd_oracle_san.so."""
+    tmp = SAN_LIB + ".tmp"
+    subprocess.check_call(["gcc", *CFLAGS, *SAN_FLAGS, "-o", tmp, SRC, "-lm"])
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
 
 
 _lib = None
@@ -69,9 +84,12 @@ def build_variant(source_text: str, out_path: str) -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
-            build()
-        _lib = ctypes.CDLL(LIB)
+        path = os.environ.get("MD_ORACLE_LIB")
+        if not path:
+            path = LIB
+            if not os.path.exists(LIB):
+                build()
+        _lib = ctypes.CDLL(path)
         _declare(_lib)
     return _lib
 

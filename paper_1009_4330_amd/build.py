@@ -34,6 +34,37 @@ def _compile(src: str) -> str:
     return obj
 
 
+SAN_LIB = os.path.join(BUILD, "asan", "libmd_mi355x_san.so")
+# host code of md_api.hip (argument checks, layouts, workspace and status
+# handling) with AddressSanitizer and UBSan; device code as in build()
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address,undefined",
+             "-Xarch_host", "-fno-sanitize-recover=all",
+             "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_sanitized() -> str:
+    """The library with md_api.hip's host code built under ASan and UBSan,
+    linked with build()'s objects of the other sources (run build() first).
+    A process loading it needs clang's ASan runtime preloaded."""
+    os.makedirs(os.path.dirname(SAN_LIB), exist_ok=True)
+    objs = [os.path.join(BUILD, os.path.splitext(f)[0] + ".o") for f in SOURCES if f != "md_api.hip"]
+    for o in objs:
+        if not os.path.exists(o):
+            raise RuntimeError(f"{o} is missing: run build() first")
+    api = os.path.join(os.path.dirname(SAN_LIB), "md_api_san.o")
+    cmd = [HIPCC, *FLAGS, *SAN_FLAGS, "-c", os.path.join(CSRC, "md_api.hip"), "-o", api]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed on md_api.hip (sanitized)")
+    res = subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-o", SAN_LIB, *objs, api],
+                         capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc link failed (sanitized)")
+    return SAN_LIB
+
+
 def build() -> str:
     """Compile every HIP source and link the shared library."""
     os.makedirs(BUILD, exist_ok=True)

@@ -12,7 +12,10 @@ from typing import Optional, Sequence
 
 import torch
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmd_mi355x.so")
+# The in-tree build; MD_LIB_PATH selects another build of the same library
+# (the sanitized host build the ABI tests load).
+LIB_PATH = os.environ.get("MD_LIB_PATH") or os.path.join(
+    os.path.dirname(os.path.abspath(__file__)), "libmd_mi355x.so")
 
 MD_OK, MD_ERR_INVALID_ARG, MD_ERR_BOX_TOO_SMALL, MD_ERR_NLIST_OVERFLOW = 0, 1, 2, 3
 MD_ERR_NONFINITE, MD_ERR_UNSUPPORTED, MD_ERR_HIP, MD_ERR_WORKSPACE = 4, 5, 6, 7

@@ -7,6 +7,7 @@ with the capacity raised to the required count plus headroom.
 """
 from __future__ import annotations
 
+import json
 import math
 from typing import Optional
 
@@ -17,6 +18,30 @@ from . import md
 from .inputs import Workload, pair_table
 
 PREC = {"fp64": md.MD_FP64, "mixed": md.MD_MIXED}
+
+# Names of the thermo row columns md_step writes (NVE), and the ones the NVT
+# and NPT variants append.
+THERMO_COLUMNS = ("step", "pe", "ke", "etotal", "temp", "press", "builds", "maxneigh")
+THERMO_NVT = THERMO_COLUMNS + ("conserved",)
+THERMO_NPT = THERMO_COLUMNS + ("conserved", "volume")
+_THERMO_INTS = ("step", "builds", "maxneigh")
+
+
+def thermo_records(rows: np.ndarray, columns=THERMO_COLUMNS) -> list:
+    """Thermo rows as dicts keyed by column name; step, build count and the
+    largest neighbour count as integers, the rest as floats."""
+    rows = np.asarray(rows, dtype=np.float64)
+    if rows.ndim != 2 or rows.shape[1] != len(columns):
+        raise ValueError(f"thermo rows of {len(columns)} columns expected, got shape {rows.shape}")
+    return [{c: (int(v) if c in _THERMO_INTS else float(v)) for c, v in zip(columns, r)}
+            for r in rows]
+
+
+def write_thermo_jsonl(fh, rows: np.ndarray, columns=THERMO_COLUMNS) -> None:
+    """Append thermo rows to an open text file, one JSON object per line
+    (floats written with full round-trip precision)."""
+    for rec in thermo_records(rows, columns):
+        fh.write(json.dumps(rec) + "\n")
 KERNEL = {"auto": md.MD_KERNEL_AUTO, "tpa": md.MD_KERNEL_TPA, "wpa": md.MD_KERNEL_WPA,
           **{f"k{k}": k for k in md.LANES},
           **{f"t{k}": md.MD_LAYOUT_TILE | k for k in md.TILE_LANES}}
@@ -47,16 +72,21 @@ def capacity_guess(w: Workload) -> int:
 class MDSystem:
     def __init__(self, w: Workload, x: np.ndarray, v: np.ndarray, prec: str = "fp64",
                  kernel: str = "tpa", capacity: Optional[int] = None, device="cuda",
-                 nvt: Optional[tuple] = None, npt: Optional[tuple] = None):
+                 nvt: Optional[tuple] = None, npt: Optional[tuple] = None,
+                 thermo_jsonl: Optional[str] = None):
         """nvt = (t_target, t_damp, chain length) runs md_step_nvt (thermo rows
         of nine columns); npt = (t_target, t_damp, chain length, p_target,
         p_damp) runs md_step_npt (ten columns, the box in self.box follows the
-        run) instead of NVE md_step."""
+        run) instead of NVE md_step.  thermo_jsonl: a file that every thermo
+        row setup() and run() return is appended to, one JSON object per row
+        (columns THERMO_COLUMNS, THERMO_NVT or THERMO_NPT)."""
         self.w = w
         self.device = device
         self.nhc = md.NHC(*nvt, device=device) if nvt else None
         self.npt = md.NPT(*npt, device=device) if npt else None
         self.cols = 10 if npt else (9 if nvt else 8)
+        self.columns = THERMO_NPT if npt else (THERMO_NVT if nvt else THERMO_COLUMNS)
+        self.thermo_jsonl = thermo_jsonl
         self.prec = PREC[prec]
         self.kernel = KERNEL[kernel]
         self.box = md.make_box(w.box)
@@ -136,7 +166,12 @@ class MDSystem:
                 continue
             self.ready = True
             self.kernel = self.nl.layout      # lanes per atom the run settled on
-            return rows.cpu().numpy() if thermo else None
+            if not thermo:
+                return None
+            r = rows.cpu().numpy()
+            r[:, 0] += self.steps_done
+            self._log(r)
+            return r
 
     def run(self, nsteps: int, thermo_every: int = 0, chunk: int = 0) -> np.ndarray:
         """Advance nsteps; returns thermo rows (every thermo_every steps)."""
@@ -165,10 +200,16 @@ class MDSystem:
             if rows_n:
                 r = th[:rows_n].cpu().numpy()
                 r[:, 0] += self.steps_done
+                self._log(r)
                 out.append(r)
             done += k
             self.steps_done += k
         return np.concatenate(out) if out else np.zeros((0, self.cols))
+
+    def _log(self, rows: np.ndarray) -> None:
+        if self.thermo_jsonl and len(rows):
+            with open(self.thermo_jsonl, "a") as fh:
+                write_thermo_jsonl(fh, rows, self.columns)
 
     # -- checkpoint / resume ----------------------------------------------------
     def checkpoint(self, path: str) -> None:
