@@ -28,6 +28,13 @@
  *     Nose-Hoover chain thermostat in the standard time-reversible splitting
  *     of Martyna, Tuckerman and Klein: a thermostat half step, the
  *     velocity-Verlet step, a thermostat half step;
+ *   - isotropic NPT integration (the NPT integrator named in "Design
+ *     objectives"): the barostat of Martyna, Tobias and Klein with
+ *     Nose-Hoover chains on the particles and on the barostat, in the
+ *     splitting of Tuckerman et al.  One term of it is parity unpinned: the
+ *     3 / N_f part of the barostat's kinetic factor alpha = 1 + 3 / N_f keeps
+ *     the extended energy conserved with or without it and moves the volume
+ *     distribution only at order 1 / N, so no test isolates it;
  *   - the vector-Jacobian products of the LJ forces (with respect to
  *     positions and (eps, sigma)) and of the Sutton-Chen forces (positions and
  *     (eps, a, c)).
