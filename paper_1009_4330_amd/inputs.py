@@ -74,10 +74,17 @@ class Workload:
     buck_C: tuple = ()
     charges: tuple = ()
     qqr2e: float = 0.0
+    # fcc unit cells along x, y, z for an orthorhombic box; () = ncell along each
+    shape: tuple = ()
+
+    @property
+    def cells_xyz(self) -> tuple:
+        return tuple(self.shape) if self.shape else (self.ncell,) * 3
 
     @property
     def natoms(self) -> int:
-        return (8 if self.lattice == "rocksalt" else 4) * self.ncell ** 3
+        c = self.cells_xyz
+        return (8 if self.lattice == "rocksalt" else 4) * c[0] * c[1] * c[2]
 
     def species(self) -> np.ndarray:
         """Species per atom in the order of initial_state's positions."""
@@ -87,8 +94,7 @@ class Workload:
 
     @property
     def box(self) -> tuple:
-        edge = self.ncell * self.a
-        return (edge, edge, edge)
+        return tuple(c * self.a for c in self.cells_xyz)
 
 
 def lj_lattice_constant(rho: float) -> float:
@@ -143,11 +149,13 @@ def scaled(w: Workload, ncell: int, **kw) -> Workload:
     return dataclasses.replace(w, name=f"{w.name}@{ncell}", ncell=ncell, **kw)
 
 
-def fcc_positions(ncell: int, a: float) -> np.ndarray:
-    """fcc lattice, SoA float64 [3][N]; atom order: cell z, y, x, then basis."""
-    idx = np.arange(ncell, dtype=np.float64)
-    cz, cy, cx = np.meshgrid(idx, idx, idx, indexing="ij")
-    out = np.empty((3, ncell, ncell, ncell, 4), dtype=np.float64)
+def fcc_positions(ncell, a: float) -> np.ndarray:
+    """fcc lattice of ncell unit cells per edge, or (nx, ny, nz) cells along
+    x, y, z; SoA float64 [3][N]; atom order: cell z, y, x, then basis."""
+    nx, ny, nz = (ncell,) * 3 if np.isscalar(ncell) else tuple(ncell)
+    cz, cy, cx = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                             np.arange(nx, dtype=np.float64), indexing="ij")
+    out = np.empty((3, nz, ny, nx, 4), dtype=np.float64)
     for b, (bx, by, bz) in enumerate(FCC_BASIS):
         out[0, ..., b] = (cx + bx) * a
         out[1, ..., b] = (cy + by) * a
@@ -207,7 +215,12 @@ def pair_table(w: Workload, which: str) -> np.ndarray:
 
 def initial_state(w: Workload, seed: Optional[int] = None):
     """(x, v, box) for a workload: perfect lattice + Gaussian velocities."""
-    x = rocksalt_positions(w.ncell, w.a) if w.lattice == "rocksalt" else fcc_positions(w.ncell, w.a)
+    if w.lattice == "rocksalt":
+        if w.shape:
+            raise ValueError("orthorhombic shapes are fcc only")
+        x = rocksalt_positions(w.ncell, w.a)
+    else:
+        x = fcc_positions(w.cells_xyz, w.a)
     v = gaussian_velocities(w.natoms, w.temp, w.mass, w.units,
                             w.seed if seed is None else seed)
     return x, v, w.box
