@@ -1,7 +1,10 @@
 """Parity at the full workload sizes, in the launch configuration bench.py
 times (AUTO lanes per atom, fused md_step): the 256,000-atom LJ melt against
-the oracle's own run of the same size, the 141k-ion Buckingham crystal and the
-500k-atom Sutton-Chen solid against the oracle's forces over all atoms."""
+the oracle's own run of the same size (NVE in both precisions, NPT in FP64),
+the 141k-ion Buckingham crystal and the 500k-atom Sutton-Chen solid against
+the oracle's forces over all atoms."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -148,4 +151,30 @@ def test_fullsize_sutton_chen_step(orc):
         assert rel(rows[:, c], ref.thermo[:, c]) < 1e-10, c
     gx, gv, gf = sysm.host_state()
     assert np.abs(min_image_diff(gx, ref.x, box)).max() < 1e-9
+    assert_fp64(gf, ref.f, 1e-9)
+
+
+def test_fullsize_lj_npt_fp64(orc):
+    """NPT at the bench's size and launch configuration (the 256k melt,
+    isotropic barostat at P = 2.0 with chains of 3, AUTO lanes per atom):
+    30 steps in FP64 against the oracle's NPT run -- rebuild steps, thermo
+    rows (energies, T, P, the conserved extended energy, the volume), final
+    box, positions, velocities and forces."""
+    w = dataclasses.replace(I.LJ_256K, temp=1.5)
+    npt = (1.5, 100 * w.dt, 3, 2.0, 50 * w.dt)
+    x, v, box = I.initial_state(w)
+    print("[fullsize] lj_melt_256k npt fp64 30 steps", flush=True)
+    s = MDSystem(w, x, v, "fp64", "auto", npt=npt)
+    rows = np.concatenate([s.setup(True), s.run(30, 5)])
+    t, td, M, p, pd = npt
+    ref, _, L = orc.md_run_npt(orc.params_for(w), x, v, box, 30, t, td, p, pd, M,
+                               thermo_every=5)
+    assert np.array_equal(rows[:, 6].astype(int), ref.thermo[:, 6].astype(int))
+    for c in (1, 2, 3, 4, 5, 8, 9):
+        assert rel(rows[:, c], ref.thermo[:, c]) < 1e-10, c
+    assert abs(ref.thermo[-1, 9] / ref.thermo[0, 9] - 1.0) > 1e-5   # the box moved
+    assert np.abs(np.array(s.box.L) / L - 1.0).max() < 1e-12
+    gx, gv, gf = s.host_state()
+    assert np.abs(min_image_diff(gx, ref.x, L)).max() < 1e-9
+    assert np.abs(gv - ref.v).max() < 1e-9
     assert_fp64(gf, ref.f, 1e-9)
