@@ -1318,8 +1318,9 @@ __device__ inline int build_row_segment(const BuildArgs& a, const BuildLds& L, i
   return mx;
 }
 
-// Sorted atoms, at least 3 cells along x: a resident grid working through
-// the row segments (build_row_segment).
+// Sorted atoms, at least 3 cells along x: the row segments
+// (build_row_segment), one per workgroup as launched; a smaller grid would
+// loop over several.
 __global__ __launch_bounds__(kBlock, 4) void k_build_rows(BuildArgs a0) {
   if (a0.gate && *a0.gate == 0) return;
   const BuildArgs a = build_view(a0);
@@ -1589,7 +1590,11 @@ hipError_t launch_build(const BuildArgs& a, hipStream_t s) {
   const double per_cell = (double)a.n / (double)ncell;
   if (a.sorted && a.nc[0] >= 3 && kMaxSlabs * 9 * per_cell <= 0.9 * kRowCap) {
     const int64_t segs = (int64_t)((a.nc[0] + kRowCells - 1) / kRowCells) * a.nc[1] * a.nc[2];
-    k_build_rows<<<resident_grid(4, segs), kBlock, 0, s>>>(a);
+    // one workgroup per row segment: the hardware deals the segments, whose
+    // work varies with their atom counts, to the CUs as they free up (a
+    // resident grid taking a fixed share each was 5 % slower, its tail the
+    // workgroups with one segment more)
+    k_build_rows<<<(unsigned)segs, kBlock, 0, s>>>(a);
   } else {
     // pieces of kHomePiece home atoms at the mean occupancy; denser cells
     // loop over further pieces
