@@ -651,7 +651,7 @@ def headline(args):
             del tpa
         else:
             line["mixed_tpa_run"] = tpa
-        vjp = guarded("adjoint", bench_vjp, reps=20)
+        vjp = guarded("adjoint", bench_vjp, reps=100)
         log(f"[bench] vjp atoms/s: {vjp}")
         if "error" not in vjp:
             line.update({"adjoint_hvp_atoms_per_s": vjp["mixed"],

@@ -772,8 +772,14 @@ md_status md_force_vjp(const md_potential* p, const double* x, int64_t n, const 
       sa.n = (int)n;
       sa.partials = at<double>(ws, L.partials);
       sa.out = at<double>(ws, L.scalars);
+      sa.params.kind = kParamsSC;
+      sa.params.eps = k.eps;
+      sa.params.a = p->sc_a;
+      sa.params.c = k.c;
+      sa.params.nexp = (double)k.n;
+      sa.params.mexp = (double)k.m;
+      sa.params.gparam = gparam;
       MD_CK(launch_sum(sa, s));
-      MD_CK(launch_sc_vjp_params(at<double>(ws, L.scalars), k, p->sc_a, gparam, s));
     }
     return MD_OK;
   }
@@ -788,9 +794,11 @@ md_status md_force_vjp(const md_potential* p, const double* x, int64_t n, const 
     sa.n = (int)n;
     sa.partials = at<double>(ws, L.partials);
     sa.out = at<double>(ws, L.scalars);
-    MD_CK(launch_sum(sa, s));
     // dL/deps = (sum_i u_i . F_i) / eps; the second sum is dL/dsigma already
-    MD_CK(launch_vjp_params(at<double>(ws, L.scalars), p->lj_eps, gparam, s));
+    sa.params.kind = kParamsLJ;
+    sa.params.eps = p->lj_eps;
+    sa.params.gparam = gparam;
+    MD_CK(launch_sum(sa, s));
   }
   return MD_OK;
 }

@@ -151,8 +151,21 @@ __global__ __launch_bounds__(kBlock) void k_sum_stage1(SumArgs a) {
   }
 }
 
-// Stage 2: one block sums the kReduceBlocks partials of each column; with
-// NHC, thread 0 then runs the thermostat chain update on the sums it wrote.
+// The adjoints' parameter gradients from the two sums (ParamArgs).
+__device__ inline void finish_params(const ParamArgs& p, const double* out) {
+  if (p.kind == kParamsLJ) {
+    p.gparam[0] = out[0] / p.eps;
+    p.gparam[1] = out[1];
+  } else if (p.kind == kParamsSC) {
+    p.gparam[0] = (out[0] + p.c * out[1]) / p.eps;
+    p.gparam[1] = (p.nexp * out[0] + 0.5 * p.mexp * p.c * out[1]) / p.a;
+    p.gparam[2] = out[1];
+  }
+}
+
+// Stage 2: one block sums the kReduceBlocks partials of each column; thread
+// 0 then runs, on the sums it wrote, the thermostat chain update (NHC) and
+// the adjoints' parameter gradients (a.params).
 template <bool NHC>
 __global__ __launch_bounds__(kReduceBlocks) void k_sum_stage2(SumArgs a, NhcArgs h) {
   __shared__ double sh[kReduceBlocks];
@@ -161,6 +174,7 @@ __global__ __launch_bounds__(kReduceBlocks) void k_sum_stage2(SumArgs a, NhcArgs
     if (threadIdx.x == 0) a.out[c] = s;
   }
   if (NHC && threadIdx.x == 0) nhc_update(h);
+  if (threadIdx.x == 0 && a.params.kind != kParamsNone) finish_params(a.params, a.out);
 }
 
 __global__ void k_thermo_row(ThermoArgs a) {
@@ -326,22 +340,6 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift_npt(
   drift_flags(xn, dd, thr2, i, finite, live, status, bin);
 }
 
-__global__ void k_vjp_params(const double* sums, double eps, double* gparam) {
-  if (threadIdx.x != 0) return;
-  gparam[0] = sums[0] / eps;
-  gparam[1] = sums[1];
-}
-
-// Sutton-Chen: L = LA + c LB with LA ~ a^n and c LB ~ a^(m/2) (A ~ a^n,
-// B ~ a^m, e ~ a^(-m/2)); sums = (LA, LB).
-__global__ void k_sc_vjp_params(const double* sums, double eps, double a, double c, double n,
-                                double m, double* gparam) {
-  if (threadIdx.x != 0) return;
-  gparam[0] = (sums[0] + c * sums[1]) / eps;
-  gparam[1] = (n * sums[0] + 0.5 * m * c * sums[1]) / a;
-  gparam[2] = sums[1];
-}
-
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -399,17 +397,6 @@ hipError_t launch_kick_drift_npt(double* x, double* v, const double* f, const do
 
 hipError_t launch_thermo_row(const ThermoArgs& a, hipStream_t s) {
   k_thermo_row<<<1, 64, 0, s>>>(a);
-  return hipGetLastError();
-}
-
-hipError_t launch_sc_vjp_params(const double* sums, const SCK& p, double a, double* gparam,
-                                hipStream_t s) {
-  k_sc_vjp_params<<<1, 64, 0, s>>>(sums, p.eps, a, p.c, (double)p.n, (double)p.m, gparam);
-  return hipGetLastError();
-}
-
-hipError_t launch_vjp_params(const double* sums, double eps, double* gparam, hipStream_t s) {
-  k_vjp_params<<<1, 64, 0, s>>>(sums, eps, gparam);
   return hipGetLastError();
 }
 

@@ -486,13 +486,27 @@ hipError_t launch_nhc(const NhcArgs& a, hipStream_t s);
 constexpr int kNhcEnergy = 16, kNhcScale = 17, kNhcKe2 = 18;   // state words after the chain
 hipError_t launch_ke(const double* v, int n, double* keatom, hipStream_t s);
 
-// Deterministic sums: cols arrays of n doubles (col c at base[c] ) -> out[cols].
+// Parameter gradients of the force adjoints, finished from their two sums
+// (out[0], out[1]) on the sum's last stage.  LJ: dL/deps = out[0] / eps,
+// dL/dsigma = out[1].  Sutton-Chen, with L = LA + c LB, LA ~ a^n and
+// c LB ~ a^(m/2): dL/deps = (LA + c LB) / eps, dL/da = (n LA + m/2 c LB) / a,
+// dL/dc = LB.
+enum { kParamsNone = 0, kParamsLJ = 1, kParamsSC = 2 };
+struct ParamArgs {
+  int kind = kParamsNone;
+  double eps = 1.0, a = 1.0, c = 0.0, nexp = 0.0, mexp = 0.0;
+  double* gparam = nullptr;
+};
+
+// Deterministic sums: cols arrays of n doubles (col c at base[c] ) -> out[cols];
+// then, with params.kind set, the adjoint's parameter gradients from out.
 struct SumArgs {
   const double* col[kReduceCols];
   int cols;
   int n;
   double* partials;
   double* out;
+  ParamArgs params;
 };
 struct NhcArgs;
 // With nhc, the thermostat chain update (launch_nhc) runs at the end of the
@@ -508,17 +522,12 @@ struct ThermoArgs {
   const double* vol;   // nullable (NPT): the volume in device memory, also a tenth column
 };
 hipError_t launch_thermo_row(const ThermoArgs& a, hipStream_t s);
-// gparam[0] = sums[0] / eps, gparam[1] = sums[1].
-hipError_t launch_vjp_params(const double* sums, double eps, double* gparam, hipStream_t s);
 // Sutton-Chen adjoint: density pass into e, then the pass for lam (dL/drho),
 // la and lb (per-atom parameter sums) and the packed (u_i, lam_i) records uq
 // ([n][4] scratch), then the position pass into gx.
 hipError_t launch_sc_vjp(const ForceArgs& a, const SCK& p, int prec, int lanes, const double* u,
                          double* e, double* lam, double* la, double* lb, double* uq, double* gx,
                          hipStream_t s);
-// gparam = (dL/deps, dL/da, dL/dc) from sums = (LA, LB per unit c).
-hipError_t launch_sc_vjp_params(const double* sums, const SCK& p, double a, double* gparam,
-                                hipStream_t s);
 
 // ------------------------------------------------------------------ NPT --
 // Barostat state (md_step_npt), doubles of md_npt.state: both chains, the
