@@ -438,8 +438,14 @@ __device__ inline void lj_pair(double s, const LJK& p, double& g, double& phi) {
   }
 }
 
+// FP32-mixed instances without energy / virial are held to six waves per
+// SIMD (at most 80 VGPRs, reached without spills): the K = 4 fused kernel
+// runs 2 % faster.  The others keep the compiler's choice: six waves made the
+// FP64 kernel 9 % slower and the energy / virial one spill.
+constexpr int lj_waves_per_eu(int prec, bool ev) { return prec == MD_MIXED && !ev ? 6 : 1; }
+
 template <int PREC, bool EV, int K, bool FUSED>
-__global__ __launch_bounds__(kBlock) void k_lj(FK a0, LJK p) {
+__global__ __launch_bounds__(kBlock, lj_waves_per_eu(PREC, EV)) void k_lj(FK a0, LJK p) {
   const FK a = with_box(a0);
   if (a.clear && blockIdx.x == 0 && threadIdx.x == 0) *a.clear = 0;
   const Lane<K> ln(a);
