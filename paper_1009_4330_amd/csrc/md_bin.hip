@@ -1582,13 +1582,16 @@ hipError_t launch_gather_int(const int* perm, int n, const int* src, int* dst, h
   return hipGetLastError();
 }
 
-// The row path needs a run's slabs (kMaxSlabs x 9 cells) in LDS; when the
-// mean occupancy says they would not fit (long cutoffs), every run would fall
-// back to one cell at a time, so the general path with home pieces is taken.
+// The row path needs a run's slabs (kMaxSlabs x 9 cells) in LDS.  It is
+// taken when their mean count plus three standard deviations of an ideal
+// gas's count (a liquid or solid varies less) fits kRowCap, so that runs
+// falling back to one cell at a time stay rare; denser cells (long cutoffs)
+// would fall back everywhere, and the general path with home pieces is taken.
 hipError_t launch_build(const BuildArgs& a, hipStream_t s) {
   const int64_t ncell = (int64_t)a.nc[0] * a.nc[1] * a.nc[2];
   const double per_cell = (double)a.n / (double)ncell;
-  if (a.sorted && a.nc[0] >= 3 && kMaxSlabs * 9 * per_cell <= 0.9 * kRowCap) {
+  const double run = kMaxSlabs * 9 * per_cell;
+  if (a.sorted && a.nc[0] >= 3 && run + 3.0 * std::sqrt(run) <= kRowCap) {
     const int64_t segs = (int64_t)((a.nc[0] + kRowCells - 1) / kRowCells) * a.nc[1] * a.nc[2];
     // one workgroup per row segment: the hardware deals the segments, whose
     // work varies with their atom counts, to the CUs as they free up (a

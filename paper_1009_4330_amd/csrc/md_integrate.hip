@@ -122,32 +122,75 @@ __global__ __launch_bounds__(kBlock) void k_ke(const double* __restrict__ v, int
   keatom[i] = a * a + b * b + c * c;
 }
 
-// Block tree sum in LDS (fixed shape, so the result is deterministic).
-__device__ inline double block_sum(double v, double* sh) {
+// Block tree sums of the first `cols` of the kReduceCols values each thread
+// holds, all columns at once: the levels across wavefronts in LDS (sh holds
+// NT x kReduceCols doubles), the levels within the first wavefront by lane
+// shuffles.  Pairing and order are those of the plain halving tree
+// (s[t] += s[t + off] for off = NT/2 .. 1), so the sums are deterministic;
+// thread 0 ends with them in v.
+template <int NT>
+__device__ inline void block_sums(double (&v)[kReduceCols], int cols, double* sh) {
   const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if (t < off) sh[t] += sh[t + off];
+#pragma unroll
+  for (int c = 0; c < kReduceCols; ++c)
+    if (c < cols) sh[c * NT + t] = v[c];
+#pragma unroll
+  for (int off = NT / 2; off >= kWave; off >>= 1) {
     __syncthreads();
+    if (t < off) {
+#pragma unroll
+      for (int c = 0; c < kReduceCols; ++c)
+        if (c < cols) sh[c * NT + t] += sh[c * NT + t + off];
+    }
   }
-  const double r = sh[0];
   __syncthreads();
-  return r;
+  if (t < kWave) {
+#pragma unroll
+    for (int c = 0; c < kReduceCols; ++c) {
+      if (c < cols) {
+        double s = sh[c * NT + t];
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_down(s, off, kWave);
+        v[c] = s;
+      }
+    }
+  }
 }
 
-// Stage 1: block b sums its contiguous chunk of each column.
+// Stage 1: block b sums its contiguous chunk of each column (the columns
+// read side by side).
 __global__ __launch_bounds__(kBlock) void k_sum_stage1(SumArgs a) {
-  __shared__ double sh[kBlock];
+  __shared__ double sh[kReduceCols * kBlock];
   const int per = (a.n + kReduceBlocks - 1) / kReduceBlocks;
   const int b0 = blockIdx.x * per;
   const int b1 = min(a.n, b0 + per);
-  for (int c = 0; c < a.cols; ++c) {
-    double s = 0.0;
-    const double* col = a.col[c];
-    for (int i = b0 + threadIdx.x; i < b1; i += kBlock) s += col[i];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) a.partials[blockIdx.x * kReduceCols + c] = s;
+  double s[kReduceCols];
+#pragma unroll
+  for (int c = 0; c < kReduceCols; ++c) s[c] = 0.0;
+  for (int i = b0 + threadIdx.x; i < b1; i += kBlock) {
+#pragma unroll
+    for (int c = 0; c < kReduceCols; ++c)
+      if (c < a.cols) s[c] += a.col[c][i];
+  }
+  block_sums<kBlock>(s, a.cols, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int c = 0; c < kReduceCols; ++c)
+      if (c < a.cols) a.partials[blockIdx.x * kReduceCols + c] = s[c];
+  }
+}
+
+// Stage 2's sums: the kReduceBlocks partials of each column, into a.out.
+__device__ inline void sum_partials(const SumArgs& a, double* sh) {
+  double s[kReduceCols];
+#pragma unroll
+  for (int c = 0; c < kReduceCols; ++c)
+    s[c] = c < a.cols ? a.partials[threadIdx.x * kReduceCols + c] : 0.0;
+  block_sums<kReduceBlocks>(s, a.cols, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int c = 0; c < kReduceCols; ++c)
+      if (c < a.cols) a.out[c] = s[c];
   }
 }
 
@@ -168,11 +211,8 @@ __device__ inline void finish_params(const ParamArgs& p, const double* out) {
 // the adjoints' parameter gradients (a.params).
 template <bool NHC>
 __global__ __launch_bounds__(kReduceBlocks) void k_sum_stage2(SumArgs a, NhcArgs h) {
-  __shared__ double sh[kReduceBlocks];
-  for (int c = 0; c < a.cols; ++c) {
-    const double s = block_sum(a.partials[threadIdx.x * kReduceCols + c], sh);
-    if (threadIdx.x == 0) a.out[c] = s;
-  }
+  __shared__ double sh[kReduceCols * kReduceBlocks];
+  sum_partials(a, sh);
   if (NHC && threadIdx.x == 0) nhc_update(h);
   if (threadIdx.x == 0 && a.params.kind != kParamsNone) finish_params(a.params, a.out);
 }
@@ -220,40 +260,61 @@ __device__ inline double sinh_over_x(double x) {
 // rebuild bound is skin/2 - (1 - s) rl/2 with s the box scale since the last
 // build (negative: rebuild now).  A box edge below nc rl (the run's cell grid
 // no longer covers rl) sets status bit 3.
+//
+// Run by the 64 lanes of one wavefront: the two chains are independent
+// within each half, so even lanes step the particle chain and odd lanes the
+// barostat chain in the same instructions, and the results are exchanged by
+// lane shuffles (the arithmetic of each chain is unchanged).  Lane 0 writes
+// the state, lane 1 the barostat chain.
 __device__ void npt_update(const NptArgs& a) {
   double* st = a.state;
-  double eta[MD_NHC_MAX], w[MD_NHC_MAX], xi[MD_NHC_MAX], wx[MD_NHC_MAX];
+  const int lane = threadIdx.x & (kWave - 1);
+  const bool baro = lane & 1;
+  double ch[MD_NHC_MAX], cw[MD_NHC_MAX];   // this lane's chain
 #pragma unroll
   for (int j = 0; j < MD_NHC_MAX; ++j) {
-    eta[j] = st[kNptEta + j];
-    w[j] = st[kNptVeta + j];
-    xi[j] = st[kNptXi + j];
-    wx[j] = st[kNptVxi + j];
+    ch[j] = st[(baro ? kNptXi : kNptEta) + j];
+    cw[j] = st[(baro ? kNptVxi : kNptVeta) + j];
   }
   double peps = st[kNptPeps];
   double L[3] = {st[kNptL], st[kNptL + 1], st[kNptL + 2]};
+  const double lref = st[kNptLref];
   double vol = L[0] * L[1] * L[2];
   const double trw = a.sums[1] + a.sums[2] + a.sums[3];
-  double ke2 = a.vsum ? a.mke * *a.vsum : st[kNptKe2];
-  NhcArgs pc{};
-  pc.M = a.M;
-  pc.Q0 = a.Q0;
-  pc.Qj = a.Qj;
-  pc.kT = a.kT;
-  pc.nf = a.nf;
-  pc.dt = a.dt;
-  NhcArgs bc = pc;
-  bc.Q0 = a.Qb;
-  bc.Qj = a.Qb;
-  bc.nf = 1.0;
-  double sc = 1.0;
+  const double vs = a.vsum ? *a.vsum : 0.0;
+  double ke2 = a.vsum ? a.mke * vs : st[kNptKe2];
+  NhcArgs c{};
+  c.M = a.M;
+  c.Q0 = baro ? a.Qb : a.Q0;
+  c.Qj = baro ? a.Qb : a.Qj;
+  c.kT = a.kT;
+  c.nf = baro ? 1.0 : a.nf;
+  c.dt = a.dt;
+  // one half step of both chains: the particle chain on ke2, the barostat
+  // chain on p_eps^2 / W; returns (particle factor, barostat factor)
+  auto chains = [&](double& fp, double& fb) {
+    double q = baro ? peps * peps / a.W : ke2;
+    const double f = nhc_half_step(c, ch, cw, q);
+    fp = __shfl(f, 0, kWave);
+    fb = __shfl(f, 1, kWave);
+    ke2 = __shfl(q, 0, kWave);
+  };
+  double sc = 1.0, vs_out = 0.0;
   if (a.end) {
     peps = peps + 0.5 * a.dt * (a.alpha * ke2 + trw - 3.0 * vol * a.ptarget);
-    const double f = nhc_half_step(pc, eta, w, ke2);
-    if (a.vsum_out) *a.vsum_out = *a.vsum * f * f;
-    sc = f;
-    double kb2 = peps * peps / a.W;
-    peps = peps * nhc_half_step(bc, xi, wx, kb2);
+    double fp, fb;
+    chains(fp, fb);
+    vs_out = vs * fp * fp;
+    sc = fp;
+    peps = peps * fb;
+  }
+  double eta[MD_NHC_MAX], w[MD_NHC_MAX], xi[MD_NHC_MAX], wx[MD_NHC_MAX];
+#pragma unroll
+  for (int j = 0; j < MD_NHC_MAX; ++j) {
+    eta[j] = __shfl(ch[j], 0, kWave);
+    w[j] = __shfl(cw[j], 0, kWave);
+    xi[j] = __shfl(ch[j], 1, kWave);
+    wx[j] = __shfl(cw[j], 1, kWave);
   }
   double e = a.nf * a.kT * eta[0] + a.kT * xi[0] + 0.5 * a.Qb * wx[0] * wx[0];
 #pragma unroll
@@ -263,37 +324,53 @@ __device__ void npt_update(const NptArgs& a) {
   for (int j = 1; j < MD_NHC_MAX; ++j)
     if (j < a.M) e += a.kT * eta[j] + a.kT * xi[j] + 0.5 * a.Qb * wx[j] * wx[j];
   e += 0.5 * peps * peps / a.W + a.ptarget * vol;
-  st[kNptVol] = vol;   // the volume of this state (thermo), before the next step's box
+  const double vol_state = vol;   // the volume of this state (thermo), before the next box
+  double ka = 0.0, kb = 0.0, dc = 0.0, de = 0.0, sb = 0.0, thr2 = 0.0;
+  bool small = false;
   if (a.start) {
-    double kb2 = peps * peps / a.W;
-    peps = peps * nhc_half_step(bc, xi, wx, kb2);
-    sc = sc * nhc_half_step(pc, eta, w, ke2);
+    double fp, fb;
+    chains(fp, fb);
+    peps = peps * fb;
+    sc = sc * fp;
     peps = peps + 0.5 * a.dt * (a.alpha * ke2 + trw - 3.0 * vol * a.ptarget);
     const double ve = peps / a.W;
     const double xa = a.alpha * ve * 0.25 * a.dt;
-    st[kNptKa] = exp(-a.alpha * ve * 0.5 * a.dt);
-    st[kNptKb] = exp(-xa) * sinh_over_x(xa);
-    const double dc = exp(ve * a.dt);
-    st[kNptDc] = dc;
-    st[kNptDe] = a.dt * exp(ve * 0.5 * a.dt) * sinh_over_x(ve * 0.5 * a.dt);
-    bool small = false;
+    ka = exp(-a.alpha * ve * 0.5 * a.dt);
+    kb = exp(-xa) * sinh_over_x(xa);
+    dc = exp(ve * a.dt);
+    de = a.dt * exp(ve * 0.5 * a.dt) * sinh_over_x(ve * 0.5 * a.dt);
     for (int d = 0; d < 3; ++d) {
       L[d] = L[d] * dc;
-      st[kNptL + d] = L[d];
       small = small || L[d] < (double)a.nc[d] * a.rl;
     }
-    if (small) atomicOr(&a.status[MD_ST_ERRORS], 8);
-    const double sb = L[0] / st[kNptLref];
+    sb = L[0] / lref;
     const double thr = 0.5 * a.skin - 0.5 * (1.0 - sb) * a.rl;
-    st[kNptSb] = sb;
-    st[kNptThr2] = thr < 0.0 ? -1.0 : thr * thr;
+    thr2 = thr < 0.0 ? -1.0 : thr * thr;
   }
+  if (lane == 1) {
+#pragma unroll
+    for (int j = 0; j < MD_NHC_MAX; ++j) {
+      st[kNptXi + j] = ch[j];
+      st[kNptVxi + j] = cw[j];
+    }
+  }
+  if (lane != 0) return;
 #pragma unroll
   for (int j = 0; j < MD_NHC_MAX; ++j) {
-    st[kNptEta + j] = eta[j];
-    st[kNptVeta + j] = w[j];
-    st[kNptXi + j] = xi[j];
-    st[kNptVxi + j] = wx[j];
+    st[kNptEta + j] = ch[j];
+    st[kNptVeta + j] = cw[j];
+  }
+  if (a.end && a.vsum_out) *a.vsum_out = vs_out;
+  st[kNptVol] = vol_state;
+  if (a.start) {
+    st[kNptKa] = ka;
+    st[kNptKb] = kb;
+    st[kNptDc] = dc;
+    st[kNptDe] = de;
+    for (int d = 0; d < 3; ++d) st[kNptL + d] = L[d];
+    if (small) atomicOr(&a.status[MD_ST_ERRORS], 8);
+    st[kNptSb] = sb;
+    st[kNptThr2] = thr2;
   }
   st[kNptPeps] = peps;
   st[kNptScale] = sc;
@@ -301,16 +378,13 @@ __device__ void npt_update(const NptArgs& a) {
   st[kNptEnergy] = e;
 }
 
+// The update runs on the first wavefront once thread 0's sums are written
+// (the barrier makes them visible to the other lanes).
 __global__ __launch_bounds__(kReduceBlocks) void k_sum_stage2_npt(SumArgs a, NptArgs h) {
-  __shared__ double sh[kReduceBlocks];
-  for (int c = 0; c < a.cols; ++c) {
-    const double s = block_sum(a.partials[threadIdx.x * kReduceCols + c], sh);
-    if (threadIdx.x == 0) a.out[c] = s;
-  }
-  if (threadIdx.x == 0) {
-    __threadfence_block();
-    npt_update(h);
-  }
+  __shared__ double sh[kReduceCols * kReduceBlocks];
+  sum_partials(a, sh);
+  __syncthreads();
+  if (threadIdx.x < kWave) npt_update(h);
 }
 
 // v <- v scale; v <- v a + (dtfm f) b; x <- x c + e v (factors from the
