@@ -422,6 +422,7 @@ WsLayout ws_layout(int64_t n, int64_t ncell) {
   L.eatom = take(sizeof(double) * nn);
   L.vatom = take(sizeof(double) * 6 * nn);
   L.keatom = take(sizeof(double) * nn);
+  L.vtrace = take(sizeof(double) * nn);
   L.sc_e = take(sizeof(double) * nn);
   L.partials = take(sizeof(double) * kReduceBlocks * kReduceCols);
   L.scalars = take(sizeof(double) * 16);
@@ -934,6 +935,8 @@ static md_status step_impl(md_state* stt, const md_potential* p, md_box* box,
   double* vatom = at<double>(ws, L.vatom);
   double* keatom = at<double>(ws, L.keatom);
   double* sums = at<double>(ws, L.scalars);
+  // NPT: every force pass leaves each atom's virial trace, which the barostat sums
+  double* const vtrace = npt ? at<double>(ws, L.vtrace) : nullptr;
 
   int* scount = at<int>(ws, L.scount);
 
@@ -1022,6 +1025,7 @@ static md_status step_impl(md_state* stt, const md_potential* p, md_box* box,
       fa.ev.eatom = eatom;
       fa.ev.vatom = vatom;
     }
+    fa.ev.vtrace = vtrace;
     fa.clear = gate;
     timing_events(&fa.t0, &fa.t1);
     return force_dispatch(p, fa, prec, kernel, at<double>(ws, L.sc_e), s);
@@ -1139,9 +1143,10 @@ static md_status step_impl(md_state* stt, const md_potential* p, md_box* box,
     // virial enters the barostat force), the kinetic sum, and the update
     // that opens step 1.  Per step: the scaled kick + drift + check (factors
     // from the update), gated rebuild in the current box, forces with the
-    // closing kick (factors a, b) storing x, f, v and |v|^2, the sums
-    // (energy, virial, |v|^2), whose last kernel runs the update closing
-    // this step and opening the next, and the thermo row.
+    // closing kick (factors a, b) storing x, f, v and |v|^2 (and, on thermo
+    // steps, energy and virial; otherwise the virial trace alone), the sums,
+    // whose last kernel runs the update closing this step and opening the
+    // next, and the thermo row.
     const double kT = stt->boltz * npt->t_target;
     NptArgs pa{};
     pa.state = nstate;
@@ -1160,21 +1165,33 @@ static md_status step_impl(md_state* stt, const md_potential* p, md_box* box,
     pa.rl = rl;
     for (int d = 0; d < 3; ++d) pa.nc[d] = nc[d];
     pa.status = status;
+    // Sums of a force pass with energy and virial (setup, thermo steps): pe,
+    // the virial's diagonal (the row's pressure), the trace, |v|^2 into
+    // sums[0..7] (5 and 6 unused).  Other steps: the trace and |v|^2 only,
+    // into sums[9], sums[10].  The barostat takes the trace column's sum in
+    // both, so a thermo row leaves the trajectory unchanged.
     SumArgs sa{};
     sa.cols = 8;
     sa.col[0] = eatom;
-    for (int q = 0; q < 6; ++q) sa.col[1 + q] = vatom + (size_t)q * n;
+    for (int q = 0; q < 3; ++q) sa.col[1 + q] = vatom + (size_t)q * n;
+    sa.col[4] = vtrace;
     sa.col[7] = keatom;
     sa.n = n;
     sa.partials = at<double>(ws, L.partials);
     sa.out = sums;
+    SumArgs sb = sa;
+    sb.cols = 2;
+    sb.col[0] = vtrace;
+    sb.col[1] = keatom;
+    for (int q = 2; q < kReduceCols; ++q) sb.col[q] = nullptr;
+    sb.out = sums + 9;
     MD_CK(launch_pack_positions(stt->x, n, xqs[0], type, s));
     if ((st = forces(true, kernel, xqs[0], nullptr)) != MD_OK) return st;
     MD_CK(launch_ke(stt->v, n, keatom, s));
     {
       NptArgs a = pa;
       a.vsum = sums + 7;
-      a.sums = sums;
+      a.trw = sums + 4;
       a.start = nsteps > 0;
       MD_CK(launch_sum_npt(sa, a, s));
     }
@@ -1210,14 +1227,14 @@ static md_status step_impl(md_state* stt, const md_potential* p, md_box* box,
       in.trig2 = trig2;
       in.bin = bin;
       in.kick = nstate + kNptKa;
-      if ((st = forces(true, kernel, cur, &in)) != MD_OK) return st;
+      if ((st = forces(th, kernel, cur, &in)) != MD_OK) return st;
       NptArgs a = pa;
-      a.vsum = sums + 7;
-      a.sums = sums;
+      a.vsum = th ? sums + 7 : sums + 10;
+      a.trw = th ? sums + 4 : sums + 9;
       a.vsum_out = th ? sums + 7 : nullptr;
       a.end = 1;
       a.start = step < nsteps;
-      MD_CK(launch_sum_npt(sa, a, s));
+      MD_CK(launch_sum_npt(th ? sa : sb, a, s));
       if (th && (st = row_out((double)step)) != MD_OK) return st;
       if (step < nsteps) {
         bin.xq = xqs[(step + 1) & 1];

@@ -33,6 +33,7 @@ struct FK {
   double* __restrict__ f;
   double* __restrict__ eatom;
   double* __restrict__ vatom;
+  double* __restrict__ vtrace;
   int* clear;
   IntArgs in;
 };
@@ -277,6 +278,13 @@ struct Acc {
     fy = fma(g, dy, fy);
     fz = fma(g, dz, fz);
   }
+  // the diagonal of add_virial alone, with the same arithmetic
+  __device__ inline void add_trace(double g, double dx, double dy, double dz) {
+    const double gx = g * dx, gy = g * dy;
+    w0 = fma(gx, dx, w0);
+    w1 = fma(gy, dy, w1);
+    w2 = fma(g * dz, dz, w2);
+  }
   __device__ inline void add_virial(double g, double dx, double dy, double dz) {
     const double gx = g * dx, gy = g * dy;
     w0 = fma(gx, dx, w0);
@@ -287,10 +295,15 @@ struct Acc {
     w5 = fma(gy, dz, w5);
   }
   template <int K>
-  __device__ inline void reduce(bool ev) {
+  __device__ inline void reduce(bool ev, bool tr = false) {
     fx = group_sum<K>(fx);
     fy = group_sum<K>(fy);
     fz = group_sum<K>(fz);
+    if (tr && !ev) {
+      w0 = group_sum<K>(w0);
+      w1 = group_sum<K>(w1);
+      w2 = group_sum<K>(w2);
+    }
     if (ev) {
       e = group_sum<K>(e);
       w0 = group_sum<K>(w0);
@@ -301,7 +314,8 @@ struct Acc {
       w5 = group_sum<K>(w5);
     }
   }
-  // Pair energy and virial are split half to each atom of the pair.
+  // Pair energy and virial are split half to each atom of the pair.  With
+  // tr (a trace-only kernel) or ev, a.vtrace (if set) gets the virial trace.
   __device__ inline void store(const FK& a, int i, bool ev, double e_extra) const {
     const int n = a.n;
     a.f[i] = fx;
@@ -309,8 +323,10 @@ struct Acc {
     a.f[2 * n + i] = fz;
     store_ev(a, i, ev, e_extra);
   }
-  __device__ inline void store_ev(const FK& a, int i, bool ev, double e_extra) const {
+  __device__ inline void store_ev(const FK& a, int i, bool ev, double e_extra,
+                                  bool tr = false) const {
     const int n = a.n;
+    if ((ev || tr) && a.vtrace) a.vtrace[i] = (0.5 * w0 + 0.5 * w1) + 0.5 * w2;
     if (ev) {
       if (a.eatom) a.eatom[i] = 0.5 * e + e_extra;
       if (a.vatom) {
@@ -336,7 +352,8 @@ struct Acc {
 template <bool FUSED>
 __device__ inline void finish_atom_with(const FK& a, const Acc& acc, int i, bool own, double xi,
                                         double yi, double zi, bool ev, double e_extra,
-                                        const double* vi, const double* xri) {
+                                        const double* vi, const double* xri,
+                                        bool tr = false) {
   const IntArgs& in = a.in;
   if (!FUSED) {
     if (own) acc.store(a, i, ev, e_extra);
@@ -346,7 +363,7 @@ __device__ inline void finish_atom_with(const FK& a, const Acc& acc, int i, bool
   bool finite = true;
   double xn[3] = {0.0, 0.0, 0.0}, dd[3] = {0.0, 0.0, 0.0};
   if (own) {
-    acc.store_ev(a, i, ev, e_extra);
+    acc.store_ev(a, i, ev, e_extra, tr);
     const double fq[3] = {acc.fx, acc.fy, acc.fz};
     const double xo[3] = {xi, yi, zi};
     double vh[3];
@@ -404,10 +421,11 @@ __device__ inline void load_int_state(const FK& a, int i, bool own, double* vi, 
 
 template <bool FUSED>
 __device__ inline void finish_atom(const FK& a, const Acc& acc, int i, bool own, double xi,
-                                   double yi, double zi, bool ev, double e_extra) {
+                                   double yi, double zi, bool ev, double e_extra,
+                                   bool tr = false) {
   double vi[3] = {0.0, 0.0, 0.0}, xri[3] = {0.0, 0.0, 0.0};
   if (FUSED) load_int_state(a, i, own, vi, xri);
-  finish_atom_with<FUSED>(a, acc, i, own, xi, yi, zi, ev, e_extra, vi, xri);
+  finish_atom_with<FUSED>(a, acc, i, own, xi, yi, zi, ev, e_extra, vi, xri, tr);
 }
 
 // The kernel's view of its arguments with the box taken from device memory
@@ -440,12 +458,17 @@ __device__ inline void lj_pair(double s, const LJK& p, double& g, double& phi) {
 
 // FP32-mixed instances without energy / virial are held to six waves per
 // SIMD (at most 80 VGPRs, reached without spills): the K = 4 fused kernel
-// runs 2 % faster.  The others keep the compiler's choice: six waves made the
+// runs 2 % faster.  The trace-only ones are too, up to K = 8 (beyond, they
+// would spill).  The others keep the compiler's choice: six waves made the
 // FP64 kernel 9 % slower and the energy / virial one spill.
-constexpr int lj_waves_per_eu(int prec, bool ev) { return prec == MD_MIXED && !ev ? 6 : 1; }
+constexpr int lj_waves_per_eu(int prec, bool ev, bool tr, int k) {
+  return prec == MD_MIXED && !ev && (!tr || k <= 8) ? 6 : 1;
+}
 
-template <int PREC, bool EV, int K, bool FUSED>
-__global__ __launch_bounds__(kBlock, lj_waves_per_eu(PREC, EV)) void k_lj(FK a0, LJK p) {
+// TR (with EV false): the virial's diagonal only, for its trace (a.vtrace),
+// as the barostat's steps without a thermo row need it.
+template <int PREC, bool EV, int K, bool FUSED, bool TR = false>
+__global__ __launch_bounds__(kBlock, lj_waves_per_eu(PREC, EV, TR, K)) void k_lj(FK a0, LJK p) {
   const FK a = with_box(a0);
   if (a.clear && blockIdx.x == 0 && threadIdx.x == 0) *a.clear = 0;
   const Lane<K> ln(a);
@@ -467,11 +490,13 @@ __global__ __launch_bounds__(kBlock, lj_waves_per_eu(PREC, EV)) void k_lj(FK a0,
       if (EV) {
         acc.e += use ? phi - p.ecut : 0.0;
         acc.add_virial(g, b.dx[u], b.dy[u], b.dz[u]);
+      } else if (TR) {
+        acc.add_trace(g, b.dx[u], b.dy[u], b.dz[u]);
       }
     }
   });
-  if (K > 1) acc.reduce<K>(EV);
-  finish_atom<FUSED>(a, acc, ln.i, ln.live && ln.s == 0, xi, yi, zi, EV, 0.0);
+  if (K > 1) acc.reduce<K>(EV, TR);
+  finish_atom<FUSED>(a, acc, ln.i, ln.live && ln.s == 0, xi, yi, zi, EV, 0.0, TR);
 }
 
 // ---------------------------------------------------- LJ, LDS-tiled --
@@ -1110,6 +1135,7 @@ FK make_fk(const ForceArgs& a) {
   k.f = a.f;
   k.eatom = a.ev.eatom;
   k.vatom = a.ev.vatom;
+  k.vtrace = a.ev.vtrace;
   k.clear = a.clear;
   k.in = a.in;
   return k;
@@ -1169,7 +1195,7 @@ hipError_t launch_pack_positions(const double* x, int n, double* xq, const int* 
 static hipError_t launch_lj_tile(const ForceArgs& a, const LJK& p, int prec, int lanes,
                                  hipStream_t s) {
   const FK k = make_fk(a);
-  const bool ev = a.ev.eatom || a.ev.vatom;
+  const bool ev = a.ev.eatom || a.ev.vatom || a.ev.vtrace;
   const TileArgs ta{a.tile, a.cell_start, a.tg};
   const unsigned grid = (unsigned)tile_nruns(a.tg);
   const bool fused = a.in.mode != MD_INT_NONE;
@@ -1202,10 +1228,16 @@ hipError_t launch_lj(const ForceArgs& a, const LJK& p, int prec, int lanes, hipS
   if (lanes & MD_LAYOUT_TILE) return launch_lj_tile(a, p, prec, lanes & ~MD_LAYOUT_TILE, s);
   const FK k = make_fk(a);
   const bool ev = a.ev.eatom || a.ev.vatom;
+  const bool fused = a.in.mode != MD_INT_NONE;
+  const bool tr = !ev && a.ev.vtrace;   // the trace alone: fused kernels only
+  if (tr && !fused) return hipErrorInvalidValue;
   return with_lanes(lanes, [&](auto kc) -> hipError_t {
     constexpr int K = decltype(kc)::value;
     const unsigned g = grid_for(a.n, K);
-    const bool fused = a.in.mode != MD_INT_NONE;
+    if (tr)
+      return prec == MD_FP64
+                 ? launch_timed(k_lj<MD_FP64, false, K, true, true>, g, s, a.t0, a.t1, k, p)
+                 : launch_timed(k_lj<MD_MIXED, false, K, true, true>, g, s, a.t0, a.t1, k, p);
     if (prec == MD_FP64) {
       if (fused)
         return ev ? launch_timed(k_lj<MD_FP64, true, K, true>, g, s, a.t0, a.t1, k, p)
@@ -1223,7 +1255,7 @@ hipError_t launch_lj(const ForceArgs& a, const LJK& p, int prec, int lanes, hipS
 
 hipError_t launch_lj_half(const ForceArgs& a, const LJK& p, int prec, int lanes, hipStream_t s) {
   const FK k = make_fk(a);
-  const bool ev = a.ev.eatom || a.ev.vatom;
+  const bool ev = a.ev.eatom || a.ev.vatom || a.ev.vtrace;
   return with_lanes(lanes, [&](auto kc) -> hipError_t {
     constexpr int K = decltype(kc)::value;
     const unsigned g = grid_for(a.n, K);
@@ -1237,7 +1269,7 @@ hipError_t launch_lj_half(const ForceArgs& a, const LJK& p, int prec, int lanes,
 
 hipError_t launch_buck(const ForceArgs& a, const BuckK& p, int prec, int lanes, hipStream_t s) {
   const FK k = make_fk(a);
-  const bool ev = a.ev.eatom || a.ev.vatom;
+  const bool ev = a.ev.eatom || a.ev.vatom || a.ev.vtrace;
   return with_lanes(lanes, [&](auto kc) -> hipError_t {
     constexpr int K = decltype(kc)::value;
     const unsigned g = grid_for(a.n, K);
@@ -1260,7 +1292,7 @@ hipError_t launch_buck(const ForceArgs& a, const BuckK& p, int prec, int lanes, 
 hipError_t launch_sc(const ForceArgs& a, const SCK& p, int prec, int lanes, double* sc_e,
                      hipStream_t s) {
   const FK k = make_fk(a);
-  const bool ev = a.ev.eatom || a.ev.vatom;
+  const bool ev = a.ev.eatom || a.ev.vatom || a.ev.vtrace;
   return with_lanes(lanes, [&](auto kc) -> hipError_t {
     constexpr int K = decltype(kc)::value;
     const unsigned g = grid_for(a.n, K);

@@ -170,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_sum_stage1(SumArgs a) {
   for (int i = b0 + threadIdx.x; i < b1; i += kBlock) {
 #pragma unroll
     for (int c = 0; c < kReduceCols; ++c)
-      if (c < a.cols) s[c] += a.col[c][i];
+      if (c < a.cols && a.col[c]) s[c] += a.col[c][i];
   }
   block_sums<kBlock>(s, a.cols, sh);
   if (threadIdx.x == 0) {
@@ -280,7 +280,7 @@ __device__ void npt_update(const NptArgs& a) {
   double L[3] = {st[kNptL], st[kNptL + 1], st[kNptL + 2]};
   const double lref = st[kNptLref];
   double vol = L[0] * L[1] * L[2];
-  const double trw = a.sums[1] + a.sums[2] + a.sums[3];
+  const double trw = *a.trw;
   const double vs = a.vsum ? *a.vsum : 0.0;
   double ke2 = a.vsum ? a.mke * vs : st[kNptKe2];
   NhcArgs c{};

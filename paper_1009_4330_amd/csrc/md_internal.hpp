@@ -193,6 +193,11 @@ struct BuckK {
 struct EVOut {
   double* eatom;   // [n] or null
   double* vatom;   // [6][n] or null
+  // [n] or null: half atom i's virial trace (w_xx + w_yy) + w_zz, the value
+  // the barostat sums.  Alone (eatom and vatom null) it asks the LJ kernel for
+  // that trace only, with fused integration; the other kernels then evaluate
+  // everything and store just the trace.
+  double* vtrace;
 };
 
 // Workspace carve-up (offsets in bytes from the workspace base).
@@ -208,6 +213,7 @@ struct WsLayout {
   size_t eatom;      // double [n]
   size_t vatom;      // double [6][n]
   size_t keatom;     // double [n]
+  size_t vtrace;     // double [n]        virial trace (NPT)
   size_t sc_e;       // double [n]        Sutton-Chen rho^-1/2
   size_t partials;   // double [kReduceBlocks][kReduceCols]
   size_t scalars;    // double [16]       reduced values
@@ -498,8 +504,9 @@ struct ParamArgs {
   double* gparam = nullptr;
 };
 
-// Deterministic sums: cols arrays of n doubles (col c at base[c] ) -> out[cols];
-// then, with params.kind set, the adjoint's parameter gradients from out.
+// Deterministic sums: cols arrays of n doubles (col c at base[c]; a null
+// column sums to 0) -> out[cols]; then, with params.kind set, the adjoint's
+// parameter gradients from out.
 struct SumArgs {
   const double* col[kReduceCols];
   int cols;
@@ -560,11 +567,11 @@ struct NptArgs {
   int nc[3];            // cell grid of the run: the box must keep L_d >= nc_d rl
   int* status;
   const double* vsum;   // sum v^2 (from the sums), or null: the carried kinetic term
-  const double* sums;   // pe, w0..w5 (the virial trace enters G_eps)
+  const double* trw;    // the virial trace summed over the atoms (enters G_eps)
   double* vsum_out;     // nullable: sum v^2 after the closing half step (thermo)
   int end, start;
 };
-// Barostat / thermostat update (one thread) at the end of the sum's last
+// Barostat / thermostat update (the first wavefront) at the end of the sum's last
 // stage: with end, the closing half of a step (G_eps half step, particle
 // chain, barostat chain; the extended energy stored); with start, the
 // opening half of the next (barostat chain, particle chain, G_eps half step,
