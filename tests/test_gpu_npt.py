@@ -2,8 +2,9 @@
 Tobias and Klein with Nose-Hoover chains on the particles and the barostat):
 thermo rows (energies, temperature, pressure, the conserved extended energy,
 the volume), rebuild steps, final positions, velocities and box; the
-frozen-barostat limit against the library's own NVT run bit for bit; a run
-split over two calls; FP32-mixed against the FP64 oracle."""
+frozen-barostat limit against the library's own NVT run bit for bit; the
+trajectory independent of the thermo interval; a run split over two calls;
+FP32-mixed against the FP64 oracle."""
 import numpy as np
 import pytest
 
@@ -61,6 +62,26 @@ def test_npt_frozen_barostat_equals_nvt(orc):
     rb = np.concatenate([b.setup(True), b.run(60, 10)])
     assert tuple(a.box.L) == tuple(box)
     assert np.array_equal(ra[:, :8], rb[:, :8])
+    for ta, tb in zip(a.host_state(), b.host_state()):
+        assert np.array_equal(ta, tb)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_npt_thermo_interval_leaves_trajectory(orc, prec):
+    """Steps with a thermo row evaluate energy and virial, the others the
+    virial's trace alone; the barostat sums the same per-atom trace column
+    either way, so thermo rows every 7 steps or only at the end leave the
+    trajectory and the box the same bit for bit."""
+    w = W
+    x, v, box = I.initial_state(w)
+    a = MDSystem(w, x, v, prec, "k4", npt=NPT)
+    a.setup(False)
+    ra = a.run(60, 7)
+    b = MDSystem(w, x, v, prec, "k4", npt=NPT)
+    b.setup(False)
+    b.run(60, 60)
+    assert len(ra) == 8 and tuple(a.box.L) == tuple(b.box.L)
+    assert tuple(a.box.L) != tuple(box)
     for ta, tb in zip(a.host_state(), b.host_state()):
         assert np.array_equal(ta, tb)
 
