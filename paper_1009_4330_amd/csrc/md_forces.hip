@@ -456,13 +456,16 @@ __device__ inline void lj_pair(double s, const LJK& p, double& g, double& phi) {
   }
 }
 
-// FP32-mixed instances without energy / virial are held to six waves per
-// SIMD (at most 80 VGPRs, reached without spills): the K = 4 fused kernel
-// runs 2 % faster.  The trace-only ones are too, up to K = 8 (beyond, they
-// would spill).  The others keep the compiler's choice: six waves made the
-// FP64 kernel 9 % slower and the energy / virial one spill.
+// FP32-mixed instances without energy / virial and with K >= 4 lanes per
+// atom are held to six waves per SIMD (at most 80 VGPRs, reached without
+// spills): on the 256k melt the fused kernel runs 2 % faster at K = 4, 5 % at
+// K = 8, 1 % at K = 16, but 6 % slower at K = 1 and 3.5 % at K = 2, which
+// keep the compiler's choice.  The trace-only ones are capped for K = 4 and 8
+// (beyond, they would spill).  FP64 and energy / virial instances keep the
+// compiler's choice too: six waves made the FP64 kernel 9 % slower and the
+// energy / virial one spill.
 constexpr int lj_waves_per_eu(int prec, bool ev, bool tr, int k) {
-  return prec == MD_MIXED && !ev && (!tr || k <= 8) ? 6 : 1;
+  return prec == MD_MIXED && !ev && k >= 4 && (!tr || k <= 8) ? 6 : 1;
 }
 
 // TR (with EV false): the virial's diagonal only, for its trace (a.vtrace),
