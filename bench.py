@@ -11,7 +11,7 @@ reported beside it; each of those extras is guarded so that its failure
 cannot suppress the headline line.
 
 Each "step" is one full velocity-Verlet step of md_step: the rebuild chain
-when the half-skin check fired (count, gather-sort, list), then the force
+when the half-skin check fired (sort, list), then the force
 kernel, which also does the closing kick, the next kick, drift and check;
 thermo output every min(100, steps) steps.  Inputs are resident in HBM before
 the timed region starts.  The roofline object describes that force kernel

@@ -426,7 +426,7 @@ WsLayout ws_layout(int64_t n, int64_t ncell) {
   L.sc_e = take(sizeof(double) * nn);
   L.partials = take(sizeof(double) * kReduceBlocks * kReduceCols);
   L.scalars = take(sizeof(double) * 16);
-  L.scount = take(sizeof(int) * (size_t)(((ncell > 0 ? ncell : 1) >> kSuperShift) + 1));
+  L.sortlb = take(sizeof(unsigned long long) * sort_words(ncell > 0 ? ncell : 1));
   L.new_start = take(sizeof(int) * (size_t)((ncell > 0 ? ncell : 1) + 1));
   L.xq = take(sizeof(double) * 4 * nn);
   L.xq2 = take(sizeof(double) * 4 * nn);
@@ -938,8 +938,9 @@ static md_status step_impl(md_state* stt, const md_potential* p, md_box* box,
   // NPT: every force pass leaves each atom's virial trace, which the barostat sums
   double* const vtrace = npt ? at<double>(ws, L.vtrace) : nullptr;
 
-  int* scount = at<int>(ws, L.scount);
-
+  // the rebuild sort's look-back words, zeroed for this call's first sort
+  unsigned long long* const sortlb = at<unsigned long long>(ws, L.sortlb);
+  MD_CK(launch_sort_clear(sortlb, ncell, s));
   int* new_start = at<int>(ws, L.new_start);
   // packed positions: the setup build and the force kernels read xq[0]
   // first; each fused step reads one buffer and drifts into the other
@@ -949,17 +950,16 @@ static md_status step_impl(md_state* stt, const md_potential* p, md_box* box,
   // count, scan, scatter, stable in-cell order with the state gathered into
   // staging, list build that copies the state back.  During a run (gated;
   // atoms in the previous build's cell order, their new cells recorded by the
-  // drift kernel): per-cell counts from the previous ranges, gather-sort with
-  // the new cell starts, list build, which also copies the new starts into
-  // cells->cell_start.  Gated kernels return at once unless the rebuild flag
-  // is set.
+  // drift kernel): one sort kernel (per-cell counts from the previous ranges,
+  // new cell starts, the state gathered into staging), list build, which also
+  // copies the new starts into cells->cell_start.  Gated kernels return at
+  // once unless the rebuild flag is set.
   auto rebuild = [&](const int* g, int layout, double* xq) -> md_status {
     int* starts = g ? new_start : cells->cell_start;
     if (g) {
-      MD_CK(launch_cell_count(cells->cell_start, cells->atom_cell, nc, count, scount, g, s));
-      MD_CK(launch_gather_sort(cells->cell_start, new_start, count, scount, cells->atom_cell, nc,
-                               bk, boxd, cells->perm, xq, stt->v, stt->id, type, n, sx, sv, sid,
-                               stype, status, g, s));
+      MD_CK(launch_sort_cells(cells->cell_start, new_start, cells->atom_cell, nc, bk, boxd,
+                              cells->perm, xq, stt->v, stt->id, type, n, sx, sv, sid, stype,
+                              status, sortlb, g, s));
     } else {
       MD_CK(launch_fill_int(count, ncell, 0, s));
       MD_CK(launch_bin_count(stt->x, n, bk, nc, cells->atom_cell, count, slot, s));

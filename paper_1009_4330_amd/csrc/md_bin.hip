@@ -272,60 +272,10 @@ __device__ inline void seg_cells(const Segs& S, int lane, const int* __restrict_
   }
 }
 
-// One wavefront per new cell, 16 per workgroup (one super-cell at a time,
-// a resident grid looping over them): the number of atoms of the surrounding
-// old ranges whose new cell this is, and the super-cell's total.  Plain
-// stores only.
-constexpr int kCountBlock = kWave * kSuperCells;
-
-// Counts of the 16 cells of super-cell sc (one wavefront per cell) and their total.
-__device__ inline void cell_count_super(const int* __restrict__ old_start,
-                                        const int* __restrict__ atom_cell, int nc0, int nc1,
-                                        int nc2, int* __restrict__ count, int* __restrict__ scount,
-                                        int sc, int lane, int wave, int* part) {
-  const int cell = __builtin_amdgcn_readfirstlane(sc * kSuperCells + wave);
-  const int nc[3] = {nc0, nc1, nc2};
-  int cnt = 0;
-  if (cell < nc0 * nc1 * nc2) {
-    const Segs S = old_segments(cell, lane, nc, old_start);
-    if (S.fits) {
-      int cid[kMaxSegs][2], sb[kMaxSegs];
-      seg_cells(S, lane, atom_cell, cid, sb);
-#pragma unroll
-      for (int q = 0; q < kMaxSegs; ++q)
-        cnt += __popcll(__ballot(cid[q][0] == cell)) + __popcll(__ballot(cid[q][1] == cell));
-    } else {
-      for (int q = 0; q < S.n; ++q) {
-        const int b = __builtin_amdgcn_readlane(S.b, q);
-        const int len = __builtin_amdgcn_readlane(S.len, q);
-        for (int t = 0; t < len; t += kWave)
-          cnt += __popcll(__ballot(t + lane < len && atom_cell[b + t + lane] == cell));
-      }
-    }
-    if (lane == 0) count[cell] = cnt;
-  }
-  if (lane == 0) part[wave] = cnt;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int tot = 0;
-#pragma unroll
-    for (int w = 0; w < kSuperCells; ++w) tot += part[w];
-    scount[sc] = tot;
-  }
-  __syncthreads();   // part is reused by the next super-cell
-}
-
-__global__ __launch_bounds__(kCountBlock) void k_cell_count(
-    const int* __restrict__ old_start, const int* __restrict__ atom_cell, int nc0, int nc1,
-    int nc2, int* __restrict__ count, int* __restrict__ scount, const int* __restrict__ gate) {
-  if (gate && *gate == 0) return;
-  __shared__ int part[kSuperCells];
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int ncell = nc0 * nc1 * nc2;
-  const BlockRange br = xcd_range((ncell + kSuperCells - 1) / kSuperCells);
-  for (int sc = br.first; sc < br.end; sc += br.step)
-    cell_count_super(old_start, atom_cell, nc0, nc1, nc2, count, scount, sc, lane, wave, part);
-}
+// The rebuild sort's super-cells (consecutive cells in the cell order, one
+// wavefront each) and its workgroup.
+constexpr int kSortCells = 16;
+constexpr int kSortBlock = kWave * kSortCells;
 
 // Gather member i into sorted slot p: its position from the packed records
 // (wrapped into the box), velocity and id from the state.
@@ -350,47 +300,24 @@ __device__ inline void put_member(int i, int p, int n, const BoxK& box,
   if (stype) stype[p] = type[i];
 }
 
-// Rebuild-time sort of atoms that are already in the previous build's cell
-// order and have moved less than a cell edge since: one wavefront per new
-// cell collects its members from the old ranges of the surrounding cells,
-// visited in increasing cell index (so in increasing atom index), which is the
-// stable counting-sort order without any atomic arrival slots.  The state is
-// gathered into the sorted staging buffers.  The cell's first slot is the
-// count of all earlier cells: the super-cell totals before its super-cell
-// plus the counts of the earlier cells of its own; it is written to
-// new_start.  If the counts do not add up to n, status bit 2 is set.
-__device__ inline void gather_cell(
-    const int* __restrict__ old_start, int* __restrict__ new_start,
-    const int* __restrict__ count, const int* __restrict__ scount,
-    const int* __restrict__ atom_cell, int nc0, int nc1, int nc2, const BoxK& box,
-    int* __restrict__ perm, const double* __restrict__ xq, const double* __restrict__ v,
-    const int* __restrict__ id, const int* __restrict__ type, int n, double* __restrict__ sx,
-    double* __restrict__ sv, int* __restrict__ sid, int* __restrict__ stype,
-    int* __restrict__ status, int cell, int lane, int* row) {
-  const int ncell = nc0 * nc1 * nc2;
-  const int nc[3] = {nc0, nc1, nc2};
-  const Segs S = old_segments(cell, lane, nc, old_start);
-  const int sc = cell >> kSuperShift;
-  int part = 0;
-  for (int q = lane; q < sc; q += kWave) part += scount[q];
-  if ((sc << kSuperShift) + lane < cell) part += count[(sc << kSuperShift) + lane];
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, kWave);
-  const int base = part;
-  const int want = count[cell];
-  if (lane == 0) {
-    new_start[cell] = base;
-    if (cell == ncell - 1) {
-      new_start[ncell] = base + want;
-      if (base + want != n) atomicOr(&status[MD_ST_ERRORS], 4);
-    }
-  }
+// Members of new cell `cell` among the previous build's atoms around it, in
+// increasing atom index (the previous order, so the stable counting-sort
+// order, with no atomic arrival slots), gathered into sorted slots
+// base .. base + want - 1.  With short segments (S.fits) the candidates' new
+// cells are the registers cid / sb that seg_cells filled; otherwise they are
+// read again.  Fewer or more members than want sets status bit 2.
+__device__ inline void gather_members(const Segs& S, const int (*cid)[2], const int* sb,
+                                      const int* __restrict__ atom_cell, int cell, int base,
+                                      int want, const BoxK& box, int* __restrict__ perm,
+                                      const double* __restrict__ xq, const double* __restrict__ v,
+                                      const int* __restrict__ id, const int* __restrict__ type,
+                                      int n, double* __restrict__ sx, double* __restrict__ sv,
+                                      int* __restrict__ sid, int* __restrict__ stype,
+                                      int* __restrict__ status, int lane, int* row) {
   const unsigned long long below = (1ull << lane) - 1;
   int found = 0;
   if (S.fits && want <= kWave) {
     // member indices in order into this wave's LDS row, then one gather
-    int cid[kMaxSegs][2], sb[kMaxSegs];
-    seg_cells(S, lane, atom_cell, cid, sb);
 #pragma unroll
     for (int q = 0; q < kMaxSegs; ++q) {
 #pragma unroll
@@ -423,29 +350,137 @@ __device__ inline void gather_cell(
   if (lane == 0 && found != want) atomicOr(&status[MD_ST_ERRORS], 4);
 }
 
-__global__ __launch_bounds__(kBlock) void k_gather_sort(
+// Look-back words of the rebuild sort, one per super-cell: the flag in the
+// top two bits (0: nothing yet, 1: the super-cell's total, 2: its inclusive
+// prefix) and the value in the low 32.  After them: the ticket counter and
+// the count of workgroups that have finished their walk.
+constexpr unsigned long long kLbTotal = 1ull << 62, kLbPrefix = 2ull << 62;
+constexpr int kLbSpinLimit = 1 << 18;   // sleeps before a wait gives up (about 0.1 s)
+
+// Rebuild-time sort of atoms that are already in the previous build's cell
+// order and have moved less than a cell edge since, in one launch: one
+// workgroup of kSortCells wavefronts per super-cell of as many consecutive
+// cells, the super-cells taken in order from a ticket counter.  Each wavefront counts its new cell's
+// members among the previous ranges of the 27 cells around it (keeping the
+// candidates' new cells in registers); the first wavefront publishes the
+// super-cell's total and adds the totals before it by a decoupled look-back:
+// walking down the earlier super-cells 64 at a time (one per lane), the
+// nearest published inclusive prefix ends the walk, published totals are
+// added and the walk goes on.  A workgroup waits only on
+// super-cells whose tickets were taken before its own, by workgroups already
+// running, so every wait ends; each wait is bounded all the same, and giving
+// up sets status bit 2.  Then every wavefront writes its cell's start and
+// gathers the state into the sorted staging buffers (positions wrapped into
+// the box).  The last workgroup to finish its walk clears the words and both
+// counters for the next rebuild (they start zeroed: launch_sort_clear).
+// Status bit 2 is also set if the counts do not add up to n (an atom moved
+// further than a cell edge).
+__global__ __launch_bounds__(kSortBlock) void k_sort_cells(
     const int* __restrict__ old_start, int* __restrict__ new_start,
-    const int* __restrict__ count, const int* __restrict__ scount,
     const int* __restrict__ atom_cell, int nc0, int nc1, int nc2, BoxK box0,
     const double* __restrict__ boxd, int* __restrict__ perm, const double* __restrict__ xq,
     const double* __restrict__ v, const int* __restrict__ id, const int* __restrict__ type, int n,
     double* __restrict__ sx, double* __restrict__ sv, int* __restrict__ sid,
-    int* __restrict__ stype, int* __restrict__ status, const int* __restrict__ gate) {
+    int* __restrict__ stype, int* __restrict__ status, unsigned long long* __restrict__ lb,
+    const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
-  const BoxK box = boxd ? box_load(boxd) : box0;
-  __shared__ int members[kBlock];
+  __shared__ int part[kSortCells];
+  __shared__ int rows[kSortCells * kWave];
+  __shared__ int sh_sc, sh_pre, sh_last;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int ncell = nc0 * nc1 * nc2;
-  constexpr int kCells = kBlock / kWave;   // cells per logical block
-  const BlockRange br = xcd_range((ncell + kCells - 1) / kCells);
-  for (int lb = br.first; lb < br.end; lb += br.step) {
-    const int cell = lb * kCells + wave;
-    if (cell < ncell)
-      gather_cell(old_start, new_start, count, scount, atom_cell, nc0, nc1, nc2, box, perm, xq,
-                  v, id, type, n, sx, sv, sid, stype, status, cell, lane,
-                  members + wave * kWave);
+  const int nsuper = (ncell + kSortCells - 1) / kSortCells;
+  unsigned* const ticket = reinterpret_cast<unsigned*>(lb + nsuper);
+  unsigned* const done = reinterpret_cast<unsigned*>(lb + nsuper + 1);
+  if (threadIdx.x == 0) sh_sc = (int)atomicAdd(ticket, 1u);
+  __syncthreads();
+  const int sc = sh_sc;
+  const int nc[3] = {nc0, nc1, nc2};
+  const int cell = __builtin_amdgcn_readfirstlane(sc * kSortCells + wave);
+  const bool live = cell < ncell;
+  Segs S{};
+  int cid[kMaxSegs][2], sb[kMaxSegs];
+  int cnt = 0;
+  if (live) {
+    S = old_segments(cell, lane, nc, old_start);
+    if (S.fits) {
+      seg_cells(S, lane, atom_cell, cid, sb);
+#pragma unroll
+      for (int q = 0; q < kMaxSegs; ++q)
+        cnt += __popcll(__ballot(cid[q][0] == cell)) + __popcll(__ballot(cid[q][1] == cell));
+    } else {
+      for (int q = 0; q < S.n; ++q) {
+        const int b = __builtin_amdgcn_readlane(S.b, q);
+        const int len = __builtin_amdgcn_readlane(S.len, q);
+        for (int t = 0; t < len; t += kWave)
+          cnt += __popcll(__ballot(t + lane < len && atom_cell[b + t + lane] == cell));
+      }
+    }
   }
+  if (lane == 0) part[wave] = cnt;
+  __syncthreads();
+  if (wave == 0) {
+    int tot = 0;
+#pragma unroll
+    for (int w = 0; w < kSortCells; ++w) tot += part[w];
+    if (lane == 0)
+      __hip_atomic_store(lb + sc, kLbTotal | (unsigned)tot, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    // the walk, 64 super-cells per step: lane l reads super-cell top - l (the
+    // box's start, below super-cell 0, reads as a prefix of 0) until every
+    // lane has a word; the nearest prefix ends the walk, else all 64 totals
+    // are added and the walk moves 64 further down
+    int pre = 0;
+    bool ok = true;
+    for (int top = sc - 1; top >= 0 && ok; top -= kWave) {
+      const int j = top - lane;
+      unsigned long long w = j >= 0 ? 0 : kLbPrefix;
+      for (int spin = 0;; ++spin) {
+        if (j >= 0 && (w >> 62) == 0)
+          w = __hip_atomic_load(lb + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__ballot((w >> 62) == 0) == 0) break;
+        if (spin == kLbSpinLimit) {
+          ok = false;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      const unsigned long long pm = __ballot((w >> 62) == 2);
+      // lanes up to and including the nearest prefix (all 64 if none)
+      const int upto = pm ? __builtin_ctzll(pm) : kWave - 1;
+      int val = lane <= upto ? (int)(unsigned)w : 0;
+#pragma unroll
+      for (int off = kWave / 2; off > 0; off >>= 1) val += __shfl_xor(val, off, kWave);
+      pre += val;
+      if (pm) break;
+    }
+    if (lane == 0) {
+      if (!ok) atomicOr(&status[MD_ST_ERRORS], 4);
+      __hip_atomic_store(lb + sc, kLbPrefix | (unsigned)(pre + tot), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      sh_pre = pre;
+      sh_last = atomicAdd(done, 1u) == (unsigned)(nsuper - 1);
+    }
+  }
+  __syncthreads();
+  if (sh_last) {
+    // every walk has ended: nothing reads the words any more
+    for (int k = threadIdx.x; k < nsuper + 2; k += kSortBlock) lb[k] = 0;
+  }
+  if (!live) return;
+  int base = sh_pre;
+  for (int w = 0; w < wave; ++w) base += part[w];
+  if (lane == 0) {
+    new_start[cell] = base;
+    if (cell == ncell - 1) {
+      new_start[ncell] = base + cnt;
+      if (base + cnt != n) atomicOr(&status[MD_ST_ERRORS], 4);
+    }
+  }
+  const BoxK box = boxd ? box_load(boxd) : box0;
+  gather_members(S, cid, sb, atom_cell, cell, base, cnt, box, perm, xq, v, id, type, n, sx, sv,
+                 sid, stype, status, lane, rows + wave * kWave);
 }
 
 __global__ __launch_bounds__(kBlock) void k_copy_back(double* __restrict__ x,
@@ -1523,14 +1558,6 @@ hipError_t launch_bin_count(double* x, int n, BoxK box, const int nc[3], int* at
   return hipGetLastError();
 }
 
-hipError_t launch_cell_count(const int* old_start, const int* atom_cell, const int nc[3],
-                             int* count, int* scount, const int* gate, hipStream_t s) {
-  const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
-  k_cell_count<<<resident_grid(2, blocks_for(ncell, kSuperCells)), kCountBlock, 0, s>>>(
-      old_start, atom_cell, nc[0], nc[1], nc[2], count, scount, gate);
-  return hipGetLastError();
-}
-
 hipError_t launch_scatter(const int* atom_cell, const int* slot, const int* cell_start, int n,
                           int* tmp_perm, const int* gate, hipStream_t s) {
   k_scatter<<<blocks_for(n), kBlock, 0, s>>>(atom_cell, slot, cell_start, n, tmp_perm, gate);
@@ -1547,15 +1574,23 @@ hipError_t launch_cell_sort(const int* tmp_perm, const int* cell_start, int ncel
   return hipGetLastError();
 }
 
-hipError_t launch_gather_sort(const int* old_start, int* new_start, const int* count,
-                              const int* scount, const int* atom_cell, const int nc[3], BoxK box,
-                              const double* boxd, int* perm, const double* xq, const double* v,
-                              const int* id, const int* type, int n, double* sx, double* sv,
-                              int* sid, int* stype, int* status, const int* gate, hipStream_t s) {
+size_t sort_words(int64_t ncell) {
+  return (size_t)((ncell + kSortCells - 1) / kSortCells) + 2;
+}
+
+hipError_t launch_sort_clear(unsigned long long* lb, int64_t ncell, hipStream_t s) {
+  return launch_fill_int(reinterpret_cast<int*>(lb), 2 * (int64_t)sort_words(ncell), 0, s);
+}
+
+hipError_t launch_sort_cells(const int* old_start, int* new_start, const int* atom_cell,
+                             const int nc[3], BoxK box, const double* boxd, int* perm,
+                             const double* xq, const double* v, const int* id, const int* type,
+                             int n, double* sx, double* sv, int* sid, int* stype, int* status,
+                             unsigned long long* lb, const int* gate, hipStream_t s) {
   const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
-  k_gather_sort<<<resident_grid(8, blocks_for(ncell * kWave)), kBlock, 0, s>>>(
-      old_start, new_start, count, scount, atom_cell, nc[0], nc[1], nc[2], box, boxd, perm, xq, v,
-      id, type, n, sx, sv, sid, type ? stype : nullptr, status, gate);
+  k_sort_cells<<<(unsigned)((ncell + kSortCells - 1) / kSortCells), kSortBlock, 0, s>>>(
+      old_start, new_start, atom_cell, nc[0], nc[1], nc[2], box, boxd, perm, xq, v, id, type, n,
+      sx, sv, sid, type ? stype : nullptr, status, lb, gate);
   return hipGetLastError();
 }
 

@@ -60,8 +60,6 @@ __device__ inline BlockRange xcd_range(int nb) {
   return BlockRange{lo + local, lo + q + (xcd < r ? 1 : 0), phys};
 }
 
-constexpr int kSuperShift = 4;       // 16 cells per super-cell for the two-level cell scan
-constexpr int kSuperCells = 1 << kSuperShift;
 
 // Periodic box as kernels see it: edges and their reciprocals (the reciprocal
 // only picks the image index; the image shift itself is d - L * k).
@@ -217,7 +215,7 @@ struct WsLayout {
   size_t sc_e;       // double [n]        Sutton-Chen rho^-1/2
   size_t partials;   // double [kReduceBlocks][kReduceCols]
   size_t scalars;    // double [16]       reduced values
-  size_t scount;     // int [ncell/16+1]  per-super-cell counts
+  size_t sortlb;     // u64 [sort_words] look-back words of the rebuild sort
   size_t new_start;  // int [ncell + 1]   cell starts of a rebuild in progress
   size_t xq;         // double [n][4]     packed positions (x, y, z, 0) for the force gathers
   size_t xq2;        // double [n][4]     second packed buffer (md_step alternates the two)
@@ -250,19 +248,20 @@ hipError_t launch_cell_sort(const int* tmp_perm, const int* cell_start, int ncel
                             const int* type, int n, double* sx, double* sv, int* sid,
                             double* sf, int* stype, const int* gate, hipStream_t s);
 // Rebuild-time sort for atoms already in the previous build's cell order that
-// moved less than a cell edge, with atom_cell holding their new cells:
-// launch_cell_count counts each new cell's members among the old ranges of
-// its 27 neighbours (plain stores into count, and per-super-cell sums into
-// scount); launch_gather_sort gathers the state (x wrapped) into staging in
-// the stable order and writes the new cell starts.  Status bit 2 is set if
-// the counts do not add up to n (some atom moved further).
-hipError_t launch_cell_count(const int* old_start, const int* atom_cell, const int nc[3],
-                             int* count, int* scount, const int* gate, hipStream_t s);
-hipError_t launch_gather_sort(const int* old_start, int* new_start, const int* count,
-                              const int* scount, const int* atom_cell, const int nc[3], BoxK box,
-                              const double* boxd, int* perm, const double* xq, const double* v,
-                              const int* id, const int* type, int n, double* sx, double* sv,
-                              int* sid, int* stype, int* status, const int* gate, hipStream_t s);
+// moved less than a cell edge, with atom_cell holding their new cells, in one
+// launch: each new cell's members counted among the old ranges of its 27
+// neighbours, the new cell starts (a decoupled look-back over super-cells of
+// consecutive cells, in the words lb of sort_words(ncell) 64-bit entries, zeroed by
+// launch_sort_clear before the first use and left zeroed by every sort), and
+// the state (x wrapped) gathered into staging in the stable order.  Status
+// bit 2 is set if the counts do not add up to n (some atom moved further).
+size_t sort_words(int64_t ncell);
+hipError_t launch_sort_clear(unsigned long long* lb, int64_t ncell, hipStream_t s);
+hipError_t launch_sort_cells(const int* old_start, int* new_start, const int* atom_cell,
+                             const int nc[3], BoxK box, const double* boxd, int* perm,
+                             const double* xq, const double* v, const int* id, const int* type,
+                             int n, double* sx, double* sv, int* sid, int* stype, int* status,
+                             unsigned long long* lb, const int* gate, hipStream_t s);
 hipError_t launch_copy_back(double* x, double* v, int* id, double* f, double* xr,
                             const double* sx, const double* sv, const int* sid,
                             const double* sf, int n, hipStream_t s);
