@@ -784,22 +784,22 @@ md_status md_force_vjp(const md_potential* p, const double* x, int64_t n, const 
     }
     return MD_OK;
   }
-  double* pe = gparam ? at<double>(ws, L.eatom) : nullptr;
-  double* ps = gparam ? at<double>(ws, L.keatom) : nullptr;
-  MD_CK(launch_lj_vjp(fa, make_lj(p), prec, lanes_of(nl->layout), u, gx, pe, ps, s));
+  // the kernel's workgroups leave their sums of u_i . F_i and of the sigma
+  // term in rows of two in the per-atom energy column (at most n / 2 doubles)
+  double* bp = gparam ? at<double>(ws, L.eatom) : nullptr;
+  int rows = 0;
+  MD_CK(launch_lj_vjp(fa, make_lj(p), prec, lanes_of(nl->layout), u, gx, bp, &rows, s));
   if (gparam) {
     SumArgs sa{};
     sa.cols = 2;
-    sa.col[0] = pe;
-    sa.col[1] = ps;
-    sa.n = (int)n;
-    sa.partials = at<double>(ws, L.partials);
+    sa.nparts = rows;
+    sa.partials = bp;
     sa.out = at<double>(ws, L.scalars);
     // dL/deps = (sum_i u_i . F_i) / eps; the second sum is dL/dsigma already
     sa.params.kind = kParamsLJ;
     sa.params.eps = p->lj_eps;
     sa.params.gparam = gparam;
-    MD_CK(launch_sum(sa, s));
+    MD_CK(launch_sum_parts(sa, s));
   }
   return MD_OK;
 }

@@ -919,13 +919,40 @@ __global__ __launch_bounds__(kBlock) void k_sc_force(FK a0, SCK p,
 
 // ------------------------------------------------------------- LJ VJP --
 
+// Sums of a and b over the workgroup in a fixed order (lane shuffles down
+// each wavefront, then the wavefronts in order), written by thread 0 to
+// out[0], out[1].  Every thread of the workgroup calls it.
+__device__ inline void block_sum2(double a, double b, double* out) {
+  __shared__ double sh[2][kBlock / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    a += __shfl_down(a, off, kWave);
+    b += __shfl_down(b, off, kWave);
+  }
+  if (lane == 0) {
+    sh[0][wave] = a;
+    sh[1][wave] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = sh[0][0], sb = sh[1][0];
+#pragma unroll
+    for (int w = 1; w < kBlock / kWave; ++w) {
+      sa += sh[0][w];
+      sb += sh[1][w];
+    }
+    out[0] = sa;
+    out[1] = sb;
+  }
+}
+
 // gx_i = sum_j [g (u_i - u_j) + 2 g' ((u_i - u_j) . d) d];
 // pe_i = u_i . F_i (for dL/deps = sum pe / eps); ps_i = sum_j (dg/dsigma)(u_i . d).
 template <int PREC, int K>
 __global__ __launch_bounds__(kBlock) void k_lj_vjp(FK a, LJK p, const double* __restrict__ u,
                                                     double* __restrict__ gx,
-                                                    double* __restrict__ pe,
-                                                    double* __restrict__ ps) {
+                                                    double* __restrict__ bp) {
   const Lane<K> ln(a);
   const int n = a.n;
   const int io = ln.live ? ln.i : n - 1;
@@ -982,13 +1009,18 @@ __global__ __launch_bounds__(kBlock) void k_lj_vjp(FK a, LJK p, const double* __
     fz = group_sum<K>(fz);
     dsig = group_sum<K>(dsig);
   }
-  if (!ln.live || ln.s != 0) return;
-  const int i = ln.i;
-  gx[i] = gxa;
-  gx[n + i] = gya;
-  gx[2 * n + i] = gza;
-  if (pe) pe[i] = uxi * fx + uyi * fy + uzi * fz;
-  if (ps) ps[i] = dsig;
+  const bool own = ln.live && ln.s == 0;
+  if (own) {
+    const int i = ln.i;
+    gx[i] = gxa;
+    gx[n + i] = gya;
+    gx[2 * n + i] = gza;
+  }
+  // the workgroup's sums of u_i . F_i and of the sigma term, into its row
+  // of bp (rows in atom order)
+  if (bp)
+    block_sum2(own ? uxi * fx + uyi * fy + uzi * fz : 0.0, own ? dsig : 0.0,
+               bp + 2 * (size_t)xcd_block());
 }
 
 // ------------------------------------------------------- Sutton-Chen VJP --
@@ -1319,14 +1351,15 @@ hipError_t launch_sc(const ForceArgs& a, const SCK& p, int prec, int lanes, doub
 }
 
 hipError_t launch_lj_vjp(const ForceArgs& a, const LJK& p, int prec, int lanes,
-                         const double* u, double* gx, double* pe, double* ps, hipStream_t s) {
+                         const double* u, double* gx, double* bp, int* rows, hipStream_t s) {
   const FK k = make_fk(a);
   return with_lanes(lanes, [&](auto kc) -> hipError_t {
     constexpr int K = decltype(kc)::value;
     const unsigned g = grid_for(a.n, K);
+    if (rows) *rows = (int)g;
     if (prec == MD_FP64)
-      return launch_timed(k_lj_vjp<MD_FP64, K>, g, s, a.t0, a.t1, k, p, u, gx, pe, ps);
-    return launch_timed(k_lj_vjp<MD_MIXED, K>, g, s, a.t0, a.t1, k, p, u, gx, pe, ps);
+      return launch_timed(k_lj_vjp<MD_FP64, K>, g, s, a.t0, a.t1, k, p, u, gx, bp);
+    return launch_timed(k_lj_vjp<MD_MIXED, K>, g, s, a.t0, a.t1, k, p, u, gx, bp);
   });
 }
 

@@ -180,12 +180,24 @@ __global__ __launch_bounds__(kBlock) void k_sum_stage1(SumArgs a) {
   }
 }
 
-// Stage 2's sums: the kReduceBlocks partials of each column, into a.out.
+// Stage 2's sums: the partials of each column, into a.out.  Stage 1's
+// kReduceBlocks rows give each thread one row; other partials (a.nparts
+// rows) are first added row by row, thread t taking rows t, t + kReduceBlocks, ...
 __device__ inline void sum_partials(const SumArgs& a, double* sh) {
   double s[kReduceCols];
+  if (a.nparts == 0) {
 #pragma unroll
-  for (int c = 0; c < kReduceCols; ++c)
-    s[c] = c < a.cols ? a.partials[threadIdx.x * kReduceCols + c] : 0.0;
+    for (int c = 0; c < kReduceCols; ++c)
+      s[c] = c < a.cols ? a.partials[threadIdx.x * kReduceCols + c] : 0.0;
+  } else {
+#pragma unroll
+    for (int c = 0; c < kReduceCols; ++c) s[c] = 0.0;
+    for (int r = threadIdx.x; r < a.nparts; r += kReduceBlocks) {
+#pragma unroll
+      for (int c = 0; c < kReduceCols; ++c)
+        if (c < a.cols) s[c] += a.partials[(size_t)r * a.cols + c];
+    }
+  }
   block_sums<kReduceBlocks>(s, a.cols, sh);
   if (threadIdx.x == 0) {
 #pragma unroll
@@ -451,6 +463,11 @@ hipError_t launch_sum(const SumArgs& a, hipStream_t s, const NhcArgs* nhc) {
     k_sum_stage2<true><<<1, kReduceBlocks, 0, s>>>(a, *nhc);
   else
     k_sum_stage2<false><<<1, kReduceBlocks, 0, s>>>(a, NhcArgs{});
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_parts(const SumArgs& a, hipStream_t s) {
+  k_sum_stage2<false><<<1, kReduceBlocks, 0, s>>>(a, NhcArgs{});
   return hipGetLastError();
 }
 

@@ -462,8 +462,11 @@ hipError_t launch_fill_double(double* p, int64_t count, double value, hipStream_
 hipError_t launch_lj(const ForceArgs& a, const LJK& p, int prec, int kernel, hipStream_t s);
 hipError_t launch_sc(const ForceArgs& a, const SCK& p, int prec, int kernel, double* sc_e,
                      hipStream_t s);
+// LJ force adjoint: gx = (dF/dx)^T u and, with bp set, per-workgroup sums of
+// u_i . F_i and of the sigma term in rows of two doubles (*rows of them, in
+// atom order), for launch_sum_parts.
 hipError_t launch_lj_vjp(const ForceArgs& a, const LJK& p, int prec, int lanes,
-                         const double* u, double* gx, double* pe, double* ps, hipStream_t s);
+                         const double* u, double* gx, double* bp, int* rows, hipStream_t s);
 
 // Integration.
 // scale (device scalar, nullable): v is multiplied by it before the kick.
@@ -513,11 +516,16 @@ struct SumArgs {
   double* partials;
   double* out;
   ParamArgs params;
+  // 0: the partials are stage 1's (kReduceBlocks rows of kReduceCols);
+  // otherwise nparts rows of cols each, written by the caller's kernel
+  int nparts;
 };
 struct NhcArgs;
 // With nhc, the thermostat chain update (launch_nhc) runs at the end of the
 // sum's last stage, on the sums it wrote.
 hipError_t launch_sum(const SumArgs& a, hipStream_t s, const NhcArgs* nhc = nullptr);
+// The last stage alone, over a.nparts rows of partials another kernel wrote.
+hipError_t launch_sum_parts(const SumArgs& a, hipStream_t s);
 // Thermo row from out = {pe, W0..W5, sv} sums.
 struct ThermoArgs {
   const double* sums;  // pe, w0..w5, sum v^2
