@@ -129,9 +129,11 @@ BuckK make_buck(const md_potential* p) {
       const double irho = A > 0.0 ? 1.0 / p->buck_rho[ab] : 0.0;
       const double row[6] = {A, A * irho, irho, p->buck_C[ab], 6.0 * p->buck_C[ab],
                              p->qqr2e * p->q[a] * p->q[b]};
+      // the FP32 row's 1 / rho carries log2(e): e^(-r / rho) = 2^(-r log2(e) / rho)
+      // for the hardware base-2 exponential
       for (int c = 0; c < 6; ++c) {
         k.row[ab][c] = row[c];
-        k.rowf[ab][c] = (float)row[c];
+        k.rowf[ab][c] = (float)(c == 2 ? row[c] * 1.4426950408889634 : row[c]);
       }
     }
   return k;

@@ -775,7 +775,7 @@ __device__ inline void buck_pair(double s, const double* row, const float* rowf,
     const float ri = __builtin_amdgcn_rcpf(r);
     const float r2i = ri * ri;
     const float r6i = r2i * r2i * r2i;
-    const float ex = expf(-r * rowf[2]);
+    const float ex = __builtin_amdgcn_exp2f(-r * rowf[2]);   // rowf[2] = log2(e) / rho
     phi = (double)(rowf[0] * ex - rowf[3] * r6i + rowf[5] * ri);
     g = (double)(ri * (rowf[1] * ex - rowf[4] * r6i * ri + rowf[5] * r2i));
   }

@@ -180,7 +180,8 @@ struct SCK {
 
 // Buckingham + cut Coulomb: per species pair ab = a * 4 + b the row
 // A, A / rho, 1 / rho, C, 6 C, qqr2e q_a q_b (A / rho and 1 / rho are 0 where
-// A is), in FP64 and FP32.
+// A is), in FP64 and FP32 (whose 1 / rho is scaled by log2(e) for a base-2
+// exponential).
 struct BuckK {
   double rc2;
   double row[16][6];
