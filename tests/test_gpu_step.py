@@ -1,5 +1,7 @@
 """md_step (velocity Verlet + half-skin rebuilds, all on the device) against
 the oracle's NVE run from the same seeded state."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -42,6 +44,27 @@ def test_c1_fp64_trajectory_and_rebuild_schedule(orc, kernel, ncell):
     assert np.array_equal(rows[:, 7].astype(int), ref.thermo[:, 7].astype(int))
     assert np.array_equal(rows[:, 0], ref.thermo[:, 0])
     # thermo quantities (pe, ke, etot, T, P)
+    for c in (1, 2, 3, 4, 5):
+        assert rel(rows[:, c], ref.thermo[:, c]) < 1e-10, c
+    assert np.abs(min_image_diff(gx, ref.x, box)).max() < 1e-9
+    assert np.abs(gv - ref.v).max() < 1e-9
+    assert rel(gf, ref.f) < 1e-8
+
+
+def test_dense_cells_trajectory_and_rebuild_schedule(orc):
+    """r_c = 5 on the 4000-atom box: three list cells per dimension with about
+    150 atoms each, so every rebuild of the run sorts cells of more than 64
+    members out of previous ranges longer than 128 atoms (the sort's paths
+    that read the candidates' cells again instead of keeping them in
+    registers)."""
+    w = dataclasses.replace(I.scaled(I.LJ_4K, 10, steps=100), rc=5.0)
+    x, v, box = I.initial_state(w)
+    ref, rows, gx, gv, gf, sysm = run_both(orc, w, x, v, "fp64", "k4", capacity=700)
+    assert sysm.cells.nc[0] == 3 and w.natoms / 27 > 128
+    want_builds = np.cumsum(ref.rebuilt)
+    print(f"[dense] {int(want_builds[-1])} builds in {w.steps} steps", flush=True)
+    assert want_builds[-1] >= 4
+    assert np.array_equal(rows[:, 6].astype(int), want_builds)
     for c in (1, 2, 3, 4, 5):
         assert rel(rows[:, c], ref.thermo[:, c]) < 1e-10, c
     assert np.abs(min_image_diff(gx, ref.x, box)).max() < 1e-9
