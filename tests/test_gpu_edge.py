@@ -1,7 +1,8 @@
 """Degenerate and boundary inputs against the oracle: a single atom, the
 two-atom minimum of md_step in a box of two cells per dimension, a clustered
-system whose cells are mostly empty, and a slab of atoms on cell faces and on
-the box faces (x = 0 and x = L before wrapping)."""
+system whose cells are mostly empty (listed from unsorted atoms, and by
+md_step's row build with its crowded runs), and a slab of atoms on cell faces
+and on the box faces (x = 0 and x = L before wrapping)."""
 import dataclasses
 
 import numpy as np
@@ -60,6 +61,38 @@ def test_clustered_atoms_mostly_empty_cells(orc, layout):
     fr = orc.lj_forces(oc.x, box, ref, 2.5)
     assert_fp64(f, fr.f)
     assert ev[0] == pytest.approx(fr.energy, rel=1e-12)
+
+
+def test_row_build_crowded_runs_against_oracle(orc):
+    """A dense droplet in a dilute box: the mean occupancy (about 9 atoms per
+    list cell) sends md_step's build down the row path, while the runs
+    through the droplet (about 48 per cell) hold more candidates than a run's
+    LDS and are built one cell at a time.  md_step's cell order and list
+    against the oracle's on the same sorted positions."""
+    w = I.scaled(I.LJ_4K, 14, temp=0.5)
+    box = w.box
+    rng = np.random.default_rng(11)
+    ax = np.arange(-8.0, 8.0001, 0.8)
+    g = np.stack(np.meshgrid(ax, ax, ax, indexing="ij")).reshape(3, -1)
+    ball = g[:, (g * g).sum(0) < 64.0] + np.array(box)[:, None] / 2
+    far = np.round(rng.uniform(0, box[0], (3, 200)) / 0.8) * 0.8
+    x_np = np.unique(np.round(np.concatenate([ball, far], axis=1), 9), axis=1)
+    x_np = np.ascontiguousarray(x_np + rng.uniform(-0.02, 0.02, x_np.shape))
+    v_np = np.zeros_like(x_np)
+    s = MDSystem(w, x_np, v_np, "fp64", "k4", capacity=400)
+    s.setup(thermo=False)
+    rl = w.rc + w.skin
+    oc = orc.bin_cells(x_np, box, rl)
+    ncell = len(oc.cell_start) - 1
+    counts = np.diff(oc.cell_start)
+    print(f"[crowded] {x_np.shape[1]} atoms, {ncell} cells, mean {x_np.shape[1] / ncell:.1f}, "
+          f"largest {counts.max()} per cell", flush=True)
+    assert 36 * x_np.shape[1] / ncell < 400 and 36 * np.sort(counts)[-27:].mean() > 960
+    xs = np.ascontiguousarray(oc.x[:, oc.perm])
+    ref, _ = orc.build_nlist(xs, box, rl)
+    assert np.array_equal(s.state.id.cpu().numpy(), oc.perm)
+    assert np.array_equal(gpu_pairs(s.nl), ref.pairs())
+    assert np.array_equal(s.nl.numneigh.cpu().numpy(), ref.numneigh)
 
 
 def test_atoms_on_cell_and_box_faces(orc):
