@@ -34,6 +34,28 @@ def test_autograd_gradients_match_oracle_vjp(orc):
     MB.assert_total(sig.grad.item(), rgp[1], mag["gsig"], u=MB.U64, what="dL/dsigma")
 
 
+@pytest.mark.parametrize("lanes", [1, 2, 8, 16, 32, 64])
+def test_vjp_every_layout_against_oracle(orc, lanes):
+    """md_force_vjp on lists in every layout K against the oracle's VJP (FP64
+    bars): the workgroups leave their partial sums of the parameter
+    gradients in rows whose number grows with K (n K / 256 of them)."""
+    x_np, _, box, _ = lj_liquid(orc, 6, 63)
+    n = x_np.shape[1]
+    u_np = I.random_unit_vectors(n, 64)
+    x, cells, nl, ws, mbox = gpu_list(x_np, box, 2.5, 0.3, lanes, 160)
+    pot = md.lj_potential(2.5, 1.1, 1.05, 0)
+    gx = torch.zeros(3, n, dtype=torch.float64, device="cuda")
+    gp = torch.zeros(2, dtype=torch.float64, device="cuda")
+    md.md_force_vjp(pot, x, mbox, nl, md.MD_FP64, dev(u_np), gx, gp, ws)
+    onl, ocells = orc.build_nlist(x_np, box, 2.8)
+    rgx, rgp = orc.lj_vjp(ocells.x, box, onl, 2.5, 1.1, 1.05, u_np)
+    assert_fp64(gx.cpu().numpy(), rgx, what="gx")
+    mag = MB.lj_magnitudes(ocells.x, box, onl, 2.5, 1.1, 1.05, u_np)
+    gp = gp.cpu().numpy()
+    MB.assert_total(gp[0], rgp[0], mag["geps"], u=MB.U64, what="dL/deps")
+    MB.assert_total(gp[1], rgp[1], mag["gsig"], u=MB.U64, what="dL/dsigma")
+
+
 @pytest.mark.parametrize("prec", [md.MD_FP64, md.MD_MIXED], ids=["fp64", "mixed"])
 def test_force_matching_fit_recovers_parameters(orc, prec):
     """Mean squared force error against the oracle's forces at (1.1, 1.05),
